@@ -1,0 +1,237 @@
+"""Fourier-Chebyshev Stokes solve, steps 2-7 of Sec. 3.4.
+
+Input: the spread monopole density f_i and dipole (torque) density g_i at the
+grid nodes (x_a, y_b, z_c), a = 0..Nx-1, b = 0..Ny-1, c = 0..Nz-1 (Chebyshev
+extrema in z).  The body force is f + (1/2) curl g (eq. fcm); the curl is taken
+spectrally (the paper's GPU route for torques).
+
+Output: the fluid velocity u and half its vorticity, omega = (1/2) curl u, at
+the nodes.
+
+Conventions (readings): x_a = a*h with h = Lx/Nx (full periods Lx, Ly; the
+paper's Sec. 2 writes the box as [-L, L], its later sections use L for the full
+side); k = 2*pi*n/L with n in FFT order; the unnormalised forward DFT and an
+inverse DFT normalised by 1/(Nx*Ny); the Nyquist row and column (n = -N/2)
+are set to zero; eta defaults to 1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import bvp, cheb
+
+
+def wavenumbers(Lx, Ly, Nx, Ny):
+    """k_x (Ny, Nx/2+1), k_y (Ny, Nx/2+1) and the Nyquist mask of rfft2."""
+    nx = np.arange(Nx // 2 + 1)
+    ny = np.fft.fftfreq(Ny, d=1.0 / Ny)
+    kx = 2.0 * np.pi * nx / Lx
+    ky = 2.0 * np.pi * ny / Ly
+    KX, KY = np.meshgrid(kx, ky)
+    nyq = np.zeros(KX.shape, dtype=bool)
+    if Nx % 2 == 0:
+        nyq[:, Nx // 2] = True
+    if Ny % 2 == 0:
+        nyq[Ny // 2, :] = True
+    return KX, KY, nyq
+
+
+def curl(ax, ay, az, ikx, iky, D):
+    """Spectral curl (i k_x, i k_y, d/dz via the Chebyshev derivative D)."""
+    return (iky * az - D(ay), D(ax) - ikx * az, ikx * ay - iky * ax)
+
+
+def dp_solve(box, kx, ky, fx, fy, fz):
+    """DP subproblem for k != 0 columns (Sec. 3.1, step 3 of Sec. 3.4).
+
+    kx, ky: (K,) wavenumbers; fx, fy, fz: (K, Nz) Chebyshev coefficients of
+    the body force.  Returns Chebyshev coefficients (p, u, v, w), each (K, Nz).
+    """
+    H, eta, Nz = box.H, box.eta, box.Nz
+    alt = (-1.0) ** np.arange(Nz)
+    Dz = lambda a: cheb.deriv(a, H, axis=-1)   # noqa: E731
+    k = np.sqrt(kx ** 2 + ky ** 2)
+    A = bvp.robin_matrices(0.5 * k * H, Nz)
+    ikx = (1j * kx)[:, None]
+    iky = (1j * ky)[:, None]
+    # pressure: eq. poissonfs with the Dirichlet-to-Neumann maps eq. DtoNmapp
+    rp = ikx * fx + iky * fy + Dz(fz)
+    zero = np.zeros(k.size)
+    p = bvp.solve(A, bvp.robin_rhs(rp, zero, zero, H))
+    pH = p.sum(axis=-1)          # p(z = H): T_n(1) = 1 (direct summation)
+    p0 = (p * alt).sum(axis=-1)  # p(z = 0): T_n(-1) = (-1)^n
+    # velocities: eq. momentumfs with eqs. DtoNmapuv and DtoNmapw
+    u = bvp.solve(A, bvp.robin_rhs((ikx * p - fx) / eta,
+                                   -1j * kx * pH / (2 * k * eta),
+                                   1j * kx * p0 / (2 * k * eta), H))
+    v = bvp.solve(A, bvp.robin_rhs((iky * p - fy) / eta,
+                                   -1j * ky * pH / (2 * k * eta),
+                                   1j * ky * p0 / (2 * k * eta), H))
+    w = bvp.solve(A, bvp.robin_rhs((Dz(p) - fz) / eta,
+                                   pH / (2 * eta), p0 / (2 * eta), H))
+    return p, u, v, w
+
+
+def correction_nodes(box, kx, ky, u, v, w):
+    """Wall correction velocity at the Chebyshev nodes (step 4 of Sec. 3.4).
+
+    u, v, w: (K, Nz) coefficients of the DP velocity.  Bottom wall: the
+    closed form of Sec. 3.2 (eqs. usolfs-corr-final .. wsolfs-corr-final) with
+    boundary data u_corr(0) = -u_DP(0) (no slip, zero wall velocity).  Slit
+    channel: App. A with zero slip lengths and wall velocities.
+    """
+    Nz = box.Nz
+    _, zc = cheb.nodes(Nz, box.H)
+    alt = (-1.0) ** np.arange(Nz)
+    k = np.sqrt(kx ** 2 + ky ** 2)
+    if box.geometry != "bw":
+        return _slit_correction(box, kx, ky, k, u, v, w, zc, alt)
+    kk = k[:, None]
+    em = np.exp(-kk * zc[None, :])            # e^{-kz}
+    u0 = -(u * alt).sum(-1)
+    v0 = -(v * alt).sum(-1)
+    w0 = -(w * alt).sum(-1)
+    Acoef = (1j * k * w0 + kx * u0 + ky * v0)[:, None]
+    ze = zc[None, :] * em
+    uc = -(kx / k)[:, None] * Acoef * ze + u0[:, None] * em
+    vc = -(ky / k)[:, None] * Acoef * ze + v0[:, None] * em
+    wc = ((k * w0 - 1j * kx * u0 - 1j * ky * v0)[:, None] * ze
+          + w0[:, None] * em)
+    return uc, vc, wc
+
+
+def _dp_and_correction(box, kx, ky, fx, fy, fz, chunk=16384):
+    """k != 0 columns: DP solve plus wall correction, added in coefficient
+    space after a Chebyshev transform of the nodal correction (step 6)."""
+    K = kx.size
+    Nz = box.Nz
+    u = np.empty((K, Nz), complex)
+    v = np.empty((K, Nz), complex)
+    w = np.empty((K, Nz), complex)
+    for lo in range(0, K, chunk):
+        sl = slice(lo, min(K, lo + chunk))
+        _, uu, vv, ww = dp_solve(box, kx[sl], ky[sl], fx[sl], fy[sl], fz[sl])
+        uc, vc, wc = correction_nodes(box, kx[sl], ky[sl], uu, vv, ww)
+        u[sl] = uu + cheb.dct1(uc, axis=-1)
+        v[sl] = vv + cheb.dct1(vc, axis=-1)
+        w[sl] = ww + cheb.dct1(wc, axis=-1)
+    return u, v, w
+
+
+def _slit_correction(box, kx, ky, k, uu, vv, ww, zc, alt):
+    """Slit-channel correction with no slip at both walls (App. A, l = 0).
+
+    Unknowns (C0, D0, Cx, Dx, Cy, Dy, Cz, Dz) of eqs. psolfs-corr-sc ..
+    wsolfs-corr-sc from the six boundary conditions (eq. 6eqs-for-constants
+    with l_0 = l_H = 0 and zero wall velocity) and the two continuity
+    conditions (eq. 2eqs-for-constants).  Reading: the D-coefficients are
+    rescaled, D~ = D e^{kH}, so every matrix entry carries at most e^{-kH} <= 1.
+    """
+    H, eta = box.H, box.eta
+    Kc = k.size
+    E = np.exp(-k * H)
+    # boundary data: u_corr = -u_DP at z = 0 and z = H
+    u0, v0, w0 = -(uu * alt).sum(-1), -(vv * alt).sum(-1), -(ww * alt).sum(-1)
+    uH, vH, wH = -uu.sum(-1), -vv.sum(-1), -ww.sum(-1)
+    M = np.zeros((Kc, 8, 8), complex)
+    b = np.zeros((Kc, 8), complex)
+    C0, D0, CX, DX, CY, DY, CZ, DZ = range(8)
+    one = np.ones(Kc)
+    # u(0) = u0, v(0) = v0, w(0) = w0
+    M[:, 0, CX], M[:, 0, DX], b[:, 0] = one, E, u0
+    M[:, 1, CY], M[:, 1, DY], b[:, 1] = one, E, v0
+    M[:, 2, CZ], M[:, 2, DZ], b[:, 2] = one, E, w0
+    # u(H) = uH, v(H) = vH
+    for row, kk, rhs, Cc, Dc in ((3, kx, uH, CX, DX), (4, ky, vH, CY, DY)):
+        c = 1j * kk * H / (2.0 * eta * k)
+        M[:, row, C0] = -c * E
+        M[:, row, D0] = c
+        M[:, row, Cc] = E
+        M[:, row, Dc] = one
+        b[:, row] = rhs
+    # w(H) = wH
+    M[:, 5, C0] = H * E / (2.0 * eta)
+    M[:, 5, D0] = H / (2.0 * eta)
+    M[:, 5, CZ] = E
+    M[:, 5, DZ] = one
+    b[:, 5] = wH
+    # continuity at z = 0 and z = H
+    M[:, 6, C0] = 1.0 / (2.0 * eta)
+    M[:, 6, D0] = E / (2.0 * eta)
+    M[:, 6, CX], M[:, 6, DX] = 1j * kx, 1j * kx * E
+    M[:, 6, CY], M[:, 6, DY] = 1j * ky, 1j * ky * E
+    M[:, 6, CZ], M[:, 6, DZ] = -k, k * E
+    M[:, 7, C0] = E / (2.0 * eta)
+    M[:, 7, D0] = 1.0 / (2.0 * eta)
+    M[:, 7, CX], M[:, 7, DX] = 1j * kx * E, 1j * kx
+    M[:, 7, CY], M[:, 7, DY] = 1j * ky * E, 1j * ky
+    M[:, 7, CZ], M[:, 7, DZ] = -k * E, k
+    X = np.linalg.solve(M, b[..., None])[..., 0]
+    kk = k[:, None]
+    z = zc[None, :]
+    em = np.exp(-kk * z)           # e^{-kz}
+    ep = np.exp(kk * (z - H))      # e^{kz} e^{-kH}
+    c0, d0 = X[:, C0:C0 + 1], X[:, D0:D0 + 1]
+    ax = (1j * kx / (2.0 * eta * k))[:, None]
+    ay = (1j * ky / (2.0 * eta * k))[:, None]
+    uc = -c0 * ax * z * em + d0 * ax * z * ep + X[:, CX:CX + 1] * em + X[:, DX:DX + 1] * ep
+    vc = -c0 * ay * z * em + d0 * ay * z * ep + X[:, CY:CY + 1] * em + X[:, DY:DY + 1] * ep
+    wc = (c0 / (2 * eta)) * z * em + (d0 / (2 * eta)) * z * ep + X[:, CZ:CZ + 1] * em + X[:, DZ:DZ + 1] * ep
+    return uc, vc, wc
+
+
+def solve_coefficients(box, Fh, Gh):
+    """Steps 2 (derivative part) to 6 in coefficient space.
+
+    Fh, Gh: complex (3, Nz, Ny, Nx/2+1) Fourier-Chebyshev coefficients of the
+    monopole and dipole densities.  Returns (uh, omh) of the same shape.
+    """
+    H, Nz = box.H, box.Nz
+    KX, KY, nyq = wavenumbers(box.Lx, box.Ly, box.Nx, box.Ny)
+    Fh = np.where(nyq[None, None], 0.0, Fh)
+    Gh = np.where(nyq[None, None], 0.0, Gh)
+    ikx, iky = 1j * KX[None], 1j * KY[None]
+    D = lambda a: cheb.deriv(a, H, axis=0)   # noqa: E731
+    # body force f + (1/2) curl g (eq. fcm), spectral curl
+    cg = curl(Gh[0], Gh[1], Gh[2], ikx, iky, D)
+    fx, fy, fz = (Fh[i] + 0.5 * cg[i] for i in range(3))
+    shape = Fh.shape[1:]
+    col = lambda a: a.reshape(Nz, -1).T     # noqa: E731  (K, Nz) columns
+    kx, ky = KX.ravel(), KY.ravel()
+    k2 = kx ** 2 + ky ** 2
+    live = (~nyq.ravel()) & (k2 > 0)
+    U = [np.zeros((kx.size, Nz), complex) for _ in range(3)]
+    cx, cy, cz = col(fx), col(fy), col(fz)
+    idx = np.nonzero(live)[0]
+    uu, vv, ww = _dp_and_correction(box, kx[idx], ky[idx], cx[idx], cy[idx],
+                                    cz[idx])
+    U[0][idx], U[1][idx], U[2][idx] = uu, vv, ww
+    # Step 5: k = 0 mode (Sec. 3.3; App. A.2 for the slit channel); w = 0.
+    k0 = np.nonzero(k2 == 0)[0]
+    for j in k0:
+        U[0][j] = bvp.zero_mode_solve(-cx[j] / box.eta, H, box.geometry)
+        U[1][j] = bvp.zero_mode_solve(-cy[j] / box.eta, H, box.geometry)
+    uh = np.stack([U[i].T.reshape(shape) for i in range(3)])
+    # vorticity: omega = (1/2) curl u in Fourier-Chebyshev space
+    cu = curl(uh[0], uh[1], uh[2], ikx, iky, D)
+    omh = 0.5 * np.stack(cu)
+    return uh, omh
+
+
+def forward_transform(box, f):
+    """Step 2: xy DFT (unnormalised) and Chebyshev transform in z."""
+    return cheb.dct1(np.fft.rfft2(f, axes=(-2, -1)), axis=-3)
+
+
+def inverse_transform(box, fh):
+    """Step 7: inverse Chebyshev transform and inverse xy DFT."""
+    return np.fft.irfft2(cheb.idct1(fh, axis=-3), s=(box.Ny, box.Nx),
+                         axes=(-2, -1))
+
+
+def stokes_solve(box, f, g):
+    """Velocity u and (1/2) curl u at the nodes from spread densities f, g."""
+    Fh = forward_transform(box, f)
+    Gh = forward_transform(box, g)
+    uh, omh = solve_coefficients(box, Fh, Gh)
+    return inverse_transform(box, uh), inverse_transform(box, omh)

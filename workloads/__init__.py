@@ -1,0 +1,217 @@
+"""Seeded synthetic workloads for the doubly-periodic FCM mobility apply.
+
+This module only draws inputs (positions, forces, torques, request streams) and
+describes grid/box parameters.  It contains none of the method's arithmetic, so
+both the CPU oracle and the GPU path can consume it without sharing code.
+
+Recipes (all seeded with ``numpy.random.default_rng(221001837 + i)`` for
+workload ``i``; draw order x, y, z, then F, then T):
+
+* ``bw64``     -- bottom wall, FP64: N=64 on a 32x32 box, z ~ U[1.5, 5],
+                  F, T ~ N(0,1); grid 48x48, Nz=32, H=8.
+* ``sc4096``   -- slit channel, FP64: N=4096 on a 128x128 box, H=10,
+                  z ~ U[1.2, 8.8], F, T ~ N(0,1); grid 192x192, Nz=48.
+* ``bw131k``   -- bottom wall, mixed precision: N=131072 on a 512x512 box,
+                  sedimented monolayer (z = 1.1 + Exp(0.3), i.e. the Boltzmann
+                  density exp(-(z-1)/0.3) restricted to z >= 1.1),
+                  F = (0,0,-1) + N(0,0.1^2), T = (0,1,0) + N(0,0.1^2);
+                  grid 768x768, Nz=32, H=12.
+* ``bw1m`` / ``sc1m`` -- the same monolayer at N=1,048,576 on a 1448x1448
+                  box, grid 2176x2176, Nz=32, H=12, positions stored as FP32;
+                  a seeded 1% subsample is used for oracle comparison.
+* ``serve``    -- 512 requests, N log-uniform in [1024, 262144], geometry
+                  bottom wall or slit channel with equal odds, box side set for
+                  N/L^2 = 0.4, grid spacing h = 1/1.731 (so the ES radius
+                  1.731 h equals the unit particle radius), Nz=32, H=12.
+
+The ES kernel uses width w=6 with the M&D optimum of the paper's Table 1:
+beta_M = 1.327*6, beta_D = 2.216*6.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+SEED_BASE = 221001837
+W = 6
+BETA_M = 1.327 * W   # Table 1, m = 6, monopole
+BETA_D = 2.216 * W   # Table 1, m = 6, dipole
+RH_OVER_H = 1.731    # Table 1, m = 6
+
+
+@dataclass(frozen=True)
+class Box:
+    """Box, grid and kernel parameters of one apply (lengths in units of a)."""
+    geometry: str          # "bw" (bottom wall) or "sc" (slit channel)
+    Lx: float
+    Ly: float
+    H: float
+    Nx: int
+    Ny: int
+    Nz: int
+    w: int = W
+    beta_m: float = BETA_M
+    beta_d: float = BETA_D
+    eta: float = 1.0
+
+    @property
+    def h(self) -> float:
+        return self.Lx / self.Nx
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    index: int
+    box: Box
+    n: int
+    precision: str         # "fp64" or "mixed"
+    heights: str           # "uniform" or "monolayer"
+    zlo: float = 0.0
+    zhi: float = 0.0
+    forces: str = "normal"  # "normal" or "roller"
+    pos_fp32: bool = False
+
+
+WORKLOADS = {
+    "bw64": Workload("bw64", 1, Box("bw", 32.0, 32.0, 8.0, 48, 48, 32), 64,
+                     "fp64", "uniform", 1.5, 5.0),
+    "sc4096": Workload("sc4096", 2, Box("sc", 128.0, 128.0, 10.0, 192, 192, 48),
+                       4096, "fp64", "uniform", 1.2, 8.8),
+    "bw131k": Workload("bw131k", 3, Box("bw", 512.0, 512.0, 12.0, 768, 768, 32),
+                       131072, "mixed", "monolayer", forces="roller"),
+    "bw1m": Workload("bw1m", 4, Box("bw", 1448.0, 1448.0, 12.0, 2176, 2176, 32),
+                     1048576, "mixed", "monolayer", forces="roller", pos_fp32=True),
+    "sc1m": Workload("sc1m", 4, Box("sc", 1448.0, 1448.0, 12.0, 2176, 2176, 32),
+                     1048576, "mixed", "monolayer", forces="roller", pos_fp32=True),
+}
+
+
+def _draw(rng: np.random.Generator, n: int, L_x: float, L_y: float,
+          heights: str, zlo: float, zhi: float, forces: str):
+    x = rng.uniform(0.0, L_x, n)
+    y = rng.uniform(0.0, L_y, n)
+    if heights == "uniform":
+        z = rng.uniform(zlo, zhi, n)
+    else:
+        z = 1.1 + rng.exponential(0.3, n)
+    if forces == "normal":
+        F = rng.standard_normal((n, 3))
+        T = rng.standard_normal((n, 3))
+    else:
+        F = np.array([0.0, 0.0, -1.0]) + 0.1 * rng.standard_normal((n, 3))
+        T = np.array([0.0, 1.0, 0.0]) + 0.1 * rng.standard_normal((n, 3))
+    pos = np.stack([x, y, z], axis=1)
+    return pos, F, T
+
+
+def particles(name: str):
+    """Seeded (pos, F, T) as float64 arrays of shape (N, 3).
+
+    Mixed-precision workloads are rounded to float32 values here (and returned
+    as float64 holding those exact float32 values) so that every consumer sees
+    the same numbers.
+    """
+    wl = WORKLOADS[name]
+    rng = np.random.default_rng(SEED_BASE + wl.index)
+    pos, F, T = _draw(rng, wl.n, wl.box.Lx, wl.box.Ly, wl.heights, wl.zlo,
+                      wl.zhi, wl.forces)
+    if wl.precision == "mixed":
+        pos = pos.astype(np.float32).astype(np.float64)
+        F = F.astype(np.float32).astype(np.float64)
+        T = T.astype(np.float32).astype(np.float64)
+    return pos, F, T
+
+
+def subsample(name: str, fraction: float = 0.01) -> np.ndarray:
+    """Seeded sorted subsample of particle indices (the 1% oracle sample)."""
+    wl = WORKLOADS[name]
+    rng = np.random.default_rng(SEED_BASE + 100 + wl.index)
+    k = max(1, int(round(fraction * wl.n)))
+    return np.sort(rng.choice(wl.n, size=k, replace=False))
+
+
+def sub_box(name: str, factor: int):
+    """A box 1/factor as wide in x and y with the same particle density.
+
+    Used to time the CPU oracle on a bounded sample of a large workload; the
+    sample is the first particles of a fresh seeded draw with the same recipe.
+    """
+    wl = WORKLOADS[name]
+    b = wl.box
+    box = replace(b, Lx=b.Lx / factor, Ly=b.Ly / factor, Nx=b.Nx // factor,
+                  Ny=b.Ny // factor)
+    box = replace(box, Lx=box.Nx * b.h, Ly=box.Ny * b.h)
+    n = int(round(wl.n * (box.Lx * box.Ly) / (b.Lx * b.Ly)))
+    rng = np.random.default_rng(SEED_BASE + 200 + wl.index)
+    pos, F, T = _draw(rng, n, box.Lx, box.Ly, wl.heights, wl.zlo, wl.zhi,
+                      wl.forces)
+    if wl.precision == "mixed":
+        pos = pos.astype(np.float32).astype(np.float64)
+        F = F.astype(np.float32).astype(np.float64)
+        T = T.astype(np.float32).astype(np.float64)
+    return box, pos, F, T
+
+
+def _smooth(n: int) -> bool:
+    for p in (2, 3, 5, 7):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+def nearest_smooth_even(x: float) -> int:
+    """Nearest even integer whose only prime factors are 2, 3, 5 and 7."""
+    best = None
+    c = max(8, int(round(x)))
+    for d in range(0, 4 * c):
+        for cand in (c - d, c + d):
+            if cand >= 8 and cand % 2 == 0 and _smooth(cand):
+                if best is None or abs(cand - x) < abs(best - x):
+                    best = cand
+        if best is not None and d > abs(best - x) + 1:
+            break
+    return best
+
+
+@dataclass(frozen=True)
+class Request:
+    rid: int
+    n: int
+    box: Box
+    seed: int
+
+
+def serving_requests(count: int = 512, nmin: int = 1024, nmax: int = 262144,
+                     area_fraction: float = 0.4, H: float = 12.0, Nz: int = 32):
+    """The serving stream: per request N, geometry and a box sized for N."""
+    rng = np.random.default_rng(SEED_BASE + 5)
+    h0 = 1.0 / RH_OVER_H
+    reqs = []
+    for r in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        geom = "bw" if rng.uniform() < 0.5 else "sc"
+        L = math.sqrt(n / area_fraction)
+        nx = nearest_smooth_even(L / h0)
+        Lb = nx * h0
+        reqs.append(Request(r, n, Box(geom, Lb, Lb, H, nx, nx, Nz),
+                            SEED_BASE + 1000 + r))
+    return reqs
+
+
+def request_particles(req: Request):
+    """Monolayer particles of one serving request (float32-exact float64)."""
+    rng = np.random.default_rng(req.seed)
+    pos, F, T = _draw(rng, req.n, req.box.Lx, req.box.Ly, "monolayer", 0, 0,
+                      "roller")
+    return (pos.astype(np.float32).astype(np.float64),
+            F.astype(np.float32).astype(np.float64),
+            T.astype(np.float32).astype(np.float64))
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = SEED_BASE + 6):
+    """Arrival times (seconds) of a Poisson process with the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, count))
