@@ -1,0 +1,162 @@
+/*
+ * fcmdp.h -- C ABI of the MI355X (gfx950) doubly-periodic FCM mobility apply.
+ *
+ * Method: Hashemi et al., "Computing hydrodynamic interactions in confined
+ * doubly-periodic geometries in linear time" (arXiv 2210.01837).
+ *
+ * Given N particles in a box periodic in x and y, either above one no-slip
+ * wall at z = 0 ("bottom wall") or between no-slip walls at z = 0 and z = H
+ * ("slit channel"), with forces F and torques T, the library computes the
+ * particle velocities U and angular velocities Omega,
+ *
+ *     [U; Omega] = M [F; T]                         (eq. grandmob, Sec. 4)
+ *
+ * where M is the FCM mobility of Sec. 2 (eqs. fcm, kernelnearwall,
+ * getpartvel, getpartvort) with the exponential-of-semicircle envelope of
+ * Sec. 3.5 (eqs. es, es-scalar), evaluated by the spectral Stokes solver of
+ * Sec. 3.4: spreading, xy FFT + Chebyshev transform, per-wavenumber BVP
+ * solves (Sec. 3.1), wall correction (Sec. 3.2, App. A), k = 0 mode
+ * (Sec. 3.3), inverse transforms and interpolation.  Torques enter through a
+ * spectral curl (the paper's GPU route, Sec. 3.4).
+ *
+ * Conventions
+ *   - Lengths: full periods Lx, Ly (x in [0, Lx), y in [0, Ly)); the grid
+ *     is x_a = a*Lx/Nx, y_b = b*Ly/Ny (hx must equal hy) and the Chebyshev
+ *     extrema z_c = (H/2)(1 + cos(pi c/(Nz-1))), c = 0..Nz-1 (c = 0 is z=H).
+ *   - ES support alpha = w*h/2 (Sec. 3.5); beta_m and beta_d are absolute
+ *     (e.g. 1.327*6 and 2.216*6 for w = 6, Table 1).
+ *   - Particle arrays are row-major [n][3] in DEVICE memory, owned by the
+ *     caller: double in FCMDP_FP64 mode, float in FCMDP_MIXED mode (FP32
+ *     spreading, FFTs and interpolation; FP64 per-wavenumber solves).
+ *   - All entry points are asynchronous on the HIP stream passed in (NULL =
+ *     the default stream) unless stated otherwise; no host synchronisation
+ *     happens inside an apply.
+ *   - A solver is not thread safe: one call in flight per solver.
+ *
+ * Errors: every function returns FCMDP_OK (0) or a negative code;
+ * fcmdp_strerror() names it.  No C++ exception crosses this ABI.
+ */
+#ifndef FCMDP_H
+#define FCMDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcmdp_solver fcmdp_solver;
+
+enum { FCMDP_BOTTOM_WALL = 0, FCMDP_SLIT_CHANNEL = 1 };
+enum { FCMDP_FP64 = 0, FCMDP_MIXED = 1 };
+enum {
+  FCMDP_OK = 0,
+  FCMDP_EINVAL = -1,   /* bad argument or unsupported size */
+  FCMDP_EDOMAIN = -2,  /* particles outside the fluid domain (see status) */
+  FCMDP_ENOMEM = -3,   /* device allocation failed */
+  FCMDP_EHIP = -4,     /* a HIP runtime call failed */
+  FCMDP_ECAPACITY = -5 /* n larger than the solver's max_particles */
+};
+
+typedef struct {
+  int geometry;        /* FCMDP_BOTTOM_WALL or FCMDP_SLIT_CHANNEL */
+  double Lx, Ly, H;    /* periods and channel height / domain top */
+  int Nx, Ny, Nz;      /* grid; Nx, Ny even, >= 8, factors in {2,3,5,7,11,13,17};
+                          8 <= Nz <= 64 */
+  int w;               /* ES support in grid cells (even, 4..8) */
+  double beta_m, beta_d; /* ES shape parameters, monopole and dipole */
+  double eta;          /* viscosity > 0 */
+  int precision;       /* FCMDP_FP64 or FCMDP_MIXED */
+  int64_t max_particles; /* capacity of the particle workspace */
+} fcmdp_params;
+
+/*
+ * Create a solver: validates p, derives h, alpha, the ES normalisations, the
+ * Chebyshev tables and FFT plans, and allocates all device workspace on the
+ * current HIP device.  Blocking (host side); ~ (2*6*Nz*Ny*Nx real words +
+ * particle buffers) of device memory, see fcmdp_workspace_bytes.
+ * Returns EINVAL for invalid parameters, ENOMEM/EHIP on allocation failure.
+ */
+int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out);
+
+/* Device bytes a solver with parameters p needs for n particles (host only). */
+int fcmdp_workspace_bytes(const fcmdp_params* p, int64_t n, size_t* bytes);
+
+/*
+ * The mobility apply (F, T) -> (U, Omega) for n particles.
+ *   pos, F: [n][3] device arrays (double in FP64 mode, float in MIXED mode).
+ *   T:      torques, or NULL for none.
+ *   U:      output velocities [n][3].
+ *   Omega:  output angular velocities [n][3], or NULL to skip.
+ * x and y are wrapped periodically.  Particles with z < 0, z > H (slit
+ * channel) or z + alpha > H (bottom wall; the forcing must vanish above the
+ * computational top) are skipped: their outputs are NaN and fcmdp_status()
+ * reports EDOMAIN after the stream has been synchronised.
+ * n = 0 is valid (no work).  Returns ECAPACITY if n > max_particles.
+ */
+int fcmdp_apply_mobility(fcmdp_solver* s, int64_t n, const void* pos,
+                         const void* F, const void* T, void* U, void* Omega,
+                         void* hip_stream);
+
+/* After the stream of the last apply has completed: FCMDP_OK, or EDOMAIN
+ * with *n_bad (if non-NULL) set to the number of skipped particles. */
+int fcmdp_status(fcmdp_solver* s, int64_t* n_bad);
+
+/* Release all device memory of s (synchronises the device first). */
+void fcmdp_destroy_solver(fcmdp_solver* s);
+
+const char* fcmdp_strerror(int code);
+
+/* Derived quantities of a solver (host only): out[0] = h, out[1] = alpha,
+ * out[2] = ES normalisation integral of the monopole kernel, out[3] = of the
+ * dipole kernel (the integral in eq. es-scalar). */
+int fcmdp_solver_info(const fcmdp_solver* s, double out[4]);
+
+/*
+ * Stage entry points (the steps of Sec. 3.4 one at a time, on caller
+ * buffers; used for per-stage parity tests).  Real element type is double
+ * in FP64 mode and float in MIXED mode.  Layouts:
+ *   grid:     real    [6][Nz][Ny][Nx]   channels (fx, fy, fz, gx, gy, gz) on
+ *             the way in (monopole density f and dipole density g, eq. fcm)
+ *             and (u, v, w, ox, oy, oz) on the way out, omega = curl(u)/2.
+ *   spectrum: complex [6][Nz][Nx/2+1][Ny] (interleaved re, im; ky fastest),
+ *             the unnormalised xy DFT of the grid per z-node.
+ * Only z-nodes c in [c_lo, c_hi] are read or written by the transform and
+ * solve stages (the band of planes that particle kernels touch).
+ */
+
+/* Step 1: spread (eq. fcm with the images of eq. kernelnearwall); writes the
+ * whole grid (zero outside the particles' kernels). */
+int fcmdp_stage_spread(fcmdp_solver* s, int64_t n, const void* pos,
+                       const void* F, const void* T, void* grid,
+                       void* hip_stream);
+
+/* Step 2 (xy part): forward real-to-complex 2-D DFT of planes c_lo..c_hi. */
+int fcmdp_stage_fft_forward(fcmdp_solver* s, const void* grid, void* spectrum,
+                            int c_lo, int c_hi, void* hip_stream);
+
+/* Steps 2 (z part) to 6 and the vorticity curl: per-wavenumber solve from
+ * the node values of f and g (planes c_lo..c_hi, zero elsewhere) to the node
+ * values of u and omega on planes c_lo..c_hi, scaled by 1/(Nx*Ny) so that
+ * fcmdp_stage_fft_inverse yields physical values.  Nyquist modes are zero. */
+int fcmdp_stage_solve(fcmdp_solver* s, const void* spectrum_in,
+                      void* spectrum_out, int c_lo, int c_hi,
+                      void* hip_stream);
+
+/* Step 7 (xy part): inverse complex-to-real 2-D DFT (unnormalised) of planes
+ * c_lo..c_hi. */
+int fcmdp_stage_fft_inverse(fcmdp_solver* s, const void* spectrum, void* grid,
+                            int c_lo, int c_hi, void* hip_stream);
+
+/* Step 8: interpolation (eqs. getpartvel, getpartvort) of u and omega from
+ * the grid (all planes may be read). */
+int fcmdp_stage_interp(fcmdp_solver* s, int64_t n, const void* pos,
+                       const void* grid, void* U, void* Omega,
+                       void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCMDP_H */

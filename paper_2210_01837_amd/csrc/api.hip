@@ -1,0 +1,524 @@
+// Host side of libfcmdp: parameter validation, derived quantities and tables,
+// device workspace, and the exported C ABI (include/fcmdp.h).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fcmdp_internal.h"
+
+using fcmdp::FFTPlan;
+
+namespace {
+
+const double kPi = 3.14159265358979323846264338327950288;
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double pp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        const double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p2) / j;
+      }
+      pp = n * (z * p0 - p1) / (z * z - 1.0);
+      const double dz = p0 / pp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+// Normalisation of the ES envelope: integral over [-alpha, alpha] of
+// exp(beta (sqrt(1 - (t/alpha)^2) - 1)), with t = alpha sin(theta).
+double es_norm(double alpha, double beta) {
+  std::vector<double> x, w;
+  gauss_legendre(160, x, w);
+  double s = 0.0;
+  for (size_t i = 0; i < x.size(); ++i) {
+    const double th = 0.5 * kPi * x[i];
+    s += w[i] * std::exp(beta * (std::cos(th) - 1.0)) * std::cos(th);
+  }
+  return alpha * 0.5 * kPi * s;
+}
+
+// cos(pi * num / den) with exact argument reduction of num modulo 2*den.
+double cospi_frac(long num, long den) {
+  long r = num % (2 * den);
+  if (r < 0) r += 2 * den;
+  return (double)std::cos((long double)kPi * (long double)r / (long double)den);
+}
+double sinpi_frac(long num, long den) {
+  long r = num % (2 * den);
+  if (r < 0) r += 2 * den;
+  return (double)std::sin((long double)kPi * (long double)r / (long double)den);
+}
+
+// Clenshaw-Curtis weights on the N extrema points of [-1, 1] (the classical
+// explicit cosine-sum formula).
+std::vector<double> clenshaw_curtis(int N) {
+  const int n = N - 1;
+  std::vector<double> w(N, 0.0);
+  std::vector<double> v(N, 1.0);
+  if (n % 2 == 0) {
+    w[0] = w[n] = 1.0 / (n * (double)n - 1.0);
+    for (int c = 1; c < n; ++c) {
+      double s = 1.0;
+      for (int k = 1; k < n / 2; ++k)
+        s -= 2.0 * cospi_frac(2L * k * c, n) / (4.0 * k * k - 1.0);
+      s -= cospi_frac((long)n * c, n) / (n * (double)n - 1.0);
+      w[c] = 2.0 * s / n;
+    }
+  } else {
+    w[0] = w[n] = 1.0 / (n * (double)n);
+    for (int c = 1; c < n; ++c) {
+      double s = 1.0;
+      for (int k = 1; k <= (n - 1) / 2; ++k)
+        s -= 2.0 * cospi_frac(2L * k * c, n) / (4.0 * k * k - 1.0);
+      w[c] = 2.0 * s / n;
+    }
+  }
+  return w;
+}
+
+bool make_plan(int n, FFTPlan* plan) {
+  plan->n = n;
+  plan->nstages = 0;
+  int m = n;
+  while (m % 8 == 0) { plan->radix[plan->nstages++] = 8; m /= 8; }
+  while (m % 4 == 0) { plan->radix[plan->nstages++] = 4; m /= 4; }
+  while (m % 2 == 0) { plan->radix[plan->nstages++] = 2; m /= 2; }
+  const int primes[] = {3, 5, 7, 11, 13, 17};
+  for (int p : primes)
+    while (m % p == 0) {
+      if (plan->nstages >= fcmdp::kMaxStages) return false;
+      plan->radix[plan->nstages++] = p;
+      m /= p;
+    }
+  return m == 1 && plan->nstages < fcmdp::kMaxStages;
+}
+
+int validate(const fcmdp_params* p) {
+  if (!p) return FCMDP_EINVAL;
+  if (p->geometry != FCMDP_BOTTOM_WALL && p->geometry != FCMDP_SLIT_CHANNEL)
+    return FCMDP_EINVAL;
+  if (p->precision != FCMDP_FP64 && p->precision != FCMDP_MIXED)
+    return FCMDP_EINVAL;
+  if (!(p->Lx > 0) || !(p->Ly > 0) || !(p->H > 0) || !(p->eta > 0))
+    return FCMDP_EINVAL;
+  if (!(p->beta_m > 0) || !(p->beta_d > 0)) return FCMDP_EINVAL;
+  if (p->Nx < 8 || p->Ny < 8 || (p->Nx & 1) || (p->Ny & 1)) return FCMDP_EINVAL;
+  if (p->Nz < 8 || p->Nz > fcmdp::kMaxNz) return FCMDP_EINVAL;
+  if (p->w != 6) return FCMDP_EINVAL;   // the kernels hold a 7-point window
+  if (p->max_particles < 0 || p->max_particles > (int64_t)1 << 30)
+    return FCMDP_EINVAL;
+  const double hx = p->Lx / p->Nx, hy = p->Ly / p->Ny;
+  if (std::fabs(hx - hy) > 1e-12 * hx) return FCMDP_EINVAL;
+  const double alpha = 0.5 * p->w * hx;
+  if (p->geometry == FCMDP_BOTTOM_WALL && !(p->H > alpha)) return FCMDP_EINVAL;
+  if (p->geometry == FCMDP_SLIT_CHANNEL && !(p->H >= 2.0 * alpha))
+    return FCMDP_EINVAL;
+  FFTPlan a, b;
+  if (!make_plan(p->Nx / 2, &a) || !make_plan(p->Ny, &b)) return FCMDP_EINVAL;
+  if ((long long)p->Nx * p->Ny >= (1LL << 31) - 1) return FCMDP_EINVAL;
+  // LDS of the single-row transforms (64 KiB per workgroup)
+  const size_t csz = p->precision == FCMDP_MIXED ? 8 : 16;
+  if (2 * (size_t)p->Ny * csz > 65536) return FCMDP_EINVAL;
+  if ((size_t)(p->Nx + 1) * csz > 65536) return FCMDP_EINVAL;
+  return FCMDP_OK;
+}
+
+// number of z-window slots: most Chebyshev nodes in a closed interval of
+// length 2 alpha, plus the one-node padding on each side and one spare.
+int z_window_slots(int Nz, double H, double alpha) {
+  std::vector<double> z(Nz);
+  for (int c = 0; c < Nz; ++c) z[c] = 0.5 * H * (1.0 + cospi_frac(c, Nz - 1));
+  int best = 0;
+  for (int c0 = 0; c0 < Nz; ++c0) {
+    int cnt = 0;
+    for (int c = c0; c < Nz; ++c)
+      if (z[c0] - z[c] <= 2.0 * alpha * (1.0 + 1e-12)) ++cnt;
+    if (cnt > best) best = cnt;
+  }
+  int zw = best + 3;
+  return zw > Nz ? Nz : zw;
+}
+
+struct Sizes {
+  size_t grid, spec, keys, vals, hist, cells, pinfo, pw, pf, psi;
+};
+
+Sizes sizes_for(const fcmdp_params* p, int64_t cap, int ZW) {
+  const size_t T = p->precision == FCMDP_MIXED ? 4 : 8;
+  Sizes s;
+  const size_t nkx = (size_t)p->Nx / 2 + 1;
+  s.grid = 6 * (size_t)p->Nz * p->Ny * p->Nx * T;
+  s.spec = 6 * (size_t)p->Nz * nkx * p->Ny * 2 * T;
+  const size_t c = cap > 0 ? (size_t)cap : 1;
+  s.keys = c * 4;
+  s.vals = c * 4;
+  const size_t nblk = (c + 2047) / 2048;
+  s.hist = 256 * nblk * 4;
+  s.cells = ((size_t)p->Nx * p->Ny + 1) * 4;
+  s.pinfo = c * 16;
+  s.pw = c * 32 * T;
+  s.pf = c * 8 * T;
+  s.psi = c * 2 * (size_t)ZW * T;
+  return s;
+}
+
+template <typename T>
+void* upload(const std::vector<T>& v, int* err) {
+  void* d = nullptr;
+  if (hipMalloc(&d, sizeof(T) * v.size()) != hipSuccess) {
+    *err = FCMDP_ENOMEM;
+    return nullptr;
+  }
+  if (hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    *err = FCMDP_EHIP;
+  return d;
+}
+
+template <typename T>
+void* upload_twiddles(int n, int count, int* err) {
+  std::vector<T> v(2 * (size_t)count);
+  for (int m = 0; m < count; ++m) {
+    v[2 * m] = (T)cospi_frac(2L * m, n);
+    v[2 * m + 1] = (T)(-sinpi_frac(2L * m, n));
+  }
+  return upload(v, err);
+}
+
+void free_all(fcmdp_solver* s) {
+  void* ptrs[] = {s->grid, s->spec, s->keyA, s->keyB, s->valA, s->valB,
+                  s->hist, s->cell_start, s->pinfo, s->pw, s->pf, s->psi,
+                  s->band, s->nbad, s->zc, s->quad, s->dct_f, s->dct_i,
+                  s->dftc, s->tw_x, s->tw_y, s->tw_r};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fcmdp_strerror(int code) {
+  switch (code) {
+    case FCMDP_OK: return "ok";
+    case FCMDP_EINVAL: return "invalid argument or unsupported size";
+    case FCMDP_EDOMAIN: return "particles outside the fluid domain";
+    case FCMDP_ENOMEM: return "device allocation failed";
+    case FCMDP_EHIP: return "HIP runtime error";
+    case FCMDP_ECAPACITY: return "more particles than the solver capacity";
+    default: return "unknown error";
+  }
+}
+
+int fcmdp_workspace_bytes(const fcmdp_params* p, int64_t n, size_t* bytes) {
+  const int v = validate(p);
+  if (v != FCMDP_OK) return v;
+  if (!bytes || n < 0) return FCMDP_EINVAL;
+  const double alpha = 0.5 * p->w * (p->Lx / p->Nx);
+  const Sizes s = sizes_for(p, n, z_window_slots(p->Nz, p->H, alpha));
+  *bytes = s.grid + s.spec + 2 * s.keys + 2 * s.vals + s.hist + s.cells +
+           s.pinfo + s.pw + s.pf + s.psi + (size_t)p->Nz * p->Nz * 16 + 65536;
+  return FCMDP_OK;
+}
+
+int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
+  if (!out) return FCMDP_EINVAL;
+  *out = nullptr;
+  int v = validate(p);
+  if (v != FCMDP_OK) return v;
+  fcmdp_solver* s = new (std::nothrow) fcmdp_solver();
+  if (!s) return FCMDP_ENOMEM;
+  s->p = *p;
+  s->mixed = p->precision == FCMDP_MIXED;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return FCMDP_EHIP;
+  }
+  const int Nz = p->Nz;
+  fcmdp::DevParams& dp = s->dp;
+  dp.geometry = p->geometry;
+  dp.Nx = p->Nx;
+  dp.Ny = p->Ny;
+  dp.Nz = Nz;
+  dp.Nkx = p->Nx / 2 + 1;
+  dp.ncells = p->Nx * p->Ny;
+  dp.half_w = p->w / 2;
+  dp.Lx = p->Lx;
+  dp.Ly = p->Ly;
+  dp.H = p->H;
+  dp.h = p->Lx / p->Nx;
+  dp.alpha = 0.5 * p->w * dp.h;
+  dp.eta = p->eta;
+  dp.beta_m = p->beta_m;
+  dp.beta_d = p->beta_d;
+  s->norm_m = es_norm(dp.alpha, p->beta_m);
+  s->norm_d = es_norm(dp.alpha, p->beta_d);
+  dp.inv_norm_m = 1.0 / s->norm_m;
+  dp.inv_norm_d = 1.0 / s->norm_d;
+  dp.ZW = z_window_slots(Nz, p->H, dp.alpha);
+  s->cap = p->max_particles;
+  {
+    int bits = 0;
+    while (((int64_t)1 << bits) <= (int64_t)dp.ncells) ++bits;
+    s->key_passes = (bits + 7) / 8;
+  }
+  make_plan(p->Nx / 2, &s->plan_x);
+  make_plan(p->Ny, &s->plan_y);
+
+  int err = FCMDP_OK;
+  const Sizes z = sizes_for(p, s->cap, dp.ZW);
+  auto alloc = [&](void** ptr, size_t bytes) {
+    if (err != FCMDP_OK) return;
+    if (hipMalloc(ptr, bytes ? bytes : 16) != hipSuccess) {
+      *ptr = nullptr;
+      err = FCMDP_ENOMEM;
+    }
+  };
+  alloc(&s->grid, z.grid);
+  alloc(&s->spec, z.spec);
+  alloc((void**)&s->keyA, z.keys);
+  alloc((void**)&s->keyB, z.keys);
+  alloc((void**)&s->valA, z.vals);
+  alloc((void**)&s->valB, z.vals);
+  alloc((void**)&s->hist, z.hist);
+  alloc((void**)&s->cell_start, z.cells);
+  alloc((void**)&s->pinfo, z.pinfo);
+  alloc(&s->pw, z.pw);
+  alloc(&s->pf, z.pf);
+  alloc(&s->psi, z.psi);
+  alloc((void**)&s->band, 2 * sizeof(int));
+  alloc((void**)&s->nbad, sizeof(unsigned int));
+
+  // Chebyshev tables
+  if (err == FCMDP_OK) {
+    const int N1 = Nz - 1;
+    std::vector<double> zc(Nz), Mf((size_t)Nz * Nz), Pi((size_t)Nz * Nz);
+    for (int c = 0; c < Nz; ++c) zc[c] = 0.5 * p->H * (1.0 + cospi_frac(c, N1));
+    for (int c = 0; c < Nz; ++c)
+      for (int n = 0; n < Nz; ++n) {
+        const double cs = cospi_frac((long)n * c, N1);
+        Pi[(size_t)c * Nz + n] = cs;
+        double m = 2.0 / N1 * cs;
+        if (c == 0 || c == N1) m *= 0.5;
+        if (n == 0 || n == N1) m *= 0.5;
+        Mf[(size_t)c * Nz + n] = m;
+      }
+    const std::vector<double> w = clenshaw_curtis(Nz);
+    const double h2 = dp.h * dp.h;
+    s->zc = (double*)upload(zc, &err);
+    s->dct_f = (double*)upload(Mf, &err);
+    s->dct_i = (double*)upload(Pi, &err);
+    if (s->mixed) {
+      std::vector<float> q(Nz);
+      for (int c = 0; c < Nz; ++c) q[c] = (float)(h2 * 0.5 * p->H * w[c]);
+      s->quad = upload(q, &err);
+    } else {
+      std::vector<double> q(Nz);
+      for (int c = 0; c < Nz; ++c) q[c] = h2 * 0.5 * p->H * w[c];
+      s->quad = upload(q, &err);
+    }
+    // small prime DFT constants
+    std::vector<double> cs;
+    const int primes[] = {3, 5, 7, 11, 13, 17};
+    cs.assign(8, 0.0);       // slot 0 for radices without constants
+    for (int P : primes) {
+      s->dft_off[P] = (int)cs.size();
+      for (int m = 0; m < P; ++m) {
+        cs.push_back(cospi_frac(2L * m, P));
+        cs.push_back(sinpi_frac(2L * m, P));
+      }
+    }
+    s->dftc = (double*)upload(cs, &err);
+    const int M = p->Nx / 2;
+    if (s->mixed) {
+      s->tw_x = upload_twiddles<float>(M, M, &err);
+      s->tw_y = upload_twiddles<float>(p->Ny, p->Ny, &err);
+      s->tw_r = upload_twiddles<float>(p->Nx, M + 1, &err);
+    } else {
+      s->tw_x = upload_twiddles<double>(M, M, &err);
+      s->tw_y = upload_twiddles<double>(p->Ny, p->Ny, &err);
+      s->tw_r = upload_twiddles<double>(p->Nx, M + 1, &err);
+    }
+  }
+  if (err == FCMDP_OK) {
+    if (fcmdp::launch_set_band(s, Nz, -1, 0) != hipSuccess ||
+        hipMemset(s->nbad, 0, sizeof(unsigned int)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+      err = FCMDP_EHIP;
+  }
+  if (err != FCMDP_OK) {
+    free_all(s);
+    delete s;
+    return err;
+  }
+  *out = s;
+  return FCMDP_OK;
+}
+
+void fcmdp_destroy_solver(fcmdp_solver* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  (void)hipDeviceSynchronize();
+  free_all(s);
+  delete s;
+}
+
+int fcmdp_solver_info(const fcmdp_solver* s, double out[4]) {
+  if (!s || !out) return FCMDP_EINVAL;
+  out[0] = s->dp.h;
+  out[1] = s->dp.alpha;
+  out[2] = s->norm_m;
+  out[3] = s->norm_d;
+  return FCMDP_OK;
+}
+
+int fcmdp_status(fcmdp_solver* s, int64_t* n_bad) {
+  if (!s) return FCMDP_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  unsigned int bad = 0;
+  if (hipMemcpy(&bad, s->nbad, sizeof(bad), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return FCMDP_EHIP;
+  if (n_bad) *n_bad = bad;
+  return bad ? FCMDP_EDOMAIN : FCMDP_OK;
+}
+
+static int check_particles(fcmdp_solver* s, int64_t n) {
+  if (!s || n < 0) return FCMDP_EINVAL;
+  if (n > s->cap) return FCMDP_ECAPACITY;
+  if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  return FCMDP_OK;
+}
+
+static int particle_front(fcmdp_solver* s, int n, const void* pos,
+                          const void* F, const void* T, hipStream_t st) {
+  if (fcmdp::launch_prep(s, n, pos, st) != hipSuccess) return FCMDP_EHIP;
+  if (fcmdp::launch_sort(s, n, st) != hipSuccess) return FCMDP_EHIP;
+  if (fcmdp::launch_records(s, n, pos, F, T, st) != hipSuccess)
+    return FCMDP_EHIP;
+  return FCMDP_OK;
+}
+
+int fcmdp_apply_mobility(fcmdp_solver* s, int64_t n, const void* pos,
+                         const void* F, const void* T, void* U, void* Omega,
+                         void* hip_stream) {
+  int v = check_particles(s, n);
+  if (v != FCMDP_OK) return v;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (n > 0 && (!pos || !F || !U)) return FCMDP_EINVAL;
+  if (n == 0) {
+    return fcmdp::launch_prep(s, 0, nullptr, st) == hipSuccess ? FCMDP_OK
+                                                               : FCMDP_EHIP;
+  }
+  const int ni = (int)n;
+  v = particle_front(s, ni, pos, F, T, st);
+  if (v != FCMDP_OK) return v;
+  if (fcmdp::launch_spread(s, s->grid, st) != hipSuccess) return FCMDP_EHIP;
+  if (fcmdp::launch_fft_forward(s, s->grid, s->spec, st) != hipSuccess)
+    return FCMDP_EHIP;
+  if (fcmdp::launch_columns(s, s->spec, s->spec, st) != hipSuccess)
+    return FCMDP_EHIP;
+  if (fcmdp::launch_fft_inverse(s, s->spec, s->grid, st) != hipSuccess)
+    return FCMDP_EHIP;
+  if (fcmdp::launch_interp(s, ni, s->grid, U, Omega, st) != hipSuccess)
+    return FCMDP_EHIP;
+  return FCMDP_OK;
+}
+
+static size_t grid_bytes(const fcmdp_solver* s) {
+  return 6 * (size_t)s->dp.Nz * s->dp.Ny * s->dp.Nx * (s->mixed ? 4 : 8);
+}
+static size_t spec_bytes(const fcmdp_solver* s) {
+  return 6 * (size_t)s->dp.Nz * s->dp.Nkx * s->dp.Ny * (s->mixed ? 8 : 16);
+}
+static bool band_ok(const fcmdp_solver* s, int lo, int hi) {
+  return lo >= 0 && hi < s->dp.Nz && lo <= hi;
+}
+
+int fcmdp_stage_spread(fcmdp_solver* s, int64_t n, const void* pos,
+                       const void* F, const void* T, void* grid,
+                       void* hip_stream) {
+  int v = check_particles(s, n);
+  if (v != FCMDP_OK) return v;
+  if (!grid || (n > 0 && (!pos || !F))) return FCMDP_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (fcmdp::launch_fill(grid, grid_bytes(s), st) != hipSuccess)
+    return FCMDP_EHIP;
+  if (n == 0) return FCMDP_OK;
+  v = particle_front(s, (int)n, pos, F, T, st);
+  if (v != FCMDP_OK) return v;
+  return fcmdp::launch_spread(s, grid, st) == hipSuccess ? FCMDP_OK
+                                                         : FCMDP_EHIP;
+}
+
+int fcmdp_stage_fft_forward(fcmdp_solver* s, const void* grid, void* spectrum,
+                            int c_lo, int c_hi, void* hip_stream) {
+  if (!s || !grid || !spectrum || !band_ok(s, c_lo, c_hi)) return FCMDP_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (fcmdp::launch_set_band(s, c_lo, c_hi, st) != hipSuccess) return FCMDP_EHIP;
+  return fcmdp::launch_fft_forward(s, grid, spectrum, st) == hipSuccess
+             ? FCMDP_OK
+             : FCMDP_EHIP;
+}
+
+int fcmdp_stage_solve(fcmdp_solver* s, const void* spectrum_in,
+                      void* spectrum_out, int c_lo, int c_hi,
+                      void* hip_stream) {
+  if (!s || !spectrum_in || !spectrum_out || !band_ok(s, c_lo, c_hi))
+    return FCMDP_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (fcmdp::launch_set_band(s, c_lo, c_hi, st) != hipSuccess) return FCMDP_EHIP;
+  return fcmdp::launch_columns(s, spectrum_in, spectrum_out, st) == hipSuccess
+             ? FCMDP_OK
+             : FCMDP_EHIP;
+}
+
+int fcmdp_stage_fft_inverse(fcmdp_solver* s, const void* spectrum, void* grid,
+                            int c_lo, int c_hi, void* hip_stream) {
+  if (!s || !grid || !spectrum || !band_ok(s, c_lo, c_hi)) return FCMDP_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (fcmdp::launch_set_band(s, c_lo, c_hi, st) != hipSuccess) return FCMDP_EHIP;
+  // the y-pass works in place: run it on the solver's own spectrum buffer
+  if (hipMemcpyAsync(s->spec, spectrum, spec_bytes(s), hipMemcpyDeviceToDevice,
+                     st) != hipSuccess)
+    return FCMDP_EHIP;
+  return fcmdp::launch_fft_inverse(s, s->spec, grid, st) == hipSuccess
+             ? FCMDP_OK
+             : FCMDP_EHIP;
+}
+
+int fcmdp_stage_interp(fcmdp_solver* s, int64_t n, const void* pos,
+                       const void* grid, void* U, void* Omega,
+                       void* hip_stream) {
+  int v = check_particles(s, n);
+  if (v != FCMDP_OK) return v;
+  if (!grid || (n > 0 && (!pos || !U))) return FCMDP_EINVAL;
+  if (n == 0) return FCMDP_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  v = particle_front(s, (int)n, pos, nullptr, nullptr, st);
+  if (v != FCMDP_OK) return v;
+  return fcmdp::launch_interp(s, (int)n, grid, U, Omega, st) == hipSuccess
+             ? FCMDP_OK
+             : FCMDP_EHIP;
+}
+
+}  // extern "C"

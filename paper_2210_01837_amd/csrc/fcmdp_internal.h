@@ -1,0 +1,142 @@
+// Internal declarations shared by the HIP translation units of libfcmdp.
+//
+// Data layout in HBM (one solver):
+//   grid      real    [6][Nz][Ny][Nx]         (T = double or float)
+//   spectrum  complex [6][Nz][Nkx][Ny]        Nkx = Nx/2+1, ky fastest
+//   particle records, in cell-sorted order:
+//     pinfo   int4    [cap]                   (ix, iy, c_first, c_last)
+//     pw      T       [cap][32]               x/y ES weights, M then D
+//     pf      T       [cap][8]                F (3), pad, torque (3), pad
+//     psi     T       [cap][2*ZW]             folded z weights, M then D
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstddef>
+
+#include "../../include/fcmdp.h"
+
+namespace fcmdp {
+
+constexpr int kMaxNz = 64;
+constexpr int kMaxStages = 24;
+constexpr int kWin = 7;        // ES window per axis: offsets -3..3 (w = 6)
+
+template <typename T> struct Cplx;
+template <> struct Cplx<float> { using type = float2; };
+template <> struct Cplx<double> { using type = double2; };
+template <typename T> using cplx_t = typename Cplx<T>::type;
+
+struct FFTPlan {
+  int n = 0;                    // transform length
+  int nstages = 0;
+  int radix[kMaxStages] = {0};
+};
+
+// Parameters the device kernels need (passed by value).
+struct DevParams {
+  int geometry;                 // 0 bottom wall, 1 slit channel
+  int Nx, Ny, Nz, Nkx;
+  int ncells;                   // Nx*Ny
+  int ZW;                       // z-window slots per particle
+  int half_w;                   // w/2 (3 for w = 6)
+  double Lx, Ly, H, h, alpha, eta;
+  double beta_m, beta_d, inv_norm_m, inv_norm_d;
+};
+
+}  // namespace fcmdp
+
+struct fcmdp_solver {
+  fcmdp_params p;
+  fcmdp::DevParams dp;
+  bool mixed = false;
+  int device = 0;
+  int64_t cap = 0;
+  double norm_m = 0, norm_d = 0;
+  int key_passes = 0;
+  int nblk_cap = 0;
+
+  // device buffers
+  void* grid = nullptr;
+  void* spec = nullptr;
+  uint32_t* keyA = nullptr;
+  uint32_t* keyB = nullptr;
+  int* valA = nullptr;
+  int* valB = nullptr;
+  uint32_t* hist = nullptr;
+  int* cell_start = nullptr;
+  int4* pinfo = nullptr;
+  void* pw = nullptr;
+  void* pf = nullptr;
+  void* psi = nullptr;
+  int* band = nullptr;          // [2]: first and last z-node touched
+  unsigned int* nbad = nullptr;
+
+  // tables (device)
+  double* zc = nullptr;         // node heights [Nz]
+  void* quad = nullptr;         // h^2 * Clenshaw-Curtis weights [Nz] (T)
+  double* dct_f = nullptr;      // forward Chebyshev transform, [c][n]
+  double* dct_i = nullptr;      // inverse, T_n(s_c), [c][n]
+  double* dftc = nullptr;       // cos/sin tables of the small prime DFTs
+  void* tw_x = nullptr;         // e^{-2 pi i m/(Nx/2)}, m < Nx/2 (complex T)
+  void* tw_y = nullptr;         // e^{-2 pi i m/Ny}
+  void* tw_r = nullptr;         // e^{-2 pi i k/Nx}, k <= Nx/2
+  fcmdp::FFTPlan plan_x, plan_y;
+  int dft_off[32] = {0};        // offset of prime P's table in dftc
+};
+
+namespace fcmdp {
+
+// --- launchers implemented in the .hip translation units -----------------
+// prep.hip
+hipError_t launch_prep(const fcmdp_solver* s, int n, const void* pos,
+                       hipStream_t st);
+hipError_t launch_sort(const fcmdp_solver* s, int n, hipStream_t st);
+hipError_t launch_records(const fcmdp_solver* s, int n, const void* pos,
+                          const void* F, const void* T, hipStream_t st);
+hipError_t launch_set_band(const fcmdp_solver* s, int lo, int hi,
+                           hipStream_t st);
+hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t st);
+// spread_interp.hip
+hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st);
+hipError_t launch_interp(const fcmdp_solver* s, int n, const void* grid,
+                         void* U, void* Omega, hipStream_t st);
+// fft.hip
+hipError_t launch_fft_forward(const fcmdp_solver* s, const void* grid,
+                              void* spec, hipStream_t st);
+hipError_t launch_fft_inverse(const fcmdp_solver* s, void* spec, void* grid,
+                              hipStream_t st);
+// columns.hip
+hipError_t launch_columns(const fcmdp_solver* s, const void* spec_in,
+                          void* spec_out, hipStream_t st);
+
+// --- small device helpers ------------------------------------------------
+__host__ __device__ inline int wrap_index(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Conservative z-node window [cA, cB] of a particle at height z: every node
+// with z_c in [max(0, z - alpha), min(H, z + alpha)] lies inside it (the
+// analytic node index is padded by one node each way against rounding).
+__device__ inline void z_window(const DevParams& dp, double z, int* cA,
+                                int* cB) {
+  const double N1 = dp.Nz - 1;
+  const double zlo = fmax(0.0, z - dp.alpha);
+  const double zhi = fmin(dp.H, z + dp.alpha);
+  const double sh = fmin(1.0, fmax(-1.0, 2.0 * zhi / dp.H - 1.0));
+  const double sl = fmin(1.0, fmax(-1.0, 2.0 * zlo / dp.H - 1.0));
+  const double th_hi = N1 / M_PI * acos(sh);   // smaller index (higher z)
+  const double th_lo = N1 / M_PI * acos(sl);
+  int a = (int)ceil(th_hi) - 1;
+  int b = (int)floor(th_lo) + 1;
+  a = a < 0 ? 0 : a;
+  b = b > dp.Nz - 1 ? dp.Nz - 1 : b;
+  // the host sizes ZW so that this clamp never removes a supported node
+  if (b > a + dp.ZW - 1) b = a + dp.ZW - 1;
+  *cA = a;
+  *cB = b;
+}
+
+}  // namespace fcmdp

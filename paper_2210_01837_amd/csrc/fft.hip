@@ -1,0 +1,357 @@
+// xy Fourier transforms (step 2 and step 7 of Sec. 3.4, the periodic part of
+// the paper's 3D FFT), hand-written mixed-radix Stockham FFTs in LDS.
+//
+//  forward: x-pass  real rows (Nx) -> half spectrum (Nx/2+1), written
+//           transposed so that y becomes the contiguous axis:
+//              grid[p][y][x]  ->  spec[p][kx][y]
+//           y-pass  complex rows of length Ny, in place (contiguous).
+//  inverse: y-pass (sign +) in place, then the complex-to-real x-pass that
+//           reads the transposed layout back into real rows.
+//
+// The real transforms use the standard packing of a length-Nx real row into
+// a length-Nx/2 complex sequence z_n = x_{2n} + i x_{2n+1}, one complex FFT,
+// and a split step with the twiddles e^{-2 pi i k/Nx}.  Only planes inside the
+// particle band [band[0], band[1]] are transformed.  All transforms are
+// unnormalised; the 1/(Nx Ny) factor is applied by the column solve.
+#include "fcmdp_internal.h"
+
+namespace fcmdp {
+
+template <typename C> __device__ inline C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename C> __device__ inline C cadd(C a, C b) {
+  C r; r.x = a.x + b.x; r.y = a.y + b.y; return r;
+}
+template <typename C> __device__ inline C csub(C a, C b) {
+  C r; r.x = a.x - b.x; r.y = a.y - b.y; return r;
+}
+// multiply by (sign * i)
+template <typename C, typename T> __device__ inline C cmul_si(C a, T sign) {
+  C r; r.x = -sign * a.y; r.y = sign * a.x; return r;
+}
+template <typename C, typename T> __device__ inline C cscale(C a, T s) {
+  C r; r.x = a.x * s; r.y = a.y * s; return r;
+}
+
+// ---- small DFTs: y_k = sum_q v_q e^{sign 2 pi i q k / R} --------------------
+template <typename T, typename C>
+__device__ inline void dft2(C* v) {
+  const C a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <typename T, typename C>
+__device__ inline void dft4(C* v, T sign) {
+  const C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+  const C s13 = cadd(v[1], v[3]), d13 = cmul_si<C, T>(csub(v[1], v[3]), sign);
+  v[0] = cadd(s02, s13);
+  v[2] = csub(s02, s13);
+  v[1] = cadd(d02, d13);
+  v[3] = csub(d02, d13);
+}
+
+template <typename T, typename C>
+__device__ inline void dft8(C* v, T sign) {
+  C e[4] = {v[0], v[2], v[4], v[6]};
+  C o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<T, C>(e, sign);
+  dft4<T, C>(o, sign);
+  const T r = T(0.70710678118654752440084436210484903928);
+  C w1; w1.x = r; w1.y = sign * r;
+  C w3; w3.x = -r; w3.y = sign * r;
+  const C t0 = o[0];
+  const C t1 = cmul(o[1], w1);
+  const C t2 = cmul_si<C, T>(o[2], sign);
+  const C t3 = cmul(o[3], w3);
+  v[0] = cadd(e[0], t0); v[4] = csub(e[0], t0);
+  v[1] = cadd(e[1], t1); v[5] = csub(e[1], t1);
+  v[2] = cadd(e[2], t2); v[6] = csub(e[2], t2);
+  v[3] = cadd(e[3], t3); v[7] = csub(e[3], t3);
+}
+
+// odd prime P: pair terms j and P-j; cs[2m], cs[2m+1] = cos, sin(2 pi m/P)
+template <typename T, typename C, int P>
+__device__ inline void dft_prime(C* v, const T* cs, T sign) {
+  constexpr int Hh = (P - 1) / 2;
+  C a[Hh], b[Hh];
+  C y0 = v[0];
+#pragma unroll
+  for (int j = 1; j <= Hh; ++j) {
+    a[j - 1] = cadd(v[j], v[P - j]);
+    b[j - 1] = csub(v[j], v[P - j]);
+    y0 = cadd(y0, a[j - 1]);
+  }
+  C out[P];
+  out[0] = y0;
+#pragma unroll
+  for (int k = 1; k <= Hh; ++k) {
+    C A = v[0];
+    C B; B.x = T(0); B.y = T(0);
+#pragma unroll
+    for (int j = 1; j <= Hh; ++j) {
+      const int m = (j * k) % P;
+      const T c = cs[2 * m], s = cs[2 * m + 1];
+      A.x += a[j - 1].x * c; A.y += a[j - 1].y * c;
+      B.x += b[j - 1].x * s; B.y += b[j - 1].y * s;
+    }
+    const C iB = cmul_si<C, T>(B, sign);
+    out[k] = cadd(A, iB);
+    out[P - k] = csub(A, iB);
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) v[k] = out[k];
+}
+
+// One Stockham stage over nrows transforms of length N stored row-major.
+template <typename T, int R>
+__device__ inline void fft_stage(const cplx_t<T>* __restrict__ src,
+                                 cplx_t<T>* __restrict__ dst, int N, int Ns,
+                                 int nrows, const cplx_t<T>* __restrict__ tw,
+                                 const double* __restrict__ cs_d, T sign) {
+  using C = cplx_t<T>;
+  const int nb = N / R;
+  const int twstep = N / (Ns * R);
+  T cs[2 * R];
+  if constexpr (R != 2 && R != 4 && R != 8) {
+#pragma unroll
+    for (int m = 0; m < 2 * R; ++m) cs[m] = (T)cs_d[m];
+  }
+  const int total = nrows * nb;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int r = idx / nb;
+    const int j = idx - r * nb;
+    const int base = r * N;
+    C v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = src[base + j + q * nb];
+    const int k = j % Ns;
+    if (Ns > 1) {
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        C w = tw[q * k * twstep];
+        w.y *= -sign;            // tw holds e^{-i...}; sign=-1 keeps it
+        v[q] = cmul(v[q], w);
+      }
+    }
+    if constexpr (R == 2) dft2<T, C>(v);
+    else if constexpr (R == 4) dft4<T, C>(v, sign);
+    else if constexpr (R == 8) dft8<T, C>(v, sign);
+    else dft_prime<T, C, R>(v, cs, sign);
+    const int out = (j - k) * R + k;
+#pragma unroll
+    for (int q = 0; q < R; ++q) dst[base + out + q * Ns] = v[q];
+  }
+}
+
+// In-LDS FFT of nrows rows; returns the buffer holding the result.
+template <typename T>
+__device__ cplx_t<T>* fft_lds(cplx_t<T>* a, cplx_t<T>* b, int N,
+                              const FFTPlan& plan, int nrows,
+                              const cplx_t<T>* __restrict__ tw,
+                              const double* __restrict__ dftc,
+                              const int* __restrict__ dft_off, T sign) {
+  cplx_t<T>* src = a;
+  cplx_t<T>* dst = b;
+  int Ns = 1;
+  for (int s = 0; s < plan.nstages; ++s) {
+    const int R = plan.radix[s];
+    const double* cs = dftc + dft_off[R];
+    switch (R) {
+      case 2: fft_stage<T, 2>(src, dst, N, Ns, nrows, tw, cs, sign); break;
+      case 3: fft_stage<T, 3>(src, dst, N, Ns, nrows, tw, cs, sign); break;
+      case 4: fft_stage<T, 4>(src, dst, N, Ns, nrows, tw, cs, sign); break;
+      case 5: fft_stage<T, 5>(src, dst, N, Ns, nrows, tw, cs, sign); break;
+      case 7: fft_stage<T, 7>(src, dst, N, Ns, nrows, tw, cs, sign); break;
+      case 8: fft_stage<T, 8>(src, dst, N, Ns, nrows, tw, cs, sign); break;
+      case 11: fft_stage<T, 11>(src, dst, N, Ns, nrows, tw, cs, sign); break;
+      case 13: fft_stage<T, 13>(src, dst, N, Ns, nrows, tw, cs, sign); break;
+      case 17: fft_stage<T, 17>(src, dst, N, Ns, nrows, tw, cs, sign); break;
+      default: break;
+    }
+    __syncthreads();
+    cplx_t<T>* t = src; src = dst; dst = t;
+    Ns *= R;
+  }
+  return src;
+}
+
+struct DftOff { int off[32]; };
+
+// ---- x-pass, real -> half spectrum, transposed write -------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fft_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
+            const T* __restrict__ grid, cplx_t<T>* __restrict__ spec,
+            const cplx_t<T>* __restrict__ tw, const cplx_t<T>* __restrict__ rtw,
+            const double* __restrict__ dftc, DftOff doff, int rows) {
+  using C = cplx_t<T>;
+  extern __shared__ unsigned char lds_raw[];
+  C* bufA = reinterpret_cast<C*>(lds_raw);
+  const int M = dp.Nx / 2;
+  C* bufB = bufA + rows * M;
+  const int p = blockIdx.y;
+  const int c = p % dp.Nz;
+  if (c < band[0] || c > band[1]) return;
+  const int y0 = blockIdx.x * rows;
+  const int nr = min(rows, dp.Ny - y0);
+  const C* src = reinterpret_cast<const C*>(grid + ((size_t)p * dp.Ny + y0) * dp.Nx);
+  for (int idx = threadIdx.x; idx < nr * M; idx += blockDim.x) bufA[idx] = src[idx];
+  __syncthreads();
+  C* Z = fft_lds<T>(bufA, bufB, M, plan, nr, tw, dftc, doff.off, T(-1));
+  const size_t pbase = (size_t)p * dp.Nkx * dp.Ny;
+  for (int idx = threadIdx.x; idx < nr * (M + 1); idx += blockDim.x) {
+    const int k = idx / nr;
+    const int r = idx - k * nr;
+    const C zk = Z[r * M + (k == M ? 0 : k)];
+    C zc = Z[r * M + (k == 0 ? 0 : M - k)];
+    zc.y = -zc.y;
+    const C e = cscale(cadd(zk, zc), T(0.5));
+    const C d = csub(zk, zc);
+    C o; o.x = T(0.5) * d.y; o.y = T(-0.5) * d.x;      // -i d / 2
+    spec[pbase + (size_t)k * dp.Ny + y0 + r] = cadd(e, cmul(rtw[k], o));
+  }
+}
+
+// ---- y-pass, in place, contiguous rows ------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fft_y(DevParams dp, FFTPlan plan, const int* __restrict__ band,
+        cplx_t<T>* __restrict__ spec, const cplx_t<T>* __restrict__ tw,
+        const double* __restrict__ dftc, DftOff doff, int rows, T sign) {
+  using C = cplx_t<T>;
+  extern __shared__ unsigned char lds_raw[];
+  C* bufA = reinterpret_cast<C*>(lds_raw);
+  C* bufB = bufA + rows * dp.Ny;
+  const int p = blockIdx.y;
+  const int c = p % dp.Nz;
+  if (c < band[0] || c > band[1]) return;
+  const int k0 = blockIdx.x * rows;
+  const int nr = min(rows, dp.Nkx - k0);
+  C* row = spec + ((size_t)p * dp.Nkx + k0) * dp.Ny;
+  for (int idx = threadIdx.x; idx < nr * dp.Ny; idx += blockDim.x) bufA[idx] = row[idx];
+  __syncthreads();
+  C* res = fft_lds<T>(bufA, bufB, dp.Ny, plan, nr, tw, dftc, doff.off, sign);
+  for (int idx = threadIdx.x; idx < nr * dp.Ny; idx += blockDim.x) row[idx] = res[idx];
+}
+
+// ---- x-pass, half spectrum -> real, transposed read -----------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fft_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
+            const cplx_t<T>* __restrict__ spec, T* __restrict__ grid,
+            const cplx_t<T>* __restrict__ tw, const cplx_t<T>* __restrict__ rtw,
+            const double* __restrict__ dftc, DftOff doff, int rows) {
+  using C = cplx_t<T>;
+  extern __shared__ unsigned char lds_raw[];
+  const int M = dp.Nx / 2;
+  C* bufA = reinterpret_cast<C*>(lds_raw);        // rows * M
+  C* bufB = bufA + rows * M;                        // rows * (M + 1)
+  const int p = blockIdx.y;
+  const int c = p % dp.Nz;
+  if (c < band[0] || c > band[1]) return;
+  const int y0 = blockIdx.x * rows;
+  const int nr = min(rows, dp.Ny - y0);
+  const size_t pbase = (size_t)p * dp.Nkx * dp.Ny;
+  for (int idx = threadIdx.x; idx < nr * (M + 1); idx += blockDim.x) {
+    const int k = idx / nr;
+    const int r = idx - k * nr;
+    bufB[r * (M + 1) + k] = spec[pbase + (size_t)k * dp.Ny + y0 + r];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nr * M; idx += blockDim.x) {
+    const int r = idx / M;
+    const int k = idx - r * M;
+    C xk = bufB[r * (M + 1) + k];
+    C xm = bufB[r * (M + 1) + (M - k)];
+    if (k == 0) { xk.y = T(0); xm.y = T(0); }
+    xm.y = -xm.y;                                   // conj(X_{M-k})
+    const C A = cadd(xk, xm);
+    const C B = csub(xk, xm);
+    C w = rtw[k];
+    w.y = -w.y;                                     // e^{+2 pi i k/Nx}
+    const C wb = cmul(w, B);
+    C z; z.x = A.x - wb.y; z.y = A.y + wb.x;        // A + i w B
+    bufA[r * M + k] = z;
+  }
+  __syncthreads();
+  C* res = fft_lds<T>(bufA, bufB, M, plan, nr, tw, dftc, doff.off, T(1));
+  C* dst = reinterpret_cast<C*>(grid + ((size_t)p * dp.Ny + y0) * dp.Nx);
+  for (int idx = threadIdx.x; idx < nr * M; idx += blockDim.x) dst[idx] = res[idx];
+}
+
+static int rows_for(int len, size_t elem, int bufs_extra, int maxrows) {
+  // two ping-pong buffers of rows*len complex words within 64 KiB
+  size_t per = 2 * (size_t)len * elem + (size_t)bufs_extra * elem;
+  int r = (int)(65536 / per);
+  if (r < 1) r = 1;
+  if (r > maxrows) r = maxrows;
+  return r;
+}
+
+template <typename T>
+static hipError_t fwd_impl(const fcmdp_solver* s, const T* grid, void* spec,
+                           hipStream_t st) {
+  using C = cplx_t<T>;
+  const DevParams& dp = s->dp;
+  DftOff doff;
+  for (int i = 0; i < 32; ++i) doff.off[i] = s->dft_off[i];
+  const int M = dp.Nx / 2;
+  const int planes = 6 * dp.Nz;
+  int rows = rows_for(M, sizeof(C), 0, 16);
+  if (rows > dp.Ny) rows = dp.Ny;
+  size_t lds = 2 * (size_t)rows * M * sizeof(C);
+  hipLaunchKernelGGL(k_fft_x_r2c<T>, dim3((dp.Ny + rows - 1) / rows, planes),
+                     dim3(256), lds, st, dp, s->plan_x, s->band, grid, (C*)spec,
+                     (const C*)s->tw_x, (const C*)s->tw_r, s->dftc, doff, rows);
+  int ry = rows_for(dp.Ny, sizeof(C), 0, 16);
+  if (ry > dp.Nkx) ry = dp.Nkx;
+  lds = 2 * (size_t)ry * dp.Ny * sizeof(C);
+  hipLaunchKernelGGL(k_fft_y<T>, dim3((dp.Nkx + ry - 1) / ry, planes),
+                     dim3(256), lds, st, dp, s->plan_y, s->band, (C*)spec,
+                     (const C*)s->tw_y, s->dftc, doff, ry, T(-1));
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t inv_impl(const fcmdp_solver* s, void* spec, T* grid,
+                           hipStream_t st) {
+  using C = cplx_t<T>;
+  const DevParams& dp = s->dp;
+  DftOff doff;
+  for (int i = 0; i < 32; ++i) doff.off[i] = s->dft_off[i];
+  const int M = dp.Nx / 2;
+  const int planes = 6 * dp.Nz;
+  int ry = rows_for(dp.Ny, sizeof(C), 0, 16);
+  if (ry > dp.Nkx) ry = dp.Nkx;
+  size_t lds = 2 * (size_t)ry * dp.Ny * sizeof(C);
+  hipLaunchKernelGGL(k_fft_y<T>, dim3((dp.Nkx + ry - 1) / ry, planes),
+                     dim3(256), lds, st, dp, s->plan_y, s->band, (C*)spec,
+                     (const C*)s->tw_y, s->dftc, doff, ry, T(1));
+  int rows = rows_for(M, sizeof(C), 1, 16);
+  if (rows > dp.Ny) rows = dp.Ny;
+  lds = (size_t)rows * (2 * M + 1) * sizeof(C);
+  hipLaunchKernelGGL(k_fft_x_c2r<T>, dim3((dp.Ny + rows - 1) / rows, planes),
+                     dim3(256), lds, st, dp, s->plan_x, s->band, (const C*)spec,
+                     grid, (const C*)s->tw_x, (const C*)s->tw_r, s->dftc, doff,
+                     rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_forward(const fcmdp_solver* s, const void* grid,
+                              void* spec, hipStream_t st) {
+  return s->mixed ? fwd_impl<float>(s, (const float*)grid, spec, st)
+                  : fwd_impl<double>(s, (const double*)grid, spec, st);
+}
+
+hipError_t launch_fft_inverse(const fcmdp_solver* s, void* spec, void* grid,
+                              hipStream_t st) {
+  return s->mixed ? inv_impl<float>(s, spec, (float*)grid, st)
+                  : inv_impl<double>(s, spec, (double*)grid, st);
+}
+
+}  // namespace fcmdp

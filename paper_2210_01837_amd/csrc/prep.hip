@@ -1,0 +1,362 @@
+// Particle preparation: domain checks and cell keys, the z-band of touched
+// Chebyshev planes, a stable LSD radix sort of particles by xy cell, cell
+// start offsets, and per-particle ES weight records in sorted order.
+//
+// The sort makes every later reduction order a function of the input alone
+// (particles of one cell keep their input order), so spreading is
+// deterministic without atomics.
+#include "fcmdp_internal.h"
+#include "es.h"
+
+namespace fcmdp {
+
+// ----------------------------------------------------------------------------
+// prep: keys, band, domain errors
+// ----------------------------------------------------------------------------
+template <typename Tin>
+__global__ void __launch_bounds__(256)
+k_prep(DevParams dp, int n, const Tin* __restrict__ pos,
+       uint32_t* __restrict__ keys, int* __restrict__ band,
+       unsigned int* __restrict__ nbad) {
+  __shared__ int s_lo, s_hi, s_bad;
+  if (threadIdx.x == 0) {
+    s_lo = dp.Nz;
+    s_hi = -1;
+    s_bad = 0;
+  }
+  __syncthreads();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
+    const double x = (double)pos[3 * (size_t)j + 0];
+    const double y = (double)pos[3 * (size_t)j + 1];
+    const double z = (double)pos[3 * (size_t)j + 2];
+    bool ok = isfinite(x) && isfinite(y) && isfinite(z) && z >= 0.0;
+    if (ok) ok = dp.geometry == 0 ? (z + dp.alpha <= dp.H) : (z <= dp.H);
+    if (!ok) {
+      keys[j] = (uint32_t)dp.ncells;
+      atomicAdd(&s_bad, 1);
+    } else {
+      int ix, iy;
+      double fx, fy;
+      cell_of(wrap_coord(x, dp.Lx), dp.h, dp.Nx, &ix, &fx);
+      cell_of(wrap_coord(y, dp.Ly), dp.h, dp.Ny, &iy, &fy);
+      keys[j] = (uint32_t)(iy * dp.Nx + ix);
+      int cA, cB;
+      z_window(dp, z, &cA, &cB);
+      atomicMin(&s_lo, cA);
+      atomicMax(&s_hi, cB);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_hi >= 0) {
+      atomicMin(&band[0], s_lo);
+      atomicMax(&band[1], s_hi);
+    }
+    if (s_bad) atomicAdd(nbad, (unsigned)s_bad);
+  }
+}
+
+__global__ void k_init_band(int* band, unsigned int* nbad, int lo, int hi,
+                            int reset_bad) {
+  band[0] = lo;
+  band[1] = hi;
+  if (reset_bad) *nbad = 0u;
+}
+
+hipError_t launch_prep(const fcmdp_solver* s, int n, const void* pos,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_init_band, dim3(1), dim3(1), 0, st, s->band, s->nbad,
+                     s->dp.Nz, -1, 1);
+  if (n == 0) return hipGetLastError();
+  dim3 grid((n + 255) / 256);
+  if (s->mixed)
+    hipLaunchKernelGGL(k_prep<float>, grid, dim3(256), 0, st, s->dp, n,
+                       (const float*)pos, s->keyA, s->band, s->nbad);
+  else
+    hipLaunchKernelGGL(k_prep<double>, grid, dim3(256), 0, st, s->dp, n,
+                       (const double*)pos, s->keyA, s->band, s->nbad);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_band(const fcmdp_solver* s, int lo, int hi,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_init_band, dim3(1), dim3(1), 0, st, s->band, s->nbad,
+                     lo, hi, 0);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// zero fill (a kernel rather than a memset so that it is safe inside
+// captured graphs)
+// ----------------------------------------------------------------------------
+__global__ void k_fill_zero(uint4* p, size_t n16, unsigned char* tail,
+                            size_t ntail) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+  if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  const size_t n16 = bytes / 16;
+  const size_t ntail = bytes - n16 * 16;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st,
+                     (uint4*)ptr, n16, (unsigned char*)ptr + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits.  One block sorts 2048 consecutive
+// items per pass: 4 waves x 8 rounds x 64 lanes.  Stable ranks inside a
+// 64-item chunk come from eight ballots (lanes with an equal digit), chunk
+// counts are prefix-summed per digit in LDS, and block offsets come from a
+// digit-major exclusive scan of all block histograms.
+// ----------------------------------------------------------------------------
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 2048;
+constexpr int kSortChunks = kSortItems / 64;   // 32
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_hist(int n, const uint32_t* __restrict__ keys, int shift, int nblk,
+             uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortItems;
+  for (int i = threadIdx.x; i < kSortItems; i += kSortThreads) {
+    const int g = base + i;
+    if (g < n) atomicAdd(&h[(keys[g] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of len entries with one 1024-thread block
+__global__ void __launch_bounds__(1024)
+k_exclusive_scan(uint32_t* __restrict__ a, int len) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (len + 1023) / 1024;
+  const int lo = t * per;
+  const int hi = min(len, lo + per);
+  uint32_t sum = 0;
+  for (int i = lo; i < hi; ++i) sum += a[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;   // exclusive prefix of this thread's chunk
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_scatter(int n, const uint32_t* __restrict__ kin,
+                const int* __restrict__ vin, uint32_t* __restrict__ kout,
+                int* __restrict__ vout, int shift, int nblk,
+                const uint32_t* __restrict__ offs, int first_pass) {
+  __shared__ uint32_t cnt[kSortChunks][256];
+  __shared__ uint32_t boff[256];
+  const int t = threadIdx.x;
+  for (int i = t; i < kSortChunks * 256; i += kSortThreads)
+    (&cnt[0][0])[i] = 0u;
+  boff[t] = offs[t * nblk + blockIdx.x];
+  __syncthreads();
+
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t key[8];
+  int val[8];
+  int dig[8];
+  int rank[8];
+  const int base = blockIdx.x * kSortItems;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int q = wave * 8 + r;
+    const int g = base + q * 64 + lane;
+    const bool active = g < n;
+    uint32_t k = active ? kin[g] : 0u;
+    int v = active ? (first_pass ? g : vin[g]) : 0;
+    const int d = (int)((k >> shift) & 255u);
+    uint64_t mask = __ballot(active);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bal = __ballot(((d >> b) & 1) != 0);
+      mask &= ((d >> b) & 1) ? bal : ~bal;
+    }
+    key[r] = k;
+    val[r] = v;
+    dig[r] = active ? d : -1;
+    rank[r] = __popcll(mask & lt_mask);
+    if (active && (mask & lt_mask) == 0ull)   // lowest lane of this digit
+      cnt[q][d] = (uint32_t)__popcll(mask);
+  }
+  __syncthreads();
+  {  // per digit: exclusive prefix over chunks
+    uint32_t run = 0;
+    for (int q = 0; q < kSortChunks; ++q) {
+      const uint32_t c = cnt[q][t];
+      cnt[q][t] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    if (dig[r] < 0) continue;
+    const int q = wave * 8 + r;
+    const uint32_t dst = boff[dig[r]] + cnt[q][dig[r]] + (uint32_t)rank[r];
+    kout[dst] = key[r];
+    vout[dst] = val[r];
+  }
+}
+
+// cell_start[c] = first sorted position with key >= c, for c = 0..ncells
+__global__ void k_cell_start(int n, int ncells, const uint32_t* __restrict__ keys,
+                             int* __restrict__ cell_start) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > ncells) return;
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] < (uint32_t)c) lo = mid + 1; else hi = mid;
+  }
+  cell_start[c] = lo;
+}
+
+hipError_t launch_sort(const fcmdp_solver* s, int n, hipStream_t st) {
+  const int ncells = s->dp.ncells;
+  if (n > 0) {
+    const int nblk = (n + kSortItems - 1) / kSortItems;
+    uint32_t* kin = s->keyA;
+    uint32_t* kout = s->keyB;
+    int* vin = s->valA;
+    int* vout = s->valB;
+    for (int pass = 0; pass < s->key_passes; ++pass) {
+      const int shift = 8 * pass;
+      hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st,
+                         n, kin, shift, nblk, s->hist);
+      hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(1024), 0, st,
+                         s->hist, 256 * nblk);
+      hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortThreads), 0,
+                         st, n, kin, vin, kout, vout, shift, nblk, s->hist,
+                         pass == 0 ? 1 : 0);
+      uint32_t* tk = kin; kin = kout; kout = tk;
+      int* tv = vin; vin = vout; vout = tv;
+    }
+    // the result lives in keyA/valA when the pass count is even
+    if (kin != s->keyA) {
+      hipMemcpyAsync(s->keyA, kin, sizeof(uint32_t) * n,
+                     hipMemcpyDeviceToDevice, st);
+      hipMemcpyAsync(s->valA, vin, sizeof(int) * n, hipMemcpyDeviceToDevice,
+                     st);
+    }
+  }
+  hipLaunchKernelGGL(k_cell_start, dim3((ncells + 1 + 255) / 256), dim3(256),
+                     0, st, n, ncells, s->keyA, s->cell_start);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// per-particle records in sorted order
+// ----------------------------------------------------------------------------
+template <typename Tin, typename T>
+__global__ void __launch_bounds__(256)
+k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
+          const int* __restrict__ perm, const Tin* __restrict__ pos,
+          const Tin* __restrict__ F, const Tin* __restrict__ Tq,
+          const double* __restrict__ zc, int4* __restrict__ pinfo,
+          T* __restrict__ pw, T* __restrict__ pf, T* __restrict__ psi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || skeys[i] >= (uint32_t)dp.ncells) return;
+  const int j = perm[i];
+  const double x = wrap_coord((double)pos[3 * (size_t)j + 0], dp.Lx);
+  const double y = wrap_coord((double)pos[3 * (size_t)j + 1], dp.Ly);
+  const double z = (double)pos[3 * (size_t)j + 2];
+  int ix, iy;
+  double fx, fy;
+  cell_of(x, dp.h, dp.Nx, &ix, &fx);
+  cell_of(y, dp.h, dp.Ny, &iy, &fy);
+  int cA, cB;
+  z_window(dp, z, &cA, &cB);
+  pinfo[i] = make_int4(ix, iy, cA, cB);
+  T* w = pw + (size_t)i * 32;
+#pragma unroll
+  for (int d = 0; d < kWin; ++d) {
+    const double tx = ((double)(d - 3) - fx) * dp.h;
+    const double ty = ((double)(d - 3) - fy) * dp.h;
+    w[d] = es_eval<T>(tx, dp.alpha, dp.beta_m, dp.inv_norm_m);
+    w[8 + d] = es_eval<T>(ty, dp.alpha, dp.beta_m, dp.inv_norm_m);
+    w[16 + d] = es_eval<T>(tx, dp.alpha, dp.beta_d, dp.inv_norm_d);
+    w[24 + d] = es_eval<T>(ty, dp.alpha, dp.beta_d, dp.inv_norm_d);
+  }
+  w[7] = w[15] = w[23] = w[31] = T(0);
+  T* ps = psi + (size_t)i * 2 * dp.ZW;
+  const double zim_top = 2.0 * dp.H - z;
+  for (int sl = 0; sl < dp.ZW; ++sl) {
+    const int c = cA + sl;
+    T pm = T(0), pd = T(0);
+    if (c <= cB) {
+      const double zcv = zc[c];
+      pm = es_eval<T>(zcv - z, dp.alpha, dp.beta_m, dp.inv_norm_m) -
+           es_eval<T>(zcv + z, dp.alpha, dp.beta_m, dp.inv_norm_m);
+      pd = es_eval<T>(zcv - z, dp.alpha, dp.beta_d, dp.inv_norm_d) -
+           es_eval<T>(zcv + z, dp.alpha, dp.beta_d, dp.inv_norm_d);
+      if (dp.geometry == 1) {
+        pm -= es_eval<T>(zcv - zim_top, dp.alpha, dp.beta_m, dp.inv_norm_m);
+        pd -= es_eval<T>(zcv - zim_top, dp.alpha, dp.beta_d, dp.inv_norm_d);
+      }
+    }
+    ps[sl] = pm;
+    ps[dp.ZW + sl] = pd;
+  }
+  T* f = pf + (size_t)i * 8;
+  if (F) {
+    f[0] = (T)F[3 * (size_t)j + 0];
+    f[1] = (T)F[3 * (size_t)j + 1];
+    f[2] = (T)F[3 * (size_t)j + 2];
+  } else {
+    f[0] = f[1] = f[2] = T(0);
+  }
+  f[3] = T(0);
+  if (Tq) {
+    f[4] = (T)Tq[3 * (size_t)j + 0];
+    f[5] = (T)Tq[3 * (size_t)j + 1];
+    f[6] = (T)Tq[3 * (size_t)j + 2];
+  } else {
+    f[4] = f[5] = f[6] = T(0);
+  }
+  f[7] = T(0);
+}
+
+hipError_t launch_records(const fcmdp_solver* s, int n, const void* pos,
+                          const void* F, const void* T, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  dim3 grid((n + 255) / 256);
+  if (s->mixed)
+    hipLaunchKernelGGL((k_records<float, float>), grid, dim3(256), 0, st,
+                       s->dp, n, s->keyA, s->valA, (const float*)pos,
+                       (const float*)F, (const float*)T, s->zc, s->pinfo,
+                       (float*)s->pw, (float*)s->pf, (float*)s->psi);
+  else
+    hipLaunchKernelGGL((k_records<double, double>), grid, dim3(256), 0, st,
+                       s->dp, n, s->keyA, s->valA, (const double*)pos,
+                       (const double*)F, (const double*)T, s->zc, s->pinfo,
+                       (double*)s->pw, (double*)s->pf, (double*)s->psi);
+  return hipGetLastError();
+}
+
+}  // namespace fcmdp

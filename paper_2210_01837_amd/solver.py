@@ -1,0 +1,178 @@
+"""Python binding of the MI355X doubly-periodic FCM mobility apply.
+
+Argument marshalling only: every step runs in libfcmdp's HIP kernels.  Torch
+tensors provide device memory and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib as L
+
+GEOMETRY = {"bw": L.BOTTOM_WALL, "sc": L.SLIT_CHANNEL,
+            "bottom_wall": L.BOTTOM_WALL, "slit_channel": L.SLIT_CHANNEL}
+PRECISION = {"fp64": L.FP64, "mixed": L.MIXED}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_params(geometry, Lx, Ly, H, Nx, Ny, Nz, w=6, beta_m=1.327 * 6,
+                beta_d=2.216 * 6, eta=1.0, precision="mixed",
+                max_particles=0) -> L.Params:
+    return L.Params(GEOMETRY[geometry], float(Lx), float(Ly), float(H),
+                    int(Nx), int(Ny), int(Nz), int(w), float(beta_m),
+                    float(beta_d), float(eta), PRECISION[precision],
+                    int(max_particles))
+
+
+def workspace_bytes(n, **kw) -> int:
+    p = make_params(**kw)
+    out = ctypes.c_size_t(0)
+    L.check(L.lib().fcmdp_workspace_bytes(ctypes.byref(p), int(n),
+                                          ctypes.byref(out)),
+            "fcmdp_workspace_bytes")
+    return out.value
+
+
+class Solver:
+    """create_solver(geometry, Lx, Ly, H, grid, w, beta) of the C ABI."""
+
+    def __init__(self, geometry, Lx, Ly, H, Nx, Ny, Nz, w=6, beta_m=1.327 * 6,
+                 beta_d=2.216 * 6, eta=1.0, precision="mixed",
+                 max_particles=1 << 20):
+        self.params = make_params(geometry, Lx, Ly, H, Nx, Ny, Nz, w, beta_m,
+                                  beta_d, eta, precision, max_particles)
+        self.precision = precision
+        self.Nx, self.Ny, self.Nz = int(Nx), int(Ny), int(Nz)
+        self._h = ctypes.c_void_p(0)
+        L.check(L.lib().fcmdp_create_solver(ctypes.byref(self.params),
+                                            ctypes.byref(self._h)),
+                "fcmdp_create_solver")
+
+    @classmethod
+    def from_box(cls, box, precision="mixed", max_particles=1 << 20):
+        return cls(box.geometry, box.Lx, box.Ly, box.H, box.Nx, box.Ny, box.Nz,
+                   box.w, box.beta_m, box.beta_d, box.eta, precision,
+                   max_particles)
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def close(self):
+        if self._h and self._h.value:
+            L.lib().fcmdp_destroy_solver(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        out = (ctypes.c_double * 4)()
+        L.check(L.lib().fcmdp_solver_info(self._h, out), "fcmdp_solver_info")
+        return {"h": out[0], "alpha": out[1], "norm_m": out[2],
+                "norm_d": out[3]}
+
+    def _check_particles(self, *ts):
+        for t in ts:
+            if t is None:
+                continue
+            if t.dtype != self.dtype or not t.is_cuda or not t.is_contiguous():
+                raise TypeError("particle arrays must be contiguous device "
+                                f"tensors of dtype {self.dtype}")
+            if t.dim() != 2 or t.shape[1] != 3:
+                raise ValueError("particle arrays must have shape (n, 3)")
+
+    def apply(self, pos, F, T=None, U=None, Omega=None, want_omega=True,
+              stream=None):
+        """(U, Omega) = M (F, T); Omega is None if want_omega is False."""
+        import torch
+        n = pos.shape[0]
+        if U is None:
+            U = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
+        if Omega is None and want_omega:
+            Omega = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
+        self._check_particles(pos, F, T, U, Omega)
+        L.check(L.lib().fcmdp_apply_mobility(
+            self._h, n, _ptr(pos), _ptr(F), _ptr(T), _ptr(U), _ptr(Omega),
+            _stream(stream)), "fcmdp_apply_mobility")
+        return U, Omega
+
+    def status(self):
+        bad = ctypes.c_int64(0)
+        code = L.lib().fcmdp_status(self._h, ctypes.byref(bad))
+        if code not in (L.OK, L.EDOMAIN):
+            L.check(code, "fcmdp_status")
+        return code, bad.value
+
+    # --- stage entry points -------------------------------------------------
+    def grid_shape(self):
+        return (6, self.Nz, self.Ny, self.Nx)
+
+    def spectrum_shape(self):
+        return (6, self.Nz, self.Nx // 2 + 1, self.Ny)
+
+    def stage_spread(self, pos, F, T=None, stream=None):
+        import torch
+        grid = torch.empty(self.grid_shape(), dtype=self.dtype,
+                           device=pos.device)
+        self._check_particles(pos, F, T)
+        L.check(L.lib().fcmdp_stage_spread(self._h, pos.shape[0], _ptr(pos),
+                                           _ptr(F), _ptr(T), _ptr(grid),
+                                           _stream(stream)),
+                "fcmdp_stage_spread")
+        return grid
+
+    def _cplx(self):
+        import torch
+        return torch.complex128 if self.precision == "fp64" else torch.complex64
+
+    def stage_fft_forward(self, grid, c_lo, c_hi, stream=None):
+        import torch
+        spec = torch.zeros(self.spectrum_shape(), dtype=self._cplx(),
+                           device=grid.device)
+        L.check(L.lib().fcmdp_stage_fft_forward(self._h, _ptr(grid), _ptr(spec),
+                                                c_lo, c_hi, _stream(stream)),
+                "fcmdp_stage_fft_forward")
+        return spec
+
+    def stage_solve(self, spec, c_lo, c_hi, stream=None):
+        import torch
+        out = torch.zeros_like(spec)
+        L.check(L.lib().fcmdp_stage_solve(self._h, _ptr(spec), _ptr(out), c_lo,
+                                          c_hi, _stream(stream)),
+                "fcmdp_stage_solve")
+        return out
+
+    def stage_fft_inverse(self, spec, c_lo, c_hi, stream=None):
+        import torch
+        grid = torch.zeros(self.grid_shape(), dtype=self.dtype,
+                           device=spec.device)
+        L.check(L.lib().fcmdp_stage_fft_inverse(self._h, _ptr(spec), _ptr(grid),
+                                                c_lo, c_hi, _stream(stream)),
+                "fcmdp_stage_fft_inverse")
+        return grid
+
+    def stage_interp(self, pos, grid, stream=None):
+        import torch
+        n = pos.shape[0]
+        U = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
+        Om = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
+        self._check_particles(pos)
+        L.check(L.lib().fcmdp_stage_interp(self._h, n, _ptr(pos), _ptr(grid),
+                                           _ptr(U), _ptr(Om), _stream(stream)),
+                "fcmdp_stage_interp")
+        return U, Om

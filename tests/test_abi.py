@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/fcmdp.h declares, and rejects invalid parameters
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fcmdp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fcmdp_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2210_01837_amd import _lib
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "fcmdp_apply_mobility" in names and "fcmdp_create_solver" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror(L):
+    from paper_2210_01837_amd import _lib
+    for code in (0, -1, -2, -3, -4, -5):
+        assert _lib.strerror(code)
+    assert _lib.strerror(-99) == "unknown error"
+
+
+def _params(**kw):
+    from paper_2210_01837_amd import make_params
+    base = dict(geometry="bw", Lx=32.0, Ly=32.0, H=8.0, Nx=48, Ny=48, Nz=32,
+                precision="fp64", max_particles=64)
+    base.update(kw)
+    return make_params(**base)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(Nx=47), dict(Ny=6), dict(Nz=7), dict(Nz=65), dict(Nx=38),  # 19 prime
+    dict(Ly=31.0), dict(H=1.9), dict(w=4), dict(eta=0.0),
+    dict(geometry="sc", H=3.9), dict(max_particles=-1), dict(beta_m=-1.0),
+])
+def test_invalid_parameters_rejected(L, bad):
+    from paper_2210_01837_amd import _lib
+    p = _params(**bad)
+    h = ctypes.c_void_p(0)
+    assert L.fcmdp_create_solver(ctypes.byref(p), ctypes.byref(h)) == _lib.EINVAL
+    assert not h.value
+    nb = ctypes.c_size_t(0)
+    assert L.fcmdp_workspace_bytes(ctypes.byref(p), 10, ctypes.byref(nb)) == _lib.EINVAL
+
+
+def test_workspace_bytes_scales(L):
+    from paper_2210_01837_amd import workspace_bytes
+    kw = dict(geometry="bw", Lx=1448.0, Ly=1448.0, H=12.0, Nx=2176, Ny=2176,
+              Nz=32, precision="mixed")
+    small = workspace_bytes(1000, **kw)
+    big = workspace_bytes(1 << 20, **kw)
+    grid = 6 * 32 * 2176 * 2176 * 4
+    assert small > 2 * grid and big > small
+    kw64 = dict(kw, Nx=768, Ny=768, Lx=512.0, Ly=512.0)
+    assert (workspace_bytes(1 << 17, **dict(kw64, precision="fp64"))
+            > workspace_bytes(1 << 17, **kw64))
+
+
+def test_null_arguments(L):
+    from paper_2210_01837_amd import _lib
+    assert L.fcmdp_create_solver(None, None) == _lib.EINVAL
+    assert L.fcmdp_apply_mobility(None, 1, None, None, None, None, None, None) == _lib.EINVAL
+    assert L.fcmdp_status(None, None) == _lib.EINVAL
+    L.fcmdp_destroy_solver(None)

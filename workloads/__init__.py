@@ -215,3 +215,20 @@ def poisson_arrivals(count: int, rate: float, seed: int = SEED_BASE + 6):
     """Arrival times (seconds) of a Poisson process with the given rate."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, count))
+
+
+def random_array(shape, seed: int, complex_: bool = False):
+    """Seeded N(0,1) array (complex: independent real and imaginary parts);
+    stage-level inputs for parity tests."""
+    rng = np.random.default_rng(SEED_BASE + 300 + seed)
+    a = rng.standard_normal(shape)
+    if complex_:
+        a = a + 1j * rng.standard_normal(shape)
+    return a
+
+
+def random_particles(box: Box, n: int, seed: int, zlo: float, zhi: float):
+    """Seeded uniform particles in [0,Lx) x [0,Ly) x [zlo, zhi] with
+    N(0,1) forces and torques."""
+    rng = np.random.default_rng(SEED_BASE + 400 + seed)
+    return _draw(rng, n, box.Lx, box.Ly, "uniform", zlo, zhi, "normal")
