@@ -114,6 +114,19 @@ const char* fcmdp_strerror(int code);
 int fcmdp_solver_info(const fcmdp_solver* s, double out[4]);
 
 /*
+ * Per-stage timing with HIP events on the apply's stream (tracing).  When
+ * enabled, every fcmdp_apply_mobility brackets its stages with events:
+ *   0 particle prep + sort + records, 1 spread, 2 forward xy FFT,
+ *   3 column solve, 4 inverse xy FFT, 5 interpolation.
+ * fcmdp_stage_times() waits for the recorded events, returns the summed
+ * milliseconds per stage in ms[0..5], the z-band of the last apply in
+ * ms[6] (first node) and ms[7] (last node), the number of applies timed in
+ * *napplies, and resets the accumulators.  Blocking (host side).
+ */
+int fcmdp_set_profiling(fcmdp_solver* s, int enable);
+int fcmdp_stage_times(fcmdp_solver* s, double ms[8], int64_t* napplies);
+
+/*
  * Stage entry points (the steps of Sec. 3.4 one at a time, on caller
  * buffers; used for per-stage parity tests).  Real element type is double
  * in FP64 mode and float in MIXED mode.  Layouts:

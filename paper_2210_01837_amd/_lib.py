@@ -77,6 +77,11 @@ def lib() -> ctypes.CDLL:
         L.fcmdp_stage_fft_inverse.restype = ci
         L.fcmdp_stage_interp.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.fcmdp_stage_interp.restype = ci
+        L.fcmdp_set_profiling.argtypes = [vp, ci]
+        L.fcmdp_set_profiling.restype = ci
+        L.fcmdp_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(i64)]
+        L.fcmdp_stage_times.restype = ci
         _lib = L
     return _lib
 

@@ -375,6 +375,8 @@ void fcmdp_destroy_solver(fcmdp_solver* s) {
   if (!s) return;
   (void)hipSetDevice(s->device);
   (void)hipDeviceSynchronize();
+  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  s->events.clear();
   free_all(s);
   delete s;
 }
@@ -427,18 +429,70 @@ int fcmdp_apply_mobility(fcmdp_solver* s, int64_t n, const void* pos,
                                                                : FCMDP_EHIP;
   }
   const int ni = (int)n;
+  hipEvent_t ev[7] = {};
+  const bool prof = s->profiling;
+  if (prof) {
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) return FCMDP_EHIP;
+  }
+  auto mark = [&](int i) {
+    if (prof) (void)hipEventRecord(ev[i], st);
+  };
+  mark(0);
   v = particle_front(s, ni, pos, F, T, st);
   if (v != FCMDP_OK) return v;
+  mark(1);
   if (fcmdp::launch_spread(s, s->grid, st) != hipSuccess) return FCMDP_EHIP;
+  mark(2);
   if (fcmdp::launch_fft_forward(s, s->grid, s->spec, st) != hipSuccess)
     return FCMDP_EHIP;
+  mark(3);
   if (fcmdp::launch_columns(s, s->spec, s->spec, st) != hipSuccess)
     return FCMDP_EHIP;
+  mark(4);
   if (fcmdp::launch_fft_inverse(s, s->spec, s->grid, st) != hipSuccess)
     return FCMDP_EHIP;
+  mark(5);
   if (fcmdp::launch_interp(s, ni, s->grid, U, Omega, st) != hipSuccess)
     return FCMDP_EHIP;
+  mark(6);
+  if (prof) s->events.insert(s->events.end(), ev, ev + 7);
   return FCMDP_OK;
+}
+
+int fcmdp_set_profiling(fcmdp_solver* s, int enable) {
+  if (!s) return FCMDP_EINVAL;
+  s->profiling = enable != 0;
+  return FCMDP_OK;
+}
+
+int fcmdp_stage_times(fcmdp_solver* s, double ms[8], int64_t* napplies) {
+  if (!s || !ms) return FCMDP_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  for (int i = 0; i < 8; ++i) ms[i] = 0.0;
+  const size_t na = s->events.size() / 7;
+  int rc = FCMDP_OK;
+  if (na && hipEventSynchronize(s->events.back()) != hipSuccess) rc = FCMDP_EHIP;
+  for (size_t a = 0; a < na && rc == FCMDP_OK; ++a)
+    for (int i = 0; i < 6; ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, s->events[7 * a + i],
+                              s->events[7 * a + i + 1]) != hipSuccess) {
+        rc = FCMDP_EHIP;
+        break;
+      }
+      ms[i] += t;
+    }
+  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  s->events.clear();
+  int band[2] = {0, -1};
+  if (rc == FCMDP_OK &&
+      hipMemcpy(band, s->band, sizeof(band), hipMemcpyDeviceToHost) != hipSuccess)
+    rc = FCMDP_EHIP;
+  ms[6] = band[0];
+  ms[7] = band[1];
+  if (napplies) *napplies = (int64_t)na;
+  return rc;
 }
 
 static size_t grid_bytes(const fcmdp_solver* s) {

@@ -14,6 +14,7 @@
 
 #include <cstdint>
 #include <cstddef>
+#include <vector>
 
 #include "../../include/fcmdp.h"
 
@@ -84,6 +85,10 @@ struct fcmdp_solver {
   void* tw_r = nullptr;         // e^{-2 pi i k/Nx}, k <= Nx/2
   fcmdp::FFTPlan plan_x, plan_y;
   int dft_off[32] = {0};        // offset of prime P's table in dftc
+
+  // tracing: events of applies not yet summed, 7 per apply
+  bool profiling = false;
+  std::vector<hipEvent_t> events;
 };
 
 namespace fcmdp {

@@ -111,6 +111,23 @@ class Solver:
             _stream(stream)), "fcmdp_apply_mobility")
         return U, Omega
 
+    STAGES = ("particles", "spread", "fft_forward", "columns", "fft_inverse",
+              "interp")
+
+    def set_profiling(self, enable=True):
+        L.check(L.lib().fcmdp_set_profiling(self._h, int(bool(enable))),
+                "fcmdp_set_profiling")
+
+    def stage_times(self):
+        """Summed ms per stage since the last call, the number of applies,
+        and the z-band (first, last node) of the last apply."""
+        ms = (ctypes.c_double * 8)()
+        na = ctypes.c_int64(0)
+        L.check(L.lib().fcmdp_stage_times(self._h, ms, ctypes.byref(na)),
+                "fcmdp_stage_times")
+        return (dict(zip(self.STAGES, ms[:6])), na.value,
+                (int(ms[6]), int(ms[7])))
+
     def status(self):
         bad = ctypes.c_int64(0)
         code = L.lib().fcmdp_status(self._h, ctypes.byref(bad))
