@@ -23,27 +23,9 @@
 // and is solved here in O(Nz) by elimination from the top coefficient down,
 // folding the dense row along the way.
 #include "fcmdp_internal.h"
+#include "colmath.h"
 
 namespace fcmdp {
-
-struct Z2 {
-  double x, y;
-};
-__device__ inline Z2 zmk(double a, double b) { Z2 r; r.x = a; r.y = b; return r; }
-__device__ inline Z2 operator+(Z2 a, Z2 b) { return zmk(a.x + b.x, a.y + b.y); }
-__device__ inline Z2 operator-(Z2 a, Z2 b) { return zmk(a.x - b.x, a.y - b.y); }
-__device__ inline Z2 operator*(double s, Z2 a) { return zmk(s * a.x, s * a.y); }
-__device__ inline Z2 operator*(Z2 a, Z2 b) {
-  return zmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ inline Z2 zdiv(Z2 a, double d) { return zmk(a.x / d, a.y / d); }
-// i * s * a for real s
-__device__ inline Z2 imul(double s, Z2 a) { return zmk(-s * a.y, s * a.x); }
-
-struct ColParams {
-  DevParams dp;
-  double scale;       // 1 / (Nx Ny)
-};
 
 // Chebyshev derivative d/dz (coefficients), b[N-1] = 0,
 // c_{n-1} b_{n-1} = b_{n+1} + 2 n a_n, times 2/H.
@@ -134,32 +116,6 @@ __device__ void bvp_zero_mode(const Z2* r, double H, int N, int geometry,
   } else {
     y[0] = -0.5 * (Sp + Sm);
     y[1] = -0.5 * (Sp - Sm);
-  }
-}
-
-// 6x6 real Gaussian elimination with partial pivoting, complex RHS.
-__device__ void solve6(double A[6][6], Z2 b[6]) {
-  for (int c = 0; c < 6; ++c) {
-    int piv = c;
-    double best = fabs(A[c][c]);
-    for (int r = c + 1; r < 6; ++r)
-      if (fabs(A[r][c]) > best) { best = fabs(A[r][c]); piv = r; }
-    if (piv != c) {
-      for (int k = 0; k < 6; ++k) { double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
-      Z2 t = b[c]; b[c] = b[piv]; b[piv] = t;
-    }
-    const double inv = 1.0 / A[c][c];
-    for (int r = c + 1; r < 6; ++r) {
-      const double f = A[r][c] * inv;
-      if (f == 0.0) continue;
-      for (int k = c; k < 6; ++k) A[r][k] -= f * A[c][k];
-      b[r] = b[r] - f * b[c];
-    }
-  }
-  for (int c = 5; c >= 0; --c) {
-    Z2 v = b[c];
-    for (int k = c + 1; k < 6; ++k) v = v - A[c][k] * b[k];
-    b[c] = zdiv(v, A[c][c]);
   }
 }
 
@@ -350,6 +306,8 @@ k_columns(ColParams cp, const int* __restrict__ band,
 
 hipError_t launch_columns(const fcmdp_solver* s, const void* spec_in,
                           void* spec_out, hipStream_t st) {
+  if (s->dp.Nz <= 32 && !s->force_generic_columns)
+    return launch_columns_seg(s, spec_in, spec_out, st);
   ColParams cp;
   cp.dp = s->dp;
   cp.scale = 1.0 / ((double)s->dp.Nx * (double)s->dp.Ny);

@@ -86,6 +86,9 @@ struct fcmdp_solver {
   fcmdp::FFTPlan plan_x, plan_y;
   int dft_off[32] = {0};        // offset of prime P's table in dftc
 
+  // use the one-thread-per-column solver even when Nz <= 32 (tests)
+  bool force_generic_columns = false;
+
   // tracing: events of applies not yet summed, 7 per apply
   bool profiling = false;
   std::vector<hipEvent_t> events;
@@ -112,9 +115,11 @@ hipError_t launch_fft_forward(const fcmdp_solver* s, const void* grid,
                               void* spec, hipStream_t st);
 hipError_t launch_fft_inverse(const fcmdp_solver* s, void* spec, void* grid,
                               hipStream_t st);
-// columns.hip
+// columns.hip (dispatches to columns_seg.hip for Nz <= 32)
 hipError_t launch_columns(const fcmdp_solver* s, const void* spec_in,
                           void* spec_out, hipStream_t st);
+hipError_t launch_columns_seg(const fcmdp_solver* s, const void* spec_in,
+                              void* spec_out, hipStream_t st);
 
 // --- small device helpers ------------------------------------------------
 __host__ __device__ inline int wrap_index(int i, int n) {
