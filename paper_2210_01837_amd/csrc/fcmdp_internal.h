@@ -88,6 +88,8 @@ struct fcmdp_solver {
 
   // use the one-thread-per-column solver even when Nz <= 32 (tests)
   bool force_generic_columns = false;
+  // use the one-thread-per-particle interpolation (tests)
+  bool force_simple_interp = false;
 
   // tracing: events of applies not yet summed, 7 per apply
   bool profiling = false;

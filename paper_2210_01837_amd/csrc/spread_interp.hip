@@ -174,9 +174,222 @@ k_interp(DevParams dp, int n, const uint32_t* __restrict__ skeys,
   }
 }
 
+// Tiled interpolation: a workgroup owns a TILE x TILE block of xy cells and
+// interpolates the particles whose cell lies in it.  The grid values of the
+// block plus its 3-cell halo are staged in LDS, ZC z-planes at a time; the
+// particles' weights are cached in LDS; an 8-lane group handles one particle
+// (lane = x-offset of the 7-point window) and reduces its partial sums with
+// shuffles in a fixed order, so results are deterministic.
+constexpr int kTile = 16;
+constexpr int kRX = kTile + 6;
+
+template <typename T, int ZC>
+__global__ void __launch_bounds__(256)
+k_interp_tiled(DevParams dp, const int* __restrict__ band,
+               const int* __restrict__ cell_start,
+               const int4* __restrict__ pinfo, const T* __restrict__ pw,
+               const T* __restrict__ psi, const T* __restrict__ quad,
+               const T* __restrict__ grid, const int* __restrict__ perm,
+               T* __restrict__ U, T* __restrict__ Om, int cap) {
+  extern __shared__ unsigned char lds_raw[];
+  const int ZW = dp.ZW;
+  T* G = reinterpret_cast<T*>(lds_raw);                 // [ZC][6][kRX][kRX]
+  T* pcw = G + ZC * 6 * kRX * kRX;                      // [cap][32]
+  T* pcz = pcw + cap * 32;                              // [cap][2 ZW]
+  T* acc = pcz + cap * 2 * ZW;                          // [cap][6]
+  int4* pci = reinterpret_cast<int4*>(acc + cap * 6);   // [cap]
+  int* pcj = reinterpret_cast<int*>(pci + cap);         // [cap]
+  int* pcp = pcj + cap;                                 // [cap]
+  __shared__ int rowoff[kTile + 1];
+  __shared__ int rowstart[kTile];
+
+  const int lo = band[0], hi = band[1];
+  if (lo > hi) return;
+  const int tid = threadIdx.x;
+  const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
+  if (tid < kTile) {
+    const int iy = ty0 + tid;
+    int s0 = 0, e0 = 0;
+    if (iy < dp.Ny) {
+      s0 = cell_start[iy * dp.Nx + tx0];
+      e0 = cell_start[iy * dp.Nx + min(tx0 + kTile, dp.Nx)];
+    }
+    rowstart[tid] = s0;
+    rowoff[tid + 1] = e0 - s0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    rowoff[0] = 0;
+    for (int r = 0; r < kTile; ++r) rowoff[r + 1] += rowoff[r];
+  }
+  __syncthreads();
+  const int nhome = rowoff[kTile];
+  if (nhome == 0) return;
+  const size_t plane = (size_t)dp.Nx * dp.Ny;
+  const size_t chstride = plane * dp.Nz;
+  const int g = tid / 8, l = tid % 8;
+  constexpr int NG = 256 / 8;
+
+  for (int base = 0; base < nhome; base += cap) {
+    const int np = min(cap, nhome - base);
+    for (int h = tid; h < np; h += 256) {
+      const int hp = base + h;
+      int r = 0;
+      while (r + 1 < kTile && rowoff[r + 1] <= hp) ++r;
+      const int p = rowstart[r] + (hp - rowoff[r]);
+      pcp[h] = p;
+      pci[h] = pinfo[p];
+      pcj[h] = perm[p];
+    }
+    __syncthreads();
+    for (int e = tid; e < np * 32; e += 256) pcw[e] = pw[(size_t)pcp[e >> 5] * 32 + (e & 31)];
+    for (int e = tid; e < np * 2 * ZW; e += 256) {
+      const int h = e / (2 * ZW);
+      pcz[e] = psi[(size_t)pcp[h] * 2 * ZW + (e - h * 2 * ZW)];
+    }
+    for (int e = tid; e < np * 6; e += 256) acc[e] = T(0);
+    __syncthreads();
+    for (int c0 = lo; c0 <= hi; c0 += ZC) {
+      const int nz = min(ZC, hi - c0 + 1);
+      for (int e = tid; e < nz * 6 * kRX * kRX; e += 256) {
+        const int rx = e % kRX;
+        int t = e / kRX;
+        const int ry = t % kRX;
+        t /= kRX;
+        const int ch = t % 6;
+        const int sidx = t / 6;
+        const int a = wrap_index(tx0 - 3 + rx, dp.Nx);
+        const int b = wrap_index(ty0 - 3 + ry, dp.Ny);
+        G[e] = grid[ch * chstride + (size_t)(c0 + sidx) * plane + (size_t)b * dp.Nx + a];
+      }
+      __syncthreads();
+      for (int h = g; h < np; h += NG) {
+        const int4 inf = pci[h];
+        if (inf.w < c0 || inf.z > c0 + nz - 1) continue;   // no z overlap
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+        if (l < 7) {
+          const T* w = pcw + h * 32;
+          const T* ps = pcz + h * 2 * ZW;
+          const T wxm = w[l], wxd = w[16 + l];
+          const int rx = inf.x - tx0 + l;
+          const int ry0 = inf.y - ty0;
+          for (int dy = 0; dy < 7; ++dy) {
+            const T wm = wxm * w[8 + dy];
+            const T wd = wxd * w[24 + dy];
+            if (wm == T(0) && wd == T(0)) continue;
+            const int ry = ry0 + dy;
+#pragma unroll
+            for (int sidx = 0; sidx < ZC; ++sidx) {
+              const int c = c0 + sidx;
+              const int zi = c - inf.z;
+              if (sidx < nz && zi >= 0 && zi < ZW) {
+                const T q = quad[c];
+                const T qm = q * ps[zi] * wm;
+                const T qd = q * ps[ZW + zi] * wd;
+                const T* gp = G + (sidx * 6 * kRX + ry) * kRX + rx;
+                constexpr int CS = kRX * kRX;
+                a0 += qm * gp[0];
+                a1 += qm * gp[CS];
+                a2 += qm * gp[2 * CS];
+                a3 += qd * gp[3 * CS];
+                a4 += qd * gp[4 * CS];
+                a5 += qd * gp[5 * CS];
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1) {
+          a0 += __shfl_xor(a0, m, 8);
+          a1 += __shfl_xor(a1, m, 8);
+          a2 += __shfl_xor(a2, m, 8);
+          a3 += __shfl_xor(a3, m, 8);
+          a4 += __shfl_xor(a4, m, 8);
+          a5 += __shfl_xor(a5, m, 8);
+        }
+        if (l == 0) {
+          T* ac = acc + h * 6;
+          ac[0] += a0; ac[1] += a1; ac[2] += a2;
+          ac[3] += a3; ac[4] += a4; ac[5] += a5;
+        }
+      }
+      __syncthreads();
+    }
+    for (int h = tid; h < np; h += 256) {
+      const int j = pcj[h];
+      const T* ac = acc + h * 6;
+      U[3 * (size_t)j + 0] = ac[0];
+      U[3 * (size_t)j + 1] = ac[1];
+      U[3 * (size_t)j + 2] = ac[2];
+      if (Om) {
+        Om[3 * (size_t)j + 0] = ac[3];
+        Om[3 * (size_t)j + 1] = ac[4];
+        Om[3 * (size_t)j + 2] = ac[5];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// NaN outputs for particles outside the domain (sorted to the end)
+template <typename T>
+__global__ void k_interp_invalid(int n, int ncells, const uint32_t* __restrict__ skeys,
+                                 const int* __restrict__ perm, T* __restrict__ U,
+                                 T* __restrict__ Om) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || skeys[i] < (uint32_t)ncells) return;
+  const int j = perm[i];
+  const T nan = T(NAN);
+  U[3 * (size_t)j + 0] = U[3 * (size_t)j + 1] = U[3 * (size_t)j + 2] = nan;
+  if (Om) Om[3 * (size_t)j + 0] = Om[3 * (size_t)j + 1] = Om[3 * (size_t)j + 2] = nan;
+}
+
+template <typename T, int ZC>
+static size_t interp_lds(int ZW, int cap) {
+  return (size_t)ZC * 6 * kRX * kRX * sizeof(T) +
+         (size_t)cap * (32 + 2 * ZW + 6) * sizeof(T) + (size_t)cap * (16 + 8);
+}
+
+template <typename T>
+static hipError_t interp_tiled(const fcmdp_solver* s, int n, const T* grid,
+                               T* U, T* Om, hipStream_t st) {
+  const DevParams& dp = s->dp;
+  hipLaunchKernelGGL(k_interp_invalid<T>, dim3((n + 255) / 256), dim3(256), 0,
+                     st, n, dp.ncells, s->keyA, s->valA, U, Om);
+  dim3 g((dp.Nx + kTile - 1) / kTile, (dp.Ny + kTile - 1) / kTile);
+  const size_t limit = 65536;
+  int cap = 64;
+  while (cap > 8 && interp_lds<T, 4>(dp.ZW, cap) > limit) cap -= 8;
+  if (interp_lds<T, 4>(dp.ZW, cap) <= limit) {
+    const size_t lds4 = interp_lds<T, 4>(dp.ZW, cap);
+    hipLaunchKernelGGL((k_interp_tiled<T, 4>), g, dim3(256), lds4, st, dp,
+                       s->band,
+                       s->cell_start, s->pinfo, (const T*)s->pw,
+                       (const T*)s->psi, (const T*)s->quad, grid, s->valA, U,
+                       Om, cap);
+    return hipGetLastError();
+  }
+  cap = 64;
+  while (cap > 8 && interp_lds<T, 2>(dp.ZW, cap) > limit) cap -= 8;
+  const size_t lds2 = interp_lds<T, 2>(dp.ZW, cap);
+  hipLaunchKernelGGL((k_interp_tiled<T, 2>), g, dim3(256), lds2, st, dp,
+                     s->band,
+                     s->cell_start, s->pinfo, (const T*)s->pw,
+                     (const T*)s->psi, (const T*)s->quad, grid, s->valA, U, Om,
+                     cap);
+  return hipGetLastError();
+}
+
 hipError_t launch_interp(const fcmdp_solver* s, int n, const void* grid,
                          void* U, void* Omega, hipStream_t st) {
   if (n == 0) return hipSuccess;
+  if (!s->force_simple_interp) {
+    if (s->mixed)
+      return interp_tiled<float>(s, n, (const float*)grid, (float*)U,
+                                 (float*)Omega, st);
+    return interp_tiled<double>(s, n, (const double*)grid, (double*)U,
+                                (double*)Omega, st);
+  }
   dim3 g((n + 255) / 256);
   if (s->mixed)
     hipLaunchKernelGGL(k_interp<float>, g, dim3(256), 0, st, s->dp, n,
