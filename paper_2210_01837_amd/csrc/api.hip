@@ -169,7 +169,7 @@ Sizes sizes_for(const fcmdp_params* p, int64_t cap, int ZW) {
   s.keys = c * 4;
   s.vals = c * 4;
   const size_t nblk = (c + 2047) / 2048;
-  s.hist = 256 * nblk * 4;
+  s.hist = (256 * nblk + 256) * 4;   // block histograms + digit totals
   s.cells = ((size_t)p->Nx * p->Ny + 1) * 4;
   s.pinfo = c * 16;
   s.pw = c * 32 * T;
@@ -205,6 +205,7 @@ void free_all(fcmdp_solver* s) {
   void* ptrs[] = {s->grid, s->spec, s->keyA, s->keyB, s->valA, s->valB,
                   s->hist, s->cell_start, s->pinfo, s->pw, s->pf, s->psi,
                   s->band, s->nbad, s->zc, s->quad, s->dct_f, s->dct_i,
+                  s->dct_f32, s->dct_i32,
                   s->dftc, s->tw_x, s->tw_y, s->tw_r};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -273,6 +274,7 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
   dp.inv_norm_d = 1.0 / s->norm_d;
   dp.ZW = z_window_slots(Nz, p->H, dp.alpha);
   s->cap = p->max_particles;
+  s->nblk_cap = (int)((s->cap > 0 ? s->cap : 1) + 2047) / 2048;
   {
     int bits = 0;
     while (((int64_t)1 << bits) <= (int64_t)dp.ncells) ++bits;
@@ -324,6 +326,11 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
     s->zc = (double*)upload(zc, &err);
     s->dct_f = (double*)upload(Mf, &err);
     s->dct_i = (double*)upload(Pi, &err);
+    if (s->mixed) {
+      std::vector<float> mf(Mf.begin(), Mf.end()), pf(Pi.begin(), Pi.end());
+      s->dct_f32 = (float*)upload(mf, &err);
+      s->dct_i32 = (float*)upload(pf, &err);
+    }
     if (s->mixed) {
       std::vector<float> q(Nz);
       for (int c = 0; c < Nz; ++c) q[c] = (float)(h2 * 0.5 * p->H * w[c]);

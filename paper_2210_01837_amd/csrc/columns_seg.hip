@@ -37,9 +37,38 @@ __device__ inline double shd(double a, int src) { return __shfl(a, src, kSeg); }
 __device__ inline Z2 shz(Z2 a, int src) {
   return zmk(__shfl(a.x, src, kSeg), __shfl(a.y, src, kSeg));
 }
-__device__ inline double red(double a) {
-#pragma unroll
-  for (int m = 1; m < kSeg; m <<= 1) a += __shfl_xor(a, m, kSeg);
+// DPP moves inside 16-lane rows (an 8-lane group is half a row; values that
+// cross a group edge are discarded by the callers' lane guards).
+//   from_up<K>(v):   value of lane l + K    (row_shl:K)
+//   from_down<K>(v): value of lane l - K    (row_shr:K)
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(dpp_i<CTRL>(hi), dpp_i<CTRL>(lo));
+}
+template <int K> __device__ __forceinline__ double from_up(double v) {
+  return dpp_d<0x100 + K>(v);
+}
+template <int K> __device__ __forceinline__ double from_down(double v) {
+  return dpp_d<0x110 + K>(v);
+}
+template <int K> __device__ __forceinline__ Z2 from_up(Z2 a) {
+  return zmk(from_up<K>(a.x), from_up<K>(a.y));
+}
+template <int K> __device__ __forceinline__ Z2 from_down(Z2 a) {
+  return zmk(from_down<K>(a.x), from_down<K>(a.y));
+}
+
+// sum over the 8 lanes of a group: quad_perm xor 1, xor 2, then the
+// half-row mirror pairs each quad with the other quad of the group
+__device__ __forceinline__ double red(double a) {
+  a += dpp_d<0xB1>(a);
+  a += dpp_d<0x4E>(a);
+  a += dpp_d<0x141>(a);
   return a;
 }
 __device__ inline Z2 red(Z2 a) { return zmk(red(a.x), red(a.y)); }
@@ -58,17 +87,16 @@ __device__ inline Vec seg_deriv(const Vec& a, int l, double s2H) {
   const Z2 E = q[0] + q[2];     // even-n terms of this lane
   const Z2 O = q[1] + q[3];     // odd-n terms
   Z2 sE = E, sO = O;            // inclusive suffix sums over lanes
-#pragma unroll
-  for (int k = 1; k < kSeg; k <<= 1) {
-    const int src = l + k < kSeg ? l + k : kSeg - 1;
-    const Z2 tE = shz(sE, src), tO = shz(sO, src);
-    if (l + k < kSeg) {
-      sE = sE + tE;
-      sO = sO + tO;
-    }
+  {
+    Z2 tE = from_up<1>(sE), tO = from_up<1>(sO);
+    if (l + 1 < kSeg) { sE = sE + tE; sO = sO + tO; }
+    tE = from_up<2>(sE); tO = from_up<2>(sO);
+    if (l + 2 < kSeg) { sE = sE + tE; sO = sO + tO; }
+    tE = from_up<4>(sE); tO = from_up<4>(sO);
+    if (l + 4 < kSeg) { sE = sE + tE; sO = sO + tO; }
   }
-  Z2 SE = shz(sE, l + 1 < kSeg ? l + 1 : kSeg - 1);
-  Z2 SO = shz(sO, l + 1 < kSeg ? l + 1 : kSeg - 1);
+  Z2 SE = from_up<1>(sE);
+  Z2 SO = from_up<1>(sO);
   if (l == kSeg - 1) {
     SE = zmk(0, 0);
     SO = zmk(0, 0);
@@ -84,15 +112,31 @@ __device__ inline Vec seg_deriv(const Vec& a, int l, double s2H) {
 
 // Operator data of one parity for the Robin BVP (depends on kappa only).
 // Slot s = 0, 1 of lane l is unknown i = 2l + s, coefficient m = 2i + p.
+// Only what the scans produce is kept; the row coefficients are recomputed.
 struct Par {
   double alpha[2];
   double P[2];
   double invD[2];
-  double a[2];
-  double e[2];
-  double lo[2], di[2], up[2];
   double eP;
 };
+
+struct Row {
+  double lo, di, up;   // B^2 row m: c_{m-2}/(4m(m-1)), 1/(2(m^2-1)), 1/(4m(m+1))
+  bool row;            // an interior row (m >= 2, m < N)
+};
+
+__device__ inline Row row_of(int m, int N) {
+  Row r;
+  r.row = m >= 2 && m < N;
+  if (r.row) {
+    r.lo = (m == 2 ? 2.0 : 1.0) / (4.0 * m * (m - 1));
+    r.di = 1.0 / (2.0 * ((double)m * m - 1.0));
+    r.up = (m + 2 < N) ? 1.0 / (4.0 * m * (m + 1)) : 0.0;
+  } else {
+    r.lo = r.di = r.up = 0.0;
+  }
+  return r;
+}
 
 __device__ inline void m2mul(const double* A, const double* B, double* C) {
   C[0] = A[0] * B[0] + A[1] * B[2];
@@ -101,29 +145,24 @@ __device__ inline void m2mul(const double* A, const double* B, double* C) {
   C[3] = A[2] * B[1] + A[3] * B[3];
 }
 
-__device__ Par seg_prepare(double kappa, int N, int l, int p) {
+__device__ __forceinline__ Par seg_prepare(double kappa, int N, int l, int p) {
   Par q;
   const double k2 = kappa * kappa;
   double T[2][4];
-  double Dd[2], Uu[2];
+  double Dd[2], Uu[2], e[2];
   bool act[2], row[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const int i = 2 * l + s;
-    const int m = 2 * i + p;
+    const int m = 4 * l + 2 * s + p;
     act[s] = m < N;
-    row[s] = act[s] && i >= 1;
-    q.e[s] = act[s] ? (double)m * m + kappa : 0.0;
+    const Row rw = row_of(m, N);
+    row[s] = rw.row;
+    e[s] = act[s] ? (double)m * m + kappa : 0.0;
     if (row[s]) {
-      q.lo[s] = (m - 2 == 0 ? 2.0 : 1.0) / (4.0 * m * (m - 1));
-      q.di[s] = 1.0 / (2.0 * ((double)m * m - 1.0));
-      q.up[s] = (m + 2 < N) ? 1.0 / (4.0 * m * (m + 1)) : 0.0;
-      const double L = -k2 * q.lo[s];
-      Dd[s] = 1.0 + k2 * q.di[s];
-      Uu[s] = -k2 * q.up[s];
-      T[s][0] = 0.0; T[s][1] = -L; T[s][2] = Uu[s]; T[s][3] = Dd[s];
+      Dd[s] = 1.0 + k2 * rw.di;
+      Uu[s] = -k2 * rw.up;
+      T[s][0] = 0.0; T[s][1] = k2 * rw.lo; T[s][2] = Uu[s]; T[s][3] = Dd[s];
     } else {
-      q.lo[s] = q.di[s] = q.up[s] = 0.0;
       Dd[s] = 1.0;
       Uu[s] = 0.0;
       T[s][0] = 1.0; T[s][1] = 0.0; T[s][2] = 0.0; T[s][3] = 1.0;
@@ -132,26 +171,32 @@ __device__ Par seg_prepare(double kappa, int N, int l, int p) {
   // suffix products of the 2x2 Moebius matrices, normalised (only ratios matter)
   double Y[4];
   m2mul(T[0], T[1], Y);
-#pragma unroll
-  for (int k = 1; k < kSeg; k <<= 1) {
-    const int src = l + k < kSeg ? l + k : kSeg - 1;
-    double Yk[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) Yk[e] = shd(Y[e], src);
-    if (l + k < kSeg) {
+  auto mstep = [&](double* Yk, bool take) {
+    if (take) {
       double Z[4];
       m2mul(Y, Yk, Z);
       const double sc = fmax(fmax(fabs(Z[0]), fabs(Z[1])), fmax(fabs(Z[2]), fabs(Z[3])));
       const double inv = sc > 0.0 ? 1.0 / sc : 1.0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) Y[e] = Z[e] * inv;
+      for (int c = 0; c < 4; ++c) Y[c] = Z[c] * inv;
     }
+  };
+  {
+    double Yk[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Yk[c] = from_up<1>(Y[c]);
+    mstep(Yk, l + 1 < kSeg);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Yk[c] = from_up<2>(Y[c]);
+    mstep(Yk, l + 2 < kSeg);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Yk[c] = from_up<4>(Y[c]);
+    mstep(Yk, l + 4 < kSeg);
   }
   double X[4];
   {
-    const int src = l + 1 < kSeg ? l + 1 : kSeg - 1;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) X[e] = shd(Y[e], src);
+    for (int c = 0; c < 4; ++c) X[c] = from_up<1>(Y[c]);
     if (l == kSeg - 1) { X[0] = 1.0; X[1] = 0.0; X[2] = 0.0; X[3] = 1.0; }
   }
   double S1[4], S0[4];
@@ -166,85 +211,89 @@ __device__ Par seg_prepare(double kappa, int N, int l, int p) {
   double anext[2];
   anext[0] = q.alpha[1];
   {
-    const double t = shd(q.alpha[0], l + 1 < kSeg ? l + 1 : kSeg - 1);
+    const double t = from_up<1>(q.alpha[0]);
     anext[1] = (l + 1 < kSeg) ? t : 0.0;
   }
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    if (row[s]) {
-      const double delta = Dd[s] + Uu[s] * anext[s];
-      q.invD[s] = 1.0 / delta;
-      q.a[s] = -Uu[s] * q.invD[s];
-    } else {
-      q.invD[s] = 0.0;
-      q.a[s] = 0.0;
-    }
-  }
+  for (int s = 0; s < 2; ++s)
+    q.invD[s] = row[s] ? 1.0 / (Dd[s] + Uu[s] * anext[s]) : 0.0;
   // prefix products P_i = alpha_i P_{i-1}
   double Yp = q.alpha[0] * q.alpha[1];
-#pragma unroll
-  for (int k = 1; k < kSeg; k <<= 1) {
-    const double t = shd(Yp, l >= k ? l - k : 0);
-    if (l >= k) Yp *= t;
+  {
+    double t = from_down<1>(Yp);
+    if (l >= 1) Yp *= t;
+    t = from_down<2>(Yp);
+    if (l >= 2) Yp *= t;
+    t = from_down<4>(Yp);
+    if (l >= 4) Yp *= t;
   }
-  double Pin = shd(Yp, l >= 1 ? l - 1 : 0);
+  double Pin = from_down<1>(Yp);
   if (l == 0) Pin = 1.0;
   q.P[0] = q.alpha[0] * Pin;
   q.P[1] = q.alpha[1] * q.P[0];
-  q.eP = red(q.e[0] * q.P[0] + q.e[1] * q.P[1]);
+  q.eP = red(e[0] * q.P[0] + e[1] * q.P[1]);
   return q;
 }
 
 // Robin BVP y'' - k^2 y = r, (d/dz + k) y(H) = gH, (d/dz - k) y(0) = g0.
-__device__ Vec seg_solve(const Par* q, const Vec& r, Z2 gH, Z2 g0, double H,
-                         int l) {
+__device__ __forceinline__ Vec seg_solve(const Par* q, const Vec& r, Z2 gH, Z2 g0, double H,
+                         double kappa, int N, int l) {
   const double h2 = 0.25 * H * H;
+  const double k2 = kappa * kappa;
   Vec y;
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     const Par& Q = q[p];
+    const int m0 = 4 * l + p, m1 = 4 * l + 2 + p;
+    const Row w0 = row_of(m0, N), w1 = row_of(m1, N);
     const Z2 r0 = r.v[p], r1 = r.v[2 + p];
-    const Z2 rm2 = shz(r1, l >= 1 ? l - 1 : 0);          // r_{m-2} of slot 0
-    const Z2 rp2 = shz(r0, l + 1 < kSeg ? l + 1 : kSeg - 1);  // r_{m+2} of slot 1
-    const Z2 R0 = h2 * (Q.lo[0] * rm2 - Q.di[0] * r0 + Q.up[0] * r1);
-    const Z2 R1 = h2 * (Q.lo[1] * r0 - Q.di[1] * r1 + Q.up[1] * rp2);
+    const Z2 rm2 = from_down<1>(r1);                     // r_{m-2} of slot 0
+    const Z2 rp2 = from_up<1>(r0);                       // r_{m+2} of slot 1
+    const Z2 R0 = h2 * (w0.lo * rm2 - w0.di * r0 + w0.up * r1);
+    const Z2 R1 = h2 * (w1.lo * r0 - w1.di * r1 + w1.up * rp2);
     const Z2 b0 = Q.invD[0] * R0, b1 = Q.invD[1] * R1;
+    const double a0 = k2 * w0.up * Q.invD[0];   // -U_i / Delta_i
+    const double a1 = k2 * w1.up * Q.invD[1];
     // beta: suffix affine recurrence beta_i = a_i beta_{i+1} + b_i
-    double A = Q.a[0] * Q.a[1];
-    Z2 B = Q.a[0] * b1 + b0;
-#pragma unroll
-    for (int k = 1; k < kSeg; k <<= 1) {
-      const int src = l + k < kSeg ? l + k : kSeg - 1;
-      const double Ak = shd(A, src);
-      const Z2 Bk = shz(B, src);
-      if (l + k < kSeg) {
-        B = A * Bk + B;
-        A = A * Ak;
-      }
+    double A = a0 * a1;
+    Z2 B = a0 * b1 + b0;
+    {
+      double Ak = from_up<1>(A);
+      Z2 Bk = from_up<1>(B);
+      if (l + 1 < kSeg) { B = A * Bk + B; A = A * Ak; }
+      Ak = from_up<2>(A);
+      Bk = from_up<2>(B);
+      if (l + 2 < kSeg) { B = A * Bk + B; A = A * Ak; }
+      Ak = from_up<4>(A);
+      Bk = from_up<4>(B);
+      if (l + 4 < kSeg) { B = A * Bk + B; A = A * Ak; }
     }
-    Z2 bin = shz(B, l + 1 < kSeg ? l + 1 : kSeg - 1);
+    Z2 bin = from_up<1>(B);
     if (l == kSeg - 1) bin = zmk(0, 0);
-    const Z2 be1 = Q.a[1] * bin + b1;
-    Z2 be0 = Q.a[0] * be1 + b0;
+    const Z2 be1 = a1 * bin + b1;
+    Z2 be0 = a0 * be1 + b0;
     if (l == 0) be0 = zmk(0, 0);
     // Q_i = alpha_i Q_{i-1} + beta_i (prefix), Q_0 = 0
     double Aq = Q.alpha[1] * Q.alpha[0];
     Z2 Bq = Q.alpha[1] * be0 + be1;
-#pragma unroll
-    for (int k = 1; k < kSeg; k <<= 1) {
-      const int src = l >= k ? l - k : 0;
-      const double Ak = shd(Aq, src);
-      const Z2 Bk = shz(Bq, src);
-      if (l >= k) {
-        Bq = Aq * Bk + Bq;
-        Aq = Aq * Ak;
-      }
+    {
+      double Ak = from_down<1>(Aq);
+      Z2 Bk = from_down<1>(Bq);
+      if (l >= 1) { Bq = Aq * Bk + Bq; Aq = Aq * Ak; }
+      Ak = from_down<2>(Aq);
+      Bk = from_down<2>(Bq);
+      if (l >= 2) { Bq = Aq * Bk + Bq; Aq = Aq * Ak; }
+      Ak = from_down<4>(Aq);
+      Bk = from_down<4>(Bq);
+      if (l >= 4) { Bq = Aq * Bk + Bq; Aq = Aq * Ak; }
     }
-    Z2 qin = shz(Bq, l >= 1 ? l - 1 : 0);
+    Z2 qin = from_down<1>(Bq);
     if (l == 0) qin = zmk(0, 0);
     const Z2 Q0 = Q.alpha[0] * qin + be0;
     const Z2 Q1 = Q.alpha[1] * Q0 + be1;
-    const Z2 eQ = red(Q.e[0] * Q0 + Q.e[1] * Q1);
+    const double e0 = m0 < N ? (double)m0 * m0 + kappa : 0.0;
+    const double e1 = m1 < N ? (double)m1 * m1 + kappa : 0.0;
+    const Z2 eQ = red(e0 * Q0 + e1 * Q1);
     const Z2 g = p == 0 ? (0.25 * H) * (gH - g0) : (0.25 * H) * (gH + g0);
     const Z2 y0 = zdiv(g - eQ, Q.eP);
     y.v[p] = Q.P[0] * y0 + Q0;
@@ -253,16 +302,74 @@ __device__ Vec seg_solve(const Par* q, const Vec& r, Z2 gH, Z2 g0, double H,
   return y;
 }
 
+// 6x6 real system with complex right-hand side, one row per lane of the
+// 8-lane group (lanes 6, 7 idle): Gaussian elimination with partial pivoting.
+// A lane passes its row (a[0..5], b); on return lanes 0..5 hold x[lane].
+__device__ __forceinline__ Z2 seg_solve6(double a[6], Z2 b, int l) {
+  const bool active = l < 6;
+  for (int c = 0; c < 6; ++c) {
+    // pivot: largest |a[c]| among rows c..5 (lowest lane wins ties)
+    double v = (active && l >= c) ? fabs(a[c]) : -1.0;
+    int who = l;
+#pragma unroll
+    for (int m = 1; m < kSeg; m <<= 1) {
+      const double ov = __shfl_xor(v, m, kSeg);
+      const int ow = __shfl_xor(who, m, kSeg);
+      if (ov > v || (ov == v && ow < who)) { v = ov; who = ow; }
+    }
+    // swap rows c and who
+    double pr[6];
+    Z2 pb;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pr[k] = shd(a[k], who);
+    pb = shz(b, who);
+    double cr[6];
+    Z2 cb;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) cr[k] = shd(a[k], c);
+    cb = shz(b, c);
+    if (l == who && who != c) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a[k] = cr[k];
+      b = cb;
+    }
+    if (l == c) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a[k] = pr[k];
+      b = pb;
+    }
+    // eliminate below the pivot (pivot row = pr, pb)
+    if (active && l > c) {
+      const double f = a[c] / pr[c];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a[k] -= f * pr[k];
+      b = b - f * pb;
+    }
+  }
+  // back substitution: x_c = (b_c - sum_{k>c} a_ck x_k) / a_cc
+  Z2 x = zmk(0, 0);
+  for (int c = 5; c >= 0; --c) {
+    Z2 s = b;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k > c) s = s - a[k] * shz(x, k);
+    const Z2 xc = zdiv(s, a[c]);
+    const Z2 xb = shz(xc, c);
+    if (l == c) x = xb;
+  }
+  return x;
+}
+
 // k = 0: y'' = r with y(0) = 0 and y'(H) = 0 (bottom wall) or y(H) = 0.
-__device__ Vec seg_zero_mode(const Vec& r, double H, int N, int geometry,
+__device__ __forceinline__ Vec seg_zero_mode(const Vec& r, double H, int N, int geometry,
                              int l) {
   const double h2 = 0.25 * H * H;
   Vec y = vzero();
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     const Z2 r0 = r.v[p], r1 = r.v[2 + p];
-    const Z2 rm2 = shz(r1, l >= 1 ? l - 1 : 0);
-    const Z2 rp2 = shz(r0, l + 1 < kSeg ? l + 1 : kSeg - 1);
+    const Z2 rm2 = from_down<1>(r1);
+    const Z2 rp2 = from_up<1>(r0);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int m = 4 * l + 2 * s + p;
@@ -332,7 +439,142 @@ __device__ inline void seg_basis(const double fb[kNpl], const double* __restrict
   }
 }
 
-template <typename T>
+// Steps 2 (derivative part) to 6 for one column, from the Chebyshev
+// coefficients A[0..2] of f + (1/2)(ik_y g_z, -ik_x g_z, ik_x g_y - ik_y g_x)
+// and A[3], A[4] of g_x, g_y: body force, DP solve, wall correction, k = 0.
+template <int GEOM>
+__device__ __forceinline__ void seg_column_solve(const Vec* A, const DevParams& dp,
+                                 const double* __restrict__ zc,
+                                 const double* __restrict__ Mf, int N, int l,
+                                 double kx, double ky, double k, Vec& U,
+                                 Vec& V, Vec& W) {
+  const double H = dp.H, eta = dp.eta, s2H = 2.0 / H;
+  U = vzero();
+  V = vzero();
+  W = vzero();
+  const Vec dgy = seg_deriv(A[4], l, s2H);
+  const Vec dgx = seg_deriv(A[3], l, s2H);
+  Vec fx, fy, fz;
+#pragma unroll
+  for (int j = 0; j < kNpl; ++j) {
+    fx.v[j] = A[0].v[j] - 0.5 * dgy.v[j];
+    fy.v[j] = A[1].v[j] + 0.5 * dgx.v[j];
+    fz.v[j] = A[2].v[j];
+  }
+  if (k == 0.0) {
+    Vec r;
+#pragma unroll
+    for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * fx.v[j];
+    U = seg_zero_mode(r, H, N, dp.geometry, l);
+#pragma unroll
+    for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * fy.v[j];
+    V = seg_zero_mode(r, H, N, dp.geometry, l);
+  } else {
+    const double kappa = 0.5 * k * H;
+    Par q[2];
+    q[0] = seg_prepare(kappa, N, l, 0);
+    q[1] = seg_prepare(kappa, N, l, 1);
+    const Vec dfz = seg_deriv(fz, l, s2H);
+    Vec r;
+#pragma unroll
+    for (int j = 0; j < kNpl; ++j)
+      r.v[j] = imul(kx, fx.v[j]) + imul(ky, fy.v[j]) + dfz.v[j];
+    const Vec p = seg_solve(q, r, zmk(0, 0), zmk(0, 0), H, kappa, N, l);
+    const Z2 pH = bsum_top(p), p0 = bsum_bottom(p);
+    const double ie = 1.0 / eta;
+    {
+      const Vec dp_ = seg_deriv(p, l, s2H);
+#pragma unroll
+      for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (dp_.v[j] - fz.v[j]);
+    }
+    W = seg_solve(q, r, (0.5 / eta) * pH, (0.5 / eta) * p0, H, kappa, N, l);
+#pragma unroll
+    for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(kx, p.v[j]) - fx.v[j]);
+    U = seg_solve(q, r, imul(-kx / (2.0 * k * eta), pH),
+                  imul(kx / (2.0 * k * eta), p0), H, kappa, N, l);
+#pragma unroll
+    for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(ky, p.v[j]) - fy.v[j]);
+    V = seg_solve(q, r, imul(-ky / (2.0 * k * eta), pH),
+                  imul(ky / (2.0 * k * eta), p0), H, kappa, N, l);
+
+    // wall correction, evaluated on all nodes and transformed
+    const Z2 u0 = -1.0 * bsum_bottom(U), v0 = -1.0 * bsum_bottom(V),
+             w0 = -1.0 * bsum_bottom(W);
+    double fb[kNpl], E[kNpl], ZE[kNpl];
+#pragma unroll
+    for (int j = 0; j < kNpl; ++j) {
+      const int c = 4 * l + j;
+      fb[j] = c < N ? exp(-k * zc[c]) : 0.0;
+    }
+    seg_basis(fb, zc, Mf, N, l, E, ZE);
+    if (dp.geometry == 0) {
+      const Z2 Ac = imul(k, w0) + kx * u0 + ky * v0;
+      const Z2 Bc = k * w0 - imul(kx, u0) - imul(ky, v0);
+      const double rx = kx / k, ry = ky / k;
+#pragma unroll
+      for (int j = 0; j < kNpl; ++j) {
+        U.v[j] = U.v[j] + (-rx * ZE[j]) * Ac + E[j] * u0;
+        V.v[j] = V.v[j] + (-ry * ZE[j]) * Ac + E[j] * v0;
+        W.v[j] = W.v[j] + ZE[j] * Bc + E[j] * w0;
+      }
+    } else {
+      const Z2 uH = -1.0 * bsum_top(U), vH = -1.0 * bsum_top(V),
+               wH = -1.0 * bsum_top(W);
+      const double Ex = exp(-k * H);
+      const double hh = H / (2.0 * eta), e2 = 1.0 / (2.0 * eta);
+      const Z2 uL0 = (1.0 / k) * (kx * u0 + ky * v0);
+      const Z2 uT0 = (1.0 / k) * (kx * v0 - ky * u0);
+      const Z2 uLH = (1.0 / k) * (kx * uH + ky * vH);
+      const Z2 uTH = (1.0 / k) * (kx * vH - ky * uH);
+      // longitudinal 6x6 system, one row per lane (unknowns C0, D0~,
+      // i C_L, i D_L~, C_z, D_z~; D~ = D e^{kH})
+      double row6[6] = {0, 0, 0, 0, 0, 0};
+      Z2 rhs6 = zmk(0, 0);
+      switch (l) {
+        case 0: row6[2] = 1; row6[3] = Ex; rhs6 = imul(1.0, uL0); break;
+        case 1: row6[4] = 1; row6[5] = Ex; rhs6 = w0; break;
+        case 2: row6[0] = hh * Ex; row6[1] = -hh; row6[2] = Ex; row6[3] = 1;
+                rhs6 = imul(1.0, uLH); break;
+        case 3: row6[0] = hh * Ex; row6[1] = hh; row6[4] = Ex; row6[5] = 1;
+                rhs6 = wH; break;
+        case 4: row6[0] = e2; row6[1] = e2 * Ex; row6[2] = k; row6[3] = k * Ex;
+                row6[4] = -k; row6[5] = k * Ex; break;
+        case 5: row6[0] = e2 * Ex; row6[1] = e2; row6[2] = k * Ex; row6[3] = k;
+                row6[4] = -k * Ex; row6[5] = k; break;
+        default: break;
+      }
+      const Z2 x6 = seg_solve6(row6, rhs6, l);
+      const Z2 C0 = shz(x6, 0), D0 = shz(x6, 1);
+      const Z2 CL = imul(-1.0, shz(x6, 2)), DL = imul(-1.0, shz(x6, 3));
+      const Z2 Cz = shz(x6, 4), Dz = shz(x6, 5);
+      const double det = 1.0 - Ex * Ex;
+      const Z2 CT = zdiv(uT0 - Ex * uTH, det);
+      const Z2 DT = zdiv(uTH - Ex * uT0, det);
+      const double rx = kx / k, ry = ky / k;
+      const Z2 Cx = rx * CL - ry * CT, Cy = ry * CL + rx * CT;
+      const Z2 Dx = rx * DL - ry * DT, Dy = ry * DL + rx * DT;
+      double Ep[kNpl], ZEp[kNpl];
+#pragma unroll
+      for (int j = 0; j < kNpl; ++j) {
+        const int c = 4 * l + j;
+        fb[j] = c < N ? exp(k * (zc[c] - H)) : 0.0;
+      }
+      seg_basis(fb, zc, Mf, N, l, Ep, ZEp);
+      const double ax = kx / (2.0 * eta * k), ay = ky / (2.0 * eta * k);
+      const Z2 pu0 = imul(-ax, C0), pu1 = imul(ax, D0);
+      const Z2 pv0 = imul(-ay, C0), pv1 = imul(ay, D0);
+#pragma unroll
+      for (int j = 0; j < kNpl; ++j) {
+        U.v[j] = U.v[j] + ZE[j] * pu0 + ZEp[j] * pu1 + E[j] * Cx + Ep[j] * Dx;
+        V.v[j] = V.v[j] + ZE[j] * pv0 + ZEp[j] * pv1 + E[j] * Cy + Ep[j] * Dy;
+        W.v[j] = W.v[j] + (e2 * ZE[j]) * C0 + (e2 * ZEp[j]) * D0 + E[j] * Cz +
+                 Ep[j] * Dz;
+      }
+    }
+  }
+}
+
+template <typename T, int GEOM>
 __global__ void __launch_bounds__(256)
 k_columns_seg(ColParams cp, const int* __restrict__ band,
               const cplx_t<T>* __restrict__ in, cplx_t<T>* __restrict__ out,
@@ -369,6 +611,7 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
     Vec A[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) A[v] = vzero();
+#pragma unroll 1
     for (int c = 0; c < P; ++c) {
       const int ca = lo + c;
       Z2 val[6];
@@ -391,114 +634,7 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
         for (int v = 0; v < 5; ++v) A[v].v[j] = A[v].v[j] + m * comb[v];
       }
     }
-    const Vec dgy = seg_deriv(A[4], l, s2H);
-    const Vec dgx = seg_deriv(A[3], l, s2H);
-    Vec fx, fy, fz;
-#pragma unroll
-    for (int j = 0; j < kNpl; ++j) {
-      fx.v[j] = A[0].v[j] - 0.5 * dgy.v[j];
-      fy.v[j] = A[1].v[j] + 0.5 * dgx.v[j];
-      fz.v[j] = A[2].v[j];
-    }
-    if (k == 0.0) {
-      Vec r;
-#pragma unroll
-      for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * fx.v[j];
-      U = seg_zero_mode(r, H, N, dp.geometry, l);
-#pragma unroll
-      for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * fy.v[j];
-      V = seg_zero_mode(r, H, N, dp.geometry, l);
-    } else {
-      const double kappa = 0.5 * k * H;
-      Par q[2];
-      q[0] = seg_prepare(kappa, N, l, 0);
-      q[1] = seg_prepare(kappa, N, l, 1);
-      const Vec dfz = seg_deriv(fz, l, s2H);
-      Vec r;
-#pragma unroll
-      for (int j = 0; j < kNpl; ++j)
-        r.v[j] = imul(kx, fx.v[j]) + imul(ky, fy.v[j]) + dfz.v[j];
-      const Vec p = seg_solve(q, r, zmk(0, 0), zmk(0, 0), H, l);
-      const Z2 pH = bsum_top(p), p0 = bsum_bottom(p);
-      const double ie = 1.0 / eta;
-#pragma unroll
-      for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(kx, p.v[j]) - fx.v[j]);
-      U = seg_solve(q, r, imul(-kx / (2.0 * k * eta), pH),
-                    imul(kx / (2.0 * k * eta), p0), H, l);
-#pragma unroll
-      for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(ky, p.v[j]) - fy.v[j]);
-      V = seg_solve(q, r, imul(-ky / (2.0 * k * eta), pH),
-                    imul(ky / (2.0 * k * eta), p0), H, l);
-      const Vec dp_ = seg_deriv(p, l, s2H);
-#pragma unroll
-      for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (dp_.v[j] - fz.v[j]);
-      W = seg_solve(q, r, (0.5 / eta) * pH, (0.5 / eta) * p0, H, l);
-
-      // wall correction, evaluated on all nodes and transformed
-      const Z2 u0 = -1.0 * bsum_bottom(U), v0 = -1.0 * bsum_bottom(V),
-               w0 = -1.0 * bsum_bottom(W);
-      double fb[kNpl], E[kNpl], ZE[kNpl];
-#pragma unroll
-      for (int j = 0; j < kNpl; ++j) {
-        const int c = 4 * l + j;
-        fb[j] = c < N ? exp(-k * zc[c]) : 0.0;
-      }
-      seg_basis(fb, zc, Mf, N, l, E, ZE);
-      if (dp.geometry == 0) {
-        const Z2 Ac = imul(k, w0) + kx * u0 + ky * v0;
-        const Z2 Bc = k * w0 - imul(kx, u0) - imul(ky, v0);
-        const double rx = kx / k, ry = ky / k;
-#pragma unroll
-        for (int j = 0; j < kNpl; ++j) {
-          U.v[j] = U.v[j] + (-rx * ZE[j]) * Ac + E[j] * u0;
-          V.v[j] = V.v[j] + (-ry * ZE[j]) * Ac + E[j] * v0;
-          W.v[j] = W.v[j] + ZE[j] * Bc + E[j] * w0;
-        }
-      } else {
-        const Z2 uH = -1.0 * bsum_top(U), vH = -1.0 * bsum_top(V),
-                 wH = -1.0 * bsum_top(W);
-        const double Ex = exp(-k * H);
-        const double hh = H / (2.0 * eta), e2 = 1.0 / (2.0 * eta);
-        const Z2 uL0 = (1.0 / k) * (kx * u0 + ky * v0);
-        const Z2 uT0 = (1.0 / k) * (kx * v0 - ky * u0);
-        const Z2 uLH = (1.0 / k) * (kx * uH + ky * vH);
-        const Z2 uTH = (1.0 / k) * (kx * vH - ky * uH);
-        double M6[6][6] = {{0, 0, 1, Ex, 0, 0},
-                           {0, 0, 0, 0, 1, Ex},
-                           {hh * Ex, -hh, Ex, 1, 0, 0},
-                           {hh * Ex, hh, 0, 0, Ex, 1},
-                           {e2, e2 * Ex, k, k * Ex, -k, k * Ex},
-                           {e2 * Ex, e2, k * Ex, k, -k * Ex, k}};
-        Z2 X[6] = {imul(1.0, uL0), w0, imul(1.0, uLH), wH, zmk(0, 0), zmk(0, 0)};
-        solve6(M6, X);
-        const Z2 C0 = X[0], D0 = X[1];
-        const Z2 CL = imul(-1.0, X[2]), DL = imul(-1.0, X[3]);
-        const Z2 Cz = X[4], Dz = X[5];
-        const double det = 1.0 - Ex * Ex;
-        const Z2 CT = zdiv(uT0 - Ex * uTH, det);
-        const Z2 DT = zdiv(uTH - Ex * uT0, det);
-        const double rx = kx / k, ry = ky / k;
-        const Z2 Cx = rx * CL - ry * CT, Cy = ry * CL + rx * CT;
-        const Z2 Dx = rx * DL - ry * DT, Dy = ry * DL + rx * DT;
-        double Ep[kNpl], ZEp[kNpl];
-#pragma unroll
-        for (int j = 0; j < kNpl; ++j) {
-          const int c = 4 * l + j;
-          fb[j] = c < N ? exp(k * (zc[c] - H)) : 0.0;
-        }
-        seg_basis(fb, zc, Mf, N, l, Ep, ZEp);
-        const double ax = kx / (2.0 * eta * k), ay = ky / (2.0 * eta * k);
-        const Z2 pu0 = imul(-ax, C0), pu1 = imul(ax, D0);
-        const Z2 pv0 = imul(-ay, C0), pv1 = imul(ay, D0);
-#pragma unroll
-        for (int j = 0; j < kNpl; ++j) {
-          U.v[j] = U.v[j] + ZE[j] * pu0 + ZEp[j] * pu1 + E[j] * Cx + Ep[j] * Dx;
-          V.v[j] = V.v[j] + ZE[j] * pv0 + ZEp[j] * pv1 + E[j] * Cy + Ep[j] * Dy;
-          W.v[j] = W.v[j] + (e2 * ZE[j]) * C0 + (e2 * ZEp[j]) * D0 + E[j] * Cz +
-                   Ep[j] * Dz;
-        }
-      }
-    }
+    seg_column_solve<GEOM>(A, dp, zc, Mf, N, l, kx, ky, k, U, V, W);
   }
   DU = seg_deriv(U, l, s2H);
   DV = seg_deriv(V, l, s2H);
@@ -520,6 +656,7 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
   if (!valid) return;
   const C* cb = buf + cl * 5 * 32;
   const double sc = cp.scale;
+#pragma unroll 1
   for (int c = l; c < P; c += kSeg) {
     const int ca = lo + c;
     const double* prow = Pi + ca * N;
@@ -551,25 +688,212 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
   }
 }
 
-hipError_t launch_columns_seg(const fcmdp_solver* s, const void* spec_in,
-                              void* spec_out, hipStream_t st) {
-  ColParams cp;
-  cp.dp = s->dp;
-  cp.scale = 1.0 / ((double)s->dp.Nx * (double)s->dp.Ny);
+// ---------------------------------------------------------------------------
+// Mixed-precision variant: the two Chebyshev transforms as FP32 MFMA
+// products at workgroup level (a 32 x P matrix against all node vectors of
+// 16 columns, and back), the per-column solve in FP64 on eight lanes as above.
+//   X[c][v]  = band node values of the five forward vectors, v = col*10 +
+//              vec*2 + (re, im)                                   (LDS, fp32)
+//   Cf[n][v] = sum_c Mt[n][c] X[c][v]          (v_mfma_f32_16x16x4f32)
+//   solve: Cf -> coefficients of u, v, w, du/dz, dv/dz (in place)
+//   D[c][v]  = sum_n T_n(s_c) Cf[n][v]         (MFMA again), then omega and
+//              the 1/(Nx Ny) scale at the nodes.
+// Operand layout of v_mfma_f32_16x16x4f32 (wave64): A[i][k] comes from lane
+// i + 16k, B[k][j] from lane j + 16k, and D[4(l/16) + r][l%16] is returned in
+// register r of lane l.
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kMCols = 16;                 // columns per workgroup
+constexpr int kMV = kMCols * 10;           // real node vectors per workgroup
+constexpr int kMThreads = kMCols * kSeg;   // 128
+
+template <int GEOM>
+__global__ void __launch_bounds__(kMThreads)
+k_columns_mfma(ColParams cp, const int* __restrict__ band,
+               const float2* __restrict__ in, float2* __restrict__ out,
+               const double* __restrict__ zc, const double* __restrict__ Mf,
+               const float* __restrict__ Mf32, const float* __restrict__ Pi32) {
+  __shared__ float XD[32 * kMV];   // X (forward input), later D (inverse output)
+  __shared__ float CF[32 * kMV];   // coefficients
+  const DevParams& dp = cp.dp;
+  const int lo = band[0], hi = band[1];
+  if (lo > hi) return;
+  const int K = dp.Nkx * dp.Ny;
+  const int N = dp.Nz;
+  const int P = hi - lo + 1;
+  const int Kp = (P + 3) & ~3;             // node count padded for k-steps of 4
+  const size_t PS = (size_t)K;
+  const int tid = threadIdx.x;
+  const int idx0 = blockIdx.x * kMCols;
+  const int wave = tid >> 6, lane = tid & 63;
+
+  // --- A: node values and the nodal part of the body force ---------------
+  for (int it = tid; it < Kp * kMCols; it += kMThreads) {
+    const int c = it / kMCols, col = it % kMCols;
+    const int idx = idx0 + col;
+    float* xr = XD + c * kMV + col * 10;
+    if (c < P && idx < K) {
+      const int kxi = idx / dp.Ny, kyi = idx - kxi * dp.Ny;
+      const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
+      const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
+      const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
+      float2 v[6];
+#pragma unroll
+      for (int ch = 0; ch < 6; ++ch) v[ch] = in[(ch * N + lo + c) * PS + idx];
+      // f~x = Fx + (1/2) i ky Gz ; f~y = Fy - (1/2) i kx Gz ;
+      // f~z = Fz + (1/2)(i kx Gy - i ky Gx)
+      xr[0] = v[0].x - 0.5f * ky * v[5].y;
+      xr[1] = v[0].y + 0.5f * ky * v[5].x;
+      xr[2] = v[1].x + 0.5f * kx * v[5].y;
+      xr[3] = v[1].y - 0.5f * kx * v[5].x;
+      xr[4] = v[2].x - 0.5f * kx * v[4].y + 0.5f * ky * v[3].y;
+      xr[5] = v[2].y + 0.5f * kx * v[4].x - 0.5f * ky * v[3].x;
+      xr[6] = v[3].x; xr[7] = v[3].y;
+      xr[8] = v[4].x; xr[9] = v[4].y;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 10; ++e) xr[e] = 0.f;
+    }
+  }
+  __syncthreads();
+
+  // --- B: forward Chebyshev transform, Cf = Mt X ----------------------------
+  {
+    const int i16 = lane & 15, k4 = lane >> 4;
+    for (int tile = wave; tile < 2 * (kMV / 16); tile += kMThreads / 64) {
+      const int n0 = (tile & 1) * 16, v0 = (tile >> 1) * 16;
+      f4v acc = {0.f, 0.f, 0.f, 0.f};
+      const int n = n0 + i16;
+      for (int kk = 0; kk < Kp; kk += 4) {
+        const int c = kk + k4;
+        const float a = (c < P && n < N) ? Mf32[(lo + c) * N + n] : 0.f;
+        const float b = XD[c * kMV + v0 + i16];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) CF[(n0 + 4 * k4 + r) * kMV + v0 + i16] = acc[r];
+    }
+  }
+  __syncthreads();
+
+  // --- C: per-column FP64 solve on eight lanes ------------------------------
+  {
+    const int cl = tid / kSeg, l = tid % kSeg;
+    const int idx = idx0 + cl;
+    const bool valid = idx < K;
+    const int kxi = valid ? idx / dp.Ny : 0;
+    const int kyi = valid ? idx - kxi * dp.Ny : 0;
+    const bool nyq = !valid || kxi == dp.Nx / 2 || kyi == dp.Ny / 2;
+    const double kx = 2.0 * M_PI * kxi / dp.Lx;
+    const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
+    const double ky = 2.0 * M_PI * nyi / dp.Ly;
+    const double k = sqrt(kx * kx + ky * ky);
+    const double s2H = 2.0 / dp.H;
+    Vec U = vzero(), V = vzero(), W = vzero();
+    if (!nyq) {
+      Vec A[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int j = 0; j < kNpl; ++j) {
+          const float* cr = CF + (4 * l + j) * kMV + cl * 10 + 2 * v;
+          A[v].v[j] = zmk((double)cr[0], (double)cr[1]);
+        }
+      seg_column_solve<GEOM>(A, dp, zc, Mf, N, l, kx, ky, k, U, V, W);
+    }
+    const Vec DU = seg_deriv(U, l, s2H);
+    const Vec DV = seg_deriv(V, l, s2H);
+    const Vec* vs[5] = {&U, &V, &W, &DU, &DV};
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int j = 0; j < kNpl; ++j) {
+        float* cr = CF + (4 * l + j) * kMV + cl * 10 + 2 * v;
+        cr[0] = (float)vs[v]->v[j].x;
+        cr[1] = (float)vs[v]->v[j].y;
+      }
+  }
+  __syncthreads();
+
+  // --- D: inverse transform to the band nodes, D = T Cf -----------------------
+  {
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int ctiles = (P + 15) / 16;
+    for (int tile = wave; tile < ctiles * (kMV / 16); tile += kMThreads / 64) {
+      const int c0 = (tile % ctiles) * 16, v0 = (tile / ctiles) * 16;
+      f4v acc = {0.f, 0.f, 0.f, 0.f};
+      const int c = c0 + i16;
+      for (int kk = 0; kk < 32; kk += 4) {
+        const int n = kk + k4;
+        const float a = (c < P && n < N) ? Pi32[(lo + c) * N + n] : 0.f;
+        const float b = CF[n * kMV + v0 + i16];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) XD[(c0 + 4 * k4 + r) * kMV + v0 + i16] = acc[r];
+    }
+  }
+  __syncthreads();
+
+  // --- E: omega = (1/2) curl u at the nodes, scale, store ----------------------
+  const float sc = (float)cp.scale;
+  for (int it = tid; it < P * kMCols; it += kMThreads) {
+    const int c = it / kMCols, col = it % kMCols;
+    const int idx = idx0 + col;
+    if (idx >= K) continue;
+    const int kxi = idx / dp.Ny, kyi = idx - kxi * dp.Ny;
+    const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
+    const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
+    const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
+    const float* d = XD + c * kMV + col * 10;
+    const float ur = d[0], ui = d[1], vr = d[2], vi = d[3], wr = d[4], wi = d[5];
+    const float dur = d[6], dui = d[7], dvr = d[8], dvi = d[9];
+    float2 o[6];
+    o[0] = make_float2(sc * ur, sc * ui);
+    o[1] = make_float2(sc * vr, sc * vi);
+    o[2] = make_float2(sc * wr, sc * wi);
+    // ox = (i ky w - dv/dz)/2, oy = (du/dz - i kx w)/2, oz = (i kx v - i ky u)/2
+    o[3] = make_float2(0.5f * sc * (-ky * wi - dvr), 0.5f * sc * (ky * wr - dvi));
+    o[4] = make_float2(0.5f * sc * (dur + kx * wi), 0.5f * sc * (dui - kx * wr));
+    o[5] = make_float2(0.5f * sc * (-kx * vi + ky * ui),
+                       0.5f * sc * (kx * vr - ky * ur));
+#pragma unroll
+    for (int ch = 0; ch < 6; ++ch) out[(ch * N + lo + c) * PS + idx] = o[ch];
+  }
+}
+
+template <int GEOM>
+static void launch_seg_geom(const fcmdp_solver* s, const ColParams& cp,
+                            const void* spec_in, void* spec_out, hipStream_t st) {
   const int K = s->dp.Nkx * s->dp.Ny;
-  if (s->mixed) {
+  if (s->mixed && s->dct_f32 && !s->force_vector_dct) {
+    hipLaunchKernelGGL((k_columns_mfma<GEOM>), dim3((K + kMCols - 1) / kMCols),
+                       dim3(kMThreads), 0, st, cp, s->band,
+                       (const float2*)spec_in, (float2*)spec_out, s->zc,
+                       s->dct_f, s->dct_f32, s->dct_i32);
+  } else if (s->mixed) {
     constexpr int cols = ColsPerBlock<float>::value;
-    hipLaunchKernelGGL(k_columns_seg<float>, dim3((K + cols - 1) / cols),
+    hipLaunchKernelGGL((k_columns_seg<float, GEOM>), dim3((K + cols - 1) / cols),
                        dim3(cols * kSeg), cols * 5 * 32 * sizeof(float2), st,
                        cp, s->band, (const float2*)spec_in, (float2*)spec_out,
                        s->zc, s->dct_f, s->dct_i);
   } else {
     constexpr int cols = ColsPerBlock<double>::value;
-    hipLaunchKernelGGL(k_columns_seg<double>, dim3((K + cols - 1) / cols),
+    hipLaunchKernelGGL((k_columns_seg<double, GEOM>), dim3((K + cols - 1) / cols),
                        dim3(cols * kSeg), cols * 5 * 32 * sizeof(double2), st,
                        cp, s->band, (const double2*)spec_in, (double2*)spec_out,
                        s->zc, s->dct_f, s->dct_i);
   }
+}
+
+hipError_t launch_columns_seg(const fcmdp_solver* s, const void* spec_in,
+                              void* spec_out, hipStream_t st) {
+  ColParams cp;
+  cp.dp = s->dp;
+  cp.scale = 1.0 / ((double)s->dp.Nx * (double)s->dp.Ny);
+  if (s->dp.geometry == 0)
+    launch_seg_geom<0>(s, cp, spec_in, spec_out, st);
+  else
+    launch_seg_geom<1>(s, cp, spec_in, spec_out, st);
   return hipGetLastError();
 }
 

@@ -79,6 +79,8 @@ struct fcmdp_solver {
   void* quad = nullptr;         // h^2 * Clenshaw-Curtis weights [Nz] (T)
   double* dct_f = nullptr;      // forward Chebyshev transform, [c][n]
   double* dct_i = nullptr;      // inverse, T_n(s_c), [c][n]
+  float* dct_f32 = nullptr;     // float copies for the MFMA transforms
+  float* dct_i32 = nullptr;
   double* dftc = nullptr;       // cos/sin tables of the small prime DFTs
   void* tw_x = nullptr;         // e^{-2 pi i m/(Nx/2)}, m < Nx/2 (complex T)
   void* tw_y = nullptr;         // e^{-2 pi i m/Ny}
@@ -90,6 +92,10 @@ struct fcmdp_solver {
   bool force_generic_columns = false;
   // use the one-thread-per-particle interpolation (tests)
   bool force_simple_interp = false;
+  // use the untiled gather spread (tests)
+  bool force_simple_spread = false;
+  // use the per-lane FP64 Chebyshev transforms in the mixed path (tests)
+  bool force_vector_dct = false;
 
   // tracing: events of applies not yet summed, 7 per apply
   bool profiling = false;
@@ -129,22 +135,24 @@ __host__ __device__ inline int wrap_index(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-// Conservative z-node window [cA, cB] of a particle at height z: every node
-// with z_c in [max(0, z - alpha), min(H, z + alpha)] lies inside it (the
-// analytic node index is padded by one node each way against rounding).
-__device__ inline void z_window(const DevParams& dp, double z, int* cA,
-                                int* cB) {
+// z-node window [cA, cB] of a particle at height z: exactly the Chebyshev
+// nodes with |z_c - z| <= alpha (the support of the envelope; the wall images
+// only reach nodes inside this range).  An analytic first guess from the
+// node formula is corrected against the node table with the same double
+// comparison the envelope uses.  cB < cA means no node (cannot happen for
+// particles inside the domain).
+__device__ inline void z_window(const DevParams& dp, const double* zc,
+                                double z, int* cA, int* cB) {
   const double N1 = dp.Nz - 1;
-  const double zlo = fmax(0.0, z - dp.alpha);
   const double zhi = fmin(dp.H, z + dp.alpha);
   const double sh = fmin(1.0, fmax(-1.0, 2.0 * zhi / dp.H - 1.0));
-  const double sl = fmin(1.0, fmax(-1.0, 2.0 * zlo / dp.H - 1.0));
-  const double th_hi = N1 / M_PI * acos(sh);   // smaller index (higher z)
-  const double th_lo = N1 / M_PI * acos(sl);
-  int a = (int)ceil(th_hi) - 1;
-  int b = (int)floor(th_lo) + 1;
-  a = a < 0 ? 0 : a;
-  b = b > dp.Nz - 1 ? dp.Nz - 1 : b;
+  int a = (int)ceil(N1 / M_PI * acos(sh));
+  a = a < 0 ? 0 : (a > dp.Nz - 1 ? dp.Nz - 1 : a);
+  while (a > 0 && fabs(zc[a - 1] - z) <= dp.alpha) --a;
+  while (a < dp.Nz - 1 && fabs(zc[a] - z) > dp.alpha && zc[a] > z) ++a;
+  int b = a;
+  while (b + 1 < dp.Nz && fabs(zc[b + 1] - z) <= dp.alpha) ++b;
+  if (fabs(zc[a] - z) > dp.alpha) b = a - 1;   // empty
   // the host sizes ZW so that this clamp never removes a supported node
   if (b > a + dp.ZW - 1) b = a + dp.ZW - 1;
   *cA = a;

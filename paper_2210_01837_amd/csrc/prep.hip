@@ -16,8 +16,8 @@ namespace fcmdp {
 template <typename Tin>
 __global__ void __launch_bounds__(256)
 k_prep(DevParams dp, int n, const Tin* __restrict__ pos,
-       uint32_t* __restrict__ keys, int* __restrict__ band,
-       unsigned int* __restrict__ nbad) {
+       const double* __restrict__ zc, uint32_t* __restrict__ keys,
+       int* __restrict__ band, unsigned int* __restrict__ nbad) {
   __shared__ int s_lo, s_hi, s_bad;
   if (threadIdx.x == 0) {
     s_lo = dp.Nz;
@@ -42,9 +42,11 @@ k_prep(DevParams dp, int n, const Tin* __restrict__ pos,
       cell_of(wrap_coord(y, dp.Ly), dp.h, dp.Ny, &iy, &fy);
       keys[j] = (uint32_t)(iy * dp.Nx + ix);
       int cA, cB;
-      z_window(dp, z, &cA, &cB);
-      atomicMin(&s_lo, cA);
-      atomicMax(&s_hi, cB);
+      z_window(dp, zc, z, &cA, &cB);
+      if (cB >= cA) {
+        atomicMin(&s_lo, cA);
+        atomicMax(&s_hi, cB);
+      }
     }
   }
   __syncthreads();
@@ -72,10 +74,10 @@ hipError_t launch_prep(const fcmdp_solver* s, int n, const void* pos,
   dim3 grid((n + 255) / 256);
   if (s->mixed)
     hipLaunchKernelGGL(k_prep<float>, grid, dim3(256), 0, st, s->dp, n,
-                       (const float*)pos, s->keyA, s->band, s->nbad);
+                       (const float*)pos, s->zc, s->keyA, s->band, s->nbad);
   else
     hipLaunchKernelGGL(k_prep<double>, grid, dim3(256), 0, st, s->dp, n,
-                       (const double*)pos, s->keyA, s->band, s->nbad);
+                       (const double*)pos, s->zc, s->keyA, s->band, s->nbad);
   return hipGetLastError();
 }
 
@@ -134,32 +136,6 @@ k_radix_hist(int n, const uint32_t* __restrict__ keys, int shift, int nblk,
   }
   __syncthreads();
   hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
-}
-
-// exclusive scan of len entries with one 1024-thread block
-__global__ void __launch_bounds__(1024)
-k_exclusive_scan(uint32_t* __restrict__ a, int len) {
-  __shared__ uint32_t part[1024];
-  const int t = threadIdx.x;
-  const int per = (len + 1023) / 1024;
-  const int lo = t * per;
-  const int hi = min(len, lo + per);
-  uint32_t sum = 0;
-  for (int i = lo; i < hi; ++i) sum += a[i];
-  part[t] = sum;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t v = t >= off ? part[t - off] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  uint32_t run = part[t] - sum;   // exclusive prefix of this thread's chunk
-  for (int i = lo; i < hi; ++i) {
-    const uint32_t v = a[i];
-    a[i] = run;
-    run += v;
-  }
 }
 
 __global__ void __launch_bounds__(kSortThreads)
@@ -224,6 +200,46 @@ k_radix_scatter(int n, const uint32_t* __restrict__ kin,
   }
 }
 
+// Digit-major exclusive scan of the block histograms in two launches:
+// (1) block d scans the nblk counts of digit d and records the digit total;
+// (2) block d adds the totals of all smaller digits.
+__global__ void __launch_bounds__(256)
+k_scan_digit(uint32_t* __restrict__ hist, int nblk, uint32_t* __restrict__ tot) {
+  __shared__ uint32_t part[256];
+  uint32_t* a = hist + (size_t)blockIdx.x * nblk;
+  const int t = threadIdx.x;
+  uint32_t carry = 0;
+  for (int base = 0; base < nblk; base += 256) {
+    const int i = base + t;
+    const uint32_t v = i < nblk ? a[i] : 0u;
+    part[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t u = t >= off ? part[t - off] : 0u;
+      __syncthreads();
+      part[t] += u;
+      __syncthreads();
+    }
+    if (i < nblk) a[i] = carry + part[t] - v;
+    carry += part[255];
+    __syncthreads();
+  }
+  if (t == 0) tot[blockIdx.x] = carry;
+}
+
+__global__ void __launch_bounds__(256)
+k_scan_add(uint32_t* __restrict__ hist, int nblk, const uint32_t* __restrict__ tot) {
+  __shared__ uint32_t off;
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int d = 0; d < (int)blockIdx.x; ++d) s += tot[d];
+    off = s;
+  }
+  __syncthreads();
+  uint32_t* a = hist + (size_t)blockIdx.x * nblk;
+  for (int i = threadIdx.x; i < nblk; i += 256) a[i] += off;
+}
+
 // cell_start[c] = first sorted position with key >= c, for c = 0..ncells
 __global__ void k_cell_start(int n, int ncells, const uint32_t* __restrict__ keys,
                              int* __restrict__ cell_start) {
@@ -249,8 +265,10 @@ hipError_t launch_sort(const fcmdp_solver* s, int n, hipStream_t st) {
       const int shift = 8 * pass;
       hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st,
                          n, kin, shift, nblk, s->hist);
-      hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(1024), 0, st,
-                         s->hist, 256 * nblk);
+      hipLaunchKernelGGL(k_scan_digit, dim3(256), dim3(256), 0, st, s->hist,
+                         nblk, s->hist + 256 * (size_t)s->nblk_cap);
+      hipLaunchKernelGGL(k_scan_add, dim3(256), dim3(256), 0, st, s->hist,
+                         nblk, s->hist + 256 * (size_t)s->nblk_cap);
       hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortThreads), 0,
                          st, n, kin, vin, kout, vout, shift, nblk, s->hist,
                          pass == 0 ? 1 : 0);
@@ -291,7 +309,7 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
   cell_of(x, dp.h, dp.Nx, &ix, &fx);
   cell_of(y, dp.h, dp.Ny, &iy, &fy);
   int cA, cB;
-  z_window(dp, z, &cA, &cB);
+  z_window(dp, zc, z, &cA, &cB);
   pinfo[i] = make_int4(ix, iy, cA, cB);
   T* w = pw + (size_t)i * 32;
 #pragma unroll

@@ -99,7 +99,179 @@ k_spread(DevParams dp, const int* __restrict__ band,
   }
 }
 
+// Tiled spread: a workgroup owns 32 x 8 grid columns.  The particle records of
+// the 38 x 14 cells whose kernels can reach the tile are copied once into LDS
+// in (row, x) cell order, so every thread's 7 x 7 cell neighbourhood is seven
+// contiguous LDS segments; the per-thread summation order is the cell-sorted
+// order, hence deterministic.  A tile whose halo holds more particles than
+// the LDS capacity falls back to reading the records from global memory.
+constexpr int kSpTX = 32, kSpTY = 8;
+constexpr int kSpRX = kSpTX + 6, kSpRY = kSpTY + 6;
+constexpr int kSpCells = kSpRX * kSpRY;     // 532
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_spread_tiled(DevParams dp, const int* __restrict__ band,
+               const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
+               const T* __restrict__ pw, const T* __restrict__ pf,
+               const T* __restrict__ psi, T* __restrict__ grid, int cap) {
+  extern __shared__ unsigned char lds_raw[];
+  const int ZW = dp.ZW;
+  constexpr int kRec = 36;                  // 28 weights, 6 forces, 2 ints
+  T* rec = reinterpret_cast<T*>(lds_raw);                  // [cap][kRec]
+  T* zrec = rec + cap * kRec;                              // [cap][2 ZW]
+  __shared__ int cs[kSpCells + 1];
+  __shared__ int gbase[kSpCells];
+  const int lo = band[0], hi = band[1];
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * kSpTX, y0 = blockIdx.y * kSpTY;
+  const int tx = tid % kSpTX, ty = tid / kSpTX;
+  const int a = x0 + tx, b = y0 + ty;
+  const bool inside = a < dp.Nx && b < dp.Ny;
+  if (lo > hi) return;
+  // region cell counts and LDS offsets
+  for (int q = tid; q < kSpCells; q += 256) {
+    const int rx = q % kSpRX, ry = q / kSpRX;
+    const int gx = wrap_index(x0 - 3 + rx, dp.Nx);
+    const int gy = wrap_index(y0 - 3 + ry, dp.Ny);
+    const int g = gy * dp.Nx + gx;
+    const int s0 = cell_start[g];
+    gbase[q] = s0;
+    cs[q + 1] = cell_start[g + 1] - s0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    cs[0] = 0;
+    for (int q = 0; q < kSpCells; ++q) cs[q + 1] += cs[q];
+  }
+  __syncthreads();
+  const int total = cs[kSpCells];
+  const bool staged = total <= cap;
+  if (staged) {
+    for (int slot = tid; slot < total; slot += 256) {
+      int lo_q = 0, hi_q = kSpCells - 1;     // last q with cs[q] <= slot
+      while (lo_q < hi_q) {
+        const int mid = (lo_q + hi_q + 1) >> 1;
+        if (cs[mid] <= slot) lo_q = mid; else hi_q = mid - 1;
+      }
+      const int p = gbase[lo_q] + (slot - cs[lo_q]);
+      T* r = rec + slot * kRec;
+      const T* w = pw + (size_t)p * 32;
+#pragma unroll
+      for (int d = 0; d < 7; ++d) {
+        r[d] = w[d];
+        r[7 + d] = w[8 + d];
+        r[14 + d] = w[16 + d];
+        r[21 + d] = w[24 + d];
+      }
+      const T* f = pf + (size_t)p * 8;
+      r[28] = f[0]; r[29] = f[1]; r[30] = f[2];
+      r[31] = f[4]; r[32] = f[5]; r[33] = f[6];
+      const int4 inf = pinfo[p];
+      reinterpret_cast<int*>(r + 34)[0] = inf.z;
+      reinterpret_cast<int*>(r + 34)[sizeof(T) == 4 ? 1 : 2] = inf.w;
+      const T* ps = psi + (size_t)p * 2 * ZW;
+      T* zr = zrec + slot * 2 * ZW;
+      for (int e = 0; e < 2 * ZW; ++e) zr[e] = ps[e];
+    }
+  }
+  __syncthreads();
+  if (!inside) return;
+  const size_t plane = (size_t)dp.Nx * dp.Ny;
+  const size_t chstride = plane * dp.Nz;
+  const int ra = tx + 3, rb = ty + 3;
+  for (int c0 = lo; c0 <= hi; c0 += kZC) {
+    T acc[kZC][6];
+#pragma unroll
+    for (int s = 0; s < kZC; ++s)
+#pragma unroll
+      for (int ch = 0; ch < 6; ++ch) acc[s][ch] = T(0);
+    for (int dyi = 0; dyi < kWin; ++dyi) {
+      const int ry = rb - (dyi - 3);          // cells that reach row b with weight dyi
+      for (int dxi = 0; dxi < kWin; ++dxi) {
+        const int q = ry * kSpRX + ra - (dxi - 3);
+        if (staged) {
+          const int s0 = cs[q], s1 = cs[q + 1];
+          for (int sl = s0; sl < s1; ++sl) {
+            const T* r = rec + sl * kRec;
+            const int cA = reinterpret_cast<const int*>(r + 34)[0];
+            const int cB = reinterpret_cast<const int*>(r + 34)[sizeof(T) == 4 ? 1 : 2];
+            if (cB < c0 || cA >= c0 + kZC) continue;
+            const T wm = r[dxi] * r[7 + dyi];
+            const T wd = r[14 + dxi] * r[21 + dyi];
+            if (wm == T(0) && wd == T(0)) continue;
+            const T f0 = r[28] * wm, f1 = r[29] * wm, f2 = r[30] * wm;
+            const T t0 = r[31] * wd, t1 = r[32] * wd, t2 = r[33] * wd;
+            const T* zr = zrec + sl * 2 * ZW;
+#pragma unroll
+            for (int s = 0; s < kZC; ++s) {
+              const int zi = c0 + s - cA;
+              if (zi >= 0 && zi < ZW) {
+                const T pm = zr[zi], pd = zr[ZW + zi];
+                acc[s][0] += f0 * pm; acc[s][1] += f1 * pm; acc[s][2] += f2 * pm;
+                acc[s][3] += t0 * pd; acc[s][4] += t1 * pd; acc[s][5] += t2 * pd;
+              }
+            }
+          }
+        } else {
+          const int p0 = gbase[q];
+          const int p1 = p0 + (cs[q + 1] - cs[q]);
+          for (int p = p0; p < p1; ++p) {
+            const int4 inf = pinfo[p];
+            if (inf.w < c0 || inf.z >= c0 + kZC) continue;
+            const T* w = pw + (size_t)p * 32;
+            const T wm = w[dxi] * w[8 + dyi];
+            const T wd = w[16 + dxi] * w[24 + dyi];
+            if (wm == T(0) && wd == T(0)) continue;
+            const T* f = pf + (size_t)p * 8;
+            const T f0 = f[0] * wm, f1 = f[1] * wm, f2 = f[2] * wm;
+            const T t0 = f[4] * wd, t1 = f[5] * wd, t2 = f[6] * wd;
+            const T* ps = psi + (size_t)p * 2 * ZW;
+#pragma unroll
+            for (int s = 0; s < kZC; ++s) {
+              const int zi = c0 + s - inf.z;
+              if (zi >= 0 && zi < ZW) {
+                const T pm = ps[zi], pd = ps[ZW + zi];
+                acc[s][0] += f0 * pm; acc[s][1] += f1 * pm; acc[s][2] += f2 * pm;
+                acc[s][3] += t0 * pd; acc[s][4] += t1 * pd; acc[s][5] += t2 * pd;
+              }
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kZC; ++s) {
+      const int c = c0 + s;
+      if (c <= hi) {
+#pragma unroll
+        for (int ch = 0; ch < 6; ++ch)
+          grid[ch * chstride + c * plane + (size_t)b * dp.Nx + a] = acc[s][ch];
+      }
+    }
+  }
+}
+
 hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st) {
+  if (!s->force_simple_spread) {
+    dim3 g((s->dp.Nx + kSpTX - 1) / kSpTX, (s->dp.Ny + kSpTY - 1) / kSpTY);
+    const size_t esz = s->mixed ? 4 : 8;
+    const size_t per = (36 + 2 * (size_t)s->dp.ZW) * esz;
+    int cap = (int)(98304 / per);        // at most 96 KiB of staged records
+    if (cap > 256) cap = 256;
+    const size_t lds = (size_t)cap * per;
+    if (s->mixed)
+      hipLaunchKernelGGL(k_spread_tiled<float>, g, dim3(256), lds, st, s->dp,
+                         s->band, s->cell_start, s->pinfo, (const float*)s->pw,
+                         (const float*)s->pf, (const float*)s->psi,
+                         (float*)grid, cap);
+    else
+      hipLaunchKernelGGL(k_spread_tiled<double>, g, dim3(256), lds, st, s->dp,
+                         s->band, s->cell_start, s->pinfo, (const double*)s->pw,
+                         (const double*)s->pf, (const double*)s->psi,
+                         (double*)grid, cap);
+    return hipGetLastError();
+  }
   dim3 block(128);
   dim3 g((s->dp.Nx + 127) / 128, s->dp.Ny);
   if (s->mixed)
@@ -202,11 +374,13 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
   int* pcp = pcj + cap;                                 // [cap]
   __shared__ int rowoff[kTile + 1];
   __shared__ int rowstart[kTile];
+  __shared__ int ytab[kRX];
 
   const int lo = band[0], hi = band[1];
   if (lo > hi) return;
   const int tid = threadIdx.x;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
+  if (tid < kRX) ytab[tid] = wrap_index(ty0 - 3 + tid, dp.Ny);
   if (tid < kTile) {
     const int iy = ty0 + tid;
     int s0 = 0, e0 = 0;
@@ -229,6 +403,9 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
   const size_t chstride = plane * dp.Nz;
   const int g = tid / 8, l = tid % 8;
   constexpr int NG = 256 / 8;
+  constexpr int kRG = 256 / kRX;              // row groups in the staging loop
+  const int rx = tid % kRX, rg = tid / kRX;
+  const int xa = wrap_index(tx0 - 3 + rx, dp.Nx);
 
   for (int base = 0; base < nhome; base += cap) {
     const int np = min(cap, nhome - base);
@@ -251,16 +428,18 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
     __syncthreads();
     for (int c0 = lo; c0 <= hi; c0 += ZC) {
       const int nz = min(ZC, hi - c0 + 1);
-      for (int e = tid; e < nz * 6 * kRX * kRX; e += 256) {
-        const int rx = e % kRX;
-        int t = e / kRX;
-        const int ry = t % kRX;
-        t /= kRX;
-        const int ch = t % 6;
-        const int sidx = t / 6;
-        const int a = wrap_index(tx0 - 3 + rx, dp.Nx);
-        const int b = wrap_index(ty0 - 3 + ry, dp.Ny);
-        G[e] = grid[ch * chstride + (size_t)(c0 + sidx) * plane + (size_t)b * dp.Nx + a];
+      // stage rows of kRX values: thread (rg, rx), 11 rows per sweep
+      if (tid < kRG * kRX) {
+        const int rows = nz * 6 * kRX;
+        const size_t base0 = (size_t)c0 * plane + xa;
+        for (int row = rg; row < rows; row += kRG) {
+          const int ry = row % kRX;
+          const int t = row / kRX;
+          const int ch = t % 6;
+          const int sidx = t / 6;
+          G[row * kRX + rx] = grid[ch * chstride + base0 + (size_t)sidx * plane +
+                                   (size_t)ytab[ry] * dp.Nx];
+        }
       }
       __syncthreads();
       for (int h = g; h < np; h += NG) {
@@ -271,7 +450,7 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
           const T* w = pcw + h * 32;
           const T* ps = pcz + h * 2 * ZW;
           const T wxm = w[l], wxd = w[16 + l];
-          const int rx = inf.x - tx0 + l;
+          const int px = inf.x - tx0 + l;
           const int ry0 = inf.y - ty0;
           for (int dy = 0; dy < 7; ++dy) {
             const T wm = wxm * w[8 + dy];
@@ -286,7 +465,7 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
                 const T q = quad[c];
                 const T qm = q * ps[zi] * wm;
                 const T qd = q * ps[ZW + zi] * wd;
-                const T* gp = G + (sidx * 6 * kRX + ry) * kRX + rx;
+                const T* gp = G + (sidx * 6 * kRX + ry) * kRX + px;
                 constexpr int CS = kRX * kRX;
                 a0 += qm * gp[0];
                 a1 += qm * gp[CS];
@@ -357,8 +536,8 @@ static hipError_t interp_tiled(const fcmdp_solver* s, int n, const T* grid,
   hipLaunchKernelGGL(k_interp_invalid<T>, dim3((n + 255) / 256), dim3(256), 0,
                      st, n, dp.ncells, s->keyA, s->valA, U, Om);
   dim3 g((dp.Nx + kTile - 1) / kTile, (dp.Ny + kTile - 1) / kTile);
-  const size_t limit = 65536;
-  int cap = 64;
+  const size_t limit = 81920;      // two workgroups per CU (160 KiB LDS)
+  int cap = 128;
   while (cap > 8 && interp_lds<T, 4>(dp.ZW, cap) > limit) cap -= 8;
   if (interp_lds<T, 4>(dp.ZW, cap) <= limit) {
     const size_t lds4 = interp_lds<T, 4>(dp.ZW, cap);
@@ -369,7 +548,7 @@ static hipError_t interp_tiled(const fcmdp_solver* s, int n, const T* grid,
                        Om, cap);
     return hipGetLastError();
   }
-  cap = 64;
+  cap = 128;
   while (cap > 8 && interp_lds<T, 2>(dp.ZW, cap) > limit) cap -= 8;
   const size_t lds2 = interp_lds<T, 2>(dp.ZW, cap);
   hipLaunchKernelGGL((k_interp_tiled<T, 2>), g, dim3(256), lds2, st, dp,

@@ -1,0 +1,59 @@
+"""Write the stored oracle values used by the large-scale GPU parity tests.
+
+    python tests/golden/make_fixtures.py [bw131k] [bw1m] [sc1m]
+
+For each workload this draws the seeded inputs (workloads.particles), runs
+the CPU oracle's full apply -- every particle is spread and the whole grid is
+solved -- and interpolates only the seeded 1% sample (workloads.subsample).
+It stores <name>_oracle_sample.npz with the sample indices and the oracle's
+U and Omega (float64).  Only oracle/ and workloads/ are used.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+from oracle import fcm, stokes  # noqa: E402
+
+
+def make(name: str) -> str:
+    wl = workloads.WORKLOADS[name]
+    pos, F, T = workloads.particles(name)
+    idx = workloads.subsample(name)
+    s = fcm.Solver(wl.box)
+    t0 = time.time()
+    p = s.wrap(pos)
+    f, g = s.spread(p, F, T)
+    print(f"{name}: spread {time.time() - t0:.0f} s", flush=True)
+    Fh = stokes.forward_transform(wl.box, f)
+    del f
+    Gh = stokes.forward_transform(wl.box, g)
+    del g
+    uh, omh = stokes.solve_coefficients(wl.box, Fh, Gh)
+    del Fh, Gh
+    print(f"{name}: solve {time.time() - t0:.0f} s", flush=True)
+    u = stokes.inverse_transform(wl.box, uh)
+    del uh
+    om = stokes.inverse_transform(wl.box, omh)
+    del omh
+    U, Om = s.interp(p[idx], u, om)
+    out = os.path.join(HERE, f"{name}_oracle_sample.npz")
+    np.savez_compressed(out, index=idx, U=U, Omega=Om)
+    print(f"{name}: wrote {out} ({len(idx)} particles) in {time.time() - t0:.0f} s",
+          flush=True)
+    return out
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or ["bw131k", "bw1m", "sc1m"]
+    for nm in names:
+        make(nm)
