@@ -74,6 +74,44 @@ def cpu_baseline(name, factor=8):
     }
 
 
+def serving_bench(count=512, loads=(0.5, 0.8, 0.95), streams=4):
+    """The mixed serving stream: per-request latency at Poisson loads given
+    as fractions of the saturated request rate (all requests at t = 0)."""
+    import torch
+
+    import workloads
+    from paper_2210_01837_amd import serving
+
+    reqs = workloads.serving_requests(count)
+    jobs = []
+    for r in reqs:
+        pos, F, T = workloads.request_particles(r)
+        dev = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in (pos, F, T)]
+        jobs.append(serving.Job(r.rid, r.box, *dev))
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * 0.6)
+    pool = serving.SolverPool(budget)
+    at0 = [0.0] * count
+    t0 = time.perf_counter()
+    serving.serve(jobs, at0, budget=budget, streams=streams, pool=pool)
+    warm_s = time.perf_counter() - t0
+    sat = serving.latency_summary(
+        serving.serve(jobs, at0, budget=budget, streams=streams, pool=pool))
+    print(f"[bench] serving saturated: {sat}", file=sys.stderr, flush=True)
+    out = {"requests": count, "streams": streams, "budget_bytes": budget,
+           "solvers_created": pool.created, "solvers_evicted": pool.evicted,
+           "warmup_s": warm_s, "saturated": sat, "poisson": {}}
+    for f in loads:
+        arr = workloads.poisson_arrivals(count, f * sat["requests_per_s"]) * 1e3
+        res = serving.latency_summary(
+            serving.serve(jobs, list(arr), budget=budget, streams=streams,
+                          pool=pool))
+        print(f"[bench] serving load {f}: {res}", file=sys.stderr, flush=True)
+        out["poisson"][str(f)] = res
+    pool.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +119,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="bw1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must "
@@ -178,6 +218,13 @@ def main():
     }
     del P, Fd, Td, U, Om
     s.close()
+    if not args.no_serving:
+        sv = serving_bench(args.serving_requests)
+        line["serving"] = sv
+        p = sv["poisson"].get("0.8")
+        if p:
+            line["latency_p50_ms"] = p["p50_ms"]
+            line["latency_p99_ms"] = p["p99_ms"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(name)
     print(json.dumps(line), flush=True)

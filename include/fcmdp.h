@@ -127,6 +127,26 @@ int fcmdp_set_profiling(fcmdp_solver* s, int enable);
 int fcmdp_stage_times(fcmdp_solver* s, double ms[8], int64_t* napplies);
 
 /*
+ * Kernel variants.  Every step has a default kernel chosen at creation from
+ * the sizes; the alternatives below compute the same quantities with a
+ * different parallel decomposition and exist for cross-checks and tuning.
+ * value: 0/1 for the switches; for the FFT row counts a power of two (rows
+ * per workgroup of the wave-per-row x and y passes, 0 = default), rejected
+ * with FCMDP_EINVAL if the rows do not fit in LDS.  Not thread safe with
+ * respect to applies on the same solver.
+ */
+enum {
+  FCMDP_VARIANT_GENERIC_FFT = 0,     /* workgroup-per-row-batch transforms */
+  FCMDP_VARIANT_FFT_ROWS_X = 1,      /* rows per workgroup, x pass (1..16) */
+  FCMDP_VARIANT_FFT_ROWS_Y = 2,      /* rows per workgroup, y pass (1..8) */
+  FCMDP_VARIANT_SIMPLE_SPREAD = 3,   /* thread-per-column gather spread */
+  FCMDP_VARIANT_SIMPLE_INTERP = 4,   /* thread-per-particle interpolation */
+  FCMDP_VARIANT_GENERIC_COLUMNS = 5, /* thread-per-wavenumber column solve */
+  FCMDP_VARIANT_VECTOR_DCT = 6       /* FP64 Chebyshev transforms in MIXED */
+};
+int fcmdp_set_variant(fcmdp_solver* s, int key, int value);
+
+/*
  * Stage entry points (the steps of Sec. 3.4 one at a time, on caller
  * buffers; used for per-stage parity tests).  Real element type is double
  * in FP64 mode and float in MIXED mode.  Layouts:

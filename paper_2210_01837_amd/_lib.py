@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
         L.fcmdp_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(i64)]
         L.fcmdp_stage_times.restype = ci
+        L.fcmdp_set_variant.argtypes = [vp, ci, ci]
+        L.fcmdp_set_variant.restype = ci
         _lib = L
     return _lib
 

@@ -109,6 +109,47 @@ bool make_plan(int n, FFTPlan* plan) {
   return m == 1 && plan->nstages < fcmdp::kMaxStages;
 }
 
+// Plan for the row-owned transforms: radix 8 for the power-of-two part (one
+// 16, 4 or 2 for the remainder), then the odd primes.  Picks the fewest
+// threads per row (64, 128 or 256) for which every stage leaves at most
+// wave_nbi_cap(R) butterflies per thread; false if none does.
+bool make_wave_plan(int n, bool fp32, FFTPlan* plan, int* tpr) {
+  plan->n = n;
+  plan->nstages = 0;
+  int m = n, a = 0;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  std::vector<int> r;
+  if (a % 3 == 1) {
+    if (a >= 4) { r.push_back(16); a -= 4; } else { r.push_back(2); a -= 1; }
+  } else if (a % 3 == 2) {
+    r.push_back(4);
+    a -= 2;
+  }
+  while (a >= 3) { r.push_back(8); a -= 3; }
+  const int primes[] = {3, 5, 7, 11, 13, 17};
+  for (int q : primes)
+    while (m % q == 0) { r.push_back(q); m /= q; }
+  if (m != 1 || (int)r.size() >= fcmdp::kMaxStages) return false;
+  for (int t = 64; t <= 256; t *= 2) {
+    bool ok = true;
+    for (int R : r)
+      if ((n / R + t - 1) / t > fcmdp::wave_nbi_cap(fp32, R)) ok = false;
+    if (ok) {
+      for (int R : r) plan->radix[plan->nstages++] = R;
+      *tpr = t;
+      return true;
+    }
+  }
+  return false;
+}
+
+// largest power of two <= maxrows with rows * row_bytes within the LDS budget
+int rows_fitting(size_t row_bytes, int maxrows) {
+  int r = maxrows;
+  while (r > 1 && (size_t)r * row_bytes > fcmdp::kLdsBudget) r /= 2;
+  return (size_t)r * row_bytes <= fcmdp::kLdsBudget ? r : 0;
+}
+
 int validate(const fcmdp_params* p) {
   if (!p) return FCMDP_EINVAL;
   if (p->geometry != FCMDP_BOTTOM_WALL && p->geometry != FCMDP_SLIT_CHANNEL)
@@ -132,10 +173,11 @@ int validate(const fcmdp_params* p) {
   FFTPlan a, b;
   if (!make_plan(p->Nx / 2, &a) || !make_plan(p->Ny, &b)) return FCMDP_EINVAL;
   if ((long long)p->Nx * p->Ny >= (1LL << 31) - 1) return FCMDP_EINVAL;
-  // LDS of the single-row transforms (64 KiB per workgroup)
+  // LDS of the workgroup-per-row transforms (one row, two buffers), which
+  // every size must support; the wave-per-row transforms need less
   const size_t csz = p->precision == FCMDP_MIXED ? 8 : 16;
-  if (2 * (size_t)p->Ny * csz > 65536) return FCMDP_EINVAL;
-  if ((size_t)(p->Nx + 1) * csz > 65536) return FCMDP_EINVAL;
+  if (2 * (size_t)p->Ny * csz > fcmdp::kLdsBudget) return FCMDP_EINVAL;
+  if ((size_t)(p->Nx + 1) * csz > fcmdp::kLdsBudget) return FCMDP_EINVAL;
   return FCMDP_OK;
 }
 
@@ -206,7 +248,7 @@ void free_all(fcmdp_solver* s) {
                   s->hist, s->cell_start, s->pinfo, s->pw, s->pf, s->psi,
                   s->band, s->nbad, s->zc, s->quad, s->dct_f, s->dct_i,
                   s->dct_f32, s->dct_i32,
-                  s->dftc, s->tw_x, s->tw_y, s->tw_r};
+                  s->dftc, s->dftc_t, s->tw_x, s->tw_y, s->tw_r};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -282,6 +324,18 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
   }
   make_plan(p->Nx / 2, &s->plan_x);
   make_plan(p->Ny, &s->plan_y);
+  {
+    const bool fp32 = s->mixed;
+    const size_t csz = fp32 ? 8 : 16;
+    // row-owned transforms in single precision only (the double-precision
+    // stages do not fit the register budget of a 1024-thread workgroup)
+    s->wave_x = fp32 && make_wave_plan(p->Nx / 2, fp32, &s->wplan_x, &s->tpr_x);
+    s->wave_y = fp32 && make_wave_plan(p->Ny, fp32, &s->wplan_y, &s->tpr_y);
+    s->rows_x = rows_fitting((size_t)(p->Nx / 2 + 1) * csz, 16);
+    s->rows_y = rows_fitting((size_t)p->Ny * csz, 8);
+    if (s->rows_x == 0) s->wave_x = false;
+    if (s->rows_y == 0) s->wave_y = false;
+  }
 
   int err = FCMDP_OK;
   const Sizes z = sizes_for(p, s->cap, dp.ZW);
@@ -352,6 +406,12 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
       }
     }
     s->dftc = (double*)upload(cs, &err);
+    if (s->mixed) {
+      std::vector<float> c32(cs.begin(), cs.end());
+      s->dftc_t = upload(c32, &err);
+    } else {
+      s->dftc_t = upload(cs, &err);
+    }
     const int M = p->Nx / 2;
     if (s->mixed) {
       s->tw_x = upload_twiddles<float>(M, M, &err);
@@ -471,6 +531,43 @@ int fcmdp_set_profiling(fcmdp_solver* s, int enable) {
   if (!s) return FCMDP_EINVAL;
   s->profiling = enable != 0;
   return FCMDP_OK;
+}
+
+int fcmdp_set_variant(fcmdp_solver* s, int key, int value) {
+  if (!s) return FCMDP_EINVAL;
+  const bool on = value != 0;
+  const size_t csz = s->mixed ? 8 : 16;
+  switch (key) {
+    case FCMDP_VARIANT_GENERIC_FFT:
+      s->force_generic_fft = on;
+      return FCMDP_OK;
+    case FCMDP_VARIANT_FFT_ROWS_X:
+    case FCMDP_VARIANT_FFT_ROWS_Y: {
+      const bool x = key == FCMDP_VARIANT_FFT_ROWS_X;
+      const size_t row = x ? (size_t)(s->p.Nx / 2 + 1) * csz : (size_t)s->p.Ny * csz;
+      const int maxr = x ? 16 : 8;   // capped at 1024 threads per workgroup
+      int r = value;
+      if (r == 0) r = rows_fitting(row, maxr);
+      if (r < 1 || r > maxr || (r & (r - 1)) || (size_t)r * row > fcmdp::kLdsBudget)
+        return FCMDP_EINVAL;
+      (x ? s->rows_x : s->rows_y) = r;
+      return FCMDP_OK;
+    }
+    case FCMDP_VARIANT_SIMPLE_SPREAD:
+      s->force_simple_spread = on;
+      return FCMDP_OK;
+    case FCMDP_VARIANT_SIMPLE_INTERP:
+      s->force_simple_interp = on;
+      return FCMDP_OK;
+    case FCMDP_VARIANT_GENERIC_COLUMNS:
+      s->force_generic_columns = on;
+      return FCMDP_OK;
+    case FCMDP_VARIANT_VECTOR_DCT:
+      s->force_vector_dct = on;
+      return FCMDP_OK;
+    default:
+      return FCMDP_EINVAL;
+  }
 }
 
 int fcmdp_stage_times(fcmdp_solver* s, double ms[8], int64_t* napplies) {

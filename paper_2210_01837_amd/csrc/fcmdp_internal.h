@@ -22,6 +22,7 @@ namespace fcmdp {
 
 constexpr int kMaxNz = 64;
 constexpr int kMaxStages = 24;
+constexpr size_t kLdsBudget = 160 * 1024;   // LDS per workgroup on gfx950
 constexpr int kWin = 7;        // ES window per axis: offsets -3..3 (w = 6)
 
 template <typename T> struct Cplx;
@@ -34,6 +35,14 @@ struct FFTPlan {
   int nstages = 0;
   int radix[kMaxStages] = {0};
 };
+
+// The row-owned transforms hold all butterflies of one thread for a stage in
+// registers: at most wave_nbi_cap(R) butterflies of radix R per thread, so a
+// stage of length N needs ceil(N / (R * threads per row)) <= cap.
+__host__ __device__ constexpr int wave_nbi_cap(bool fp32, int R) {
+  return (fp32 ? 24 : 12) / R < 1 ? 1
+         : (fp32 ? 24 : 12) / R > 8 ? 8 : (fp32 ? 24 : 12) / R;
+}
 
 // Parameters the device kernels need (passed by value).
 struct DevParams {
@@ -87,6 +96,13 @@ struct fcmdp_solver {
   void* tw_r = nullptr;         // e^{-2 pi i k/Nx}, k <= Nx/2
   fcmdp::FFTPlan plan_x, plan_y;
   int dft_off[32] = {0};        // offset of prime P's table in dftc
+  // row-owned transforms (x rows of Nx/2, y rows of Ny) when every stage
+  // fits the register budget with at most 256 threads per row; rows per
+  // workgroup and threads per row of each pass
+  fcmdp::FFTPlan wplan_x, wplan_y;
+  bool wave_x = false, wave_y = false;
+  int rows_x = 0, rows_y = 0, tpr_x = 0, tpr_y = 0;
+  void* dftc_t = nullptr;       // dftc converted to T
 
   // use the one-thread-per-column solver even when Nz <= 32 (tests)
   bool force_generic_columns = false;
@@ -96,6 +112,8 @@ struct fcmdp_solver {
   bool force_simple_spread = false;
   // use the per-lane FP64 Chebyshev transforms in the mixed path (tests)
   bool force_vector_dct = false;
+  // use the workgroup-per-row-batch transforms (tests)
+  bool force_generic_fft = false;
 
   // tracing: events of applies not yet summed, 7 per apply
   bool profiling = false;

@@ -74,6 +74,31 @@ __device__ inline void dft8(C* v, T sign) {
   v[3] = cadd(e[3], t3); v[7] = csub(e[3], t3);
 }
 
+// radix 16 as two radix-8 halves (even / odd inputs) and one twiddled
+// radix-2 combination
+template <typename T, typename C>
+__device__ inline void dft16(C* v, T sign) {
+  C e[8], o[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) { e[m] = v[2 * m]; o[m] = v[2 * m + 1]; }
+  dft8<T, C>(e, sign);
+  dft8<T, C>(o, sign);
+  // cos and sin of pi k / 8, k = 0..7
+  const T c[8] = {T(1), T(0.92387953251128675613), T(0.70710678118654752440),
+                  T(0.38268343236508977173), T(0), T(-0.38268343236508977173),
+                  T(-0.70710678118654752440), T(-0.92387953251128675613)};
+  const T sn[8] = {T(0), T(0.38268343236508977173), T(0.70710678118654752440),
+                   T(0.92387953251128675613), T(1), T(0.92387953251128675613),
+                   T(0.70710678118654752440), T(0.38268343236508977173)};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    C w; w.x = c[k]; w.y = sign * sn[k];
+    const C t = cmul(o[k], w);
+    v[k] = cadd(e[k], t);
+    v[k + 8] = csub(e[k], t);
+  }
+}
+
 // odd prime P: pair terms j and P-j; cs[2m], cs[2m+1] = cos, sin(2 pi m/P)
 template <typename T, typename C, int P>
 __device__ inline void dft_prime(C* v, const T* cs, T sign) {
@@ -284,10 +309,333 @@ k_fft_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   for (int idx = threadIdx.x; idx < nr * M; idx += blockDim.x) dst[idx] = res[idx];
 }
 
+// ---- row-owned in-place transforms ------------------------------------------
+// TPR threads (one to four wavefronts) own one row in LDS.  A Stockham stage
+// first reads every butterfly input of the thread into registers and then
+// writes the outputs back in place.  Butterfly j of a stage belongs to thread
+// j mod TPR, so the loop trip counts are uniform and there are no index
+// divisions by the row count.  With TPR = 64 the row is private to one
+// wavefront, whose LDS accesses complete in issue order, and stages need no
+// workgroup barrier; with more threads per row all rows of the workgroup
+// step through the (identical) stage sequence together.
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int TPR>
+__device__ __forceinline__ void row_sync() {
+  if constexpr (TPR == 64) wave_sync();
+  else __syncthreads();
+}
+
+// Not inlined: with every radix inlined into one stage loop the register
+// allocator keeps the union of all stages' live ranges.
+template <typename T, int R, int TPR>
+__device__ __noinline__ void wstage(cplx_t<T>* row, int N, int Ns, int t,
+                                       const cplx_t<T>* __restrict__ tw,
+                                       const T* __restrict__ cs, T sign) {
+  using C = cplx_t<T>;
+  constexpr int CAP = wave_nbi_cap(sizeof(T) == 4, R);
+  const int nb = N / R;
+  const int twstep = N / (Ns * R);
+  C v[CAP][R];
+#pragma unroll
+  for (int i = 0; i < CAP; ++i) {
+    const int j = t + TPR * i;
+    if (j < nb) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[i][q] = row[j + q * nb];
+    }
+  }
+  row_sync<TPR>();
+#pragma unroll
+  for (int i = 0; i < CAP; ++i) {
+    const int j = t + TPR * i;
+    if (j < nb) {
+      C* x = v[i];
+      const int k = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          C w = tw[q * k * twstep];
+          w.y *= -sign;
+          x[q] = cmul(x[q], w);
+        }
+      }
+      if constexpr (R == 2) dft2<T, C>(x);
+      else if constexpr (R == 4) dft4<T, C>(x, sign);
+      else if constexpr (R == 8) dft8<T, C>(x, sign);
+      else if constexpr (R == 16) dft16<T, C>(x, sign);
+      else dft_prime<T, C, R>(x, cs, sign);
+      const int out = (j - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) row[out + q * Ns] = x[q];
+    }
+  }
+  row_sync<TPR>();
+}
+
+template <typename T, int TPR>
+__device__ __forceinline__ void row_fft(cplx_t<T>* row, int N,
+                                        const FFTPlan& plan, int t,
+                                        const cplx_t<T>* __restrict__ tw,
+                                        const T* __restrict__ dftc,
+                                        const int* dft_off, T sign) {
+  int Ns = 1;
+  for (int s = 0; s < plan.nstages; ++s) {
+    const int R = plan.radix[s];
+    const T* cs = dftc + dft_off[R];
+    switch (R) {
+      case 2: wstage<T, 2, TPR>(row, N, Ns, t, tw, cs, sign); break;
+      case 3: wstage<T, 3, TPR>(row, N, Ns, t, tw, cs, sign); break;
+      case 4: wstage<T, 4, TPR>(row, N, Ns, t, tw, cs, sign); break;
+      case 5: wstage<T, 5, TPR>(row, N, Ns, t, tw, cs, sign); break;
+      case 7: wstage<T, 7, TPR>(row, N, Ns, t, tw, cs, sign); break;
+      case 8: wstage<T, 8, TPR>(row, N, Ns, t, tw, cs, sign); break;
+      case 11: wstage<T, 11, TPR>(row, N, Ns, t, tw, cs, sign); break;
+      case 13: wstage<T, 13, TPR>(row, N, Ns, t, tw, cs, sign); break;
+      case 16: wstage<T, 16, TPR>(row, N, Ns, t, tw, cs, sign); break;
+      case 17: wstage<T, 17, TPR>(row, N, Ns, t, tw, cs, sign); break;
+      default: break;
+    }
+    Ns *= R;
+  }
+}
+
+// split step of the real transform: X_k from Z_k and Z_{M-k} (w = e^{-2 pi i k/Nx})
+template <typename C>
+__device__ inline C r2c_post(C zk, C zm, C w) {
+  using T = decltype(zk.x);
+  zm.y = -zm.y;
+  const C e = cscale(cadd(zk, zm), T(0.5));
+  const C d = csub(zk, zm);
+  C o; o.x = T(0.5) * d.y; o.y = T(-0.5) * d.x;      // -i d / 2
+  return cadd(e, cmul(w, o));
+}
+
+// inverse split step: Z_k from X_k and X_{M-k} (w = e^{-2 pi i k/Nx})
+template <typename C>
+__device__ inline C c2r_pre(C xk, C xm, C w) {
+  xm.y = -xm.y;                                   // conj(X_{M-k})
+  const C A = cadd(xk, xm);
+  const C B = csub(xk, xm);
+  w.y = -w.y;                                     // e^{+2 pi i k/Nx}
+  const C wb = cmul(w, B);
+  C z; z.x = A.x - wb.y; z.y = A.y + wb.x;        // A + i w B
+  return z;
+}
+
+// x-pass, real rows -> half spectrum, ROWS rows per workgroup, written
+// transposed as ROWS-long runs of consecutive y.
+template <typename T, int ROWS, int TPR>
+__global__ void __launch_bounds__(ROWS * TPR)
+k_fftw_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
+             const T* __restrict__ grid, cplx_t<T>* __restrict__ spec,
+             const cplx_t<T>* __restrict__ tw, const cplx_t<T>* __restrict__ rtw,
+             const T* __restrict__ dftc, DftOff doff) {
+  using C = cplx_t<T>;
+  extern __shared__ unsigned char lds_raw[];
+  C* lds = reinterpret_cast<C*>(lds_raw);
+  const int M = dp.Nx / 2;
+  const int S = M + 1;                              // row stride in LDS
+  const int p = blockIdx.y;
+  const int c = p % dp.Nz;
+  if (c < band[0] || c > band[1]) return;           // whole workgroup
+  const int y0 = blockIdx.x * ROWS;
+  const int nr = min(ROWS, dp.Ny - y0);
+  const int wr = __builtin_amdgcn_readfirstlane(threadIdx.x / TPR);
+  const int t = threadIdx.x % TPR;
+  C* row = lds + wr * S;
+  // rows past the grid edge (tail workgroup) transform a copy of row y0
+  const int y = wr < nr ? y0 + wr : y0;
+  const C* src = reinterpret_cast<const C*>(grid + ((size_t)p * dp.Ny + y) * dp.Nx);
+#pragma unroll 4
+  for (int i = t; i < M; i += TPR) row[i] = src[i];
+  row_sync<TPR>();
+  row_fft<T, TPR>(row, M, plan, t, tw, dftc, doff.off, T(-1));
+  for (int k = t; k <= M / 2; k += TPR) {
+    const C zk = row[k];
+    if (k == 0) {
+      row[0] = r2c_post(zk, zk, rtw[0]);
+      row[M] = r2c_post(zk, zk, rtw[M]);
+    } else {
+      const C zm = row[M - k];
+      row[k] = r2c_post(zk, zm, rtw[k]);
+      if (M - k != k) row[M - k] = r2c_post(zm, zk, rtw[M - k]);
+    }
+  }
+  __syncthreads();
+  const size_t pbase = (size_t)p * dp.Nkx * dp.Ny;
+  for (int idx = threadIdx.x; idx < S * ROWS; idx += ROWS * TPR) {
+    const int k = idx / ROWS;
+    const int r = idx % ROWS;
+    if (r < nr) spec[pbase + (size_t)k * dp.Ny + y0 + r] = lds[r * S + k];
+  }
+}
+
+// y-pass, in place on contiguous rows of length Ny.
+template <typename T, int ROWS, int TPR>
+__global__ void __launch_bounds__(ROWS * TPR)
+k_fftw_y(DevParams dp, FFTPlan plan, const int* __restrict__ band,
+         cplx_t<T>* __restrict__ spec, const cplx_t<T>* __restrict__ tw,
+         const T* __restrict__ dftc, DftOff doff, T sign) {
+  using C = cplx_t<T>;
+  extern __shared__ unsigned char lds_raw[];
+  const int p = blockIdx.y;
+  const int c = p % dp.Nz;
+  if (c < band[0] || c > band[1]) return;
+  const int wr = __builtin_amdgcn_readfirstlane(threadIdx.x / TPR);
+  const int t = threadIdx.x % TPR;
+  const int kx = blockIdx.x * ROWS + wr;
+  const bool live = kx < dp.Nkx;
+  if (TPR == 64 && !live) return;                   // a whole wavefront
+  const int N = dp.Ny;
+  C* row = reinterpret_cast<C*>(lds_raw) + wr * N;
+  C* g = spec + ((size_t)p * dp.Nkx + (live ? kx : 0)) * N;
+#pragma unroll 4
+  for (int i = t; i < N; i += TPR) row[i] = g[i];
+  row_sync<TPR>();
+  row_fft<T, TPR>(row, N, plan, t, tw, dftc, doff.off, sign);
+  if (live) {
+#pragma unroll 4
+    for (int i = t; i < N; i += TPR) g[i] = row[i];
+  }
+}
+
+// x-pass, half spectrum -> real rows, reading ROWS-long runs of the
+// transposed layout.
+template <typename T, int ROWS, int TPR>
+__global__ void __launch_bounds__(ROWS * TPR)
+k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
+             const cplx_t<T>* __restrict__ spec, T* __restrict__ grid,
+             const cplx_t<T>* __restrict__ tw, const cplx_t<T>* __restrict__ rtw,
+             const T* __restrict__ dftc, DftOff doff) {
+  using C = cplx_t<T>;
+  extern __shared__ unsigned char lds_raw[];
+  C* lds = reinterpret_cast<C*>(lds_raw);
+  const int M = dp.Nx / 2;
+  const int S = M + 1;
+  const int p = blockIdx.y;
+  const int c = p % dp.Nz;
+  if (c < band[0] || c > band[1]) return;
+  const int y0 = blockIdx.x * ROWS;
+  const int nr = min(ROWS, dp.Ny - y0);
+  const size_t pbase = (size_t)p * dp.Nkx * dp.Ny;
+  for (int idx = threadIdx.x; idx < S * ROWS; idx += ROWS * TPR) {
+    const int k = idx / ROWS;
+    const int r = idx % ROWS;
+    // rows past the grid edge transform a copy of row y0
+    lds[r * S + k] = spec[pbase + (size_t)k * dp.Ny + y0 + (r < nr ? r : 0)];
+  }
+  __syncthreads();
+  const int wr = __builtin_amdgcn_readfirstlane(threadIdx.x / TPR);
+  const int t = threadIdx.x % TPR;
+  C* row = lds + wr * S;
+  for (int k = t; k <= M / 2; k += TPR) {
+    if (k == 0) {
+      C x0 = row[0], xm = row[M];
+      x0.y = T(0);
+      xm.y = T(0);
+      row[0] = c2r_pre(x0, xm, rtw[0]);
+    } else {
+      const C xk = row[k], xm = row[M - k];
+      row[k] = c2r_pre(xk, xm, rtw[k]);
+      if (M - k != k) row[M - k] = c2r_pre(xm, xk, rtw[M - k]);
+    }
+  }
+  row_sync<TPR>();
+  row_fft<T, TPR>(row, M, plan, t, tw, dftc, doff.off, T(1));
+  if (wr < nr) {
+    C* dst = reinterpret_cast<C*>(grid + ((size_t)p * dp.Ny + y0 + wr) * dp.Nx);
+#pragma unroll 4
+    for (int i = t; i < M; i += TPR) dst[i] = row[i];
+  }
+}
+
+template <typename T, int ROWS, int TPR>
+static void launch_wave_x(bool fwd, const fcmdp_solver* s, const void* in,
+                          void* out, const DftOff& doff, hipStream_t st) {
+  using C = cplx_t<T>;
+  const DevParams& dp = s->dp;
+  const int M = dp.Nx / 2;
+  const size_t lds = (size_t)ROWS * (M + 1) * sizeof(C);
+  dim3 g((dp.Ny + ROWS - 1) / ROWS, 6 * dp.Nz);
+  const T* cs = (const T*)s->dftc_t;
+  if (fwd)
+    hipLaunchKernelGGL((k_fftw_x_r2c<T, ROWS, TPR>), g, dim3(ROWS * TPR), lds,
+                       st, dp, s->wplan_x, s->band, (const T*)in, (C*)out,
+                       (const C*)s->tw_x, (const C*)s->tw_r, cs, doff);
+  else
+    hipLaunchKernelGGL((k_fftw_x_c2r<T, ROWS, TPR>), g, dim3(ROWS * TPR), lds,
+                       st, dp, s->wplan_x, s->band, (const C*)in, (T*)out,
+                       (const C*)s->tw_x, (const C*)s->tw_r, cs, doff);
+}
+
+template <typename T, int TPR>
+static void wave_x_tpr(bool fwd, const fcmdp_solver* s, const void* in,
+                       void* out, const DftOff& doff, hipStream_t st) {
+  // rows per workgroup, capped by 1024 threads
+  const int r = s->rows_x * TPR > 1024 ? 1024 / TPR : s->rows_x;
+  switch (r) {
+    case 16: launch_wave_x<T, 16, 64>(fwd, s, in, out, doff, st); break;
+    case 8: launch_wave_x<T, 8, TPR>(fwd, s, in, out, doff, st); break;
+    case 4: launch_wave_x<T, 4, TPR>(fwd, s, in, out, doff, st); break;
+    case 2: launch_wave_x<T, 2, TPR>(fwd, s, in, out, doff, st); break;
+    default: launch_wave_x<T, 1, TPR>(fwd, s, in, out, doff, st); break;
+  }
+}
+
+template <typename T>
+static void wave_x(bool fwd, const fcmdp_solver* s, const void* in, void* out,
+                   const DftOff& doff, hipStream_t st) {
+  switch (s->tpr_x) {
+    case 64: wave_x_tpr<T, 64>(fwd, s, in, out, doff, st); break;
+    case 128: wave_x_tpr<T, 128>(fwd, s, in, out, doff, st); break;
+    default: wave_x_tpr<T, 256>(fwd, s, in, out, doff, st); break;
+  }
+}
+
+template <typename T, int ROWS, int TPR>
+static void launch_wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
+                          T sign, hipStream_t st) {
+  using C = cplx_t<T>;
+  const DevParams& dp = s->dp;
+  const size_t lds = (size_t)ROWS * dp.Ny * sizeof(C);
+  dim3 g((dp.Nkx + ROWS - 1) / ROWS, 6 * dp.Nz);
+  hipLaunchKernelGGL((k_fftw_y<T, ROWS, TPR>), g, dim3(ROWS * TPR), lds, st, dp,
+                     s->wplan_y, s->band, (C*)spec, (const C*)s->tw_y,
+                     (const T*)s->dftc_t, doff, sign);
+}
+
+template <typename T, int TPR>
+static void wave_y_tpr(const fcmdp_solver* s, void* spec, const DftOff& doff,
+                       T sign, hipStream_t st) {
+  const int r = s->rows_y * TPR > 1024 ? 1024 / TPR : s->rows_y;
+  switch (r) {
+    case 8: launch_wave_y<T, 8, TPR>(s, spec, doff, sign, st); break;
+    case 4: launch_wave_y<T, 4, TPR>(s, spec, doff, sign, st); break;
+    case 2: launch_wave_y<T, 2, TPR>(s, spec, doff, sign, st); break;
+    default: launch_wave_y<T, 1, TPR>(s, spec, doff, sign, st); break;
+  }
+}
+
+template <typename T>
+static void wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
+                   T sign, hipStream_t st) {
+  switch (s->tpr_y) {
+    case 64: wave_y_tpr<T, 64>(s, spec, doff, sign, st); break;
+    case 128: wave_y_tpr<T, 128>(s, spec, doff, sign, st); break;
+    default: wave_y_tpr<T, 256>(s, spec, doff, sign, st); break;
+  }
+}
+
 static int rows_for(int len, size_t elem, int bufs_extra, int maxrows) {
-  // two ping-pong buffers of rows*len complex words within 64 KiB
+  // two ping-pong buffers of rows*len complex words within kLdsBudget
   size_t per = 2 * (size_t)len * elem + (size_t)bufs_extra * elem;
-  int r = (int)(65536 / per);
+  int r = (int)(kLdsBudget / per);
   if (r < 1) r = 1;
   if (r > maxrows) r = maxrows;
   return r;
@@ -302,15 +650,24 @@ static hipError_t fwd_impl(const fcmdp_solver* s, const T* grid, void* spec,
   for (int i = 0; i < 32; ++i) doff.off[i] = s->dft_off[i];
   const int M = dp.Nx / 2;
   const int planes = 6 * dp.Nz;
-  int rows = rows_for(M, sizeof(C), 0, 16);
-  if (rows > dp.Ny) rows = dp.Ny;
-  size_t lds = 2 * (size_t)rows * M * sizeof(C);
-  hipLaunchKernelGGL(k_fft_x_r2c<T>, dim3((dp.Ny + rows - 1) / rows, planes),
-                     dim3(256), lds, st, dp, s->plan_x, s->band, grid, (C*)spec,
-                     (const C*)s->tw_x, (const C*)s->tw_r, s->dftc, doff, rows);
+  constexpr bool kRowOwned = sizeof(T) == 4;       // single precision only
+  if (kRowOwned && s->wave_x && !s->force_generic_fft) {
+    if constexpr (kRowOwned) wave_x<T>(true, s, grid, spec, doff, st);
+  } else {
+    int rows = rows_for(M, sizeof(C), 0, 16);
+    if (rows > dp.Ny) rows = dp.Ny;
+    size_t lds = 2 * (size_t)rows * M * sizeof(C);
+    hipLaunchKernelGGL(k_fft_x_r2c<T>, dim3((dp.Ny + rows - 1) / rows, planes),
+                       dim3(256), lds, st, dp, s->plan_x, s->band, grid, (C*)spec,
+                       (const C*)s->tw_x, (const C*)s->tw_r, s->dftc, doff, rows);
+  }
+  if (kRowOwned && s->wave_y && !s->force_generic_fft) {
+    if constexpr (kRowOwned) wave_y<T>(s, spec, doff, T(-1), st);
+    return hipGetLastError();
+  }
   int ry = rows_for(dp.Ny, sizeof(C), 0, 16);
   if (ry > dp.Nkx) ry = dp.Nkx;
-  lds = 2 * (size_t)ry * dp.Ny * sizeof(C);
+  size_t lds = 2 * (size_t)ry * dp.Ny * sizeof(C);
   hipLaunchKernelGGL(k_fft_y<T>, dim3((dp.Nkx + ry - 1) / ry, planes),
                      dim3(256), lds, st, dp, s->plan_y, s->band, (C*)spec,
                      (const C*)s->tw_y, s->dftc, doff, ry, T(-1));
@@ -326,15 +683,24 @@ static hipError_t inv_impl(const fcmdp_solver* s, void* spec, T* grid,
   for (int i = 0; i < 32; ++i) doff.off[i] = s->dft_off[i];
   const int M = dp.Nx / 2;
   const int planes = 6 * dp.Nz;
-  int ry = rows_for(dp.Ny, sizeof(C), 0, 16);
-  if (ry > dp.Nkx) ry = dp.Nkx;
-  size_t lds = 2 * (size_t)ry * dp.Ny * sizeof(C);
-  hipLaunchKernelGGL(k_fft_y<T>, dim3((dp.Nkx + ry - 1) / ry, planes),
-                     dim3(256), lds, st, dp, s->plan_y, s->band, (C*)spec,
-                     (const C*)s->tw_y, s->dftc, doff, ry, T(1));
+  constexpr bool kRowOwned = sizeof(T) == 4;       // single precision only
+  if (kRowOwned && s->wave_y && !s->force_generic_fft) {
+    if constexpr (kRowOwned) wave_y<T>(s, spec, doff, T(1), st);
+  } else {
+    int ry = rows_for(dp.Ny, sizeof(C), 0, 16);
+    if (ry > dp.Nkx) ry = dp.Nkx;
+    size_t lds = 2 * (size_t)ry * dp.Ny * sizeof(C);
+    hipLaunchKernelGGL(k_fft_y<T>, dim3((dp.Nkx + ry - 1) / ry, planes),
+                       dim3(256), lds, st, dp, s->plan_y, s->band, (C*)spec,
+                       (const C*)s->tw_y, s->dftc, doff, ry, T(1));
+  }
+  if (kRowOwned && s->wave_x && !s->force_generic_fft) {
+    if constexpr (kRowOwned) wave_x<T>(false, s, spec, grid, doff, st);
+    return hipGetLastError();
+  }
   int rows = rows_for(M, sizeof(C), 1, 16);
   if (rows > dp.Ny) rows = dp.Ny;
-  lds = (size_t)rows * (2 * M + 1) * sizeof(C);
+  size_t lds = (size_t)rows * (2 * M + 1) * sizeof(C);
   hipLaunchKernelGGL(k_fft_x_c2r<T>, dim3((dp.Ny + rows - 1) / rows, planes),
                      dim3(256), lds, st, dp, s->plan_x, s->band, (const C*)spec,
                      grid, (const C*)s->tw_x, (const C*)s->tw_r, s->dftc, doff,

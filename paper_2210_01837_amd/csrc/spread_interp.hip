@@ -99,154 +99,130 @@ k_spread(DevParams dp, const int* __restrict__ band,
   }
 }
 
-// Tiled spread: a workgroup owns 32 x 8 grid columns.  The particle records of
-// the 38 x 14 cells whose kernels can reach the tile are copied once into LDS
-// in (row, x) cell order, so every thread's 7 x 7 cell neighbourhood is seven
-// contiguous LDS segments; the per-thread summation order is the cell-sorted
-// order, hence deterministic.  A tile whose halo holds more particles than
-// the LDS capacity falls back to reading the records from global memory.
-constexpr int kSpTX = 32, kSpTY = 8;
-constexpr int kSpRX = kSpTX + 6, kSpRY = kSpTY + 6;
-constexpr int kSpCells = kSpRX * kSpRY;     // 532
+// Wave-uniform spread: a wavefront owns an 8 x 8 patch of grid columns and
+// walks, in cell-sorted order, every particle of the 14 x 14 cells whose
+// kernels can reach the patch.  The particle index is the same on all lanes,
+// so its record is fetched once per wavefront (scalar loads); each lane adds
+// the particle's contribution to its own column when that column lies in the
+// particle's 7 x 7 footprint.  Loop trip counts are uniform (no divergence
+// between lanes of different cell occupancy), no LDS is used (high
+// occupancy), and every column sums its particles in a fixed order
+// (deterministic).  A first pass finds the z-nodes the region's particles
+// touch; band planes outside them are written as zeros without a particle
+// loop, and the rest are accumulated ZC planes at a time in registers.
+constexpr int kPW = 8;   // patch edge per wavefront; 4 wavefronts side by side in x
+constexpr int kSpreadZC = 10;
 
-template <typename T>
+template <typename T, int ZC>
 __global__ void __launch_bounds__(256)
-k_spread_tiled(DevParams dp, const int* __restrict__ band,
-               const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
-               const T* __restrict__ pw, const T* __restrict__ pf,
-               const T* __restrict__ psi, T* __restrict__ grid, int cap) {
-  extern __shared__ unsigned char lds_raw[];
-  const int ZW = dp.ZW;
-  constexpr int kRec = 36;                  // 28 weights, 6 forces, 2 ints
-  T* rec = reinterpret_cast<T*>(lds_raw);                  // [cap][kRec]
-  T* zrec = rec + cap * kRec;                              // [cap][2 ZW]
-  __shared__ int cs[kSpCells + 1];
-  __shared__ int gbase[kSpCells];
+k_spread_wave(DevParams dp, const int* __restrict__ band,
+              const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
+              const T* __restrict__ pw, const T* __restrict__ pf,
+              const T* __restrict__ psi, T* __restrict__ grid) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int xw = (blockIdx.x * 4 + wv) * kPW;
+  const int yw = blockIdx.y * kPW;
+  if (xw >= dp.Nx) return;                 // whole wavefront; no barriers below
   const int lo = band[0], hi = band[1];
-  const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * kSpTX, y0 = blockIdx.y * kSpTY;
-  const int tx = tid % kSpTX, ty = tid / kSpTX;
-  const int a = x0 + tx, b = y0 + ty;
+  const int a = xw + (lane & 7), b = yw + (lane >> 3);
   const bool inside = a < dp.Nx && b < dp.Ny;
-  if (lo > hi) return;
-  // region cell counts and LDS offsets
-  for (int q = tid; q < kSpCells; q += 256) {
-    const int rx = q % kSpRX, ry = q / kSpRX;
-    const int gx = wrap_index(x0 - 3 + rx, dp.Nx);
-    const int gy = wrap_index(y0 - 3 + ry, dp.Ny);
-    const int g = gy * dp.Nx + gx;
-    const int s0 = cell_start[g];
-    gbase[q] = s0;
-    cs[q + 1] = cell_start[g + 1] - s0;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    cs[0] = 0;
-    for (int q = 0; q < kSpCells; ++q) cs[q + 1] += cs[q];
-  }
-  __syncthreads();
-  const int total = cs[kSpCells];
-  const bool staged = total <= cap;
-  if (staged) {
-    for (int slot = tid; slot < total; slot += 256) {
-      int lo_q = 0, hi_q = kSpCells - 1;     // last q with cs[q] <= slot
-      while (lo_q < hi_q) {
-        const int mid = (lo_q + hi_q + 1) >> 1;
-        if (cs[mid] <= slot) lo_q = mid; else hi_q = mid - 1;
-      }
-      const int p = gbase[lo_q] + (slot - cs[lo_q]);
-      T* r = rec + slot * kRec;
-      const T* w = pw + (size_t)p * 32;
-#pragma unroll
-      for (int d = 0; d < 7; ++d) {
-        r[d] = w[d];
-        r[7 + d] = w[8 + d];
-        r[14 + d] = w[16 + d];
-        r[21 + d] = w[24 + d];
-      }
-      const T* f = pf + (size_t)p * 8;
-      r[28] = f[0]; r[29] = f[1]; r[30] = f[2];
-      r[31] = f[4]; r[32] = f[5]; r[33] = f[6];
-      const int4 inf = pinfo[p];
-      reinterpret_cast<int*>(r + 34)[0] = inf.z;
-      reinterpret_cast<int*>(r + 34)[sizeof(T) == 4 ? 1 : 2] = inf.w;
-      const T* ps = psi + (size_t)p * 2 * ZW;
-      T* zr = zrec + slot * 2 * ZW;
-      for (int e = 0; e < 2 * ZW; ++e) zr[e] = ps[e];
-    }
-  }
-  __syncthreads();
-  if (!inside) return;
+  const int ZW = dp.ZW;
   const size_t plane = (size_t)dp.Nx * dp.Ny;
   const size_t chstride = plane * dp.Nz;
-  const int ra = tx + 3, rb = ty + 3;
-  for (int c0 = lo; c0 <= hi; c0 += kZC) {
-    T acc[kZC][6];
+  const size_t col = (size_t)b * dp.Nx + a;
+  // the 14 cell rows / columns that reach the patch (fewer on a tiny grid,
+  // so that no cell is visited twice); columns split at the periodic seam
+  const int nrows = dp.Ny < 2 * kPW - 2 ? dp.Ny : 2 * kPW - 2;
+  const int ncols = dp.Nx < 2 * kPW - 2 ? dp.Nx : 2 * kPW - 2;
+  const int xs = wrap_index(xw - 3, dp.Nx);
+  const int xe0 = xs + ncols <= dp.Nx ? xs + ncols : dp.Nx;
+  const int xe1 = xs + ncols - xe0;        // cells [0, xe1) after the seam
+  // z-nodes touched by the region's particles
+  int zmin = dp.Nz, zmax = -1;
+  for (int r = 0; r < nrows; ++r) {
+    const int row = wrap_index(yw - 3 + r, dp.Ny) * dp.Nx;
+    for (int sg = 0; sg < 2; ++sg) {
+      const int ca = sg ? 0 : xs, cb = sg ? xe1 : xe0;
+      if (ca >= cb) continue;
+      const int p1 = cell_start[row + cb];
+      for (int p = cell_start[row + ca]; p < p1; ++p) {
+        const int4 inf = pinfo[p];
+        zmin = min(zmin, inf.z);
+        zmax = max(zmax, inf.w);
+      }
+    }
+  }
+  if (inside) {
+    for (int c = lo; c <= hi; ++c) {
+      if (c >= zmin && c <= zmax) continue;
 #pragma unroll
-    for (int s = 0; s < kZC; ++s)
+      for (int ch = 0; ch < 6; ++ch) grid[ch * chstride + c * plane + col] = T(0);
+    }
+  }
+  for (int c0 = zmin; c0 <= zmax; c0 += ZC) {
+    T acc[ZC][6];
+#pragma unroll
+    for (int s = 0; s < ZC; ++s)
 #pragma unroll
       for (int ch = 0; ch < 6; ++ch) acc[s][ch] = T(0);
-    for (int dyi = 0; dyi < kWin; ++dyi) {
-      const int ry = rb - (dyi - 3);          // cells that reach row b with weight dyi
-      for (int dxi = 0; dxi < kWin; ++dxi) {
-        const int q = ry * kSpRX + ra - (dxi - 3);
-        if (staged) {
-          const int s0 = cs[q], s1 = cs[q + 1];
-          for (int sl = s0; sl < s1; ++sl) {
-            const T* r = rec + sl * kRec;
-            const int cA = reinterpret_cast<const int*>(r + 34)[0];
-            const int cB = reinterpret_cast<const int*>(r + 34)[sizeof(T) == 4 ? 1 : 2];
-            if (cB < c0 || cA >= c0 + kZC) continue;
-            const T wm = r[dxi] * r[7 + dyi];
-            const T wd = r[14 + dxi] * r[21 + dyi];
-            if (wm == T(0) && wd == T(0)) continue;
-            const T f0 = r[28] * wm, f1 = r[29] * wm, f2 = r[30] * wm;
-            const T t0 = r[31] * wd, t1 = r[32] * wd, t2 = r[33] * wd;
-            const T* zr = zrec + sl * 2 * ZW;
+    for (int r = 0; r < nrows; ++r) {
+      const int row = wrap_index(yw - 3 + r, dp.Ny) * dp.Nx;
+      for (int sg = 0; sg < 2; ++sg) {
+        const int ca = sg ? 0 : xs, cb = sg ? xe1 : xe0;
+        if (ca >= cb) continue;
+        const int p0 = cell_start[row + ca], p1 = cell_start[row + cb];
+        int4 nxt = p0 < p1 ? pinfo[p0] : make_int4(0, 0, 0, -1);
+        for (int p = p0; p < p1; ++p) {
+          const int4 inf = nxt;
+          if (p + 1 < p1) nxt = pinfo[p + 1];             // prefetch
+          if (inf.w < c0 || inf.z >= c0 + ZC) continue;   // no overlap in z
+          // folded z weights of the chunk's nodes, fetched together
+          const T* ps = psi + (size_t)p * 2 * ZW;
+          T pm[ZC], pd[ZC];
 #pragma unroll
-            for (int s = 0; s < kZC; ++s) {
-              const int zi = c0 + s - cA;
-              if (zi >= 0 && zi < ZW) {
-                const T pm = zr[zi], pd = zr[ZW + zi];
-                acc[s][0] += f0 * pm; acc[s][1] += f1 * pm; acc[s][2] += f2 * pm;
-                acc[s][3] += t0 * pd; acc[s][4] += t1 * pd; acc[s][5] += t2 * pd;
-              }
-            }
+          for (int s = 0; s < ZC; ++s) {
+            const int j = c0 + s - inf.z;
+            const int jc = j < 0 ? 0 : (j >= ZW ? ZW - 1 : j);
+            pm[s] = ps[jc];
+            pd[s] = ps[ZW + jc];
           }
-        } else {
-          const int p0 = gbase[q];
-          const int p1 = p0 + (cs[q + 1] - cs[q]);
-          for (int p = p0; p < p1; ++p) {
-            const int4 inf = pinfo[p];
-            if (inf.w < c0 || inf.z >= c0 + kZC) continue;
-            const T* w = pw + (size_t)p * 32;
-            const T wm = w[dxi] * w[8 + dyi];
-            const T wd = w[16 + dxi] * w[24 + dyi];
-            if (wm == T(0) && wd == T(0)) continue;
-            const T* f = pf + (size_t)p * 8;
-            const T f0 = f[0] * wm, f1 = f[1] * wm, f2 = f[2] * wm;
-            const T t0 = f[4] * wd, t1 = f[5] * wd, t2 = f[6] * wd;
-            const T* ps = psi + (size_t)p * 2 * ZW;
 #pragma unroll
-            for (int s = 0; s < kZC; ++s) {
-              const int zi = c0 + s - inf.z;
-              if (zi >= 0 && zi < ZW) {
-                const T pm = ps[zi], pd = ps[ZW + zi];
-                acc[s][0] += f0 * pm; acc[s][1] += f1 * pm; acc[s][2] += f2 * pm;
-                acc[s][3] += t0 * pd; acc[s][4] += t1 * pd; acc[s][5] += t2 * pd;
-              }
+          for (int s = 0; s < ZC; ++s) {
+            const int j = c0 + s - inf.z;
+            if (j < 0 || j >= ZW) { pm[s] = T(0); pd[s] = T(0); }
+          }
+          int dx = a - inf.x + 3;
+          if (dx < 0) dx += dp.Nx; else if (dx >= dp.Nx) dx -= dp.Nx;
+          int dy = b - inf.y + 3;
+          if (dy < 0) dy += dp.Ny; else if (dy >= dp.Ny) dy -= dp.Ny;
+          const T* f = pf + (size_t)p * 8;
+          const T F0 = f[0], F1 = f[1], F2 = f[2];
+          const T G0 = f[4], G1 = f[5], G2 = f[6];
+          if (inside && dx >= 0 && dx <= 6 && dy >= 0 && dy <= 6) {
+            const T* w = pw + (size_t)p * 32;
+            const T wm = w[dx] * w[8 + dy];
+            const T wd = w[16 + dx] * w[24 + dy];
+            const T f0 = F0 * wm, f1 = F1 * wm, f2 = F2 * wm;
+            const T t0 = G0 * wd, t1 = G1 * wd, t2 = G2 * wd;
+#pragma unroll
+            for (int s = 0; s < ZC; ++s) {
+              acc[s][0] += f0 * pm[s]; acc[s][1] += f1 * pm[s]; acc[s][2] += f2 * pm[s];
+              acc[s][3] += t0 * pd[s]; acc[s][4] += t1 * pd[s]; acc[s][5] += t2 * pd[s];
             }
           }
         }
       }
     }
+    if (inside) {
 #pragma unroll
-    for (int s = 0; s < kZC; ++s) {
-      const int c = c0 + s;
-      if (c <= hi) {
+      for (int s = 0; s < ZC; ++s) {
+        const int c = c0 + s;
+        if (c <= zmax) {
 #pragma unroll
-        for (int ch = 0; ch < 6; ++ch)
-          grid[ch * chstride + c * plane + (size_t)b * dp.Nx + a] = acc[s][ch];
+          for (int ch = 0; ch < 6; ++ch)
+            grid[ch * chstride + c * plane + col] = acc[s][ch];
+        }
       }
     }
   }
@@ -254,22 +230,17 @@ k_spread_tiled(DevParams dp, const int* __restrict__ band,
 
 hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st) {
   if (!s->force_simple_spread) {
-    dim3 g((s->dp.Nx + kSpTX - 1) / kSpTX, (s->dp.Ny + kSpTY - 1) / kSpTY);
-    const size_t esz = s->mixed ? 4 : 8;
-    const size_t per = (36 + 2 * (size_t)s->dp.ZW) * esz;
-    int cap = (int)(98304 / per);        // at most 96 KiB of staged records
-    if (cap > 256) cap = 256;
-    const size_t lds = (size_t)cap * per;
+    dim3 g((s->dp.Nx + 4 * kPW - 1) / (4 * kPW), (s->dp.Ny + kPW - 1) / kPW);
     if (s->mixed)
-      hipLaunchKernelGGL(k_spread_tiled<float>, g, dim3(256), lds, st, s->dp,
-                         s->band, s->cell_start, s->pinfo, (const float*)s->pw,
-                         (const float*)s->pf, (const float*)s->psi,
-                         (float*)grid, cap);
+      hipLaunchKernelGGL((k_spread_wave<float, kSpreadZC>), g, dim3(256), 0, st,
+                         s->dp, s->band, s->cell_start, s->pinfo,
+                         (const float*)s->pw, (const float*)s->pf,
+                         (const float*)s->psi, (float*)grid);
     else
-      hipLaunchKernelGGL(k_spread_tiled<double>, g, dim3(256), lds, st, s->dp,
-                         s->band, s->cell_start, s->pinfo, (const double*)s->pw,
-                         (const double*)s->pf, (const double*)s->psi,
-                         (double*)grid, cap);
+      hipLaunchKernelGGL((k_spread_wave<double, kSpreadZC>), g, dim3(256), 0, st,
+                         s->dp, s->band, s->cell_start, s->pinfo,
+                         (const double*)s->pw, (const double*)s->pf,
+                         (const double*)s->psi, (double*)grid);
     return hipGetLastError();
   }
   dim3 block(128);

@@ -114,6 +114,15 @@ class Solver:
     STAGES = ("particles", "spread", "fft_forward", "columns", "fft_inverse",
               "interp")
 
+    VARIANTS = {"generic_fft": 0, "fft_rows_x": 1, "fft_rows_y": 2,
+                "simple_spread": 3, "simple_interp": 4, "generic_columns": 5,
+                "vector_dct": 6}
+
+    def set_variant(self, name, value):
+        """Select an alternative kernel (see fcmdp_set_variant)."""
+        L.check(L.lib().fcmdp_set_variant(self._h, self.VARIANTS[name], int(value)),
+                "fcmdp_set_variant")
+
     def set_profiling(self, enable=True):
         L.check(L.lib().fcmdp_set_profiling(self._h, int(bool(enable))),
                 "fcmdp_set_profiling")

@@ -217,3 +217,94 @@ def test_periodic_wrapping_of_inputs():
     U2, O2 = s.apply(_dev(shifted, "fp64"), _dev(F, "fp64"), _dev(T, "fp64"))
     assert rel_err(_np(U2), _np(U1)) < 1e-12
     assert rel_err(_np(O2), _np(O1)) < 1e-12
+
+
+# --- single-precision transforms over many factorisations --------------------
+# (row-owned kernels by default, the workgroup-per-row-batch kernels as the
+# "generic_fft" variant); one band plane, compared with numpy's FFT in FP64 on
+# the same float32-rounded input.
+FFT_SIZES = [(48, 48), (40, 56), (96, 26), (90, 1000), (1536, 1000),
+             (2176, 2176)]
+
+
+def _fft_box(nx, ny, nz=8):
+    h = 0.5
+    return Box("bw", nx * h, ny * h, 4.0, nx, ny, nz)
+
+
+@pytest.mark.parametrize("nx,ny", FFT_SIZES)
+def test_stage_fft_mixed_sizes(nx, ny):
+    box = _fft_box(nx, ny)
+    lo = hi = 3
+    nkx = nx // 2 + 1
+    print(f"[fft mixed] {nx}x{ny}", flush=True)
+    plane = workloads.random_array((6, ny, nx), 7).astype(np.float32)
+    grid = torch.zeros((6, box.Nz, ny, nx), dtype=torch.float32, device="cuda")
+    grid[:, lo] = torch.from_numpy(plane).cuda()
+    ref = np.transpose(np.fft.rfft2(plane.astype(np.float64), axes=(-2, -1)),
+                       (0, 2, 1))
+    sp = workloads.random_array((6, nkx, ny), 8, complex_=True).astype(np.complex64)
+    spec_in = torch.zeros((6, box.Nz, nkx, ny), dtype=torch.complex64, device="cuda")
+    spec_in[:, lo] = torch.from_numpy(sp).cuda()
+    refb = np.fft.irfft2(np.transpose(sp.astype(np.complex128), (0, 2, 1)),
+                         s=(ny, nx), axes=(-2, -1)) * (nx * ny)
+    s = _solver(box, "mixed", cap=16)
+    for generic in (0, 1):
+        s.set_variant("generic_fft", generic)
+        got = _np(s.stage_fft_forward(grid, lo, hi))
+        assert rel_err(got[:, lo], ref) < 2e-6, generic
+        back = _np(s.stage_fft_inverse(spec_in, lo, hi))
+        assert rel_err(back[:, lo], refb) < 2e-6, generic
+        # planes outside the band are neither read nor written
+        assert not np.any(back[:, lo + 1])
+
+
+@pytest.mark.parametrize("rows", [1, 2, 4, 8, 16])
+def test_stage_fft_mixed_rows_per_workgroup(rows):
+    nx, ny = 1536, 1000
+    box = _fft_box(nx, ny)
+    lo = hi = 2
+    print(f"[fft mixed rows] {rows}", flush=True)
+    plane = workloads.random_array((6, ny, nx), 9).astype(np.float32)
+    grid = torch.zeros((6, box.Nz, ny, nx), dtype=torch.float32, device="cuda")
+    grid[:, lo] = torch.from_numpy(plane).cuda()
+    s = _solver(box, "mixed", cap=16)
+    base = _np(s.stage_fft_forward(grid, lo, hi))
+    s.set_variant("fft_rows_x", rows)
+    s.set_variant("fft_rows_y", min(rows, 8))
+    got = _np(s.stage_fft_forward(grid, lo, hi))
+    # same butterflies in the same order: identical bits
+    assert np.array_equal(got, base)
+    with pytest.raises(Exception):
+        s.set_variant("fft_rows_x", 3)
+
+
+# --- full-size workloads against stored oracle values ------------------------
+# tests/golden/<name>_oracle_sample.npz holds the oracle's U and Omega of a
+# seeded 1% particle sample (written by tests/golden/make_fixtures.py, which
+# runs only the oracle).  The GPU runs the whole apply in the launch
+# configuration the benchmark times and is compared on that sample.
+GOLDEN = ["bw131k", "bw1m", "sc1m"]
+
+
+@pytest.mark.parametrize("name", GOLDEN)
+def test_apply_mixed_full_size_golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        f"{name}_oracle_sample.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle sample for {name}")
+    g = np.load(path)
+    wl = workloads.WORKLOADS[name]
+    pos, F, T = workloads.particles(name)
+    print(f"[golden] {name} N={len(pos)}", flush=True)
+    from paper_2210_01837_amd import Solver
+    s = Solver.from_box(wl.box, precision="mixed", max_particles=wl.n)
+    U, Om = s.apply(_dev(pos, "mixed"), _dev(F, "mixed"), _dev(T, "mixed"))
+    assert s.status() == (0, 0)
+    idx = g["index"]
+    assert np.array_equal(idx, workloads.subsample(name))
+    Ug, Og = _np(U)[idx], _np(Om)[idx]
+    assert rel_err(Ug, g["U"]) < 1e-5
+    assert rel_err(Og, g["Omega"]) < 1e-5
+    s.close()
