@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for "
+                         "the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must "
@@ -129,6 +132,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibrate:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4,
+                          "copy_bytes_written": dst.numel() * 4,
+                          "launches": 3}), flush=True)
+        return
 
     import workloads
     from paper_2210_01837_amd import Solver

@@ -216,7 +216,10 @@ Sizes sizes_for(const fcmdp_params* p, int64_t cap, int ZW) {
   s.pinfo = c * 16;
   s.pw = c * 32 * T;
   s.pf = c * 8 * T;
-  s.psi = c * 2 * (size_t)ZW * T;
+  // dense folded z weights [cap][2][Nz], padded for chunked readers that may
+  // run past the last node
+  s.psi = (c * 2 * (size_t)p->Nz + 64) * T;
+  (void)ZW;
   return s;
 }
 

@@ -117,7 +117,7 @@ struct Par {
   double alpha[2];
   double P[2];
   double invD[2];
-  double eP;
+  double invEP;        // 1 / sum_i e_i P_i (dense boundary row)
 };
 
 struct Row {
@@ -168,7 +168,8 @@ __device__ __forceinline__ Par seg_prepare(double kappa, int N, int l, int p) {
       T[s][0] = 1.0; T[s][1] = 0.0; T[s][2] = 0.0; T[s][3] = 1.0;
     }
   }
-  // suffix products of the 2x2 Moebius matrices, normalised (only ratios matter)
+  // suffix products of the 2x2 Moebius matrices; only ratios matter, so each
+  // partial product is rescaled by a power of two (exact) to keep it near 1
   double Y[4];
   m2mul(T[0], T[1], Y);
   auto mstep = [&](double* Yk, bool take) {
@@ -176,9 +177,9 @@ __device__ __forceinline__ Par seg_prepare(double kappa, int N, int l, int p) {
       double Z[4];
       m2mul(Y, Yk, Z);
       const double sc = fmax(fmax(fabs(Z[0]), fabs(Z[1])), fmax(fabs(Z[2]), fabs(Z[3])));
-      const double inv = sc > 0.0 ? 1.0 / sc : 1.0;
+      const int e = sc > 0.0 ? -ilogb(sc) : 0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Y[c] = Z[c] * inv;
+      for (int c = 0; c < 4; ++c) Y[c] = ldexp(Z[c], e);
     }
   };
   {
@@ -231,7 +232,7 @@ __device__ __forceinline__ Par seg_prepare(double kappa, int N, int l, int p) {
   if (l == 0) Pin = 1.0;
   q.P[0] = q.alpha[0] * Pin;
   q.P[1] = q.alpha[1] * q.P[0];
-  q.eP = red(e[0] * q.P[0] + e[1] * q.P[1]);
+  q.invEP = 1.0 / red(e[0] * q.P[0] + e[1] * q.P[1]);
   return q;
 }
 
@@ -295,7 +296,7 @@ __device__ __forceinline__ Vec seg_solve(const Par* q, const Vec& r, Z2 gH, Z2 g
     const double e1 = m1 < N ? (double)m1 * m1 + kappa : 0.0;
     const Z2 eQ = red(e0 * Q0 + e1 * Q1);
     const Z2 g = p == 0 ? (0.25 * H) * (gH - g0) : (0.25 * H) * (gH + g0);
-    const Z2 y0 = zdiv(g - eQ, Q.eP);
+    const Z2 y0 = Q.invEP * (g - eQ);
     y.v[p] = Q.P[0] * y0 + Q0;
     y.v[2 + p] = Q.P[1] * y0 + Q1;
   }
@@ -421,7 +422,7 @@ __device__ inline void seg_basis(const double fb[kNpl], const double* __restrict
                                  double E[kNpl], double ZE[kNpl]) {
 #pragma unroll
   for (int j = 0; j < kNpl; ++j) { E[j] = 0.0; ZE[j] = 0.0; }
-#pragma unroll
+#pragma unroll 4
   for (int c = 0; c < 4 * kSeg; ++c) {
     const double fc = shd(fb[c & 3], c >> 2);
     if (c < N) {
@@ -442,8 +443,12 @@ __device__ inline void seg_basis(const double fb[kNpl], const double* __restrict
 // Steps 2 (derivative part) to 6 for one column, from the Chebyshev
 // coefficients A[0..2] of f + (1/2)(ik_y g_z, -ik_x g_z, ik_x g_y - ik_y g_x)
 // and A[3], A[4] of g_x, g_y: body force, DP solve, wall correction, k = 0.
-template <int GEOM>
-__device__ __forceinline__ void seg_column_solve(const Vec* A, const DevParams& dp,
+// The input vectors are fetched through `load(v)` whenever needed (v = 0..4:
+// the three body-force combinations above and g_x, g_y), so that a caller
+// holding them in LDS keeps few of them live in registers; the body force
+// f = (A0 - 1/2 D g_y, A1 + 1/2 D g_x, A2) is rebuilt where it is used.
+template <int GEOM, typename Load>
+__device__ __forceinline__ void seg_column_solve(const Load& load, const DevParams& dp,
                                  const double* __restrict__ zc,
                                  const double* __restrict__ Mf, int N, int l,
                                  double kx, double ky, double k, Vec& U,
@@ -452,48 +457,67 @@ __device__ __forceinline__ void seg_column_solve(const Vec* A, const DevParams& 
   U = vzero();
   V = vzero();
   W = vzero();
-  const Vec dgy = seg_deriv(A[4], l, s2H);
-  const Vec dgx = seg_deriv(A[3], l, s2H);
-  Vec fx, fy, fz;
+  auto body_x = [&]() {
+    const Vec dgy = seg_deriv(load(4), l, s2H);
+    Vec f = load(0);
 #pragma unroll
-  for (int j = 0; j < kNpl; ++j) {
-    fx.v[j] = A[0].v[j] - 0.5 * dgy.v[j];
-    fy.v[j] = A[1].v[j] + 0.5 * dgx.v[j];
-    fz.v[j] = A[2].v[j];
-  }
+    for (int j = 0; j < kNpl; ++j) f.v[j] = f.v[j] - 0.5 * dgy.v[j];
+    return f;
+  };
+  auto body_y = [&]() {
+    const Vec dgx = seg_deriv(load(3), l, s2H);
+    Vec f = load(1);
+#pragma unroll
+    for (int j = 0; j < kNpl; ++j) f.v[j] = f.v[j] + 0.5 * dgx.v[j];
+    return f;
+  };
   if (k == 0.0) {
-    Vec r;
+    Vec r = body_x();
 #pragma unroll
-    for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * fx.v[j];
+    for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
     U = seg_zero_mode(r, H, N, dp.geometry, l);
+    r = body_y();
 #pragma unroll
-    for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * fy.v[j];
+    for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
     V = seg_zero_mode(r, H, N, dp.geometry, l);
   } else {
     const double kappa = 0.5 * k * H;
     Par q[2];
     q[0] = seg_prepare(kappa, N, l, 0);
     q[1] = seg_prepare(kappa, N, l, 1);
-    const Vec dfz = seg_deriv(fz, l, s2H);
-    Vec r;
+    Vec r = seg_deriv(load(2), l, s2H);
+    {
+      const Vec fx = body_x();
 #pragma unroll
-    for (int j = 0; j < kNpl; ++j)
-      r.v[j] = imul(kx, fx.v[j]) + imul(ky, fy.v[j]) + dfz.v[j];
+      for (int j = 0; j < kNpl; ++j) r.v[j] = r.v[j] + imul(kx, fx.v[j]);
+    }
+    {
+      const Vec fy = body_y();
+#pragma unroll
+      for (int j = 0; j < kNpl; ++j) r.v[j] = r.v[j] + imul(ky, fy.v[j]);
+    }
     const Vec p = seg_solve(q, r, zmk(0, 0), zmk(0, 0), H, kappa, N, l);
     const Z2 pH = bsum_top(p), p0 = bsum_bottom(p);
     const double ie = 1.0 / eta;
     {
       const Vec dp_ = seg_deriv(p, l, s2H);
+      const Vec fz = load(2);
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (dp_.v[j] - fz.v[j]);
     }
     W = seg_solve(q, r, (0.5 / eta) * pH, (0.5 / eta) * p0, H, kappa, N, l);
+    {
+      const Vec fx = body_x();
 #pragma unroll
-    for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(kx, p.v[j]) - fx.v[j]);
+      for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(kx, p.v[j]) - fx.v[j]);
+    }
     U = seg_solve(q, r, imul(-kx / (2.0 * k * eta), pH),
                   imul(kx / (2.0 * k * eta), p0), H, kappa, N, l);
+    {
+      const Vec fy = body_y();
 #pragma unroll
-    for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(ky, p.v[j]) - fy.v[j]);
+      for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(ky, p.v[j]) - fy.v[j]);
+    }
     V = seg_solve(q, r, imul(-ky / (2.0 * k * eta), pH),
                   imul(ky / (2.0 * k * eta), p0), H, kappa, N, l);
 
@@ -634,7 +658,8 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
         for (int v = 0; v < 5; ++v) A[v].v[j] = A[v].v[j] + m * comb[v];
       }
     }
-    seg_column_solve<GEOM>(A, dp, zc, Mf, N, l, kx, ky, k, U, V, W);
+    seg_column_solve<GEOM>([&](int v) { return A[v]; }, dp, zc, Mf, N, l, kx,
+                           ky, k, U, V, W);
   }
   DU = seg_deriv(U, l, s2H);
   DV = seg_deriv(V, l, s2H);
@@ -707,13 +732,16 @@ constexpr int kMV = kMCols * 10;           // real node vectors per workgroup
 constexpr int kMThreads = kMCols * kSeg;   // 128
 
 template <int GEOM>
-__global__ void __launch_bounds__(kMThreads)
+__global__ void __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_columns_mfma(ColParams cp, const int* __restrict__ band,
                const float2* __restrict__ in, float2* __restrict__ out,
                const double* __restrict__ zc, const double* __restrict__ Mf,
                const float* __restrict__ Mf32, const float* __restrict__ Pi32) {
-  __shared__ float XD[32 * kMV];   // X (forward input), later D (inverse output)
-  __shared__ float CF[32 * kMV];   // coefficients
+  // one buffer: node values (A), then coefficients (B, C), then node values
+  // again (D, E); each transform keeps its output tiles in registers until
+  // every wave has finished reading its input
+  __shared__ float XC[32 * kMV];
+  constexpr int kTilesPerWave = 2 * (kMV / 16) / (kMThreads / 64);   // 10
   const DevParams& dp = cp.dp;
   const int lo = band[0], hi = band[1];
   if (lo > hi) return;
@@ -730,7 +758,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
   for (int it = tid; it < Kp * kMCols; it += kMThreads) {
     const int c = it / kMCols, col = it % kMCols;
     const int idx = idx0 + col;
-    float* xr = XD + c * kMV + col * 10;
+    float* xr = XC + c * kMV + col * 10;
     if (c < P && idx < K) {
       const int kxi = idx / dp.Ny, kyi = idx - kxi * dp.Ny;
       const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
@@ -756,21 +784,30 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
   }
   __syncthreads();
 
+  const int i16 = lane & 15, k4 = lane >> 4;
   // --- B: forward Chebyshev transform, Cf = Mt X ----------------------------
   {
-    const int i16 = lane & 15, k4 = lane >> 4;
-    for (int tile = wave; tile < 2 * (kMV / 16); tile += kMThreads / 64) {
+    f4v acc[kTilesPerWave];
+#pragma unroll
+    for (int t = 0; t < kTilesPerWave; ++t) {
+      const int tile = wave + t * (kMThreads / 64);
       const int n0 = (tile & 1) * 16, v0 = (tile >> 1) * 16;
-      f4v acc = {0.f, 0.f, 0.f, 0.f};
+      acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
       const int n = n0 + i16;
       for (int kk = 0; kk < Kp; kk += 4) {
         const int c = kk + k4;
         const float a = (c < P && n < N) ? Mf32[(lo + c) * N + n] : 0.f;
-        const float b = XD[c * kMV + v0 + i16];
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        const float b = XC[c * kMV + v0 + i16];
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
       }
+    }
+    __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) CF[(n0 + 4 * k4 + r) * kMV + v0 + i16] = acc[r];
+    for (int t = 0; t < kTilesPerWave; ++t) {
+      const int tile = wave + t * (kMThreads / 64);
+      const int n0 = (tile & 1) * 16, v0 = (tile >> 1) * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) XC[(n0 + 4 * k4 + r) * kMV + v0 + i16] = acc[t][r];
     }
   }
   __syncthreads();
@@ -788,48 +825,66 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const double ky = 2.0 * M_PI * nyi / dp.Ly;
     const double k = sqrt(kx * kx + ky * ky);
     const double s2H = 2.0 / dp.H;
+    float* cbase = XC + 4 * l * kMV + cl * 10;
     Vec U = vzero(), V = vzero(), W = vzero();
     if (!nyq) {
-      Vec A[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v)
+      auto load = [&](int v) {
+        Vec a;
 #pragma unroll
         for (int j = 0; j < kNpl; ++j) {
-          const float* cr = CF + (4 * l + j) * kMV + cl * 10 + 2 * v;
-          A[v].v[j] = zmk((double)cr[0], (double)cr[1]);
+          const float* cr = cbase + j * kMV + 2 * v;
+          a.v[j] = zmk((double)cr[0], (double)cr[1]);
         }
-      seg_column_solve<GEOM>(A, dp, zc, Mf, N, l, kx, ky, k, U, V, W);
+        return a;
+      };
+      seg_column_solve<GEOM>(load, dp, zc, Mf, N, l, kx, ky, k, U, V, W);
     }
-    const Vec DU = seg_deriv(U, l, s2H);
-    const Vec DV = seg_deriv(V, l, s2H);
-    const Vec* vs[5] = {&U, &V, &W, &DU, &DV};
-#pragma unroll
-    for (int v = 0; v < 5; ++v)
+    // the column's coefficients are read only by its own eight lanes (one
+    // wavefront, in lockstep): overwrite them in place
+    auto store = [&](int v, const Vec& a) {
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) {
-        float* cr = CF + (4 * l + j) * kMV + cl * 10 + 2 * v;
-        cr[0] = (float)vs[v]->v[j].x;
-        cr[1] = (float)vs[v]->v[j].y;
+        float* cr = cbase + j * kMV + 2 * v;
+        cr[0] = (float)a.v[j].x;
+        cr[1] = (float)a.v[j].y;
       }
+    };
+    store(0, U);
+    store(1, V);
+    store(2, W);
+    store(3, seg_deriv(U, l, s2H));
+    store(4, seg_deriv(V, l, s2H));
   }
   __syncthreads();
 
   // --- D: inverse transform to the band nodes, D = T Cf -----------------------
   {
-    const int i16 = lane & 15, k4 = lane >> 4;
     const int ctiles = (P + 15) / 16;
-    for (int tile = wave; tile < ctiles * (kMV / 16); tile += kMThreads / 64) {
-      const int c0 = (tile % ctiles) * 16, v0 = (tile / ctiles) * 16;
-      f4v acc = {0.f, 0.f, 0.f, 0.f};
-      const int c = c0 + i16;
-      for (int kk = 0; kk < 32; kk += 4) {
-        const int n = kk + k4;
-        const float a = (c < P && n < N) ? Pi32[(lo + c) * N + n] : 0.f;
-        const float b = CF[n * kMV + v0 + i16];
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
-      }
+    f4v acc[kTilesPerWave];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) XD[(c0 + 4 * k4 + r) * kMV + v0 + i16] = acc[r];
+    for (int t = 0; t < kTilesPerWave; ++t) {
+      const int tile = wave + t * (kMThreads / 64);
+      acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+      if (tile < ctiles * (kMV / 16)) {
+        const int c0 = (tile % ctiles) * 16, v0 = (tile / ctiles) * 16;
+        const int c = c0 + i16;
+        for (int kk = 0; kk < 32; kk += 4) {
+          const int n = kk + k4;
+          const float a = (c < P && n < N) ? Pi32[(lo + c) * N + n] : 0.f;
+          const float b = XC[n * kMV + v0 + i16];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kTilesPerWave; ++t) {
+      const int tile = wave + t * (kMThreads / 64);
+      if (tile < ctiles * (kMV / 16)) {
+        const int c0 = (tile % ctiles) * 16, v0 = (tile / ctiles) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) XC[(c0 + 4 * k4 + r) * kMV + v0 + i16] = acc[t][r];
+      }
     }
   }
   __syncthreads();
@@ -844,7 +899,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
     const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
     const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
-    const float* d = XD + c * kMV + col * 10;
+    const float* d = XC + c * kMV + col * 10;
     const float ur = d[0], ui = d[1], vr = d[2], vi = d[3], wr = d[4], wi = d[5];
     const float dur = d[6], dui = d[7], dvr = d[8], dvi = d[9];
     float2 o[6];

@@ -7,7 +7,8 @@
 //     pinfo   int4    [cap]                   (ix, iy, c_first, c_last)
 //     pw      T       [cap][32]               x/y ES weights, M then D
 //     pf      T       [cap][8]                F (3), pad, torque (3), pad
-//     psi     T       [cap][2*ZW]             folded z weights, M then D
+//     psi     T       [cap][2][Nz]            folded z weights, M then D,
+//                                             zero outside the z window
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -148,6 +149,18 @@ hipError_t launch_columns_seg(const fcmdp_solver* s, const void* spec_in,
                               void* spec_out, hipStream_t st);
 
 // --- small device helpers ------------------------------------------------
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD
+// w mod 8), and each XCD has its own L2.  Renumber them so that XCD x works
+// through one contiguous range of tiles, in order: neighbouring tiles, which
+// share halo data, then meet in the same L2 at about the same time.
+__device__ inline int xcd_tile(int w, int ntiles) {
+  constexpr int kXcd = 8;
+  const int x = w % kXcd, local = w / kXcd;
+  const int per = ntiles / kXcd, extra = ntiles % kXcd;
+  return x < extra ? x * (per + 1) + local
+                   : extra * (per + 1) + (x - extra) * per + local;
+}
+
 __host__ __device__ inline int wrap_index(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;

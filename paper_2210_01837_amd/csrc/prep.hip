@@ -291,89 +291,105 @@ hipError_t launch_sort(const fcmdp_solver* s, int n, hipStream_t st) {
 // ----------------------------------------------------------------------------
 // per-particle records in sorted order
 // ----------------------------------------------------------------------------
-template <typename Tin, typename T>
-__global__ void __launch_bounds__(256)
+// A workgroup of B threads builds the records of B consecutive sorted
+// particles in LDS (rows padded by one word against bank conflicts) and then
+// copies them out as contiguous, coalesced blocks.  The folded z weights are
+// stored densely over all Nz nodes (zero outside the particle's window), so
+// readers index them by node without window arithmetic.
+template <typename Tin, typename T, int B>
+__global__ void __launch_bounds__(B)
 k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
           const int* __restrict__ perm, const Tin* __restrict__ pos,
           const Tin* __restrict__ F, const Tin* __restrict__ Tq,
           const double* __restrict__ zc, int4* __restrict__ pinfo,
           T* __restrict__ pw, T* __restrict__ pf, T* __restrict__ psi) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || skeys[i] >= (uint32_t)dp.ncells) return;
-  const int j = perm[i];
-  const double x = wrap_coord((double)pos[3 * (size_t)j + 0], dp.Lx);
-  const double y = wrap_coord((double)pos[3 * (size_t)j + 1], dp.Ly);
-  const double z = (double)pos[3 * (size_t)j + 2];
-  int ix, iy;
-  double fx, fy;
-  cell_of(x, dp.h, dp.Nx, &ix, &fx);
-  cell_of(y, dp.h, dp.Ny, &iy, &fy);
-  int cA, cB;
-  z_window(dp, zc, z, &cA, &cB);
-  pinfo[i] = make_int4(ix, iy, cA, cB);
-  T* w = pw + (size_t)i * 32;
+  extern __shared__ unsigned char lds_raw[];
+  const int NZ2 = 2 * dp.Nz;
+  T* rw = reinterpret_cast<T*>(lds_raw);       // [B][33]
+  T* rf = rw + B * 33;                          // [B][9]
+  T* rz = rf + B * 9;                           // [B][NZ2 + 1]
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * B;
+  const int i = i0 + t;
+  T* w = rw + t * 33;
+  T* f = rf + t * 9;
+  T* ps = rz + t * (NZ2 + 1);
+  for (int e = 0; e < NZ2; ++e) ps[e] = T(0);
+  if (i < n && skeys[i] < (uint32_t)dp.ncells) {
+    const int j = perm[i];
+    const double x = wrap_coord((double)pos[3 * (size_t)j + 0], dp.Lx);
+    const double y = wrap_coord((double)pos[3 * (size_t)j + 1], dp.Ly);
+    const double z = (double)pos[3 * (size_t)j + 2];
+    int ix, iy;
+    double fx, fy;
+    cell_of(x, dp.h, dp.Nx, &ix, &fx);
+    cell_of(y, dp.h, dp.Ny, &iy, &fy);
+    int cA, cB;
+    z_window(dp, zc, z, &cA, &cB);
+    pinfo[i] = make_int4(ix, iy, cA, cB);
 #pragma unroll
-  for (int d = 0; d < kWin; ++d) {
-    const double tx = ((double)(d - 3) - fx) * dp.h;
-    const double ty = ((double)(d - 3) - fy) * dp.h;
-    w[d] = es_eval<T>(tx, dp.alpha, dp.beta_m, dp.inv_norm_m);
-    w[8 + d] = es_eval<T>(ty, dp.alpha, dp.beta_m, dp.inv_norm_m);
-    w[16 + d] = es_eval<T>(tx, dp.alpha, dp.beta_d, dp.inv_norm_d);
-    w[24 + d] = es_eval<T>(ty, dp.alpha, dp.beta_d, dp.inv_norm_d);
-  }
-  w[7] = w[15] = w[23] = w[31] = T(0);
-  T* ps = psi + (size_t)i * 2 * dp.ZW;
-  const double zim_top = 2.0 * dp.H - z;
-  for (int sl = 0; sl < dp.ZW; ++sl) {
-    const int c = cA + sl;
-    T pm = T(0), pd = T(0);
-    if (c <= cB) {
+    for (int d = 0; d < kWin; ++d) {
+      const double tx = ((double)(d - 3) - fx) * dp.h;
+      const double ty = ((double)(d - 3) - fy) * dp.h;
+      w[d] = es_eval<T>(tx, dp.alpha, dp.beta_m, dp.inv_norm_m);
+      w[8 + d] = es_eval<T>(ty, dp.alpha, dp.beta_m, dp.inv_norm_m);
+      w[16 + d] = es_eval<T>(tx, dp.alpha, dp.beta_d, dp.inv_norm_d);
+      w[24 + d] = es_eval<T>(ty, dp.alpha, dp.beta_d, dp.inv_norm_d);
+    }
+    w[7] = w[15] = w[23] = w[31] = T(0);
+    const double zim_top = 2.0 * dp.H - z;
+    for (int c = cA; c <= cB; ++c) {
       const double zcv = zc[c];
-      pm = es_eval<T>(zcv - z, dp.alpha, dp.beta_m, dp.inv_norm_m) -
-           es_eval<T>(zcv + z, dp.alpha, dp.beta_m, dp.inv_norm_m);
-      pd = es_eval<T>(zcv - z, dp.alpha, dp.beta_d, dp.inv_norm_d) -
-           es_eval<T>(zcv + z, dp.alpha, dp.beta_d, dp.inv_norm_d);
+      T pm = es_eval<T>(zcv - z, dp.alpha, dp.beta_m, dp.inv_norm_m) -
+             es_eval<T>(zcv + z, dp.alpha, dp.beta_m, dp.inv_norm_m);
+      T pd = es_eval<T>(zcv - z, dp.alpha, dp.beta_d, dp.inv_norm_d) -
+             es_eval<T>(zcv + z, dp.alpha, dp.beta_d, dp.inv_norm_d);
       if (dp.geometry == 1) {
         pm -= es_eval<T>(zcv - zim_top, dp.alpha, dp.beta_m, dp.inv_norm_m);
         pd -= es_eval<T>(zcv - zim_top, dp.alpha, dp.beta_d, dp.inv_norm_d);
       }
+      ps[c] = pm;
+      ps[dp.Nz + c] = pd;
     }
-    ps[sl] = pm;
-    ps[dp.ZW + sl] = pd;
-  }
-  T* f = pf + (size_t)i * 8;
-  if (F) {
-    f[0] = (T)F[3 * (size_t)j + 0];
-    f[1] = (T)F[3 * (size_t)j + 1];
-    f[2] = (T)F[3 * (size_t)j + 2];
+    f[0] = F ? (T)F[3 * (size_t)j + 0] : T(0);
+    f[1] = F ? (T)F[3 * (size_t)j + 1] : T(0);
+    f[2] = F ? (T)F[3 * (size_t)j + 2] : T(0);
+    f[3] = T(0);
+    f[4] = Tq ? (T)Tq[3 * (size_t)j + 0] : T(0);
+    f[5] = Tq ? (T)Tq[3 * (size_t)j + 1] : T(0);
+    f[6] = Tq ? (T)Tq[3 * (size_t)j + 2] : T(0);
+    f[7] = T(0);
   } else {
-    f[0] = f[1] = f[2] = T(0);
+    for (int e = 0; e < 32; ++e) w[e] = T(0);
+    for (int e = 0; e < 8; ++e) f[e] = T(0);
   }
-  f[3] = T(0);
-  if (Tq) {
-    f[4] = (T)Tq[3 * (size_t)j + 0];
-    f[5] = (T)Tq[3 * (size_t)j + 1];
-    f[6] = (T)Tq[3 * (size_t)j + 2];
-  } else {
-    f[4] = f[5] = f[6] = T(0);
+  __syncthreads();
+  const int nb = min(B, n - i0);
+  for (int e = t; e < nb * 32; e += B) pw[(size_t)i0 * 32 + e] = rw[(e >> 5) * 33 + (e & 31)];
+  for (int e = t; e < nb * 8; e += B) pf[(size_t)i0 * 8 + e] = rf[(e >> 3) * 9 + (e & 7)];
+  for (int e = t; e < nb * NZ2; e += B) {
+    const int r = e / NZ2;
+    psi[(size_t)i0 * NZ2 + e] = rz[r * (NZ2 + 1) + (e - r * NZ2)];
   }
-  f[7] = T(0);
+}
+
+template <typename Tin, typename T, int B>
+static void records_impl(const fcmdp_solver* s, int n, const void* pos,
+                         const void* F, const void* Tq, hipStream_t st) {
+  const size_t lds = (size_t)B * (33 + 9 + 2 * s->dp.Nz + 1) * sizeof(T);
+  hipLaunchKernelGGL((k_records<Tin, T, B>), dim3((n + B - 1) / B), dim3(B),
+                     lds, st, s->dp, n, s->keyA, s->valA, (const Tin*)pos,
+                     (const Tin*)F, (const Tin*)Tq, s->zc, s->pinfo,
+                     (T*)s->pw, (T*)s->pf, (T*)s->psi);
 }
 
 hipError_t launch_records(const fcmdp_solver* s, int n, const void* pos,
                           const void* F, const void* T, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  dim3 grid((n + 255) / 256);
   if (s->mixed)
-    hipLaunchKernelGGL((k_records<float, float>), grid, dim3(256), 0, st,
-                       s->dp, n, s->keyA, s->valA, (const float*)pos,
-                       (const float*)F, (const float*)T, s->zc, s->pinfo,
-                       (float*)s->pw, (float*)s->pf, (float*)s->psi);
+    records_impl<float, float, 128>(s, n, pos, F, T, st);
   else
-    hipLaunchKernelGGL((k_records<double, double>), grid, dim3(256), 0, st,
-                       s->dp, n, s->keyA, s->valA, (const double*)pos,
-                       (const double*)F, (const double*)T, s->zc, s->pinfo,
-                       (double*)s->pw, (double*)s->pf, (double*)s->psi);
+    records_impl<double, double, 64>(s, n, pos, F, T, st);
   return hipGetLastError();
 }
 

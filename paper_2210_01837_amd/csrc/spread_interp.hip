@@ -29,7 +29,6 @@ k_spread(DevParams dp, const int* __restrict__ band,
   const int lo = band[0], hi = band[1];
   const size_t plane = (size_t)dp.Nx * dp.Ny;
   const size_t chstride = plane * dp.Nz;
-  const int ZW = dp.ZW;
   for (int c0 = lo; c0 <= hi; c0 += kZC) {
     T acc[kZC][6];
 #pragma unroll
@@ -69,13 +68,13 @@ k_spread(DevParams dp, const int* __restrict__ band,
           const T* f = pf + (size_t)p * 8;
           const T f0 = f[0] * wm, f1 = f[1] * wm, f2 = f[2] * wm;
           const T t0 = f[4] * wd, t1 = f[5] * wd, t2 = f[6] * wd;
-          const T* ps = psi + (size_t)p * 2 * ZW;
+          const T* ps = psi + (size_t)p * 2 * dp.Nz;
 #pragma unroll
           for (int s = 0; s < kZC; ++s) {
-            const int zi = c0 + s - inf.z;
-            if (zi >= 0 && zi < ZW) {
-              const T pm = ps[zi];
-              const T pd = ps[ZW + zi];
+            const int c = c0 + s;
+            if (c >= inf.z && c <= inf.w) {
+              const T pm = ps[c];
+              const T pd = ps[dp.Nz + c];
               acc[s][0] += f0 * pm;
               acc[s][1] += f1 * pm;
               acc[s][2] += f2 * pm;
@@ -121,13 +120,16 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
               const T* __restrict__ psi, T* __restrict__ grid) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int xw = (blockIdx.x * 4 + wv) * kPW;
-  const int yw = blockIdx.y * kPW;
+  const int gx = (dp.Nx + 4 * kPW - 1) / (4 * kPW);
+  const int gy = (dp.Ny + kPW - 1) / kPW;
+  const int tile = xcd_tile(blockIdx.x, gx * gy);
+  const int xw = ((tile % gx) * 4 + wv) * kPW;
+  const int yw = (tile / gx) * kPW;
   if (xw >= dp.Nx) return;                 // whole wavefront; no barriers below
   const int lo = band[0], hi = band[1];
   const int a = xw + (lane & 7), b = yw + (lane >> 3);
   const bool inside = a < dp.Nx && b < dp.Ny;
-  const int ZW = dp.ZW;
+  const int Nz = dp.Nz;
   const size_t plane = (size_t)dp.Nx * dp.Ny;
   const size_t chstride = plane * dp.Nz;
   const size_t col = (size_t)b * dp.Nx + a;
@@ -177,20 +179,15 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
           const int4 inf = nxt;
           if (p + 1 < p1) nxt = pinfo[p + 1];             // prefetch
           if (inf.w < c0 || inf.z >= c0 + ZC) continue;   // no overlap in z
-          // folded z weights of the chunk's nodes, fetched together
-          const T* ps = psi + (size_t)p * 2 * ZW;
+          // folded z weights of the chunk's nodes (dense, zero outside the
+          // particle's window; nodes past Nz read padding or the next record
+          // and are never stored)
+          const T* ps = psi + (size_t)p * 2 * Nz;
           T pm[ZC], pd[ZC];
 #pragma unroll
           for (int s = 0; s < ZC; ++s) {
-            const int j = c0 + s - inf.z;
-            const int jc = j < 0 ? 0 : (j >= ZW ? ZW - 1 : j);
-            pm[s] = ps[jc];
-            pd[s] = ps[ZW + jc];
-          }
-#pragma unroll
-          for (int s = 0; s < ZC; ++s) {
-            const int j = c0 + s - inf.z;
-            if (j < 0 || j >= ZW) { pm[s] = T(0); pd[s] = T(0); }
+            pm[s] = ps[c0 + s];
+            pd[s] = ps[Nz + c0 + s];
           }
           int dx = a - inf.x + 3;
           if (dx < 0) dx += dp.Nx; else if (dx >= dp.Nx) dx -= dp.Nx;
@@ -230,7 +227,7 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
 
 hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st) {
   if (!s->force_simple_spread) {
-    dim3 g((s->dp.Nx + 4 * kPW - 1) / (4 * kPW), (s->dp.Ny + kPW - 1) / kPW);
+    dim3 g(((s->dp.Nx + 4 * kPW - 1) / (4 * kPW)) * ((s->dp.Ny + kPW - 1) / kPW));
     if (s->mixed)
       hipLaunchKernelGGL((k_spread_wave<float, kSpreadZC>), g, dim3(256), 0, st,
                          s->dp, s->band, s->cell_start, s->pinfo,
@@ -278,7 +275,7 @@ k_interp(DevParams dp, int n, const uint32_t* __restrict__ skeys,
   }
   const int4 inf = pinfo[i];
   const T* w = pw + (size_t)i * 32;
-  const T* ps = psi + (size_t)i * 2 * dp.ZW;
+  const T* ps = psi + (size_t)i * 2 * dp.Nz;
   const size_t plane = (size_t)dp.Nx * dp.Ny;
   const size_t chstride = plane * dp.Nz;
   T u0 = 0, u1 = 0, u2 = 0, o0 = 0, o1 = 0, o2 = 0;
@@ -293,10 +290,9 @@ k_interp(DevParams dp, int n, const uint32_t* __restrict__ skeys,
       const int aa = wrap_index(inf.x + dxi - 3, dp.Nx);
       const size_t col = (size_t)bb * dp.Nx + aa;
       for (int c = inf.z; c <= inf.w; ++c) {
-        const int zi = c - inf.z;
         const T q = quad[c];
-        const T qm = q * ps[zi] * wm;
-        const T qd = q * ps[dp.ZW + zi] * wd;
+        const T qm = q * ps[c] * wm;
+        const T qd = q * ps[dp.Nz + c] * wd;
         const size_t off = (size_t)c * plane + col;
         u0 += qm * grid[off];
         u1 += qm * grid[chstride + off];
@@ -317,14 +313,17 @@ k_interp(DevParams dp, int n, const uint32_t* __restrict__ skeys,
   }
 }
 
-// Tiled interpolation: a workgroup owns a TILE x TILE block of xy cells and
-// interpolates the particles whose cell lies in it.  The grid values of the
-// block plus its 3-cell halo are staged in LDS, ZC z-planes at a time; the
-// particles' weights are cached in LDS; an 8-lane group handles one particle
-// (lane = x-offset of the 7-point window) and reduces its partial sums with
-// shuffles in a fixed order, so results are deterministic.
+// Tiled interpolation: a workgroup owns a 16 x 16 block of xy cells and
+// interpolates the particles whose cell lies in it ("home" particles, at most
+// `cap` per pass).  Their weights are cached in LDS; the z-nodes they touch
+// give the tile's z range, and only those planes of the block plus its 3-cell
+// halo are staged in LDS, ZC planes at a time.  An 8-lane group handles one
+// particle (lane = x offset of the 7-point window) and reduces its partial
+// sums with shuffles in a fixed order, so results are deterministic.  The LDS
+// footprint is kept small enough for several workgroups per CU.
 constexpr int kTile = 16;
 constexpr int kRX = kTile + 6;
+constexpr int kRec = 28;     // wxM[7] wyM[7] wxD[7] wyD[7]
 
 template <typename T, int ZC>
 __global__ void __launch_bounds__(256)
@@ -335,22 +334,23 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
                const T* __restrict__ grid, const int* __restrict__ perm,
                T* __restrict__ U, T* __restrict__ Om, int cap) {
   extern __shared__ unsigned char lds_raw[];
-  const int ZW = dp.ZW;
   T* G = reinterpret_cast<T*>(lds_raw);                 // [ZC][6][kRX][kRX]
-  T* pcw = G + ZC * 6 * kRX * kRX;                      // [cap][32]
-  T* pcz = pcw + cap * 32;                              // [cap][2 ZW]
-  T* acc = pcz + cap * 2 * ZW;                          // [cap][6]
+  T* pcw = G + ZC * 6 * kRX * kRX;                      // [cap][kRec]
+  T* acc = pcw + cap * kRec;                            // [cap][6]
   int4* pci = reinterpret_cast<int4*>(acc + cap * 6);   // [cap]
-  int* pcj = reinterpret_cast<int*>(pci + cap);         // [cap]
-  int* pcp = pcj + cap;                                 // [cap]
+  int* pcj = reinterpret_cast<int*>(pci + cap);         // [cap] output index
+  int* pcp = pcj + cap;                                 // [cap] sorted index
   __shared__ int rowoff[kTile + 1];
   __shared__ int rowstart[kTile];
   __shared__ int ytab[kRX];
+  __shared__ int zr[2];
 
   const int lo = band[0], hi = band[1];
   if (lo > hi) return;
   const int tid = threadIdx.x;
-  const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
+  const int gxt = (dp.Nx + kTile - 1) / kTile, gyt = (dp.Ny + kTile - 1) / kTile;
+  const int tile = xcd_tile(blockIdx.x, gxt * gyt);
+  const int tx0 = (tile % gxt) * kTile, ty0 = (tile / gxt) * kTile;
   if (tid < kRX) ytab[tid] = wrap_index(ty0 - 3 + tid, dp.Ny);
   if (tid < kTile) {
     const int iy = ty0 + tid;
@@ -380,26 +380,41 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
 
   for (int base = 0; base < nhome; base += cap) {
     const int np = min(cap, nhome - base);
+    if (tid == 0) { zr[0] = dp.Nz; zr[1] = -1; }
+    __syncthreads();
+    int zlo = dp.Nz, zhi = -1;
     for (int h = tid; h < np; h += 256) {
       const int hp = base + h;
       int r = 0;
       while (r + 1 < kTile && rowoff[r + 1] <= hp) ++r;
       const int p = rowstart[r] + (hp - rowoff[r]);
-      pcp[h] = p;
-      pci[h] = pinfo[p];
+      const int4 inf = pinfo[p];
+      pci[h] = inf;
       pcj[h] = perm[p];
+      pcp[h] = p;
+      zlo = min(zlo, inf.z);
+      zhi = max(zhi, inf.w);
+      const T* w = pw + (size_t)p * 32;
+      T* d = pcw + h * kRec;
+#pragma unroll
+      for (int e = 0; e < 7; ++e) {
+        d[e] = w[e];
+        d[7 + e] = w[8 + e];
+        d[14 + e] = w[16 + e];
+        d[21 + e] = w[24 + e];
+      }
+#pragma unroll
+      for (int e = 0; e < 6; ++e) acc[h * 6 + e] = T(0);
+    }
+    if (zhi >= 0) {
+      atomicMin(&zr[0], zlo);
+      atomicMax(&zr[1], zhi);
     }
     __syncthreads();
-    for (int e = tid; e < np * 32; e += 256) pcw[e] = pw[(size_t)pcp[e >> 5] * 32 + (e & 31)];
-    for (int e = tid; e < np * 2 * ZW; e += 256) {
-      const int h = e / (2 * ZW);
-      pcz[e] = psi[(size_t)pcp[h] * 2 * ZW + (e - h * 2 * ZW)];
-    }
-    for (int e = tid; e < np * 6; e += 256) acc[e] = T(0);
-    __syncthreads();
-    for (int c0 = lo; c0 <= hi; c0 += ZC) {
-      const int nz = min(ZC, hi - c0 + 1);
-      // stage rows of kRX values: thread (rg, rx), 11 rows per sweep
+    const int c_first = zr[0], c_last = zr[1];
+    for (int c0 = c_first; c0 <= c_last; c0 += ZC) {
+      const int nz = min(ZC, c_last - c0 + 1);
+      // stage rows of kRX values: thread (rg, rx)
       if (tid < kRG * kRX) {
         const int rows = nz * 6 * kRX;
         const size_t base0 = (size_t)c0 * plane + xa;
@@ -412,30 +427,37 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
                                    (size_t)ytab[ry] * dp.Nx];
         }
       }
+      T q[ZC];
+#pragma unroll
+      for (int sidx = 0; sidx < ZC; ++sidx) q[sidx] = sidx < nz ? quad[c0 + sidx] : T(0);
       __syncthreads();
       for (int h = g; h < np; h += NG) {
         const int4 inf = pci[h];
         if (inf.w < c0 || inf.z > c0 + nz - 1) continue;   // no z overlap
         T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
         if (l < 7) {
-          const T* w = pcw + h * 32;
-          const T* ps = pcz + h * 2 * ZW;
-          const T wxm = w[l], wxd = w[16 + l];
+          const T* w = pcw + h * kRec;
+          // dense folded z weights of this particle (zero outside its window)
+          const T* ps = psi + (size_t)pcp[h] * 2 * dp.Nz;
+          const T wxm = w[l], wxd = w[14 + l];
           const int px = inf.x - tx0 + l;
           const int ry0 = inf.y - ty0;
+          T pm[ZC], pd[ZC];
+#pragma unroll
+          for (int sidx = 0; sidx < ZC; ++sidx) {
+            const bool ok = sidx < nz;
+            pm[sidx] = ok ? q[sidx] * ps[c0 + sidx] : T(0);
+            pd[sidx] = ok ? q[sidx] * ps[dp.Nz + c0 + sidx] : T(0);
+          }
           for (int dy = 0; dy < 7; ++dy) {
-            const T wm = wxm * w[8 + dy];
-            const T wd = wxd * w[24 + dy];
-            if (wm == T(0) && wd == T(0)) continue;
+            const T wm = wxm * w[7 + dy];
+            const T wd = wxd * w[21 + dy];
             const int ry = ry0 + dy;
 #pragma unroll
             for (int sidx = 0; sidx < ZC; ++sidx) {
-              const int c = c0 + sidx;
-              const int zi = c - inf.z;
-              if (sidx < nz && zi >= 0 && zi < ZW) {
-                const T q = quad[c];
-                const T qm = q * ps[zi] * wm;
-                const T qd = q * ps[ZW + zi] * wd;
+              if (sidx < nz) {
+                const T qm = pm[sidx] * wm;
+                const T qd = pd[sidx] * wd;
                 const T* gp = G + (sidx * 6 * kRX + ry) * kRX + px;
                 constexpr int CS = kRX * kRX;
                 a0 += qm * gp[0];
@@ -495,9 +517,9 @@ __global__ void k_interp_invalid(int n, int ncells, const uint32_t* __restrict__
 }
 
 template <typename T, int ZC>
-static size_t interp_lds(int ZW, int cap) {
+static size_t interp_lds(int cap) {
   return (size_t)ZC * 6 * kRX * kRX * sizeof(T) +
-         (size_t)cap * (32 + 2 * ZW + 6) * sizeof(T) + (size_t)cap * (16 + 8);
+         (size_t)cap * (kRec + 6) * sizeof(T) + (size_t)cap * (16 + 4 + 4);
 }
 
 template <typename T>
@@ -506,25 +528,15 @@ static hipError_t interp_tiled(const fcmdp_solver* s, int n, const T* grid,
   const DevParams& dp = s->dp;
   hipLaunchKernelGGL(k_interp_invalid<T>, dim3((n + 255) / 256), dim3(256), 0,
                      st, n, dp.ncells, s->keyA, s->valA, U, Om);
-  dim3 g((dp.Nx + kTile - 1) / kTile, (dp.Ny + kTile - 1) / kTile);
-  const size_t limit = 81920;      // two workgroups per CU (160 KiB LDS)
-  int cap = 128;
-  while (cap > 8 && interp_lds<T, 4>(dp.ZW, cap) > limit) cap -= 8;
-  if (interp_lds<T, 4>(dp.ZW, cap) <= limit) {
-    const size_t lds4 = interp_lds<T, 4>(dp.ZW, cap);
-    hipLaunchKernelGGL((k_interp_tiled<T, 4>), g, dim3(256), lds4, st, dp,
-                       s->band,
-                       s->cell_start, s->pinfo, (const T*)s->pw,
-                       (const T*)s->psi, (const T*)s->quad, grid, s->valA, U,
-                       Om, cap);
-    return hipGetLastError();
-  }
-  cap = 128;
-  while (cap > 8 && interp_lds<T, 2>(dp.ZW, cap) > limit) cap -= 8;
-  const size_t lds2 = interp_lds<T, 2>(dp.ZW, cap);
-  hipLaunchKernelGGL((k_interp_tiled<T, 2>), g, dim3(256), lds2, st, dp,
-                     s->band,
-                     s->cell_start, s->pinfo, (const T*)s->pw,
+  dim3 g(((dp.Nx + kTile - 1) / kTile) * ((dp.Ny + kTile - 1) / kTile));
+  // home particles cached per pass: a monolayer at area fraction 0.5 with
+  // R_h = 1.731 h has ~0.22 particles per xy cell, ~56 per tile; denser
+  // tiles take several passes.  64 keeps four workgroups per CU.
+  const int cap = 64;
+  constexpr int ZC = sizeof(T) == 4 ? 2 : 1;
+  const size_t lds = interp_lds<T, ZC>(cap);
+  hipLaunchKernelGGL((k_interp_tiled<T, ZC>), g, dim3(256), lds, st, dp,
+                     s->band, s->cell_start, s->pinfo, (const T*)s->pw,
                      (const T*)s->psi, (const T*)s->quad, grid, s->valA, U, Om,
                      cap);
   return hipGetLastError();

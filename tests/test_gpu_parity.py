@@ -284,20 +284,34 @@ def test_stage_fft_mixed_rows_per_workgroup(rows):
 # seeded 1% particle sample (written by tests/golden/make_fixtures.py, which
 # runs only the oracle).  The GPU runs the whole apply in the launch
 # configuration the benchmark times and is compared on that sample.
-GOLDEN = ["bw131k", "bw1m", "sc1m"]
+#
+# Mixed-precision tolerance: the grids are FP32, so every grid value carries a
+# relative rounding error ~6e-8 of its own size.  In these monolayers every
+# particle sediments with F_z ~ -1, so the grid is dominated by the uniform
+# layer while the velocities come from its fluctuations, about sqrt(N) times
+# smaller: the relative error grows like 6e-8 * sqrt(N) * c.  Above one wall
+# (bw1m) c is small (measured 1.8e-6); between two walls the flow driven by
+# the fluctuations is screened beyond the gap H and c is large (measured
+# 7.8e-5 at N = 1M, insensitive to the FFT, DCT, spread and interpolation
+# variants; the FP64 path gives 3.6e-8).  Hence 2e-4 for sc1m.
+GOLDEN = {"bw131k": 1e-5, "bw1m": 1e-5, "sc1m": 2e-4}
 
 
-@pytest.mark.parametrize("name", GOLDEN)
-def test_apply_mixed_full_size_golden(name):
+def _golden(name):
     import os
     path = os.path.join(os.path.dirname(__file__), "golden",
                         f"{name}_oracle_sample.npz")
     if not os.path.exists(path):
         pytest.skip(f"no stored oracle sample for {name}")
-    g = np.load(path)
+    return np.load(path)
+
+
+@pytest.mark.parametrize("name", list(GOLDEN))
+def test_apply_mixed_full_size_golden(name):
+    g = _golden(name)
     wl = workloads.WORKLOADS[name]
     pos, F, T = workloads.particles(name)
-    print(f"[golden] {name} N={len(pos)}", flush=True)
+    print(f"[golden mixed] {name} N={len(pos)}", flush=True)
     from paper_2210_01837_amd import Solver
     s = Solver.from_box(wl.box, precision="mixed", max_particles=wl.n)
     U, Om = s.apply(_dev(pos, "mixed"), _dev(F, "mixed"), _dev(T, "mixed"))
@@ -305,6 +319,24 @@ def test_apply_mixed_full_size_golden(name):
     idx = g["index"]
     assert np.array_equal(idx, workloads.subsample(name))
     Ug, Og = _np(U)[idx], _np(Om)[idx]
-    assert rel_err(Ug, g["U"]) < 1e-5
-    assert rel_err(Og, g["Omega"]) < 1e-5
+    assert rel_err(Ug, g["U"]) < GOLDEN[name]
+    assert rel_err(Og, g["Omega"]) < GOLDEN[name]
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["bw1m", "sc1m"])
+def test_apply_fp64_full_size_golden(name):
+    # measured 6e-9 (bw1m) and 4e-8 (sc1m)
+    g = _golden(name)
+    wl = workloads.WORKLOADS[name]
+    pos, F, T = workloads.particles(name)
+    print(f"[golden fp64] {name} N={len(pos)}", flush=True)
+    from paper_2210_01837_amd import Solver
+    s = Solver.from_box(wl.box, precision="fp64", max_particles=wl.n)
+    U, Om = s.apply(_dev(pos, "fp64"), _dev(F, "fp64"), _dev(T, "fp64"))
+    assert s.status() == (0, 0)
+    idx = g["index"]
+    Ug, Og = _np(U)[idx], _np(Om)[idx]
+    assert rel_err(Ug, g["U"]) < 1e-6
+    assert rel_err(Og, g["Omega"]) < 1e-6
     s.close()
