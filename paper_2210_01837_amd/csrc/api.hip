@@ -334,8 +334,13 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
     // stages do not fit the register budget of a 1024-thread workgroup)
     s->wave_x = fp32 && make_wave_plan(p->Nx / 2, fp32, &s->wplan_x, &s->tpr_x);
     s->wave_y = fp32 && make_wave_plan(p->Ny, fp32, &s->wplan_y, &s->tpr_y);
-    s->rows_x = rows_fitting((size_t)(p->Nx / 2 + 1) * csz, 16);
-    s->rows_y = rows_fitting((size_t)p->Ny * csz, 8);
+    s->codelet_x = fcmdp::fft_codelet(p->Nx / 2, fp32, &s->wplan_x, &s->tpr_x);
+    s->codelet_y = fcmdp::fft_codelet(p->Ny, fp32, &s->wplan_y, &s->tpr_y);
+    if (s->codelet_x >= 0) s->wave_x = true;
+    if (s->codelet_y >= 0) s->wave_y = true;
+    s->rows_x = rows_fitting((size_t)(p->Nx / 2 + 1) * csz, 8);
+    // rows of the y pass are independent; one per workgroup packs LDS best
+    s->rows_y = s->codelet_y >= 0 ? 1 : rows_fitting((size_t)p->Ny * csz, 8);
     if (s->rows_x == 0) s->wave_x = false;
     if (s->rows_y == 0) s->wave_y = false;
   }
@@ -568,6 +573,20 @@ int fcmdp_set_variant(fcmdp_solver* s, int key, int value) {
     case FCMDP_VARIANT_VECTOR_DCT:
       s->force_vector_dct = on;
       return FCMDP_OK;
+    case FCMDP_VARIANT_NO_CODELET: {
+      const bool fp32 = s->mixed;
+      if (on) {
+        s->codelet_x = s->codelet_y = -1;
+        s->wave_x = fp32 && make_wave_plan(s->p.Nx / 2, fp32, &s->wplan_x, &s->tpr_x);
+        s->wave_y = fp32 && make_wave_plan(s->p.Ny, fp32, &s->wplan_y, &s->tpr_y);
+      } else {
+        s->codelet_x = fcmdp::fft_codelet(s->p.Nx / 2, fp32, &s->wplan_x, &s->tpr_x);
+        s->codelet_y = fcmdp::fft_codelet(s->p.Ny, fp32, &s->wplan_y, &s->tpr_y);
+        if (s->codelet_x >= 0) s->wave_x = true;
+        if (s->codelet_y >= 0) s->wave_y = true;
+      }
+      return FCMDP_OK;
+    }
     default:
       return FCMDP_EINVAL;
   }

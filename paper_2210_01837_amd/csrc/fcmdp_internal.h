@@ -103,6 +103,7 @@ struct fcmdp_solver {
   fcmdp::FFTPlan wplan_x, wplan_y;
   bool wave_x = false, wave_y = false;
   int rows_x = 0, rows_y = 0, tpr_x = 0, tpr_y = 0;
+  int codelet_x = -1, codelet_y = -1;   // fixed-plan kernels, -1 = none
   void* dftc_t = nullptr;       // dftc converted to T
 
   // use the one-thread-per-column solver even when Nz <= 32 (tests)
@@ -142,6 +143,9 @@ hipError_t launch_fft_forward(const fcmdp_solver* s, const void* grid,
                               void* spec, hipStream_t st);
 hipError_t launch_fft_inverse(const fcmdp_solver* s, void* spec, void* grid,
                               hipStream_t st);
+// index of a fixed-plan kernel for length n (its plan and threads per row are
+// written to plan / tpr), or -1
+int fft_codelet(int n, bool fp32, FFTPlan* plan, int* tpr);
 // columns.hip (dispatches to columns_seg.hip for Nz <= 32)
 hipError_t launch_columns(const fcmdp_solver* s, const void* spec_in,
                           void* spec_out, hipStream_t st);

@@ -331,19 +331,18 @@ __device__ __forceinline__ void row_sync() {
   else __syncthreads();
 }
 
-// Not inlined: with every radix inlined into one stage loop the register
-// allocator keeps the union of all stages' live ranges.
-template <typename T, int R, int TPR>
-__device__ __noinline__ void wstage(cplx_t<T>* row, int N, int Ns, int t,
-                                       const cplx_t<T>* __restrict__ tw,
-                                       const T* __restrict__ cs, T sign) {
+// One Stockham stage of radix R on a row owned by TPR threads; each thread
+// holds up to NB butterflies in registers.
+template <typename T, int R, int TPR, int NB>
+__device__ __forceinline__ void stage_body(cplx_t<T>* row, int N, int Ns, int t,
+                                           const cplx_t<T>* __restrict__ tw,
+                                           const T* __restrict__ cs, T sign) {
   using C = cplx_t<T>;
-  constexpr int CAP = wave_nbi_cap(sizeof(T) == 4, R);
   const int nb = N / R;
   const int twstep = N / (Ns * R);
-  C v[CAP][R];
+  C v[NB][R];
 #pragma unroll
-  for (int i = 0; i < CAP; ++i) {
+  for (int i = 0; i < NB; ++i) {
     const int j = t + TPR * i;
     if (j < nb) {
 #pragma unroll
@@ -352,7 +351,7 @@ __device__ __noinline__ void wstage(cplx_t<T>* row, int N, int Ns, int t,
   }
   row_sync<TPR>();
 #pragma unroll
-  for (int i = 0; i < CAP; ++i) {
+  for (int i = 0; i < NB; ++i) {
     const int j = t + TPR * i;
     if (j < nb) {
       C* x = v[i];
@@ -376,6 +375,16 @@ __device__ __noinline__ void wstage(cplx_t<T>* row, int N, int Ns, int t,
     }
   }
   row_sync<TPR>();
+}
+
+// Generic plans: the radix is chosen at run time.  Not inlined: with every
+// radix inlined into one stage loop the register allocator keeps the union
+// of all stages' live ranges.
+template <typename T, int R, int TPR>
+__device__ __noinline__ void wstage(cplx_t<T>* row, int N, int Ns, int t,
+                                    const cplx_t<T>* __restrict__ tw,
+                                    const T* __restrict__ cs, T sign) {
+  stage_body<T, R, TPR, wave_nbi_cap(sizeof(T) == 4, R)>(row, N, Ns, t, tw, cs, sign);
 }
 
 template <typename T, int TPR>
@@ -405,6 +414,41 @@ __device__ __forceinline__ void row_fft(cplx_t<T>* row, int N,
   }
 }
 
+// Fixed plans ("codelets"): the stage sequence is a template argument, each
+// stage code = 16 R + NB; stages are inlined one after another, so registers
+// are allocated per stage and nothing goes through a call stack.
+template <typename T, int TPR, int Code, int... Rest>
+__device__ __forceinline__ void run_codes(cplx_t<T>* row, int N, int Ns, int t,
+                                          const cplx_t<T>* __restrict__ tw,
+                                          const T* __restrict__ dftc,
+                                          const DftOff& doff, T sign) {
+  constexpr int R = Code >> 4, NB = Code & 15;
+  stage_body<T, R, TPR, NB>(row, N, Ns, t, tw, dftc + doff.off[R], sign);
+  if constexpr (sizeof...(Rest) > 0)
+    run_codes<T, TPR, Rest...>(row, N, Ns * R, t, tw, dftc, doff, sign);
+}
+
+struct GenericRows {
+  template <typename T, int TPR>
+  __device__ __forceinline__ static void run(cplx_t<T>* row, int N, const FFTPlan& plan, int t,
+                             const cplx_t<T>* __restrict__ tw,
+                             const T* __restrict__ dftc, const DftOff& doff,
+                             T sign) {
+    row_fft<T, TPR>(row, N, plan, t, tw, dftc, doff.off, sign);
+  }
+};
+
+template <int... Codes>
+struct FixedRows {
+  template <typename T, int TPR>
+  __device__ __forceinline__ static void run(cplx_t<T>* row, int N, const FFTPlan&, int t,
+                             const cplx_t<T>* __restrict__ tw,
+                             const T* __restrict__ dftc, const DftOff& doff,
+                             T sign) {
+    run_codes<T, TPR, Codes...>(row, N, 1, t, tw, dftc, doff, sign);
+  }
+};
+
 // split step of the real transform: X_k from Z_k and Z_{M-k} (w = e^{-2 pi i k/Nx})
 template <typename C>
 __device__ inline C r2c_post(C zk, C zm, C w) {
@@ -430,7 +474,7 @@ __device__ inline C c2r_pre(C xk, C xm, C w) {
 
 // x-pass, real rows -> half spectrum, ROWS rows per workgroup, written
 // transposed as ROWS-long runs of consecutive y.
-template <typename T, int ROWS, int TPR>
+template <typename T, int ROWS, int TPR, typename Run>
 __global__ void __launch_bounds__(ROWS * TPR)
 k_fftw_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
              const T* __restrict__ grid, cplx_t<T>* __restrict__ spec,
@@ -455,7 +499,7 @@ k_fftw_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
 #pragma unroll 4
   for (int i = t; i < M; i += TPR) row[i] = src[i];
   row_sync<TPR>();
-  row_fft<T, TPR>(row, M, plan, t, tw, dftc, doff.off, T(-1));
+  Run::template run<T, TPR>(row, M, plan, t, tw, dftc, doff, T(-1));
   for (int k = t; k <= M / 2; k += TPR) {
     const C zk = row[k];
     if (k == 0) {
@@ -477,7 +521,7 @@ k_fftw_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
 }
 
 // y-pass, in place on contiguous rows of length Ny.
-template <typename T, int ROWS, int TPR>
+template <typename T, int ROWS, int TPR, typename Run>
 __global__ void __launch_bounds__(ROWS * TPR)
 k_fftw_y(DevParams dp, FFTPlan plan, const int* __restrict__ band,
          cplx_t<T>* __restrict__ spec, const cplx_t<T>* __restrict__ tw,
@@ -498,7 +542,7 @@ k_fftw_y(DevParams dp, FFTPlan plan, const int* __restrict__ band,
 #pragma unroll 4
   for (int i = t; i < N; i += TPR) row[i] = g[i];
   row_sync<TPR>();
-  row_fft<T, TPR>(row, N, plan, t, tw, dftc, doff.off, sign);
+  Run::template run<T, TPR>(row, N, plan, t, tw, dftc, doff, sign);
   if (live) {
 #pragma unroll 4
     for (int i = t; i < N; i += TPR) g[i] = row[i];
@@ -507,7 +551,7 @@ k_fftw_y(DevParams dp, FFTPlan plan, const int* __restrict__ band,
 
 // x-pass, half spectrum -> real rows, reading ROWS-long runs of the
 // transposed layout.
-template <typename T, int ROWS, int TPR>
+template <typename T, int ROWS, int TPR, typename Run>
 __global__ void __launch_bounds__(ROWS * TPR)
 k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
              const cplx_t<T>* __restrict__ spec, T* __restrict__ grid,
@@ -547,7 +591,7 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
     }
   }
   row_sync<TPR>();
-  row_fft<T, TPR>(row, M, plan, t, tw, dftc, doff.off, T(1));
+  Run::template run<T, TPR>(row, M, plan, t, tw, dftc, doff, T(1));
   if (wr < nr) {
     C* dst = reinterpret_cast<C*>(grid + ((size_t)p * dp.Ny + y0 + wr) * dp.Nx);
 #pragma unroll 4
@@ -555,7 +599,7 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   }
 }
 
-template <typename T, int ROWS, int TPR>
+template <typename T, int ROWS, int TPR, typename Run>
 static void launch_wave_x(bool fwd, const fcmdp_solver* s, const void* in,
                           void* out, const DftOff& doff, hipStream_t st) {
   using C = cplx_t<T>;
@@ -565,71 +609,114 @@ static void launch_wave_x(bool fwd, const fcmdp_solver* s, const void* in,
   dim3 g((dp.Ny + ROWS - 1) / ROWS, 6 * dp.Nz);
   const T* cs = (const T*)s->dftc_t;
   if (fwd)
-    hipLaunchKernelGGL((k_fftw_x_r2c<T, ROWS, TPR>), g, dim3(ROWS * TPR), lds,
-                       st, dp, s->wplan_x, s->band, (const T*)in, (C*)out,
+    hipLaunchKernelGGL((k_fftw_x_r2c<T, ROWS, TPR, Run>), g, dim3(ROWS * TPR),
+                       lds, st, dp, s->wplan_x, s->band, (const T*)in, (C*)out,
                        (const C*)s->tw_x, (const C*)s->tw_r, cs, doff);
   else
-    hipLaunchKernelGGL((k_fftw_x_c2r<T, ROWS, TPR>), g, dim3(ROWS * TPR), lds,
-                       st, dp, s->wplan_x, s->band, (const C*)in, (T*)out,
+    hipLaunchKernelGGL((k_fftw_x_c2r<T, ROWS, TPR, Run>), g, dim3(ROWS * TPR),
+                       lds, st, dp, s->wplan_x, s->band, (const C*)in, (T*)out,
                        (const C*)s->tw_x, (const C*)s->tw_r, cs, doff);
 }
 
-template <typename T, int TPR>
-static void wave_x_tpr(bool fwd, const fcmdp_solver* s, const void* in,
-                       void* out, const DftOff& doff, hipStream_t st) {
+template <typename T, int TPR, typename Run>
+static void wave_x_rows(bool fwd, const fcmdp_solver* s, const void* in,
+                        void* out, const DftOff& doff, hipStream_t st) {
   // rows per workgroup, capped by 1024 threads
   const int r = s->rows_x * TPR > 1024 ? 1024 / TPR : s->rows_x;
   switch (r) {
-    case 16: launch_wave_x<T, 16, 64>(fwd, s, in, out, doff, st); break;
-    case 8: launch_wave_x<T, 8, TPR>(fwd, s, in, out, doff, st); break;
-    case 4: launch_wave_x<T, 4, TPR>(fwd, s, in, out, doff, st); break;
-    case 2: launch_wave_x<T, 2, TPR>(fwd, s, in, out, doff, st); break;
-    default: launch_wave_x<T, 1, TPR>(fwd, s, in, out, doff, st); break;
+    case 16: launch_wave_x<T, 16, 64, Run>(fwd, s, in, out, doff, st); break;
+    case 8: launch_wave_x<T, 8, TPR, Run>(fwd, s, in, out, doff, st); break;
+    case 4: launch_wave_x<T, 4, TPR, Run>(fwd, s, in, out, doff, st); break;
+    case 2: launch_wave_x<T, 2, TPR, Run>(fwd, s, in, out, doff, st); break;
+    default: launch_wave_x<T, 1, TPR, Run>(fwd, s, in, out, doff, st); break;
   }
 }
 
-template <typename T>
-static void wave_x(bool fwd, const fcmdp_solver* s, const void* in, void* out,
-                   const DftOff& doff, hipStream_t st) {
-  switch (s->tpr_x) {
-    case 64: wave_x_tpr<T, 64>(fwd, s, in, out, doff, st); break;
-    case 128: wave_x_tpr<T, 128>(fwd, s, in, out, doff, st); break;
-    default: wave_x_tpr<T, 256>(fwd, s, in, out, doff, st); break;
-  }
-}
-
-template <typename T, int ROWS, int TPR>
+template <typename T, int ROWS, int TPR, typename Run>
 static void launch_wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
                           T sign, hipStream_t st) {
   using C = cplx_t<T>;
   const DevParams& dp = s->dp;
   const size_t lds = (size_t)ROWS * dp.Ny * sizeof(C);
   dim3 g((dp.Nkx + ROWS - 1) / ROWS, 6 * dp.Nz);
-  hipLaunchKernelGGL((k_fftw_y<T, ROWS, TPR>), g, dim3(ROWS * TPR), lds, st, dp,
-                     s->wplan_y, s->band, (C*)spec, (const C*)s->tw_y,
+  hipLaunchKernelGGL((k_fftw_y<T, ROWS, TPR, Run>), g, dim3(ROWS * TPR), lds, st,
+                     dp, s->wplan_y, s->band, (C*)spec, (const C*)s->tw_y,
                      (const T*)s->dftc_t, doff, sign);
 }
 
-template <typename T, int TPR>
-static void wave_y_tpr(const fcmdp_solver* s, void* spec, const DftOff& doff,
-                       T sign, hipStream_t st) {
+template <typename T, int TPR, typename Run>
+static void wave_y_rows(const fcmdp_solver* s, void* spec, const DftOff& doff,
+                        T sign, hipStream_t st) {
   const int r = s->rows_y * TPR > 1024 ? 1024 / TPR : s->rows_y;
   switch (r) {
-    case 8: launch_wave_y<T, 8, TPR>(s, spec, doff, sign, st); break;
-    case 4: launch_wave_y<T, 4, TPR>(s, spec, doff, sign, st); break;
-    case 2: launch_wave_y<T, 2, TPR>(s, spec, doff, sign, st); break;
-    default: launch_wave_y<T, 1, TPR>(s, spec, doff, sign, st); break;
+    case 8: launch_wave_y<T, 8, TPR, Run>(s, spec, doff, sign, st); break;
+    case 4: launch_wave_y<T, 4, TPR, Run>(s, spec, doff, sign, st); break;
+    case 2: launch_wave_y<T, 2, TPR, Run>(s, spec, doff, sign, st); break;
+    default: launch_wave_y<T, 1, TPR, Run>(s, spec, doff, sign, st); break;
+  }
+}
+
+// Codelets compiled for the transform lengths of the large workloads (single
+// precision, 64 threads per row).  codelet_table[i] must agree with the
+// FixedRows instance that wave_x / wave_y launch for index i.
+struct CodeletDesc { int n; int tpr; int nst; int code[6]; };
+static const CodeletDesc kCodelets[] = {
+    {1088, 64, 3, {8 * 16 + 3, 8 * 16 + 3, 17 * 16 + 1}},           // 2176 / 2
+    {2176, 64, 3, {16 * 16 + 3, 8 * 16 + 5, 17 * 16 + 2}},          // 2176
+    {384, 64, 3, {16 * 16 + 1, 8 * 16 + 1, 3 * 16 + 2}},            // 768 / 2
+    {768, 64, 4, {4 * 16 + 3, 8 * 16 + 2, 8 * 16 + 2, 3 * 16 + 4}},  // 768
+};
+using Codelet0 = FixedRows<8 * 16 + 3, 8 * 16 + 3, 17 * 16 + 1>;
+using Codelet1 = FixedRows<16 * 16 + 3, 8 * 16 + 5, 17 * 16 + 2>;
+using Codelet2 = FixedRows<16 * 16 + 1, 8 * 16 + 1, 3 * 16 + 2>;
+using Codelet3 = FixedRows<4 * 16 + 3, 8 * 16 + 2, 8 * 16 + 2, 3 * 16 + 4>;
+
+template <typename T>
+static void wave_x(bool fwd, const fcmdp_solver* s, const void* in, void* out,
+                   const DftOff& doff, hipStream_t st) {
+  switch (s->codelet_x) {
+    case 0: wave_x_rows<T, 64, Codelet0>(fwd, s, in, out, doff, st); return;
+    case 1: wave_x_rows<T, 64, Codelet1>(fwd, s, in, out, doff, st); return;
+    case 2: wave_x_rows<T, 64, Codelet2>(fwd, s, in, out, doff, st); return;
+    case 3: wave_x_rows<T, 64, Codelet3>(fwd, s, in, out, doff, st); return;
+    default: break;
+  }
+  switch (s->tpr_x) {
+    case 64: wave_x_rows<T, 64, GenericRows>(fwd, s, in, out, doff, st); break;
+    case 128: wave_x_rows<T, 128, GenericRows>(fwd, s, in, out, doff, st); break;
+    default: wave_x_rows<T, 256, GenericRows>(fwd, s, in, out, doff, st); break;
   }
 }
 
 template <typename T>
 static void wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
                    T sign, hipStream_t st) {
-  switch (s->tpr_y) {
-    case 64: wave_y_tpr<T, 64>(s, spec, doff, sign, st); break;
-    case 128: wave_y_tpr<T, 128>(s, spec, doff, sign, st); break;
-    default: wave_y_tpr<T, 256>(s, spec, doff, sign, st); break;
+  switch (s->codelet_y) {
+    case 0: wave_y_rows<T, 64, Codelet0>(s, spec, doff, sign, st); return;
+    case 1: wave_y_rows<T, 64, Codelet1>(s, spec, doff, sign, st); return;
+    case 2: wave_y_rows<T, 64, Codelet2>(s, spec, doff, sign, st); return;
+    case 3: wave_y_rows<T, 64, Codelet3>(s, spec, doff, sign, st); return;
+    default: break;
   }
+  switch (s->tpr_y) {
+    case 64: wave_y_rows<T, 64, GenericRows>(s, spec, doff, sign, st); break;
+    case 128: wave_y_rows<T, 128, GenericRows>(s, spec, doff, sign, st); break;
+    default: wave_y_rows<T, 256, GenericRows>(s, spec, doff, sign, st); break;
+  }
+}
+
+int fft_codelet(int n, bool fp32, FFTPlan* plan, int* tpr) {
+  if (!fp32) return -1;
+  for (int i = 0; i < (int)(sizeof(kCodelets) / sizeof(kCodelets[0])); ++i) {
+    const CodeletDesc& c = kCodelets[i];
+    if (c.n != n) continue;
+    plan->n = n;
+    plan->nstages = c.nst;
+    for (int k = 0; k < c.nst; ++k) plan->radix[k] = c.code[k] >> 4;
+    *tpr = c.tpr;
+    return i;
+  }
+  return -1;
 }
 
 static int rows_for(int len, size_t elem, int bufs_extra, int maxrows) {
