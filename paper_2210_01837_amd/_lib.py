@@ -8,7 +8,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfcmdp.so")
+# FCMDP_LIBRARY selects another build of the same library (e.g. a tuning
+# variant); by default the in-tree build is used.
+LIB_PATH = os.environ.get("FCMDP_LIBRARY") or os.path.join(_HERE, "libfcmdp.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ECAPACITY = 0, -1, -2, -3, -4, -5
 BOTTOM_WALL, SLIT_CHANNEL = 0, 1

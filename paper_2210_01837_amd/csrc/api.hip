@@ -338,7 +338,7 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
     s->codelet_y = fcmdp::fft_codelet(p->Ny, fp32, &s->wplan_y, &s->tpr_y);
     if (s->codelet_x >= 0) s->wave_x = true;
     if (s->codelet_y >= 0) s->wave_y = true;
-    s->rows_x = rows_fitting((size_t)(p->Nx / 2 + 1) * csz, 8);
+    s->rows_x = rows_fitting((size_t)(p->Nx / 2 + 1) * csz, 16);
     // rows of the y pass are independent; one per workgroup packs LDS best
     s->rows_y = s->codelet_y >= 0 ? 1 : rows_fitting((size_t)p->Ny * csz, 8);
     if (s->rows_x == 0) s->wave_x = false;

@@ -100,17 +100,37 @@ k_spread(DevParams dp, const int* __restrict__ band,
 
 // Wave-uniform spread: a wavefront owns an 8 x 8 patch of grid columns and
 // walks, in cell-sorted order, every particle of the 14 x 14 cells whose
-// kernels can reach the patch.  The particle index is the same on all lanes,
-// so its record is fetched once per wavefront (scalar loads); each lane adds
-// the particle's contribution to its own column when that column lies in the
+// kernels can reach the patch.  The particle is the same on all lanes; each
+// lane adds its contribution to its own column when that column lies in the
 // particle's 7 x 7 footprint.  Loop trip counts are uniform (no divergence
-// between lanes of different cell occupancy), no LDS is used (high
-// occupancy), and every column sums its particles in a fixed order
-// (deterministic).  A first pass finds the z-nodes the region's particles
-// touch; band planes outside them are written as zeros without a particle
-// loop, and the rest are accumulated ZC planes at a time in registers.
+// between lanes of different cell occupancy) and every column sums its
+// particles in a fixed order (deterministic).
+//
+// Staged path (at most 64 particles in the region, the usual case): lane j
+// loads the record of the j-th region particle in parallel with the others
+// (x/y weights into a per-wavefront LDS block, the rest into registers), and
+// the uniform loop reads particle v's values from lane v (readlane) and from
+// LDS, so it waits on no global memory.  Denser regions take the same loop
+// with scalar loads from global memory.  A first pass finds the z-nodes the
+// region's particles touch; band planes outside them are written as zeros,
+// the rest are accumulated ZC planes at a time in registers.
 constexpr int kPW = 8;   // patch edge per wavefront; 4 wavefronts side by side in x
 constexpr int kSpreadZC = 10;
+constexpr int kStage = 64;
+
+template <typename T>
+__device__ __forceinline__ T rdlane(T x, int v) {
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), v));
+  } else {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), v);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), v);
+    return __hiloint2double(hi, lo);
+  }
+}
+__device__ __forceinline__ int rdlane_i(int x, int v) {
+  return __builtin_amdgcn_readlane(x, v);
+}
 
 template <typename T, int ZC>
 __global__ void __launch_bounds__(256)
@@ -118,6 +138,7 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
               const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
               const T* __restrict__ pw, const T* __restrict__ pf,
               const T* __restrict__ psi, T* __restrict__ grid) {
+  __shared__ T wst[4][kStage][29];           // staged x/y weights per wavefront
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gx = (dp.Nx + 4 * kPW - 1) / (4 * kPW);
@@ -140,88 +161,179 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
   const int xs = wrap_index(xw - 3, dp.Nx);
   const int xe0 = xs + ncols <= dp.Nx ? xs + ncols : dp.Nx;
   const int xe1 = xs + ncols - xe0;        // cells [0, xe1) after the seam
-  // z-nodes touched by the region's particles
-  int zmin = dp.Nz, zmax = -1;
-  for (int r = 0; r < nrows; ++r) {
+  // the region's particle ranges: lane 2r + s holds part s of cell row r
+  int sstart = 0, scnt = 0;
+  if (lane < 2 * nrows) {
+    const int r = lane >> 1, sg = lane & 1;
     const int row = wrap_index(yw - 3 + r, dp.Ny) * dp.Nx;
-    for (int sg = 0; sg < 2; ++sg) {
-      const int ca = sg ? 0 : xs, cb = sg ? xe1 : xe0;
-      if (ca >= cb) continue;
-      const int p1 = cell_start[row + cb];
-      for (int p = cell_start[row + ca]; p < p1; ++p) {
-        const int4 inf = pinfo[p];
-        zmin = min(zmin, inf.z);
-        zmax = max(zmax, inf.w);
-      }
+    const int ca = sg ? 0 : xs, cb = sg ? xe1 : xe0;
+    if (ca < cb) {
+      sstart = cell_start[row + ca];
+      scnt = cell_start[row + cb] - sstart;
     }
   }
-  if (inside) {
+  int incl = scnt;                         // inclusive prefix over lanes
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d);
+    if (lane >= d) incl += t;
+  }
+  const int soff = incl - scnt;
+  const int total = rdlane_i(incl, 63);
+
+  auto zero_outside = [&](int zmin, int zmax) {
+    if (!inside) return;
     for (int c = lo; c <= hi; ++c) {
       if (c >= zmin && c <= zmax) continue;
 #pragma unroll
       for (int ch = 0; ch < 6; ++ch) grid[ch * chstride + c * plane + col] = T(0);
     }
+  };
+  auto store_chunk = [&](int c0, int zmax, T (&acc)[ZC][6]) {
+    if (!inside) return;
+#pragma unroll
+    for (int s = 0; s < ZC; ++s) {
+      const int c = c0 + s;
+      if (c <= zmax) {
+#pragma unroll
+        for (int ch = 0; ch < 6; ++ch)
+          grid[ch * chstride + c * plane + col] = acc[s][ch];
+      }
+    }
+  };
+
+  if (total <= kStage) {
+    // lane j holds the j-th region particle (rows in order, then x)
+    int p = -1;
+    for (int r = 0; r < 2 * nrows; ++r) {
+      const int o = rdlane_i(soff, r), c = rdlane_i(scnt, r), st = rdlane_i(sstart, r);
+      if (lane >= o && lane < o + c) p = st + (lane - o);
+    }
+    const bool has = lane < total;
+    int4 inf = make_int4(0, 0, Nz, -1);
+    T F0 = 0, F1 = 0, F2 = 0, G0 = 0, G1 = 0, G2 = 0;
+    T* wrow = &wst[wv][lane][0];
+    if (has) {
+      inf = pinfo[p];
+      const T* f = pf + (size_t)p * 8;
+      F0 = f[0]; F1 = f[1]; F2 = f[2];
+      G0 = f[4]; G1 = f[5]; G2 = f[6];
+      const T* w = pw + (size_t)p * 32;
+#pragma unroll
+      for (int d = 0; d < 7; ++d) {
+        wrow[d] = w[d];
+        wrow[7 + d] = w[8 + d];
+        wrow[14 + d] = w[16 + d];
+        wrow[21 + d] = w[24 + d];
+      }
+    }
+    int zmin = inf.z, zmax = inf.w;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      zmin = min(zmin, __shfl_xor(zmin, m));
+      zmax = max(zmax, __shfl_xor(zmax, m));
+    }
+    zmin = rdlane_i(zmin, 0);
+    zmax = rdlane_i(zmax, 0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    zero_outside(zmin, zmax);
+    for (int c0 = zmin; c0 <= zmax; c0 += ZC) {
+      // this lane's particle's folded z weights for the chunk (dense, zero
+      // outside its window; nodes past Nz read padding and are never stored)
+      T pmj[ZC], pdj[ZC];
+      if (has) {
+        const T* ps = psi + (size_t)p * 2 * Nz;
+#pragma unroll
+        for (int s = 0; s < ZC; ++s) { pmj[s] = ps[c0 + s]; pdj[s] = ps[Nz + c0 + s]; }
+      } else {
+#pragma unroll
+        for (int s = 0; s < ZC; ++s) { pmj[s] = T(0); pdj[s] = T(0); }
+      }
+      T acc[ZC][6];
+#pragma unroll
+      for (int s = 0; s < ZC; ++s)
+#pragma unroll
+        for (int ch = 0; ch < 6; ++ch) acc[s][ch] = T(0);
+      for (int v = 0; v < total; ++v) {
+        const int iz = rdlane_i(inf.z, v), iw = rdlane_i(inf.w, v);
+        if (iw < c0 || iz >= c0 + ZC) continue;       // no overlap in z
+        int dx = a - rdlane_i(inf.x, v) + 3;
+        if (dx < 0) dx += dp.Nx; else if (dx >= dp.Nx) dx -= dp.Nx;
+        int dy = b - rdlane_i(inf.y, v) + 3;
+        if (dy < 0) dy += dp.Ny; else if (dy >= dp.Ny) dy -= dp.Ny;
+        T pm[ZC], pd[ZC];
+#pragma unroll
+        for (int s = 0; s < ZC; ++s) { pm[s] = rdlane(pmj[s], v); pd[s] = rdlane(pdj[s], v); }
+        const T f0v = rdlane(F0, v), f1v = rdlane(F1, v), f2v = rdlane(F2, v);
+        const T g0v = rdlane(G0, v), g1v = rdlane(G1, v), g2v = rdlane(G2, v);
+        if (inside && dx >= 0 && dx <= 6 && dy >= 0 && dy <= 6) {
+          const T* w = &wst[wv][v][0];
+          const T wm = w[dx] * w[7 + dy];
+          const T wd = w[14 + dx] * w[21 + dy];
+          const T f0 = f0v * wm, f1 = f1v * wm, f2 = f2v * wm;
+          const T t0 = g0v * wd, t1 = g1v * wd, t2 = g2v * wd;
+#pragma unroll
+          for (int s = 0; s < ZC; ++s) {
+            acc[s][0] += f0 * pm[s]; acc[s][1] += f1 * pm[s]; acc[s][2] += f2 * pm[s];
+            acc[s][3] += t0 * pd[s]; acc[s][4] += t1 * pd[s]; acc[s][5] += t2 * pd[s];
+          }
+        }
+      }
+      store_chunk(c0, zmax, acc);
+    }
+    return;
   }
+
+  // dense region: the same loop with scalar loads from global memory
+  int zmin = dp.Nz, zmax = -1;
+  for (int r = 0; r < 2 * nrows; ++r) {
+    const int st = rdlane_i(sstart, r), c = rdlane_i(scnt, r);
+    for (int q = st; q < st + c; ++q) {
+      const int4 inf = pinfo[q];
+      zmin = min(zmin, inf.z);
+      zmax = max(zmax, inf.w);
+    }
+  }
+  zero_outside(zmin, zmax);
   for (int c0 = zmin; c0 <= zmax; c0 += ZC) {
     T acc[ZC][6];
 #pragma unroll
     for (int s = 0; s < ZC; ++s)
 #pragma unroll
       for (int ch = 0; ch < 6; ++ch) acc[s][ch] = T(0);
-    for (int r = 0; r < nrows; ++r) {
-      const int row = wrap_index(yw - 3 + r, dp.Ny) * dp.Nx;
-      for (int sg = 0; sg < 2; ++sg) {
-        const int ca = sg ? 0 : xs, cb = sg ? xe1 : xe0;
-        if (ca >= cb) continue;
-        const int p0 = cell_start[row + ca], p1 = cell_start[row + cb];
-        int4 nxt = p0 < p1 ? pinfo[p0] : make_int4(0, 0, 0, -1);
-        for (int p = p0; p < p1; ++p) {
-          const int4 inf = nxt;
-          if (p + 1 < p1) nxt = pinfo[p + 1];             // prefetch
-          if (inf.w < c0 || inf.z >= c0 + ZC) continue;   // no overlap in z
-          // folded z weights of the chunk's nodes (dense, zero outside the
-          // particle's window; nodes past Nz read padding or the next record
-          // and are never stored)
-          const T* ps = psi + (size_t)p * 2 * Nz;
-          T pm[ZC], pd[ZC];
+    for (int r = 0; r < 2 * nrows; ++r) {
+      const int p0 = rdlane_i(sstart, r), p1 = p0 + rdlane_i(scnt, r);
+      for (int q = p0; q < p1; ++q) {
+        const int4 inf = pinfo[q];
+        if (inf.w < c0 || inf.z >= c0 + ZC) continue;   // no overlap in z
+        const T* ps = psi + (size_t)q * 2 * Nz;
+        T pm[ZC], pd[ZC];
+#pragma unroll
+        for (int s = 0; s < ZC; ++s) { pm[s] = ps[c0 + s]; pd[s] = ps[Nz + c0 + s]; }
+        int dx = a - inf.x + 3;
+        if (dx < 0) dx += dp.Nx; else if (dx >= dp.Nx) dx -= dp.Nx;
+        int dy = b - inf.y + 3;
+        if (dy < 0) dy += dp.Ny; else if (dy >= dp.Ny) dy -= dp.Ny;
+        const T* f = pf + (size_t)q * 8;
+        const T F0 = f[0], F1 = f[1], F2 = f[2];
+        const T G0 = f[4], G1 = f[5], G2 = f[6];
+        if (inside && dx >= 0 && dx <= 6 && dy >= 0 && dy <= 6) {
+          const T* w = pw + (size_t)q * 32;
+          const T wm = w[dx] * w[8 + dy];
+          const T wd = w[16 + dx] * w[24 + dy];
+          const T f0 = F0 * wm, f1 = F1 * wm, f2 = F2 * wm;
+          const T t0 = G0 * wd, t1 = G1 * wd, t2 = G2 * wd;
 #pragma unroll
           for (int s = 0; s < ZC; ++s) {
-            pm[s] = ps[c0 + s];
-            pd[s] = ps[Nz + c0 + s];
-          }
-          int dx = a - inf.x + 3;
-          if (dx < 0) dx += dp.Nx; else if (dx >= dp.Nx) dx -= dp.Nx;
-          int dy = b - inf.y + 3;
-          if (dy < 0) dy += dp.Ny; else if (dy >= dp.Ny) dy -= dp.Ny;
-          const T* f = pf + (size_t)p * 8;
-          const T F0 = f[0], F1 = f[1], F2 = f[2];
-          const T G0 = f[4], G1 = f[5], G2 = f[6];
-          if (inside && dx >= 0 && dx <= 6 && dy >= 0 && dy <= 6) {
-            const T* w = pw + (size_t)p * 32;
-            const T wm = w[dx] * w[8 + dy];
-            const T wd = w[16 + dx] * w[24 + dy];
-            const T f0 = F0 * wm, f1 = F1 * wm, f2 = F2 * wm;
-            const T t0 = G0 * wd, t1 = G1 * wd, t2 = G2 * wd;
-#pragma unroll
-            for (int s = 0; s < ZC; ++s) {
-              acc[s][0] += f0 * pm[s]; acc[s][1] += f1 * pm[s]; acc[s][2] += f2 * pm[s];
-              acc[s][3] += t0 * pd[s]; acc[s][4] += t1 * pd[s]; acc[s][5] += t2 * pd[s];
-            }
+            acc[s][0] += f0 * pm[s]; acc[s][1] += f1 * pm[s]; acc[s][2] += f2 * pm[s];
+            acc[s][3] += t0 * pd[s]; acc[s][4] += t1 * pd[s]; acc[s][5] += t2 * pd[s];
           }
         }
       }
     }
-    if (inside) {
-#pragma unroll
-      for (int s = 0; s < ZC; ++s) {
-        const int c = c0 + s;
-        if (c <= zmax) {
-#pragma unroll
-          for (int ch = 0; ch < 6; ++ch)
-            grid[ch * chstride + c * plane + col] = acc[s][ch];
-        }
-      }
-    }
+    store_chunk(c0, zmax, acc);
   }
 }
 
@@ -326,7 +438,7 @@ constexpr int kRX = kTile + 6;
 constexpr int kRec = 28;     // wxM[7] wyM[7] wxD[7] wyD[7]
 
 template <typename T, int ZC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_interp_tiled(DevParams dp, const int* __restrict__ band,
                const int* __restrict__ cell_start,
                const int4* __restrict__ pinfo, const T* __restrict__ pw,
@@ -412,25 +524,41 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
     }
     __syncthreads();
     const int c_first = zr[0], c_last = zr[1];
+    // staging is software pipelined: the rows of the next chunk are loaded
+    // into registers while the current chunk is interpolated from LDS.
+    // Thread (rg, rx) owns rows rg + kRG e (e = 0, 1, ...) of kRX values;
+    // with kRX = 2 kRG, row rg + kRG e is halo row rg + kRG (e & 1) of
+    // plane-channel e / 2, so every address is a compile-time offset from
+    // two per-thread row bases.
+    static_assert(kRX == 2 * kRG, "staging layout");
+    constexpr int kPer = 2 * 6 * ZC;
+    T pre[kPer];
+    const bool stager = tid < kRG * kRX;
+    const size_t yrow0 = stager ? (size_t)ytab[rg] * dp.Nx + xa : 0;
+    const size_t yrow1 = stager ? (size_t)ytab[rg + kRG] * dp.Nx + xa : 0;
+    auto fetch = [&](int c0) {
+      const int nz = min(ZC, c_last - c0 + 1);
+      const T* gb = grid + (size_t)c0 * plane;
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) {
+        const int t = e >> 1, ch = t % 6, sidx = t / 6;
+        if (stager && sidx < nz)
+          pre[e] = gb[ch * chstride + (size_t)sidx * plane + ((e & 1) ? yrow1 : yrow0)];
+      }
+    };
+    if (c_first <= c_last) fetch(c_first);
     for (int c0 = c_first; c0 <= c_last; c0 += ZC) {
       const int nz = min(ZC, c_last - c0 + 1);
-      // stage rows of kRX values: thread (rg, rx)
-      if (tid < kRG * kRX) {
-        const int rows = nz * 6 * kRX;
-        const size_t base0 = (size_t)c0 * plane + xa;
-        for (int row = rg; row < rows; row += kRG) {
-          const int ry = row % kRX;
-          const int t = row / kRX;
-          const int ch = t % 6;
-          const int sidx = t / 6;
-          G[row * kRX + rx] = grid[ch * chstride + base0 + (size_t)sidx * plane +
-                                   (size_t)ytab[ry] * dp.Nx];
-        }
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) {
+        const int sidx = (e >> 1) / 6;
+        if (stager && sidx < nz) G[(rg + kRG * e) * kRX + rx] = pre[e];
       }
       T q[ZC];
 #pragma unroll
       for (int sidx = 0; sidx < ZC; ++sidx) q[sidx] = sidx < nz ? quad[c0 + sidx] : T(0);
       __syncthreads();
+      if (c0 + ZC <= c_last) fetch(c0 + ZC);
       for (int h = g; h < np; h += NG) {
         const int4 inf = pci[h];
         if (inf.w < c0 || inf.z > c0 + nz - 1) continue;   // no z overlap
