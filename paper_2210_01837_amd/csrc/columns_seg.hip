@@ -125,16 +125,27 @@ struct Row {
   bool row;            // an interior row (m >= 2, m < N)
 };
 
+// B^2 row coefficients by m, computed at compile time (no divisions in the
+// kernels): lo = c_{m-2}/(4m(m-1)), di = 1/(2(m^2-1)), up = 1/(4m(m+1)).
+struct RowTable {
+  double lo[kMaxNz], di[kMaxNz], up[kMaxNz];
+  constexpr RowTable() : lo(), di(), up() {
+    for (int m = 2; m < kMaxNz; ++m) {
+      lo[m] = (m == 2 ? 2.0 : 1.0) / (4.0 * m * (m - 1));
+      di[m] = 1.0 / (2.0 * ((double)m * m - 1.0));
+      up[m] = 1.0 / (4.0 * m * (m + 1));
+    }
+  }
+};
+__constant__ RowTable kRowTable = RowTable();
+
 __device__ inline Row row_of(int m, int N) {
   Row r;
   r.row = m >= 2 && m < N;
-  if (r.row) {
-    r.lo = (m == 2 ? 2.0 : 1.0) / (4.0 * m * (m - 1));
-    r.di = 1.0 / (2.0 * ((double)m * m - 1.0));
-    r.up = (m + 2 < N) ? 1.0 / (4.0 * m * (m + 1)) : 0.0;
-  } else {
-    r.lo = r.di = r.up = 0.0;
-  }
+  const int mm = r.row ? m : 2;
+  r.lo = r.row ? kRowTable.lo[mm] : 0.0;
+  r.di = r.row ? kRowTable.di[mm] : 0.0;
+  r.up = (r.row && m + 2 < N) ? kRowTable.up[mm] : 0.0;
   return r;
 }
 
@@ -447,10 +458,12 @@ __device__ inline void seg_basis(const double fb[kNpl], const double* __restrict
 // the three body-force combinations above and g_x, g_y), so that a caller
 // holding them in LDS keeps few of them live in registers; the body force
 // f = (A0 - 1/2 D g_y, A1 + 1/2 D g_x, A2) is rebuilt where it is used.
-template <int GEOM, typename Load>
-__device__ __forceinline__ void seg_column_solve(const Load& load, const DevParams& dp,
-                                 const double* __restrict__ zc,
-                                 const double* __restrict__ Mf, int N, int l,
+// `basis(which, out)` returns this lane's four Chebyshev coefficients of the
+// correction's node functions: which = 0: e^{-k z}, 1: z e^{-k z},
+// 2: e^{k (z - H)}, 3: z e^{k (z - H)} (the last two for the slit channel).
+template <int GEOM, typename Load, typename Basis>
+__device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& basis,
+                                 const DevParams& dp, int N, int l,
                                  double kx, double ky, double k, Vec& U,
                                  Vec& V, Vec& W) {
   const double H = dp.H, eta = dp.eta, s2H = 2.0 / H;
@@ -475,11 +488,11 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const DevPara
     Vec r = body_x();
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
-    U = seg_zero_mode(r, H, N, dp.geometry, l);
+    U = seg_zero_mode(r, H, N, GEOM, l);
     r = body_y();
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
-    V = seg_zero_mode(r, H, N, dp.geometry, l);
+    V = seg_zero_mode(r, H, N, GEOM, l);
   } else {
     const double kappa = 0.5 * k * H;
     Par q[2];
@@ -524,14 +537,10 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const DevPara
     // wall correction, evaluated on all nodes and transformed
     const Z2 u0 = -1.0 * bsum_bottom(U), v0 = -1.0 * bsum_bottom(V),
              w0 = -1.0 * bsum_bottom(W);
-    double fb[kNpl], E[kNpl], ZE[kNpl];
-#pragma unroll
-    for (int j = 0; j < kNpl; ++j) {
-      const int c = 4 * l + j;
-      fb[j] = c < N ? exp(-k * zc[c]) : 0.0;
-    }
-    seg_basis(fb, zc, Mf, N, l, E, ZE);
-    if (dp.geometry == 0) {
+    double E[kNpl], ZE[kNpl];
+    basis(0, E);
+    basis(1, ZE);
+    if constexpr (GEOM == 0) {
       const Z2 Ac = imul(k, w0) + kx * u0 + ky * v0;
       const Z2 Bc = k * w0 - imul(kx, u0) - imul(ky, v0);
       const double rx = kx / k, ry = ky / k;
@@ -578,12 +587,8 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const DevPara
       const Z2 Cx = rx * CL - ry * CT, Cy = ry * CL + rx * CT;
       const Z2 Dx = rx * DL - ry * DT, Dy = ry * DL + rx * DT;
       double Ep[kNpl], ZEp[kNpl];
-#pragma unroll
-      for (int j = 0; j < kNpl; ++j) {
-        const int c = 4 * l + j;
-        fb[j] = c < N ? exp(k * (zc[c] - H)) : 0.0;
-      }
-      seg_basis(fb, zc, Mf, N, l, Ep, ZEp);
+      basis(2, Ep);
+      basis(3, ZEp);
       const double ax = kx / (2.0 * eta * k), ay = ky / (2.0 * eta * k);
       const Z2 pu0 = imul(-ax, C0), pu1 = imul(ax, D0);
       const Z2 pv0 = imul(-ay, C0), pv1 = imul(ay, D0);
@@ -658,7 +663,18 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
         for (int v = 0; v < 5; ++v) A[v].v[j] = A[v].v[j] + m * comb[v];
       }
     }
-    seg_column_solve<GEOM>([&](int v) { return A[v]; }, dp, zc, Mf, N, l, kx,
+    auto basis = [&](int which, double out[kNpl]) {
+      double fb[kNpl], E[kNpl], ZE[kNpl];
+#pragma unroll
+      for (int j = 0; j < kNpl; ++j) {
+        const int c = 4 * l + j;
+        fb[j] = c >= N ? 0.0 : (which < 2 ? exp(-k * zc[c]) : exp(k * (zc[c] - H)));
+      }
+      seg_basis(fb, zc, Mf, N, l, E, ZE);
+#pragma unroll
+      for (int j = 0; j < kNpl; ++j) out[j] = (which & 1) ? ZE[j] : E[j];
+    };
+    seg_column_solve<GEOM>([&](int v) { return A[v]; }, basis, dp, N, l, kx,
                            ky, k, U, V, W);
   }
   DU = seg_deriv(U, l, s2H);
@@ -714,72 +730,99 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
 }
 
 // ---------------------------------------------------------------------------
-// Mixed-precision variant: the two Chebyshev transforms as FP32 MFMA
-// products at workgroup level (a 32 x P matrix against all node vectors of
-// 16 columns, and back), the per-column solve in FP64 on eight lanes as above.
-//   X[c][v]  = band node values of the five forward vectors, v = col*10 +
-//              vec*2 + (re, im)                                   (LDS, fp32)
+// Mixed-precision variant: the Chebyshev transforms as FP32 MFMA products at
+// workgroup level (the 32 node rows of all node vectors of 16 columns, and
+// back), the per-column solve in FP64 on eight lanes as above.  Per column
+// the node vectors are the five body-force combinations (10 reals) and the
+// wall correction's node functions e^{-k z}, z e^{-k z} (and, between two
+// walls, e^{k(z-H)}, z e^{k(z-H)}), so their coefficients come out of the
+// same product.
+//   X[c][v]  = node values, v = col * kVPC + component          (LDS, fp32)
 //   Cf[n][v] = sum_c Mt[n][c] X[c][v]          (v_mfma_f32_16x16x4f32)
 //   solve: Cf -> coefficients of u, v, w, du/dz, dv/dz (in place)
 //   D[c][v]  = sum_n T_n(s_c) Cf[n][v]         (MFMA again), then omega and
-//              the 1/(Nx Ny) scale at the nodes.
+//              the 1/(Nx Ny) scale at the band nodes.
 // Operand layout of v_mfma_f32_16x16x4f32 (wave64): A[i][k] comes from lane
 // i + 16k, B[k][j] from lane j + 16k, and D[4(l/16) + r][l%16] is returned in
 // register r of lane l.
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kMCols = 16;                 // columns per workgroup
-constexpr int kMV = kMCols * 10;           // real node vectors per workgroup
 constexpr int kMThreads = kMCols * kSeg;   // 128
+template <int GEOM> struct MfmaLayout {
+  static constexpr int kBasis = GEOM == 0 ? 2 : 4;     // correction node functions
+  static constexpr int kVPC = 10 + kBasis;             // reals per column
+  static constexpr int kMV = kMCols * kVPC;            // reals per node row
+  static constexpr int kTiles = 2 * (kMV / 16);        // 16 x 16 output tiles
+  static constexpr int kTilesPerWave = kTiles / (kMThreads / 64);
+};
 
 template <int GEOM>
 __global__ void __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_columns_mfma(ColParams cp, const int* __restrict__ band,
                const float2* __restrict__ in, float2* __restrict__ out,
-               const double* __restrict__ zc, const double* __restrict__ Mf,
-               const float* __restrict__ Mf32, const float* __restrict__ Pi32) {
-  // one buffer: node values (A), then coefficients (B, C), then node values
-  // again (D, E); each transform keeps its output tiles in registers until
+               const double* __restrict__ zc, const float* __restrict__ Mf32,
+               const float* __restrict__ Pi32) {
+  using Lay = MfmaLayout<GEOM>;
+  constexpr int kVPC = Lay::kVPC, kMV = Lay::kMV;
+  // one buffer: node values (A), then coefficients (B, C), then band node
+  // values (D, E); each transform keeps its output tiles in registers until
   // every wave has finished reading its input
   __shared__ float XC[32 * kMV];
-  constexpr int kTilesPerWave = 2 * (kMV / 16) / (kMThreads / 64);   // 10
   const DevParams& dp = cp.dp;
   const int lo = band[0], hi = band[1];
   if (lo > hi) return;
   const int K = dp.Nkx * dp.Ny;
   const int N = dp.Nz;
   const int P = hi - lo + 1;
-  const int Kp = (P + 3) & ~3;             // node count padded for k-steps of 4
+  const int Np = (N + 3) & ~3;             // node count padded for k-steps of 4
   const size_t PS = (size_t)K;
   const int tid = threadIdx.x;
   const int idx0 = blockIdx.x * kMCols;
   const int wave = tid >> 6, lane = tid & 63;
+  const float H = (float)dp.H;
 
-  // --- A: node values and the nodal part of the body force ---------------
-  for (int it = tid; it < Kp * kMCols; it += kMThreads) {
+  // --- A: node values: body-force combinations (band nodes; zero elsewhere)
+  //     and the correction's node functions (all nodes) -------------------
+  for (int it = tid; it < Np * kMCols; it += kMThreads) {
     const int c = it / kMCols, col = it % kMCols;
     const int idx = idx0 + col;
-    float* xr = XC + c * kMV + col * 10;
-    if (c < P && idx < K) {
+    float* xr = XC + c * kMV + col * kVPC;
+    if (c < N && idx < K) {
       const int kxi = idx / dp.Ny, kyi = idx - kxi * dp.Ny;
       const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
       const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
       const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
-      float2 v[6];
+      if (c >= lo && c <= hi) {
+        float2 v[6];
 #pragma unroll
-      for (int ch = 0; ch < 6; ++ch) v[ch] = in[(ch * N + lo + c) * PS + idx];
-      // f~x = Fx + (1/2) i ky Gz ; f~y = Fy - (1/2) i kx Gz ;
-      // f~z = Fz + (1/2)(i kx Gy - i ky Gx)
-      xr[0] = v[0].x - 0.5f * ky * v[5].y;
-      xr[1] = v[0].y + 0.5f * ky * v[5].x;
-      xr[2] = v[1].x + 0.5f * kx * v[5].y;
-      xr[3] = v[1].y - 0.5f * kx * v[5].x;
-      xr[4] = v[2].x - 0.5f * kx * v[4].y + 0.5f * ky * v[3].y;
-      xr[5] = v[2].y + 0.5f * kx * v[4].x - 0.5f * ky * v[3].x;
-      xr[6] = v[3].x; xr[7] = v[3].y;
-      xr[8] = v[4].x; xr[9] = v[4].y;
+        for (int ch = 0; ch < 6; ++ch) v[ch] = in[(ch * N + c) * PS + idx];
+        // f~x = Fx + (1/2) i ky Gz ; f~y = Fy - (1/2) i kx Gz ;
+        // f~z = Fz + (1/2)(i kx Gy - i ky Gx)
+        xr[0] = v[0].x - 0.5f * ky * v[5].y;
+        xr[1] = v[0].y + 0.5f * ky * v[5].x;
+        xr[2] = v[1].x + 0.5f * kx * v[5].y;
+        xr[3] = v[1].y - 0.5f * kx * v[5].x;
+        xr[4] = v[2].x - 0.5f * kx * v[4].y + 0.5f * ky * v[3].y;
+        xr[5] = v[2].y + 0.5f * kx * v[4].x - 0.5f * ky * v[3].x;
+        xr[6] = v[3].x; xr[7] = v[3].y;
+        xr[8] = v[4].x; xr[9] = v[4].y;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 10; ++e) xr[e] = 0.f;
+      }
+      const float k = sqrtf(kx * kx + ky * ky);
+      const float z = (float)zc[c];
+      const float eb = expf(-k * z);
+      xr[10] = eb;
+      xr[11] = z * eb;
+      if constexpr (GEOM == 1) {
+        const float et = expf(k * (z - H));
+        xr[12] = et;
+        xr[13] = z * et;
+      }
     } else {
 #pragma unroll
-      for (int e = 0; e < 10; ++e) xr[e] = 0.f;
+      for (int e = 0; e < kVPC; ++e) xr[e] = 0.f;
     }
   }
   __syncthreads();
@@ -787,23 +830,23 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
   const int i16 = lane & 15, k4 = lane >> 4;
   // --- B: forward Chebyshev transform, Cf = Mt X ----------------------------
   {
-    f4v acc[kTilesPerWave];
+    f4v acc[Lay::kTilesPerWave];
 #pragma unroll
-    for (int t = 0; t < kTilesPerWave; ++t) {
+    for (int t = 0; t < Lay::kTilesPerWave; ++t) {
       const int tile = wave + t * (kMThreads / 64);
       const int n0 = (tile & 1) * 16, v0 = (tile >> 1) * 16;
       acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
       const int n = n0 + i16;
-      for (int kk = 0; kk < Kp; kk += 4) {
+      for (int kk = 0; kk < Np; kk += 4) {
         const int c = kk + k4;
-        const float a = (c < P && n < N) ? Mf32[(lo + c) * N + n] : 0.f;
+        const float a = (c < N && n < N) ? Mf32[c * N + n] : 0.f;
         const float b = XC[c * kMV + v0 + i16];
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < kTilesPerWave; ++t) {
+    for (int t = 0; t < Lay::kTilesPerWave; ++t) {
       const int tile = wave + t * (kMThreads / 64);
       const int n0 = (tile & 1) * 16, v0 = (tile >> 1) * 16;
 #pragma unroll
@@ -825,7 +868,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const double ky = 2.0 * M_PI * nyi / dp.Ly;
     const double k = sqrt(kx * kx + ky * ky);
     const double s2H = 2.0 / dp.H;
-    float* cbase = XC + 4 * l * kMV + cl * 10;
+    float* cbase = XC + 4 * l * kMV + cl * kVPC;
     Vec U = vzero(), V = vzero(), W = vzero();
     if (!nyq) {
       auto load = [&](int v) {
@@ -837,7 +880,11 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
         }
         return a;
       };
-      seg_column_solve<GEOM>(load, dp, zc, Mf, N, l, kx, ky, k, U, V, W);
+      auto basis = [&](int which, double o[kNpl]) {
+#pragma unroll
+        for (int j = 0; j < kNpl; ++j) o[j] = (double)cbase[j * kMV + 10 + which];
+      };
+      seg_column_solve<GEOM>(load, basis, dp, N, l, kx, ky, k, U, V, W);
     }
     // the column's coefficients are read only by its own eight lanes (one
     // wavefront, in lockstep): overwrite them in place
@@ -860,15 +907,15 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
   // --- D: inverse transform to the band nodes, D = T Cf -----------------------
   {
     const int ctiles = (P + 15) / 16;
-    f4v acc[kTilesPerWave];
+    f4v acc[Lay::kTilesPerWave];
 #pragma unroll
-    for (int t = 0; t < kTilesPerWave; ++t) {
+    for (int t = 0; t < Lay::kTilesPerWave; ++t) {
       const int tile = wave + t * (kMThreads / 64);
       acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
       if (tile < ctiles * (kMV / 16)) {
         const int c0 = (tile % ctiles) * 16, v0 = (tile / ctiles) * 16;
         const int c = c0 + i16;
-        for (int kk = 0; kk < 32; kk += 4) {
+        for (int kk = 0; kk < Np; kk += 4) {
           const int n = kk + k4;
           const float a = (c < P && n < N) ? Pi32[(lo + c) * N + n] : 0.f;
           const float b = XC[n * kMV + v0 + i16];
@@ -878,7 +925,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < kTilesPerWave; ++t) {
+    for (int t = 0; t < Lay::kTilesPerWave; ++t) {
       const int tile = wave + t * (kMThreads / 64);
       if (tile < ctiles * (kMV / 16)) {
         const int c0 = (tile % ctiles) * 16, v0 = (tile / ctiles) * 16;
@@ -899,7 +946,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
     const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
     const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
-    const float* d = XC + c * kMV + col * 10;
+    const float* d = XC + c * kMV + col * kVPC;
     const float ur = d[0], ui = d[1], vr = d[2], vi = d[3], wr = d[4], wi = d[5];
     const float dur = d[6], dui = d[7], dvr = d[8], dvi = d[9];
     float2 o[6];
@@ -924,7 +971,7 @@ static void launch_seg_geom(const fcmdp_solver* s, const ColParams& cp,
     hipLaunchKernelGGL((k_columns_mfma<GEOM>), dim3((K + kMCols - 1) / kMCols),
                        dim3(kMThreads), 0, st, cp, s->band,
                        (const float2*)spec_in, (float2*)spec_out, s->zc,
-                       s->dct_f, s->dct_f32, s->dct_i32);
+                       s->dct_f32, s->dct_i32);
   } else if (s->mixed) {
     constexpr int cols = ColsPerBlock<float>::value;
     hipLaunchKernelGGL((k_columns_seg<float, GEOM>), dim3((K + cols - 1) / cols),
