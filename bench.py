@@ -49,7 +49,63 @@ def stage_bytes(box, n, band, complex_bytes=8, real_bytes=4):
     }
 
 
-def cpu_baseline(name, factor=8):
+# the kernel each single-kernel stage launches once per apply
+STAGE_KERNEL = {"spread": "k_spread_wave", "columns": "k_columns_mfma",
+                "interp": "k_interp_tiled"}
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counters
+    (profiles/traffic_<workload>.json), or None if there are none or the
+    kernel's sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not kernel or not os.path.exists(path):
+        return None
+    from paper_2210_01837_amd.profiling import source_hash
+    with open(path) as fh:
+        t = json.load(fh)
+    k = t.get("kernels", {}).get(kernel)
+    if not k or k.get("source_hash") != source_hash(kernel):
+        return None
+    return k["bytes_per_launch"]
+
+
+def fp64_comparison(name="bw131k", steps=5):
+    """Mixed vs FP64 GPU applies on the same inputs: time and agreement."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2210_01837_amd import Solver
+    wl = workloads.WORKLOADS[name]
+    pos, F, T = workloads.particles(name)
+    out = {"workload": name, "N": wl.n}
+    res = {}
+    for prec, dt in (("mixed", torch.float32), ("fp64", torch.float64)):
+        s = Solver.from_box(wl.box, precision=prec, max_particles=wl.n)
+        Pd, Fd, Td = (torch.tensor(a, dtype=dt, device="cuda") for a in (pos, F, T))
+        U = torch.empty_like(Pd)
+        Om = torch.empty_like(Pd)
+        s.apply(Pd, Fd, Td, U=U, Omega=Om)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            s.apply(Pd, Fd, Td, U=U, Omega=Om)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"ms_{prec}"] = e0.elapsed_time(e1) / steps
+        res[prec] = (U.double().cpu().numpy(), Om.double().cpu().numpy())
+        s.close()
+    (Um, Om_m), (Ud, Od) = res["mixed"], res["fp64"]
+    out["speedup_mixed_over_fp64"] = out["ms_fp64"] / out["ms_mixed"]
+    out["rel_err_U_mixed_vs_fp64"] = float(np.linalg.norm(Um - Ud) / np.linalg.norm(Ud))
+    out["rel_err_Omega_mixed_vs_fp64"] = float(np.linalg.norm(Om_m - Od) / np.linalg.norm(Od))
+    return out
+
+
+def cpu_baseline(name, factor=4):
     """Time the oracle on a 1/factor x 1/factor sub-box of the workload."""
     import numpy as np  # noqa: F401
     from threadpoolctl import threadpool_limits
@@ -120,6 +176,7 @@ def main():
     ap.add_argument("--workload", default="bw1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-fp64-comparison", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for "
@@ -165,12 +222,16 @@ def main():
     torch.cuda.synchronize()
     s.stage_times()                         # discard warm-up events
     s.set_profiling(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record()
+    for i in range(args.steps):
         s.apply(P, Fd, Td, U=U, Omega=Om)
+        ev[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    per_apply = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
     s.set_profiling(False)
     stages, napplies, band = s.stage_times()
     code, bad = s.status()
@@ -183,11 +244,15 @@ def main():
     nbytes = stage_bytes(box, wl.n, band,
                          complex_bytes=8 if wl.precision == "mixed" else 16,
                          real_bytes=4 if wl.precision == "mixed" else 8)
+    # dominant stage; its kernel (one launch per apply for the columns,
+    # spread and interp stages) is what the roofline describes
     dom = max((k for k in nbytes), key=lambda k: avg[k])
     achieved = nbytes[dom] / (avg[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved,
+    kname = STAGE_KERNEL.get(dom)
+    roofline = {"bound": "hbm", "kernel": kname or dom, "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(name, kname),
                 "algorithmic_bytes": nbytes[dom], "avg_ms": avg[dom]}
     stage_gbs = {k: nbytes[k] / (avg[k] * 1e-3) / 1e9 for k in nbytes}
 
@@ -211,6 +276,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_apply_median": per_apply[len(per_apply) // 2],
+        "ms_per_apply_max": per_apply[-1],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -232,6 +299,10 @@ def main():
     }
     del P, Fd, Td, U, Om
     s.close()
+    if not args.no_fp64_comparison:
+        line["fp64_comparison"] = fp64_comparison()
+        print(f"[bench] fp64 comparison: {line['fp64_comparison']}",
+              file=sys.stderr, flush=True)
     if not args.no_serving:
         sv = serving_bench(args.serving_requests)
         line["serving"] = sv
