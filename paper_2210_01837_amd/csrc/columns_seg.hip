@@ -737,7 +737,7 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
 // wall correction's node functions e^{-k z}, z e^{-k z} (and, between two
 // walls, e^{k(z-H)}, z e^{k(z-H)}), so their coefficients come out of the
 // same product.
-//   X[c][v]  = node values, v = col * kVPC + component          (LDS, fp32)
+//   X[c][v]  = node values (layout in MfmaLayout)                    (LDS, fp32)
 //   Cf[n][v] = sum_c Mt[n][c] X[c][v]          (v_mfma_f32_16x16x4f32)
 //   solve: Cf -> coefficients of u, v, w, du/dz, dv/dz (in place)
 //   D[c][v]  = sum_n T_n(s_c) Cf[n][v]         (MFMA again), then omega and
@@ -748,14 +748,24 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kMCols = 16;                 // columns per workgroup
 constexpr int kMThreads = kMCols * kSeg;   // 128
+// XC columns: [0, 160) the five complex node vectors of the 16 columns
+// (col * 10 + component; rows = band nodes c - lo), then [160, 160 + 16 NB)
+// the NB correction node functions (col * NB + b; rows = all nodes c).
 template <int GEOM> struct MfmaLayout {
   static constexpr int kBasis = GEOM == 0 ? 2 : 4;     // correction node functions
-  static constexpr int kVPC = 10 + kBasis;             // reals per column
-  static constexpr int kMV = kMCols * kVPC;            // reals per node row
-  static constexpr int kTiles = 2 * (kMV / 16);        // 16 x 16 output tiles
-  static constexpr int kTilesPerWave = kTiles / (kMThreads / 64);
+  static constexpr int kSpec = kMCols * 10;            // spectral reals per row
+  static constexpr int kMV = kSpec + kMCols * kBasis;  // reals per row
+  static constexpr int kSpecTiles = 2 * (kSpec / 16);  // forward, band rows
+  static constexpr int kBasisTiles = 2 * kBasis;       // forward, all nodes
+  static constexpr int kFwdPerWave =
+      (kSpecTiles + kBasisTiles) / (kMThreads / 64);
+  static constexpr int kInvPerWave = 2 * (kSpec / 16) / (kMThreads / 64);
 };
 
+// Asynchronous copy of one group's band inputs into LDS: one instruction
+// moves 8 rows of 16 columns (16 bytes per lane).  K is even, so a lane's
+// column pair never straddles the end; columns past the end are redirected
+// to the last pair (loaded, never used).
 template <int GEOM>
 __global__ void __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_columns_mfma(ColParams cp, const int* __restrict__ band,
@@ -763,7 +773,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
                const double* __restrict__ zc, const float* __restrict__ Mf32,
                const float* __restrict__ Pi32) {
   using Lay = MfmaLayout<GEOM>;
-  constexpr int kVPC = Lay::kVPC, kMV = Lay::kMV;
+  constexpr int kMV = Lay::kMV, kSpec = Lay::kSpec, NB = Lay::kBasis;
   // one buffer: node values (A), then coefficients (B, C), then band node
   // values (D, E); each transform keeps its output tiles in registers until
   // every wave has finished reading its input
@@ -774,28 +784,31 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
   const int K = dp.Nkx * dp.Ny;
   const int N = dp.Nz;
   const int P = hi - lo + 1;
-  const int Np = (N + 3) & ~3;             // node count padded for k-steps of 4
+  const int Pp = (P + 3) & ~3;             // band rows padded for k-steps of 4
+  const int Np = (N + 3) & ~3;             // node count padded likewise
   const size_t PS = (size_t)K;
   const int tid = threadIdx.x;
-  const int idx0 = blockIdx.x * kMCols;
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const float H = (float)dp.H;
+  const int idx0 = blockIdx.x * kMCols;
 
-  // --- A: node values: body-force combinations (band nodes; zero elsewhere)
-  //     and the correction's node functions (all nodes) -------------------
-  for (int it = tid; it < Np * kMCols; it += kMThreads) {
-    const int c = it / kMCols, col = it % kMCols;
+  // --- A: band node values of the body-force combinations, and the
+  //     correction's node functions at all nodes --------------------------
+#pragma unroll
+  for (int i = 0; i < 32 * kMCols / kMThreads; ++i) {
+    const int it = tid + i * kMThreads;
+    const int c = it / kMCols, col = it % kMCols;      // band-relative row
     const int idx = idx0 + col;
-    float* xr = XC + c * kMV + col * kVPC;
-    if (c < N && idx < K) {
-      const int kxi = idx / dp.Ny, kyi = idx - kxi * dp.Ny;
-      const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
-      const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
-      const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
-      if (c >= lo && c <= hi) {
+    float* xr = XC + c * kMV + col * 10;
+    if (c < Pp) {
+      if (c < P && idx < K) {
+        const int kxi = idx / dp.Ny, kyi = idx - kxi * dp.Ny;
+        const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
+        const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
+        const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
         float2 v[6];
 #pragma unroll
-        for (int ch = 0; ch < 6; ++ch) v[ch] = in[(ch * N + c) * PS + idx];
+        for (int ch = 0; ch < 6; ++ch) v[ch] = in[(ch * N + lo + c) * PS + idx];
         // f~x = Fx + (1/2) i ky Gz ; f~y = Fy - (1/2) i kx Gz ;
         // f~z = Fz + (1/2)(i kx Gy - i ky Gx)
         xr[0] = v[0].x - 0.5f * ky * v[5].y;
@@ -810,45 +823,71 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
 #pragma unroll
         for (int e = 0; e < 10; ++e) xr[e] = 0.f;
       }
-      const float k = sqrtf(kx * kx + ky * ky);
-      const float z = (float)zc[c];
-      const float eb = expf(-k * z);
-      xr[10] = eb;
-      xr[11] = z * eb;
-      if constexpr (GEOM == 1) {
-        const float et = expf(k * (z - H));
-        xr[12] = et;
-        xr[13] = z * et;
+    }
+    // c is also the absolute node of the correction functions
+    float* br = XC + c * kMV + kSpec + col * NB;
+    if (c < Np) {
+      float eb = 0.f, ezb = 0.f, et = 0.f, ezt = 0.f;
+      if (c < N && idx < K) {
+        const int kxi = idx / dp.Ny, kyi = idx - kxi * dp.Ny;
+        const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
+        const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
+        const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
+        const float k = sqrtf(kx * kx + ky * ky);
+        const float z = (float)zc[c];
+        eb = expf(-k * z);
+        ezb = z * eb;
+        if constexpr (GEOM == 1) {
+          et = expf(k * (z - H));
+          ezt = z * et;
+        }
       }
-    } else {
-#pragma unroll
-      for (int e = 0; e < kVPC; ++e) xr[e] = 0.f;
+      br[0] = eb;
+      br[1] = ezb;
+      if constexpr (GEOM == 1) {
+        br[2] = et;
+        br[3] = ezt;
+      }
     }
   }
   __syncthreads();
 
   const int i16 = lane & 15, k4 = lane >> 4;
   // --- B: forward Chebyshev transform, Cf = Mt X ----------------------------
+  //     spectral tiles sum over the band nodes, correction tiles over all
   {
-    f4v acc[Lay::kTilesPerWave];
+    f4v acc[Lay::kFwdPerWave];
 #pragma unroll
-    for (int t = 0; t < Lay::kTilesPerWave; ++t) {
+    for (int t = 0; t < Lay::kFwdPerWave; ++t) {
       const int tile = wave + t * (kMThreads / 64);
-      const int n0 = (tile & 1) * 16, v0 = (tile >> 1) * 16;
       acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+      const int n0 = (tile & 1) * 16;
       const int n = n0 + i16;
-      for (int kk = 0; kk < Np; kk += 4) {
-        const int c = kk + k4;
-        const float a = (c < N && n < N) ? Mf32[c * N + n] : 0.f;
-        const float b = XC[c * kMV + v0 + i16];
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+      if (tile < Lay::kSpecTiles) {
+        const int v0 = (tile >> 1) * 16;
+        for (int kk = 0; kk < Pp; kk += 4) {
+          const int c = kk + k4;
+          const float a = (c < P && n < N) ? Mf32[(lo + c) * N + n] : 0.f;
+          const float b = XC[c * kMV + v0 + i16];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        }
+      } else {
+        const int v0 = kSpec + ((tile - Lay::kSpecTiles) >> 1) * 16;
+        for (int kk = 0; kk < Np; kk += 4) {
+          const int c = kk + k4;
+          const float a = (c < N && n < N) ? Mf32[c * N + n] : 0.f;
+          const float b = XC[c * kMV + v0 + i16];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < Lay::kTilesPerWave; ++t) {
+    for (int t = 0; t < Lay::kFwdPerWave; ++t) {
       const int tile = wave + t * (kMThreads / 64);
-      const int n0 = (tile & 1) * 16, v0 = (tile >> 1) * 16;
+      const int n0 = (tile & 1) * 16;
+      const int v0 = tile < Lay::kSpecTiles ? (tile >> 1) * 16
+                                            : kSpec + ((tile - Lay::kSpecTiles) >> 1) * 16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) XC[(n0 + 4 * k4 + r) * kMV + v0 + i16] = acc[t][r];
     }
@@ -868,21 +907,22 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const double ky = 2.0 * M_PI * nyi / dp.Ly;
     const double k = sqrt(kx * kx + ky * ky);
     const double s2H = 2.0 / dp.H;
-    float* cbase = XC + 4 * l * kMV + cl * kVPC;
+    float* cbase = XC + 4 * l * kMV + cl * 10;
+    float* bbase = XC + 4 * l * kMV + kSpec + cl * NB;
     Vec U = vzero(), V = vzero(), W = vzero();
     if (!nyq) {
       auto load = [&](int v) {
         Vec a;
 #pragma unroll
         for (int j = 0; j < kNpl; ++j) {
-          const float* cr = cbase + j * kMV + 2 * v;
+          float* cr = cbase + j * kMV + 2 * v;
           a.v[j] = zmk((double)cr[0], (double)cr[1]);
         }
         return a;
       };
       auto basis = [&](int which, double o[kNpl]) {
 #pragma unroll
-        for (int j = 0; j < kNpl; ++j) o[j] = (double)cbase[j * kMV + 10 + which];
+        for (int j = 0; j < kNpl; ++j) o[j] = (double)bbase[j * kMV + which];
       };
       seg_column_solve<GEOM>(load, basis, dp, N, l, kx, ky, k, U, V, W);
     }
@@ -907,12 +947,12 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
   // --- D: inverse transform to the band nodes, D = T Cf -----------------------
   {
     const int ctiles = (P + 15) / 16;
-    f4v acc[Lay::kTilesPerWave];
+    f4v acc[Lay::kInvPerWave];
 #pragma unroll
-    for (int t = 0; t < Lay::kTilesPerWave; ++t) {
+    for (int t = 0; t < Lay::kInvPerWave; ++t) {
       const int tile = wave + t * (kMThreads / 64);
       acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
-      if (tile < ctiles * (kMV / 16)) {
+      if (tile < ctiles * (kSpec / 16)) {
         const int c0 = (tile % ctiles) * 16, v0 = (tile / ctiles) * 16;
         const int c = c0 + i16;
         for (int kk = 0; kk < Np; kk += 4) {
@@ -925,9 +965,9 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < Lay::kTilesPerWave; ++t) {
+    for (int t = 0; t < Lay::kInvPerWave; ++t) {
       const int tile = wave + t * (kMThreads / 64);
-      if (tile < ctiles * (kMV / 16)) {
+      if (tile < ctiles * (kSpec / 16)) {
         const int c0 = (tile % ctiles) * 16, v0 = (tile / ctiles) * 16;
 #pragma unroll
         for (int r = 0; r < 4; ++r) XC[(c0 + 4 * k4 + r) * kMV + v0 + i16] = acc[t][r];
@@ -946,7 +986,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
     const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
     const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
-    const float* d = XC + c * kMV + col * kVPC;
+    float* d = XC + c * kMV + col * 10;
     const float ur = d[0], ui = d[1], vr = d[2], vi = d[3], wr = d[4], wi = d[5];
     const float dur = d[6], dui = d[7], dvr = d[8], dvi = d[9];
     float2 o[6];
