@@ -338,9 +338,11 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
     s->codelet_y = fcmdp::fft_codelet(p->Ny, fp32, &s->wplan_y, &s->tpr_y);
     if (s->codelet_x >= 0) s->wave_x = true;
     if (s->codelet_y >= 0) s->wave_y = true;
-    s->rows_x = rows_fitting((size_t)(p->Nx / 2 + 1) * csz, 16);
+    // LDS rows carry one pad element per 32
+    const int mx = p->Nx / 2, my = p->Ny - 1;
+    s->rows_x = rows_fitting((size_t)(mx + (mx >> 5) + 1) * csz, 16);
     // rows of the y pass are independent; one per workgroup packs LDS best
-    s->rows_y = s->codelet_y >= 0 ? 1 : rows_fitting((size_t)p->Ny * csz, 8);
+    s->rows_y = s->codelet_y >= 0 ? 1 : rows_fitting((size_t)(my + (my >> 5) + 1) * csz, 8);
     if (s->rows_x == 0) s->wave_x = false;
     if (s->rows_y == 0) s->wave_y = false;
   }
@@ -552,7 +554,8 @@ int fcmdp_set_variant(fcmdp_solver* s, int key, int value) {
     case FCMDP_VARIANT_FFT_ROWS_X:
     case FCMDP_VARIANT_FFT_ROWS_Y: {
       const bool x = key == FCMDP_VARIANT_FFT_ROWS_X;
-      const size_t row = x ? (size_t)(s->p.Nx / 2 + 1) * csz : (size_t)s->p.Ny * csz;
+      const int len = x ? s->p.Nx / 2 : s->p.Ny - 1;      // last index of a row
+      const size_t row = (size_t)(len + (len >> 5) + 1) * csz;
       const int maxr = x ? 16 : 8;   // capped at 1024 threads per workgroup
       int r = value;
       if (r == 0) r = rows_fitting(row, maxr);

@@ -754,7 +754,9 @@ constexpr int kMThreads = kMCols * kSeg;   // 128
 template <int GEOM> struct MfmaLayout {
   static constexpr int kBasis = GEOM == 0 ? 2 : 4;     // correction node functions
   static constexpr int kSpec = kMCols * 10;            // spectral reals per row
-  static constexpr int kMV = kSpec + kMCols * kBasis;  // reals per row
+  // reals per row; the odd pad spreads the eight lanes of a column (rows
+  // 4l + j) over different LDS banks
+  static constexpr int kMV = kSpec + kMCols * kBasis + 1;
   static constexpr int kSpecTiles = 2 * (kSpec / 16);  // forward, band rows
   static constexpr int kBasisTiles = 2 * kBasis;       // forward, all nodes
   static constexpr int kFwdPerWave =

@@ -319,6 +319,10 @@ k_fft_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
 // workgroup barrier; with more threads per row all rows of the workgroup
 // step through the (identical) stage sequence together.
 
+// LDS rows are padded by one element every 32, so that the strided
+// butterfly writes of the early stages spread over the banks.
+__host__ __device__ constexpr int lp(int i) { return i + (i >> 5); }
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -346,7 +350,7 @@ __device__ __forceinline__ void stage_body(cplx_t<T>* row, int N, int Ns, int t,
     const int j = t + TPR * i;
     if (j < nb) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[i][q] = row[j + q * nb];
+      for (int q = 0; q < R; ++q) v[i][q] = row[lp(j + q * nb)];
     }
   }
   row_sync<TPR>();
@@ -371,7 +375,7 @@ __device__ __forceinline__ void stage_body(cplx_t<T>* row, int N, int Ns, int t,
       else dft_prime<T, C, R>(x, cs, sign);
       const int out = (j - k) * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) row[out + q * Ns] = x[q];
+      for (int q = 0; q < R; ++q) row[lp(out + q * Ns)] = x[q];
     }
   }
   row_sync<TPR>();
@@ -484,7 +488,7 @@ k_fftw_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   extern __shared__ unsigned char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
   const int M = dp.Nx / 2;
-  const int S = M + 1;                              // row stride in LDS
+  const int S = lp(M) + 1;                          // padded row stride in LDS
   const int p = blockIdx.y;
   const int c = p % dp.Nz;
   if (c < band[0] || c > band[1]) return;           // whole workgroup
@@ -497,26 +501,26 @@ k_fftw_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   const int y = wr < nr ? y0 + wr : y0;
   const C* src = reinterpret_cast<const C*>(grid + ((size_t)p * dp.Ny + y) * dp.Nx);
 #pragma unroll 4
-  for (int i = t; i < M; i += TPR) row[i] = src[i];
+  for (int i = t; i < M; i += TPR) row[lp(i)] = src[i];
   row_sync<TPR>();
   Run::template run<T, TPR>(row, M, plan, t, tw, dftc, doff, T(-1));
   for (int k = t; k <= M / 2; k += TPR) {
-    const C zk = row[k];
+    const C zk = row[lp(k)];
     if (k == 0) {
       row[0] = r2c_post(zk, zk, rtw[0]);
-      row[M] = r2c_post(zk, zk, rtw[M]);
+      row[lp(M)] = r2c_post(zk, zk, rtw[M]);
     } else {
-      const C zm = row[M - k];
-      row[k] = r2c_post(zk, zm, rtw[k]);
-      if (M - k != k) row[M - k] = r2c_post(zm, zk, rtw[M - k]);
+      const C zm = row[lp(M - k)];
+      row[lp(k)] = r2c_post(zk, zm, rtw[k]);
+      if (M - k != k) row[lp(M - k)] = r2c_post(zm, zk, rtw[M - k]);
     }
   }
   __syncthreads();
   const size_t pbase = (size_t)p * dp.Nkx * dp.Ny;
-  for (int idx = threadIdx.x; idx < S * ROWS; idx += ROWS * TPR) {
+  for (int idx = threadIdx.x; idx < (M + 1) * ROWS; idx += ROWS * TPR) {
     const int k = idx / ROWS;
     const int r = idx % ROWS;
-    if (r < nr) spec[pbase + (size_t)k * dp.Ny + y0 + r] = lds[r * S + k];
+    if (r < nr) spec[pbase + (size_t)k * dp.Ny + y0 + r] = lds[r * S + lp(k)];
   }
 }
 
@@ -537,15 +541,15 @@ k_fftw_y(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   const bool live = kx < dp.Nkx;
   if (TPR == 64 && !live) return;                   // a whole wavefront
   const int N = dp.Ny;
-  C* row = reinterpret_cast<C*>(lds_raw) + wr * N;
+  C* row = reinterpret_cast<C*>(lds_raw) + wr * (lp(N - 1) + 1);
   C* g = spec + ((size_t)p * dp.Nkx + (live ? kx : 0)) * N;
 #pragma unroll 4
-  for (int i = t; i < N; i += TPR) row[i] = g[i];
+  for (int i = t; i < N; i += TPR) row[lp(i)] = g[i];
   row_sync<TPR>();
   Run::template run<T, TPR>(row, N, plan, t, tw, dftc, doff, sign);
   if (live) {
 #pragma unroll 4
-    for (int i = t; i < N; i += TPR) g[i] = row[i];
+    for (int i = t; i < N; i += TPR) g[i] = row[lp(i)];
   }
 }
 
@@ -561,18 +565,18 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   extern __shared__ unsigned char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
   const int M = dp.Nx / 2;
-  const int S = M + 1;
+  const int S = lp(M) + 1;                          // padded row stride in LDS
   const int p = blockIdx.y;
   const int c = p % dp.Nz;
   if (c < band[0] || c > band[1]) return;
   const int y0 = blockIdx.x * ROWS;
   const int nr = min(ROWS, dp.Ny - y0);
   const size_t pbase = (size_t)p * dp.Nkx * dp.Ny;
-  for (int idx = threadIdx.x; idx < S * ROWS; idx += ROWS * TPR) {
+  for (int idx = threadIdx.x; idx < (M + 1) * ROWS; idx += ROWS * TPR) {
     const int k = idx / ROWS;
     const int r = idx % ROWS;
     // rows past the grid edge transform a copy of row y0
-    lds[r * S + k] = spec[pbase + (size_t)k * dp.Ny + y0 + (r < nr ? r : 0)];
+    lds[r * S + lp(k)] = spec[pbase + (size_t)k * dp.Ny + y0 + (r < nr ? r : 0)];
   }
   __syncthreads();
   const int wr = __builtin_amdgcn_readfirstlane(threadIdx.x / TPR);
@@ -580,14 +584,14 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   C* row = lds + wr * S;
   for (int k = t; k <= M / 2; k += TPR) {
     if (k == 0) {
-      C x0 = row[0], xm = row[M];
+      C x0 = row[0], xm = row[lp(M)];
       x0.y = T(0);
       xm.y = T(0);
       row[0] = c2r_pre(x0, xm, rtw[0]);
     } else {
-      const C xk = row[k], xm = row[M - k];
-      row[k] = c2r_pre(xk, xm, rtw[k]);
-      if (M - k != k) row[M - k] = c2r_pre(xm, xk, rtw[M - k]);
+      const C xk = row[lp(k)], xm = row[lp(M - k)];
+      row[lp(k)] = c2r_pre(xk, xm, rtw[k]);
+      if (M - k != k) row[lp(M - k)] = c2r_pre(xm, xk, rtw[M - k]);
     }
   }
   row_sync<TPR>();
@@ -595,7 +599,7 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   if (wr < nr) {
     C* dst = reinterpret_cast<C*>(grid + ((size_t)p * dp.Ny + y0 + wr) * dp.Nx);
 #pragma unroll 4
-    for (int i = t; i < M; i += TPR) dst[i] = row[i];
+    for (int i = t; i < M; i += TPR) dst[i] = row[lp(i)];
   }
 }
 
@@ -605,7 +609,7 @@ static void launch_wave_x(bool fwd, const fcmdp_solver* s, const void* in,
   using C = cplx_t<T>;
   const DevParams& dp = s->dp;
   const int M = dp.Nx / 2;
-  const size_t lds = (size_t)ROWS * (M + 1) * sizeof(C);
+  const size_t lds = (size_t)ROWS * (lp(M) + 1) * sizeof(C);
   dim3 g((dp.Ny + ROWS - 1) / ROWS, 6 * dp.Nz);
   const T* cs = (const T*)s->dftc_t;
   if (fwd)
@@ -637,7 +641,7 @@ static void launch_wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
                           T sign, hipStream_t st) {
   using C = cplx_t<T>;
   const DevParams& dp = s->dp;
-  const size_t lds = (size_t)ROWS * dp.Ny * sizeof(C);
+  const size_t lds = (size_t)ROWS * (lp(dp.Ny - 1) + 1) * sizeof(C);
   dim3 g((dp.Nkx + ROWS - 1) / ROWS, 6 * dp.Nz);
   hipLaunchKernelGGL((k_fftw_y<T, ROWS, TPR, Run>), g, dim3(ROWS * TPR), lds, st,
                      dp, s->wplan_y, s->band, (C*)spec, (const C*)s->tw_y,
