@@ -25,6 +25,7 @@ __device__ inline Z2 imul(double s, Z2 a) { return zmk(-s * a.y, s * a.x); }
 struct ColParams {
   DevParams dp;
   double scale;       // 1 / (Nx Ny)
+  double kxs, kys;    // 2 pi / Lx, 2 pi / Ly
 };
 
 // 6x6 real Gaussian elimination with partial pivoting, complex RHS.

@@ -311,6 +311,8 @@ hipError_t launch_columns(const fcmdp_solver* s, const void* spec_in,
   ColParams cp;
   cp.dp = s->dp;
   cp.scale = 1.0 / ((double)s->dp.Nx * (double)s->dp.Ny);
+  cp.kxs = 2.0 * M_PI / s->dp.Lx;
+  cp.kys = 2.0 * M_PI / s->dp.Ly;
   const int K = s->dp.Nkx * s->dp.Ny;
   dim3 g((K + 63) / 64);
   const bool small = s->dp.Nz <= 32;

@@ -759,15 +759,18 @@ template <int GEOM> struct MfmaLayout {
   static constexpr int kMV = kSpec + kMCols * kBasis + 1;
   static constexpr int kSpecTiles = 2 * (kSpec / 16);  // forward, band rows
   static constexpr int kBasisTiles = 2 * kBasis;       // forward, all nodes
-  static constexpr int kFwdPerWave =
-      (kSpecTiles + kBasisTiles) / (kMThreads / 64);
   static constexpr int kInvPerWave = 2 * (kSpec / 16) / (kMThreads / 64);
 };
 
-// Asynchronous copy of one group's band inputs into LDS: one instruction
-// moves 8 rows of 16 columns (16 bytes per lane).  K is even, so a lane's
-// column pair never straddles the end; columns past the end are redirected
-// to the last pair (loaded, never used).
+// (kx, ky) indices of column col of a group whose first column has indices
+// (kx0, ky0): columns run over ky fastest.
+__device__ __forceinline__ void col_index(int kx0, int ky0, int col, int Ny,
+                                          int& kxi, int& kyi) {
+  kxi = kx0;
+  kyi = ky0 + col;
+  while (kyi >= Ny) { kyi -= Ny; ++kxi; }
+}
+
 template <int GEOM>
 __global__ void __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_columns_mfma(ColParams cp, const int* __restrict__ band,
@@ -793,6 +796,30 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const float H = (float)dp.H;
   const int idx0 = blockIdx.x * kMCols;
+  // (kx, ky) index of the group's first column; the others follow in ky
+  const int kx0 = idx0 / dp.Ny, ky0 = idx0 - kx0 * dp.Ny;
+  const float kxs = (float)cp.kxs, kys = (float)cp.kys;
+  const int i16 = lane & 15, k4 = lane >> 4;
+
+  // Matrix operands of the transforms, loaded once per wavefront (before the
+  // node values, so that their latency overlaps).  Wavefront w computes the
+  // output rows 16 w .. 16 w + 15 of every forward tile, and the band rows
+  // c0w .. c0w + 15 of every inverse tile.
+  static_assert(kMThreads == 128, "two wavefronts per workgroup");
+  const int ctiles = (P + 15) / 16;          // 1 or 2 (P <= N <= 32)
+  const int c0w = ctiles == 2 ? wave * 16 : 0;
+  float aS[8], aB[8], aI[8];
+  {
+    const int n = wave * 16 + i16;
+    const int cI = c0w + i16;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = 4 * j + k4;
+      aS[j] = (c < P && n < N) ? Mf32[(lo + c) * N + n] : 0.f;
+      aB[j] = (c < N && n < N) ? Mf32[c * N + n] : 0.f;
+      aI[j] = (cI < P && c < N) ? Pi32[(lo + cI) * N + c] : 0.f;
+    }
+  }
 
   // --- A: band node values of the body-force combinations, and the
   //     correction's node functions at all nodes --------------------------
@@ -801,13 +828,14 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const int it = tid + i * kMThreads;
     const int c = it / kMCols, col = it % kMCols;      // band-relative row
     const int idx = idx0 + col;
+    int kxi, kyi;
+    col_index(kx0, ky0, col, dp.Ny, kxi, kyi);
+    const float kx = kxs * (float)kxi;
+    const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
+    const float ky = kys * (float)nyi;
     float* xr = XC + c * kMV + col * 10;
-    if (c < Pp) {
+    {
       if (c < P && idx < K) {
-        const int kxi = idx / dp.Ny, kyi = idx - kxi * dp.Ny;
-        const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
-        const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
-        const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
         float2 v[6];
 #pragma unroll
         for (int ch = 0; ch < 6; ++ch) v[ch] = in[(ch * N + lo + c) * PS + idx];
@@ -828,13 +856,9 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     }
     // c is also the absolute node of the correction functions
     float* br = XC + c * kMV + kSpec + col * NB;
-    if (c < Np) {
+    {
       float eb = 0.f, ezb = 0.f, et = 0.f, ezt = 0.f;
       if (c < N && idx < K) {
-        const int kxi = idx / dp.Ny, kyi = idx - kxi * dp.Ny;
-        const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
-        const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
-        const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
         const float k = sqrtf(kx * kx + ky * ky);
         const float z = (float)zc[c];
         eb = expf(-k * z);
@@ -854,44 +878,43 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
   }
   __syncthreads();
 
-  const int i16 = lane & 15, k4 = lane >> 4;
   // --- B: forward Chebyshev transform, Cf = Mt X ----------------------------
-  //     spectral tiles sum over the band nodes, correction tiles over all
+  //     spectral tiles sum over the band nodes, correction tiles over all;
+  //     wavefront w owns the tiles (w, v0) for every column block v0
   {
-    f4v acc[Lay::kFwdPerWave];
+    constexpr int kST = Lay::kSpecTiles / 2, kBT = Lay::kBasisTiles / 2;
+    f4v acc[kST + kBT];
 #pragma unroll
-    for (int t = 0; t < Lay::kFwdPerWave; ++t) {
-      const int tile = wave + t * (kMThreads / 64);
-      acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
-      const int n0 = (tile & 1) * 16;
-      const int n = n0 + i16;
-      if (tile < Lay::kSpecTiles) {
-        const int v0 = (tile >> 1) * 16;
-        for (int kk = 0; kk < Pp; kk += 4) {
-          const int c = kk + k4;
-          const float a = (c < P && n < N) ? Mf32[(lo + c) * N + n] : 0.f;
-          const float b = XC[c * kMV + v0 + i16];
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
-        }
-      } else {
-        const int v0 = kSpec + ((tile - Lay::kSpecTiles) >> 1) * 16;
-        for (int kk = 0; kk < Np; kk += 4) {
-          const int c = kk + k4;
-          const float a = (c < N && n < N) ? Mf32[c * N + n] : 0.f;
-          const float b = XC[c * kMV + v0 + i16];
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
-        }
+    for (int t = 0; t < kST + kBT; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+    // k-steps outermost: the independent tiles keep the matrix pipe busy
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float* row = XC + (4 * j + k4) * kMV + i16;
+      if (4 * j < Pp) {
+        float b[kST];
+#pragma unroll
+        for (int t = 0; t < kST; ++t) b[t] = row[t * 16];
+#pragma unroll
+        for (int t = 0; t < kST; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aS[j], b[t], acc[t], 0, 0, 0);
+      }
+      if (4 * j < Np) {
+        float b[kBT];
+#pragma unroll
+        for (int t = 0; t < kBT; ++t) b[t] = row[kSpec + t * 16];
+#pragma unroll
+        for (int t = 0; t < kBT; ++t)
+          acc[kST + t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aB[j], b[t], acc[kST + t],
+                                                              0, 0, 0);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < Lay::kFwdPerWave; ++t) {
-      const int tile = wave + t * (kMThreads / 64);
-      const int n0 = (tile & 1) * 16;
-      const int v0 = tile < Lay::kSpecTiles ? (tile >> 1) * 16
-                                            : kSpec + ((tile - Lay::kSpecTiles) >> 1) * 16;
+    for (int t = 0; t < kST + kBT; ++t) {
+      const int v0 = t < kST ? t * 16 : kSpec + (t - kST) * 16;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) XC[(n0 + 4 * k4 + r) * kMV + v0 + i16] = acc[t][r];
+      for (int r = 0; r < 4; ++r)
+        XC[(wave * 16 + 4 * k4 + r) * kMV + v0 + i16] = acc[t][r];
     }
   }
   __syncthreads();
@@ -901,12 +924,12 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const int cl = tid / kSeg, l = tid % kSeg;
     const int idx = idx0 + cl;
     const bool valid = idx < K;
-    const int kxi = valid ? idx / dp.Ny : 0;
-    const int kyi = valid ? idx - kxi * dp.Ny : 0;
+    int kxi, kyi;
+    col_index(kx0, ky0, cl, dp.Ny, kxi, kyi);
     const bool nyq = !valid || kxi == dp.Nx / 2 || kyi == dp.Ny / 2;
-    const double kx = 2.0 * M_PI * kxi / dp.Lx;
+    const double kx = cp.kxs * kxi;
     const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
-    const double ky = 2.0 * M_PI * nyi / dp.Ly;
+    const double ky = cp.kys * nyi;
     const double k = sqrt(kx * kx + ky * ky);
     const double s2H = 2.0 / dp.H;
     float* cbase = XC + 4 * l * kMV + cl * 10;
@@ -947,32 +970,37 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
   __syncthreads();
 
   // --- D: inverse transform to the band nodes, D = T Cf -----------------------
+  //     wavefront w owns the tiles (c0w, v0); with one band tile the two
+  //     wavefronts split the column blocks
   {
-    const int ctiles = (P + 15) / 16;
-    f4v acc[Lay::kInvPerWave];
+    constexpr int kIT = Lay::kInvPerWave;
+    // tiles of this wavefront: with two band tiles, every column block;
+    // with one, the column blocks w, w + 2, ...
+    const int nt = ctiles == 2 ? kIT : kIT / 2;
+    auto col0 = [&](int t) { return ctiles == 2 ? t * 16 : (wave + 2 * t) * 16; };
+    f4v acc[kIT];
 #pragma unroll
-    for (int t = 0; t < Lay::kInvPerWave; ++t) {
-      const int tile = wave + t * (kMThreads / 64);
-      acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
-      if (tile < ctiles * (kSpec / 16)) {
-        const int c0 = (tile % ctiles) * 16, v0 = (tile / ctiles) * 16;
-        const int c = c0 + i16;
-        for (int kk = 0; kk < Np; kk += 4) {
-          const int n = kk + k4;
-          const float a = (c < P && n < N) ? Pi32[(lo + c) * N + n] : 0.f;
-          const float b = XC[n * kMV + v0 + i16];
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
-        }
+    for (int t = 0; t < kIT; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (4 * j < Np) {
+        const float* row = XC + (4 * j + k4) * kMV + i16;
+        float b[kIT];
+#pragma unroll
+        for (int t = 0; t < kIT; ++t) b[t] = t < nt ? row[col0(t)] : 0.f;
+#pragma unroll
+        for (int t = 0; t < kIT; ++t)
+          if (t < nt)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aI[j], b[t], acc[t], 0, 0, 0);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < Lay::kInvPerWave; ++t) {
-      const int tile = wave + t * (kMThreads / 64);
-      if (tile < ctiles * (kSpec / 16)) {
-        const int c0 = (tile % ctiles) * 16, v0 = (tile / ctiles) * 16;
+    for (int t = 0; t < kIT; ++t) {
+      if (t < nt) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) XC[(c0 + 4 * k4 + r) * kMV + v0 + i16] = acc[t][r];
+        for (int r = 0; r < 4; ++r)
+          XC[(c0w + 4 * k4 + r) * kMV + col0(t) + i16] = acc[t][r];
       }
     }
   }
@@ -984,10 +1012,11 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const int c = it / kMCols, col = it % kMCols;
     const int idx = idx0 + col;
     if (idx >= K) continue;
-    const int kxi = idx / dp.Ny, kyi = idx - kxi * dp.Ny;
-    const float kx = (float)(2.0 * M_PI * kxi / dp.Lx);
+    int kxi, kyi;
+    col_index(kx0, ky0, col, dp.Ny, kxi, kyi);
+    const float kx = kxs * (float)kxi;
     const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
-    const float ky = (float)(2.0 * M_PI * nyi / dp.Ly);
+    const float ky = kys * (float)nyi;
     float* d = XC + c * kMV + col * 10;
     const float ur = d[0], ui = d[1], vr = d[2], vi = d[3], wr = d[4], wi = d[5];
     const float dur = d[6], dui = d[7], dvr = d[8], dvi = d[9];
@@ -1034,6 +1063,8 @@ hipError_t launch_columns_seg(const fcmdp_solver* s, const void* spec_in,
   ColParams cp;
   cp.dp = s->dp;
   cp.scale = 1.0 / ((double)s->dp.Nx * (double)s->dp.Ny);
+  cp.kxs = 2.0 * M_PI / s->dp.Lx;
+  cp.kys = 2.0 * M_PI / s->dp.Ly;
   if (s->dp.geometry == 0)
     launch_seg_geom<0>(s, cp, spec_in, spec_out, st);
   else
