@@ -143,8 +143,11 @@ enum {
   FCMDP_VARIANT_SIMPLE_INTERP = 4,   /* thread-per-particle interpolation */
   FCMDP_VARIANT_GENERIC_COLUMNS = 5, /* thread-per-wavenumber column solve */
   FCMDP_VARIANT_VECTOR_DCT = 6,      /* FP64 Chebyshev transforms in MIXED */
-  FCMDP_VARIANT_NO_CODELET = 7       /* run-time-plan row transforms even
+  FCMDP_VARIANT_NO_CODELET = 7,      /* run-time-plan row transforms even
                                         where a fixed-plan kernel exists */
+  FCMDP_VARIANT_NO_PIPELINE = 8      /* one workgroup per y row instead of
+                                        the persistent row loop that loads
+                                        the next row during a transform */
 };
 int fcmdp_set_variant(fcmdp_solver* s, int key, int value);
 

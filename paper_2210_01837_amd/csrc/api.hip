@@ -292,7 +292,9 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
   if (!s) return FCMDP_ENOMEM;
   s->p = *p;
   s->mixed = p->precision == FCMDP_MIXED;
-  if (hipGetDevice(&s->device) != hipSuccess) {
+  if (hipGetDevice(&s->device) != hipSuccess ||
+      hipDeviceGetAttribute(&s->num_cu, hipDeviceAttributeMultiprocessorCount,
+                            s->device) != hipSuccess) {
     delete s;
     return FCMDP_EHIP;
   }
@@ -338,11 +340,11 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
     s->codelet_y = fcmdp::fft_codelet(p->Ny, fp32, &s->wplan_y, &s->tpr_y);
     if (s->codelet_x >= 0) s->wave_x = true;
     if (s->codelet_y >= 0) s->wave_y = true;
-    // LDS rows carry one pad element per 32
-    const int mx = p->Nx / 2, my = p->Ny - 1;
-    s->rows_x = rows_fitting((size_t)(mx + (mx >> 5) + 1) * csz, 16);
+    const size_t row_x = (size_t)fcmdp::fft_lds_row(s->codelet_x, p->Nx / 2, true) * csz;
+    const size_t row_y = (size_t)fcmdp::fft_lds_row(s->codelet_y, p->Ny, false) * csz;
+    s->rows_x = rows_fitting(row_x, 16);
     // rows of the y pass are independent; one per workgroup packs LDS best
-    s->rows_y = s->codelet_y >= 0 ? 1 : rows_fitting((size_t)(my + (my >> 5) + 1) * csz, 8);
+    s->rows_y = s->codelet_y >= 0 ? 1 : rows_fitting(row_y, 8);
     if (s->rows_x == 0) s->wave_x = false;
     if (s->rows_y == 0) s->wave_y = false;
   }
@@ -554,8 +556,10 @@ int fcmdp_set_variant(fcmdp_solver* s, int key, int value) {
     case FCMDP_VARIANT_FFT_ROWS_X:
     case FCMDP_VARIANT_FFT_ROWS_Y: {
       const bool x = key == FCMDP_VARIANT_FFT_ROWS_X;
-      const int len = x ? s->p.Nx / 2 : s->p.Ny - 1;      // last index of a row
-      const size_t row = (size_t)(len + (len >> 5) + 1) * csz;
+      // rows of the fixed plan (the larger) when there is one
+      const size_t row =
+          (size_t)fcmdp::fft_lds_row(x ? s->codelet_x : s->codelet_y,
+                                     x ? s->p.Nx / 2 : s->p.Ny, x) * csz;
       const int maxr = x ? 16 : 8;   // capped at 1024 threads per workgroup
       int r = value;
       if (r == 0) r = rows_fitting(row, maxr);
@@ -590,6 +594,9 @@ int fcmdp_set_variant(fcmdp_solver* s, int key, int value) {
       }
       return FCMDP_OK;
     }
+    case FCMDP_VARIANT_NO_PIPELINE:
+      s->force_no_pipeline = on;
+      return FCMDP_OK;
     default:
       return FCMDP_EINVAL;
   }

@@ -116,6 +116,9 @@ struct fcmdp_solver {
   bool force_vector_dct = false;
   // use the workgroup-per-row-batch transforms (tests)
   bool force_generic_fft = false;
+  // launch one workgroup per y row instead of the persistent row loop (tests)
+  bool force_no_pipeline = false;
+  int num_cu = 0;               // compute units of the device
 
   // tracing: events of applies not yet summed, 7 per apply
   bool profiling = false;
@@ -146,6 +149,10 @@ hipError_t launch_fft_inverse(const fcmdp_solver* s, void* spec, void* grid,
 // index of a fixed-plan kernel for length n (its plan and threads per row are
 // written to plan / tpr), or -1
 int fft_codelet(int n, bool fp32, FFTPlan* plan, int* tpr);
+// LDS elements per row of the row-owned transforms of length n (x: Nx/2,
+// with room for the Nyquist element; y: Ny) for fixed plan `codelet` (-1:
+// run-time plan)
+int fft_lds_row(int codelet, int n, bool x);
 // columns.hip (dispatches to columns_seg.hip for Nz <= 32)
 hipError_t launch_columns(const fcmdp_solver* s, const void* spec_in,
                           void* spec_out, hipStream_t st);

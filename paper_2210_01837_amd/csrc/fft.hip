@@ -319,9 +319,6 @@ k_fft_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
 // workgroup barrier; with more threads per row all rows of the workgroup
 // step through the (identical) stage sequence together.
 
-// LDS rows are padded by one element every 32, so that the strided
-// butterfly writes of the early stages spread over the banks.
-__host__ __device__ constexpr int lp(int i) { return i + (i >> 5); }
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -336,7 +333,8 @@ __device__ __forceinline__ void row_sync() {
 }
 
 // One Stockham stage of radix R on a row owned by TPR threads; each thread
-// holds up to NB butterflies in registers.
+// holds up to NB butterflies in registers.  Rows are stored unpadded
+// (run-time plans).
 template <typename T, int R, int TPR, int NB>
 __device__ __forceinline__ void stage_body(cplx_t<T>* row, int N, int Ns, int t,
                                            const cplx_t<T>* __restrict__ tw,
@@ -350,7 +348,7 @@ __device__ __forceinline__ void stage_body(cplx_t<T>* row, int N, int Ns, int t,
     const int j = t + TPR * i;
     if (j < nb) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[i][q] = row[lp(j + q * nb)];
+      for (int q = 0; q < R; ++q) v[i][q] = row[j + q * nb];
     }
   }
   row_sync<TPR>();
@@ -375,7 +373,7 @@ __device__ __forceinline__ void stage_body(cplx_t<T>* row, int N, int Ns, int t,
       else dft_prime<T, C, R>(x, cs, sign);
       const int out = (j - k) * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) row[lp(out + q * Ns)] = x[q];
+      for (int q = 0; q < R; ++q) row[out + q * Ns] = x[q];
     }
   }
   row_sync<TPR>();
@@ -418,20 +416,6 @@ __device__ __forceinline__ void row_fft(cplx_t<T>* row, int N,
   }
 }
 
-// Fixed plans ("codelets"): the stage sequence is a template argument, each
-// stage code = 16 R + NB; stages are inlined one after another, so registers
-// are allocated per stage and nothing goes through a call stack.
-template <typename T, int TPR, int Code, int... Rest>
-__device__ __forceinline__ void run_codes(cplx_t<T>* row, int N, int Ns, int t,
-                                          const cplx_t<T>* __restrict__ tw,
-                                          const T* __restrict__ dftc,
-                                          const DftOff& doff, T sign) {
-  constexpr int R = Code >> 4, NB = Code & 15;
-  stage_body<T, R, TPR, NB>(row, N, Ns, t, tw, dftc + doff.off[R], sign);
-  if constexpr (sizeof...(Rest) > 0)
-    run_codes<T, TPR, Rest...>(row, N, Ns * R, t, tw, dftc, doff, sign);
-}
-
 struct GenericRows {
   template <typename T, int TPR>
   __device__ __forceinline__ static void run(cplx_t<T>* row, int N, const FFTPlan& plan, int t,
@@ -440,18 +424,196 @@ struct GenericRows {
                              T sign) {
     row_fft<T, TPR>(row, N, plan, t, tw, dftc, doff.off, sign);
   }
+  // LDS elements a row of n occupies
+  __host__ __device__ static constexpr int span(int n) { return n; }
 };
+
+// ---- fixed plans ("codelets") ----------------------------------------------
+// The stage sequence is a template argument (stage code = 16 R + NB); stages
+// are inlined one after another, so registers are allocated per stage and
+// nothing goes through a call stack.
+//
+// Between stages s and s + 1 the row is stored in LDS with the layout
+//   element i at i + (i / B) * pad          (B a power of two),
+// chosen per boundary at compile time.  B divides both the read stride of
+// stage s + 1 (N / R_{s+1}) and the write stride of stage s (or every
+// radix-R_s block of stage s lies within one B-segment), so that every
+// butterfly input and output sits at a constant offset from one address per
+// butterfly; the pad spreads the strided writes of stage s (lanes R_s
+// elements apart for the first stage) over the LDS banks.  Before the first
+// and after the last stage the row is unpadded.
+struct RowLay {
+  int B, pad;
+};
+
+// bank conflicts of one access of 64 lanes to 8-byte elements at the given
+// element indices: 64 four-byte banks, 32 lanes per cycle
+constexpr int lds_conflicts(const int* idx) {
+  int cost = 0;
+  for (int g = 0; g < 2; ++g) {
+    int cnt[64] = {};
+    int worst = 0;
+    for (int l = 32 * g; l < 32 * g + 32; ++l) {
+      if (idx[l] < 0) continue;
+      for (int h = 0; h < 2; ++h) {
+        const int b = (2 * idx[l] + h) & 63;
+        if (++cnt[b] > worst) worst = cnt[b];
+      }
+    }
+    cost += worst;
+  }
+  return cost;
+}
+
+constexpr int lay_at(RowLay L, int i) { return i + (i / L.B) * L.pad; }
+
+// layout after a stage of radix R with input stride Ns (next stage reads
+// with stride nbn) in a row of length N
+constexpr RowLay choose_lay(int N, int R, int Ns, int nbn) {
+  RowLay best{N, 0};                                // unpadded
+  int best_cost = 1 << 30;
+  for (int B = 1; B < N; B *= 2) {
+    const bool write_lin = Ns % B == 0 || B % (Ns * R) == 0;
+    const bool read_lin = nbn % B == 0;
+    if (!write_lin || !read_lin) continue;
+    // at most one pad element per eight, so that rows grow by 12.5% at most
+    const int max_pad = B >= 8 ? B / 8 : 1;
+    for (int pad = 0; pad <= max_pad; ++pad) {
+      const RowLay L{B, pad};
+      int w[64] = {}, r[64] = {};
+      for (int t = 0; t < 64; ++t) {
+        const int k = t % Ns;
+        const int out = (t - k) * R + k;            // stage output, q = 0
+        w[t] = t < N / R ? lay_at(L, out) : -1;
+        r[t] = t < nbn ? lay_at(L, t) : -1;         // next stage input, q = 0
+      }
+      // conflicts first, then the smallest row
+      const int cost = (lds_conflicts(w) + lds_conflicts(r)) * (1 << 20) +
+                       lay_at(L, N - 1);
+      if (cost < best_cost) {
+        best_cost = cost;
+        best = L;
+      }
+    }
+  }
+  return best;
+}
+
+template <int... Codes>
+struct CodeletLayout {
+  static constexpr int kStages = sizeof...(Codes);
+  static constexpr int kRad[kStages] = {(Codes >> 4)...};
+  static constexpr int kN = (1 * ... * (Codes >> 4));
+  struct Table {
+    RowLay lay[kStages + 1];                        // lay[s]: input of stage s
+    int span;
+    constexpr Table() : lay(), span(kN) {
+      lay[0] = RowLay{kN, 0};
+      int Ns = 1;
+      for (int s = 0; s < kStages; ++s) {
+        if (s + 1 < kStages)
+          lay[s + 1] = choose_lay(kN, kRad[s], Ns, kN / kRad[s + 1]);
+        else
+          lay[s + 1] = RowLay{kN, 0};
+        const int e = lay_at(lay[s + 1], kN - 1) + 1;
+        if (e > span) span = e;
+        Ns *= kRad[s];
+      }
+    }
+  };
+  static constexpr Table kTable = Table();
+};
+
+// One stage of a fixed plan: every size is a compile-time constant, inputs
+// in layout LI, outputs in layout LO.
+template <typename T, int R, int TPR, int NB, int N, int NS, int BI, int PI, int BO,
+          int PO>
+__device__ __forceinline__ void stage_fixed(cplx_t<T>* row, int t,
+                                            const cplx_t<T>* __restrict__ tw,
+                                            const T* __restrict__ cs, T sign) {
+  using C = cplx_t<T>;
+  constexpr RowLay LI{BI, PI}, LO{BO, PO};
+  constexpr int nb = N / R;
+  constexpr int twstep = N / (NS * R);
+  static_assert(nb % BI == 0 || BI >= N, "stage input layout not linear");
+  static_assert(NS % BO == 0 || BO % (NS * R) == 0 || BO >= N,
+                "stage output layout not linear");
+  constexpr int rstep = lay_at(LI, nb);             // offset of input q = 1
+  constexpr int wstep = NS % BO == 0 ? lay_at(LO, NS) : NS;
+  C v[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int j = t + TPR * i;
+    if (j < nb) {
+      const int base = (int)((unsigned)j / BI) * PI + j;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[i][q] = row[base + q * rstep];
+    }
+  }
+  row_sync<TPR>();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int j = t + TPR * i;
+    if (j < nb) {
+      C* x = v[i];
+      const int k = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          C w = tw[q * k * twstep];
+          w.y *= -sign;
+          x[q] = cmul(x[q], w);
+        }
+      }
+      if constexpr (R == 2) dft2<T, C>(x);
+      else if constexpr (R == 4) dft4<T, C>(x, sign);
+      else if constexpr (R == 8) dft8<T, C>(x, sign);
+      else if constexpr (R == 16) dft16<T, C>(x, sign);
+      else dft_prime<T, C, R>(x, cs, sign);
+      const int out = (j - k) * R + k;
+      const int base = (int)((unsigned)out / BO) * PO + out;
+#pragma unroll
+      for (int q = 0; q < R; ++q) row[base + q * wstep] = x[q];
+    }
+  }
+  row_sync<TPR>();
+}
+
+template <typename T, int TPR, typename Lay, int S, int NS, int Code, int... Rest>
+__device__ __forceinline__ void run_codes(cplx_t<T>* row, int t,
+                                          const cplx_t<T>* __restrict__ tw,
+                                          const T* __restrict__ dftc,
+                                          const DftOff& doff, T sign) {
+  constexpr int R = Code >> 4, NB = Code & 15;
+  constexpr RowLay LI = Lay::kTable.lay[S], LO = Lay::kTable.lay[S + 1];
+  stage_fixed<T, R, TPR, NB, Lay::kN, NS, LI.B, LI.pad, LO.B, LO.pad>(
+      row, t, tw, dftc + doff.off[R], sign);
+  if constexpr (sizeof...(Rest) > 0)
+    run_codes<T, TPR, Lay, S + 1, NS * R, Rest...>(row, t, tw, dftc, doff, sign);
+}
 
 template <int... Codes>
 struct FixedRows {
+  using Lay = CodeletLayout<Codes...>;
+  static constexpr int kN = Lay::kN;                // transform length
   template <typename T, int TPR>
-  __device__ __forceinline__ static void run(cplx_t<T>* row, int N, const FFTPlan&, int t,
+  __device__ __forceinline__ static void run(cplx_t<T>* row, int, const FFTPlan&, int t,
                              const cplx_t<T>* __restrict__ tw,
                              const T* __restrict__ dftc, const DftOff& doff,
                              T sign) {
-    run_codes<T, TPR, Codes...>(row, N, 1, t, tw, dftc, doff, sign);
+    run_codes<T, TPR, Lay, 0, 1, Codes...>(row, t, tw, dftc, doff, sign);
+  }
+  __host__ __device__ static constexpr int span(int n) {
+    return n > Lay::kTable.span ? n : Lay::kTable.span;
   }
 };
+
+// LDS row stride of the x passes (Nx/2 + 1 elements at least, odd so that the
+// transposed accesses of 16 rows fall into different banks)
+template <typename Run>
+__host__ __device__ constexpr int x_stride(int M) {
+  return Run::span(M + 1) | 1;
+}
 
 // split step of the real transform: X_k from Z_k and Z_{M-k} (w = e^{-2 pi i k/Nx})
 template <typename C>
@@ -488,7 +650,7 @@ k_fftw_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   extern __shared__ unsigned char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
   const int M = dp.Nx / 2;
-  const int S = lp(M) + 1;                          // padded row stride in LDS
+  const int S = x_stride<Run>(M);                   // row stride in LDS
   const int p = blockIdx.y;
   const int c = p % dp.Nz;
   if (c < band[0] || c > band[1]) return;           // whole workgroup
@@ -501,18 +663,18 @@ k_fftw_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   const int y = wr < nr ? y0 + wr : y0;
   const C* src = reinterpret_cast<const C*>(grid + ((size_t)p * dp.Ny + y) * dp.Nx);
 #pragma unroll 4
-  for (int i = t; i < M; i += TPR) row[lp(i)] = src[i];
+  for (int i = t; i < M; i += TPR) row[i] = src[i];
   row_sync<TPR>();
   Run::template run<T, TPR>(row, M, plan, t, tw, dftc, doff, T(-1));
   for (int k = t; k <= M / 2; k += TPR) {
-    const C zk = row[lp(k)];
+    const C zk = row[k];
     if (k == 0) {
       row[0] = r2c_post(zk, zk, rtw[0]);
-      row[lp(M)] = r2c_post(zk, zk, rtw[M]);
+      row[M] = r2c_post(zk, zk, rtw[M]);
     } else {
-      const C zm = row[lp(M - k)];
-      row[lp(k)] = r2c_post(zk, zm, rtw[k]);
-      if (M - k != k) row[lp(M - k)] = r2c_post(zm, zk, rtw[M - k]);
+      const C zm = row[M - k];
+      row[k] = r2c_post(zk, zm, rtw[k]);
+      if (M - k != k) row[M - k] = r2c_post(zm, zk, rtw[M - k]);
     }
   }
   __syncthreads();
@@ -520,7 +682,7 @@ k_fftw_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   for (int idx = threadIdx.x; idx < (M + 1) * ROWS; idx += ROWS * TPR) {
     const int k = idx / ROWS;
     const int r = idx % ROWS;
-    if (r < nr) spec[pbase + (size_t)k * dp.Ny + y0 + r] = lds[r * S + lp(k)];
+    if (r < nr) spec[pbase + (size_t)k * dp.Ny + y0 + r] = lds[r * S + k];
   }
 }
 
@@ -541,15 +703,77 @@ k_fftw_y(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   const bool live = kx < dp.Nkx;
   if (TPR == 64 && !live) return;                   // a whole wavefront
   const int N = dp.Ny;
-  C* row = reinterpret_cast<C*>(lds_raw) + wr * (lp(N - 1) + 1);
+  C* row = reinterpret_cast<C*>(lds_raw) + wr * Run::span(N);
   C* g = spec + ((size_t)p * dp.Nkx + (live ? kx : 0)) * N;
 #pragma unroll 4
-  for (int i = t; i < N; i += TPR) row[lp(i)] = g[i];
+  for (int i = t; i < N; i += TPR) row[i] = g[i];
   row_sync<TPR>();
   Run::template run<T, TPR>(row, N, plan, t, tw, dftc, doff, sign);
   if (live) {
 #pragma unroll 4
-    for (int i = t; i < N; i += TPR) g[i] = row[lp(i)];
+    for (int i = t; i < N; i += TPR) g[i] = row[i];
+  }
+}
+
+// y-pass as a persistent loop: workgroup g (one wavefront) transforms the
+// band rows g, g + G, ... and loads the next row into registers while the
+// current one is transformed in LDS, so that every wavefront keeps memory
+// requests in flight through its arithmetic.  Fixed-length plans only.
+template <typename T, typename Run>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_fftw_y_pipe(DevParams dp, FFTPlan plan, const int* __restrict__ band,
+              cplx_t<T>* __restrict__ spec, const cplx_t<T>* __restrict__ tw,
+              const T* __restrict__ dftc, DftOff doff, T sign) {
+  using C = cplx_t<T>;
+  constexpr int N = Run::kN;                        // == dp.Ny
+  constexpr int PER = (N + 63) / 64;
+  extern __shared__ unsigned char lds_raw[];
+  C* row = reinterpret_cast<C*>(lds_raw);
+  const int lo = band[0], hi = band[1];
+  if (lo > hi) return;
+  const int P = hi - lo + 1;
+  const int total = 6 * P * dp.Nkx;                 // band rows
+  const int t = threadIdx.x;
+  int r = blockIdx.x;
+  if (r >= total) return;
+  // row r: kx fastest, then band plane, then channel
+  auto row_ptr = [&](int rr) {
+    const int kx = rr % dp.Nkx, q = rr / dp.Nkx;
+    const int ch = q / P, c = lo + q - ch * P;
+    return spec + ((size_t)(ch * dp.Nz + c) * dp.Nkx + kx) * N;
+  };
+  C pre[PER];
+  {
+    const C* g = row_ptr(r);
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+      if (t + 64 * i < N) pre[i] = g[t + 64 * i];
+  }
+  for (; r < total; r += gridDim.x) {
+    C* g = row_ptr(r);
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+      if (t + 64 * i < N) row[t + 64 * i] = pre[i];
+    const int rn = r + gridDim.x;
+    if (rn < total) {
+      const C* gn = row_ptr(rn);
+#pragma unroll
+      for (int i = 0; i < PER; ++i)
+        if (t + 64 * i < N) pre[i] = gn[t + 64 * i];
+    }
+    wave_sync();
+    // the tables and the lane index are opaque to the optimiser inside the
+    // loop, so that table loads and LDS addresses are not hoisted out of it
+    // (which would hold every twiddle and address of the plan in registers)
+    const C* twl = tw;
+    const T* csl = dftc;
+    int tl = t;
+    asm volatile("" : "+s"(twl), "+s"(csl), "+v"(tl));
+    Run::template run<T, 64>(row, N, plan, tl, twl, csl, doff, sign);
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+      if (t + 64 * i < N) g[t + 64 * i] = row[t + 64 * i];
+    wave_sync();
   }
 }
 
@@ -565,7 +789,7 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   extern __shared__ unsigned char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
   const int M = dp.Nx / 2;
-  const int S = lp(M) + 1;                          // padded row stride in LDS
+  const int S = x_stride<Run>(M);                   // row stride in LDS
   const int p = blockIdx.y;
   const int c = p % dp.Nz;
   if (c < band[0] || c > band[1]) return;
@@ -576,7 +800,7 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
     const int k = idx / ROWS;
     const int r = idx % ROWS;
     // rows past the grid edge transform a copy of row y0
-    lds[r * S + lp(k)] = spec[pbase + (size_t)k * dp.Ny + y0 + (r < nr ? r : 0)];
+    lds[r * S + k] = spec[pbase + (size_t)k * dp.Ny + y0 + (r < nr ? r : 0)];
   }
   __syncthreads();
   const int wr = __builtin_amdgcn_readfirstlane(threadIdx.x / TPR);
@@ -584,14 +808,14 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   C* row = lds + wr * S;
   for (int k = t; k <= M / 2; k += TPR) {
     if (k == 0) {
-      C x0 = row[0], xm = row[lp(M)];
+      C x0 = row[0], xm = row[M];
       x0.y = T(0);
       xm.y = T(0);
       row[0] = c2r_pre(x0, xm, rtw[0]);
     } else {
-      const C xk = row[lp(k)], xm = row[lp(M - k)];
-      row[lp(k)] = c2r_pre(xk, xm, rtw[k]);
-      if (M - k != k) row[lp(M - k)] = c2r_pre(xm, xk, rtw[M - k]);
+      const C xk = row[k], xm = row[M - k];
+      row[k] = c2r_pre(xk, xm, rtw[k]);
+      if (M - k != k) row[M - k] = c2r_pre(xm, xk, rtw[M - k]);
     }
   }
   row_sync<TPR>();
@@ -599,7 +823,7 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   if (wr < nr) {
     C* dst = reinterpret_cast<C*>(grid + ((size_t)p * dp.Ny + y0 + wr) * dp.Nx);
 #pragma unroll 4
-    for (int i = t; i < M; i += TPR) dst[i] = row[lp(i)];
+    for (int i = t; i < M; i += TPR) dst[i] = row[i];
   }
 }
 
@@ -609,7 +833,7 @@ static void launch_wave_x(bool fwd, const fcmdp_solver* s, const void* in,
   using C = cplx_t<T>;
   const DevParams& dp = s->dp;
   const int M = dp.Nx / 2;
-  const size_t lds = (size_t)ROWS * (lp(M) + 1) * sizeof(C);
+  const size_t lds = (size_t)ROWS * x_stride<Run>(M) * sizeof(C);
   dim3 g((dp.Ny + ROWS - 1) / ROWS, 6 * dp.Nz);
   const T* cs = (const T*)s->dftc_t;
   if (fwd)
@@ -641,7 +865,7 @@ static void launch_wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
                           T sign, hipStream_t st) {
   using C = cplx_t<T>;
   const DevParams& dp = s->dp;
-  const size_t lds = (size_t)ROWS * (lp(dp.Ny - 1) + 1) * sizeof(C);
+  const size_t lds = (size_t)ROWS * Run::span(dp.Ny) * sizeof(C);
   dim3 g((dp.Nkx + ROWS - 1) / ROWS, 6 * dp.Nz);
   hipLaunchKernelGGL((k_fftw_y<T, ROWS, TPR, Run>), g, dim3(ROWS * TPR), lds, st,
                      dp, s->wplan_y, s->band, (C*)spec, (const C*)s->tw_y,
@@ -658,6 +882,21 @@ static void wave_y_rows(const fcmdp_solver* s, void* spec, const DftOff& doff,
     case 2: launch_wave_y<T, 2, TPR, Run>(s, spec, doff, sign, st); break;
     default: launch_wave_y<T, 1, TPR, Run>(s, spec, doff, sign, st); break;
   }
+}
+
+// Persistent y-pass: as many one-wavefront workgroups as stay resident (LDS
+// and registers allow eight per compute unit).
+template <typename T, typename Run>
+static void wave_y_pipe(const fcmdp_solver* s, void* spec, const DftOff& doff,
+                        T sign, hipStream_t st) {
+  using C = cplx_t<T>;
+  const DevParams& dp = s->dp;
+  const size_t lds = (size_t)Run::span(dp.Ny) * sizeof(C);
+  const int per_cu = (int)std::min<size_t>(8, kLdsBudget / lds);
+  const int g = std::max(1, s->num_cu) * std::max(1, per_cu);
+  hipLaunchKernelGGL((k_fftw_y_pipe<T, Run>), dim3(g), dim3(64), lds, st, dp,
+                     s->wplan_y, s->band, (C*)spec, (const C*)s->tw_y,
+                     (const T*)s->dftc_t, doff, sign);
 }
 
 // Codelets compiled for the transform lengths of the large workloads (single
@@ -695,6 +934,15 @@ static void wave_x(bool fwd, const fcmdp_solver* s, const void* in, void* out,
 template <typename T>
 static void wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
                    T sign, hipStream_t st) {
+  if (!s->force_no_pipeline) {
+    switch (s->codelet_y) {
+      case 0: wave_y_pipe<T, Codelet0>(s, spec, doff, sign, st); return;
+      case 1: wave_y_pipe<T, Codelet1>(s, spec, doff, sign, st); return;
+      case 2: wave_y_pipe<T, Codelet2>(s, spec, doff, sign, st); return;
+      case 3: wave_y_pipe<T, Codelet3>(s, spec, doff, sign, st); return;
+      default: break;
+    }
+  }
   switch (s->codelet_y) {
     case 0: wave_y_rows<T, 64, Codelet0>(s, spec, doff, sign, st); return;
     case 1: wave_y_rows<T, 64, Codelet1>(s, spec, doff, sign, st); return;
@@ -706,6 +954,16 @@ static void wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
     case 64: wave_y_rows<T, 64, GenericRows>(s, spec, doff, sign, st); break;
     case 128: wave_y_rows<T, 128, GenericRows>(s, spec, doff, sign, st); break;
     default: wave_y_rows<T, 256, GenericRows>(s, spec, doff, sign, st); break;
+  }
+}
+
+int fft_lds_row(int codelet, int n, bool x) {
+  switch (codelet) {
+    case 0: return x ? x_stride<Codelet0>(n) : Codelet0::span(n);
+    case 1: return x ? x_stride<Codelet1>(n) : Codelet1::span(n);
+    case 2: return x ? x_stride<Codelet2>(n) : Codelet2::span(n);
+    case 3: return x ? x_stride<Codelet3>(n) : Codelet3::span(n);
+    default: return x ? x_stride<GenericRows>(n) : GenericRows::span(n);
   }
 }
 

@@ -250,7 +250,7 @@ def test_stage_fft_mixed_sizes(nx, ny):
                          s=(ny, nx), axes=(-2, -1)) * (nx * ny)
     s = _solver(box, "mixed", cap=16)
     results = {}
-    for variant in ("default", "no_codelet", "generic_fft"):
+    for variant in ("default", "no_pipeline", "no_codelet", "generic_fft"):
         if variant != "default":
             s.set_variant(variant, 1)
         got = _np(s.stage_fft_forward(grid, lo, hi))
@@ -267,6 +267,9 @@ def test_stage_fft_mixed_sizes(nx, ny):
     sl = (slice(None), lo)
     assert rel_err(results["default"][0][sl], results["no_codelet"][0][sl]) < 1e-6
     assert rel_err(results["default"][1][sl], results["no_codelet"][1][sl]) < 1e-6
+    # the persistent (prefetching) kernels run the same plan per row
+    assert rel_err(results["default"][0][sl], results["no_pipeline"][0][sl]) < 1e-6
+    assert rel_err(results["default"][1][sl], results["no_pipeline"][1][sl]) < 1e-6
 
 
 @pytest.mark.parametrize("rows", [1, 2, 4, 8, 16])
