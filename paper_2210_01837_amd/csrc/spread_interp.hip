@@ -106,17 +106,21 @@ k_spread(DevParams dp, const int* __restrict__ band,
 // between lanes of different cell occupancy) and every column sums its
 // particles in a fixed order (deterministic).
 //
-// Staged path (at most 64 particles in the region, the usual case): lane j
-// loads the record of the j-th region particle in parallel with the others
-// (x/y weights into a per-wavefront LDS block, the rest into registers), and
-// the uniform loop reads particle v's values from lane v (readlane) and from
-// LDS, so it waits on no global memory.  Denser regions take the same loop
-// with scalar loads from global memory.  A first pass finds the z-nodes the
-// region's particles touch; band planes outside them are written as zeros,
-// the rest are accumulated ZC planes at a time in registers.
+// Staged path (at most kStage particles in the region, the usual case): lane
+// j loads the record of the j-th region particle in parallel with the others
+// (x/y weights, and per z-chunk its folded z weights, into a per-wavefront
+// LDS block; position and strengths into registers), and the uniform loop
+// reads particle v's values with LDS broadcasts and readlanes, so it waits on
+// no global memory.  Denser regions take the same loop with scalar loads
+// from global memory.  A first pass finds the z-nodes the region's particles
+// touch; band planes outside them are written as zeros, the rest are split
+// into equal chunks of at most ZC planes accumulated in registers.
 constexpr int kPW = 8;   // patch edge per wavefront; 4 wavefronts side by side in x
-constexpr int kSpreadZC = 10;
-constexpr int kStage = 64;
+constexpr int kSpreadZC = 10;                        // at most 14
+template <typename T> struct SpreadStage;            // staged particles per region
+template <> struct SpreadStage<float> { static constexpr int n = 64; };
+template <> struct SpreadStage<double> { static constexpr int n = 32; };
+constexpr int kStage = 64;                           // (upper bound of both)
 
 template <typename T>
 __device__ __forceinline__ T rdlane(T x, int v) {
@@ -132,13 +136,55 @@ __device__ __forceinline__ int rdlane_i(int x, int v) {
   return __builtin_amdgcn_readlane(x, v);
 }
 
+// LDS record of a staged particle: x/y weights of the M and D kernels
+// (4 x 7), then the folded z weights of the current chunk (ZC of each).
+template <int ZC> struct SpreadRec {
+  static constexpr int kPM = 28, kPD = 28 + ZC;
+  static constexpr int kLen = 28 + 2 * ZC + 1;     // odd stride
+};
+
+// One z-chunk of K planes (K <= ZC) over the staged particles.
+template <typename T, int ZC, int K>
+__device__ __forceinline__ void spread_chunk(const T* __restrict__ recw, int total,
+                                             int c0, int a, int b, bool inside,
+                                             const DevParams& dp, const int4& inf,
+                                             T F0, T F1, T F2, T G0, T G1, T G2,
+                                             T (&acc)[ZC][6]) {
+  using Rec = SpreadRec<ZC>;
+  for (int v = 0; v < total; ++v) {
+    const int iz = rdlane_i(inf.z, v), iw = rdlane_i(inf.w, v);
+    if (iw < c0 || iz >= c0 + K) continue;         // no overlap in z
+    int dx = a - rdlane_i(inf.x, v) + 3;
+    if (dx < 0) dx += dp.Nx; else if (dx >= dp.Nx) dx -= dp.Nx;
+    int dy = b - rdlane_i(inf.y, v) + 3;
+    if (dy < 0) dy += dp.Ny; else if (dy >= dp.Ny) dy -= dp.Ny;
+    const T f0v = rdlane(F0, v), f1v = rdlane(F1, v), f2v = rdlane(F2, v);
+    const T g0v = rdlane(G0, v), g1v = rdlane(G1, v), g2v = rdlane(G2, v);
+    if (inside && dx >= 0 && dx <= 6 && dy >= 0 && dy <= 6) {
+      const T* r = recw + v * Rec::kLen;
+      const T wm = r[dx] * r[7 + dy];
+      const T wd = r[14 + dx] * r[21 + dy];
+      const T f0 = f0v * wm, f1 = f1v * wm, f2 = f2v * wm;
+      const T t0 = g0v * wd, t1 = g1v * wd, t2 = g2v * wd;
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+        const T pm = r[Rec::kPM + s], pd = r[Rec::kPD + s];
+        acc[s][0] += f0 * pm; acc[s][1] += f1 * pm; acc[s][2] += f2 * pm;
+        acc[s][3] += t0 * pd; acc[s][4] += t1 * pd; acc[s][5] += t2 * pd;
+      }
+    }
+  }
+}
+
 template <typename T, int ZC>
 __global__ void __launch_bounds__(256)
 k_spread_wave(DevParams dp, const int* __restrict__ band,
               const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
               const T* __restrict__ pw, const T* __restrict__ pf,
               const T* __restrict__ psi, T* __restrict__ grid) {
-  __shared__ T wst[4][kStage][29];           // staged x/y weights per wavefront
+  using Rec = SpreadRec<ZC>;
+  constexpr int kS = SpreadStage<T>::n;
+  __shared__ T rec[4][kS][Rec::kLen];       // staged particle records per wavefront
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gx = (dp.Nx + 4 * kPW - 1) / (4 * kPW);
@@ -202,7 +248,7 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
     }
   };
 
-  if (total <= kStage) {
+  if (total <= kS) {
     // lane j holds the j-th region particle (rows in order, then x)
     int p = -1;
     for (int r = 0; r < 2 * nrows; ++r) {
@@ -212,7 +258,8 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
     const bool has = lane < total;
     int4 inf = make_int4(0, 0, Nz, -1);
     T F0 = 0, F1 = 0, F2 = 0, G0 = 0, G1 = 0, G2 = 0;
-    T* wrow = &wst[wv][lane][0];
+    T* recw = &rec[wv][0][0];
+    T* mine = &rec[wv][has ? lane : 0][0];
     if (has) {
       inf = pinfo[p];
       const T* f = pf + (size_t)p * 8;
@@ -221,10 +268,10 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
       const T* w = pw + (size_t)p * 32;
 #pragma unroll
       for (int d = 0; d < 7; ++d) {
-        wrow[d] = w[d];
-        wrow[7 + d] = w[8 + d];
-        wrow[14 + d] = w[16 + d];
-        wrow[21 + d] = w[24 + d];
+        mine[d] = w[d];
+        mine[7 + d] = w[8 + d];
+        mine[14 + d] = w[16 + d];
+        mine[21 + d] = w[24 + d];
       }
     }
     int zmin = inf.z, zmax = inf.w;
@@ -235,53 +282,48 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
     }
     zmin = rdlane_i(zmin, 0);
     zmax = rdlane_i(zmax, 0);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     zero_outside(zmin, zmax);
-    for (int c0 = zmin; c0 <= zmax; c0 += ZC) {
+    // equal chunks of at most ZC planes
+    const int range = zmax - zmin + 1;
+    const int npass = (range + ZC - 1) / ZC;
+    const int zc = npass > 0 ? (range + npass - 1) / npass : ZC;
+    for (int c0 = zmin; c0 <= zmax; c0 += zc) {
       // this lane's particle's folded z weights for the chunk (dense, zero
       // outside its window; nodes past Nz read padding and are never stored)
-      T pmj[ZC], pdj[ZC];
       if (has) {
         const T* ps = psi + (size_t)p * 2 * Nz;
 #pragma unroll
-        for (int s = 0; s < ZC; ++s) { pmj[s] = ps[c0 + s]; pdj[s] = ps[Nz + c0 + s]; }
-      } else {
-#pragma unroll
-        for (int s = 0; s < ZC; ++s) { pmj[s] = T(0); pdj[s] = T(0); }
+        for (int s = 0; s < ZC; ++s) {
+          if (s < zc) {
+            mine[Rec::kPM + s] = ps[c0 + s];
+            mine[Rec::kPD + s] = ps[Nz + c0 + s];
+          }
+        }
       }
+      // the records are read by every lane of this wavefront only
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       T acc[ZC][6];
 #pragma unroll
       for (int s = 0; s < ZC; ++s)
 #pragma unroll
         for (int ch = 0; ch < 6; ++ch) acc[s][ch] = T(0);
-      for (int v = 0; v < total; ++v) {
-        const int iz = rdlane_i(inf.z, v), iw = rdlane_i(inf.w, v);
-        if (iw < c0 || iz >= c0 + ZC) continue;       // no overlap in z
-        int dx = a - rdlane_i(inf.x, v) + 3;
-        if (dx < 0) dx += dp.Nx; else if (dx >= dp.Nx) dx -= dp.Nx;
-        int dy = b - rdlane_i(inf.y, v) + 3;
-        if (dy < 0) dy += dp.Ny; else if (dy >= dp.Ny) dy -= dp.Ny;
-        T pm[ZC], pd[ZC];
-#pragma unroll
-        for (int s = 0; s < ZC; ++s) { pm[s] = rdlane(pmj[s], v); pd[s] = rdlane(pdj[s], v); }
-        const T f0v = rdlane(F0, v), f1v = rdlane(F1, v), f2v = rdlane(F2, v);
-        const T g0v = rdlane(G0, v), g1v = rdlane(G1, v), g2v = rdlane(G2, v);
-        if (inside && dx >= 0 && dx <= 6 && dy >= 0 && dy <= 6) {
-          const T* w = &wst[wv][v][0];
-          const T wm = w[dx] * w[7 + dy];
-          const T wd = w[14 + dx] * w[21 + dy];
-          const T f0 = f0v * wm, f1 = f1v * wm, f2 = f2v * wm;
-          const T t0 = g0v * wd, t1 = g1v * wd, t2 = g2v * wd;
-#pragma unroll
-          for (int s = 0; s < ZC; ++s) {
-            acc[s][0] += f0 * pm[s]; acc[s][1] += f1 * pm[s]; acc[s][2] += f2 * pm[s];
-            acc[s][3] += t0 * pd[s]; acc[s][4] += t1 * pd[s]; acc[s][5] += t2 * pd[s];
-          }
-        }
+#define FCMDP_CHUNK(K)                                                         \
+  case K:                                                                      \
+    if constexpr (K <= ZC)                                                     \
+      spread_chunk<T, ZC, K>(recw, total, c0, a, b, inside, dp, inf, F0, F1,   \
+                             F2, G0, G1, G2, acc);                             \
+    break;
+      switch (zc) {
+        FCMDP_CHUNK(1) FCMDP_CHUNK(2) FCMDP_CHUNK(3) FCMDP_CHUNK(4) FCMDP_CHUNK(5)
+        FCMDP_CHUNK(6) FCMDP_CHUNK(7) FCMDP_CHUNK(8) FCMDP_CHUNK(9) FCMDP_CHUNK(10)
+        FCMDP_CHUNK(11) FCMDP_CHUNK(12) FCMDP_CHUNK(13) FCMDP_CHUNK(14)
+        default: break;
       }
-      store_chunk(c0, zmax, acc);
+#undef FCMDP_CHUNK
+      store_chunk(c0, min(zmax, c0 + zc - 1), acc);
+      __builtin_amdgcn_wave_barrier();
     }
     return;
   }
