@@ -110,6 +110,16 @@ __device__ inline Vec seg_deriv(const Vec& a, int l, double s2H) {
   return b;
 }
 
+// 1/x from the hardware estimate and two Newton steps (within an ulp or two
+// of the rounded quotient; x is a normal, finite number here).
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Operator data of one parity for the Robin BVP (depends on kappa only).
 // Slot s = 0, 1 of lane l is unknown i = 2l + s, coefficient m = 2i + p.
 // Only what the scans produce is kept; the row coefficients are recomputed.
@@ -214,8 +224,8 @@ __device__ __forceinline__ Par seg_prepare(double kappa, int N, int l, int p) {
   double S1[4], S0[4];
   m2mul(T[1], X, S1);
   m2mul(T[0], S1, S0);
-  q.alpha[1] = S1[1] / S1[3];
-  q.alpha[0] = S0[1] / S0[3];
+  q.alpha[1] = S1[1] * frcp(S1[3]);
+  q.alpha[0] = S0[1] * frcp(S0[3]);
   if (l == 0) q.alpha[0] = 1.0;              // i = 0: P_0 = 1
   if (!act[0]) q.alpha[0] = 0.0;
   if (!act[1]) q.alpha[1] = 0.0;
@@ -228,7 +238,7 @@ __device__ __forceinline__ Par seg_prepare(double kappa, int N, int l, int p) {
   }
 #pragma unroll
   for (int s = 0; s < 2; ++s)
-    q.invD[s] = row[s] ? 1.0 / (Dd[s] + Uu[s] * anext[s]) : 0.0;
+    q.invD[s] = row[s] ? frcp(Dd[s] + Uu[s] * anext[s]) : 0.0;
   // prefix products P_i = alpha_i P_{i-1}
   double Yp = q.alpha[0] * q.alpha[1];
   {
@@ -243,7 +253,7 @@ __device__ __forceinline__ Par seg_prepare(double kappa, int N, int l, int p) {
   if (l == 0) Pin = 1.0;
   q.P[0] = q.alpha[0] * Pin;
   q.P[1] = q.alpha[1] * q.P[0];
-  q.invEP = 1.0 / red(e[0] * q.P[0] + e[1] * q.P[1]);
+  q.invEP = frcp(red(e[0] * q.P[0] + e[1] * q.P[1]));
   return q;
 }
 
@@ -511,28 +521,27 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     }
     const Vec p = seg_solve(q, r, zmk(0, 0), zmk(0, 0), H, kappa, N, l);
     const Z2 pH = bsum_top(p), p0 = bsum_bottom(p);
-    const double ie = 1.0 / eta;
+    const double ie = frcp(eta), ik = frcp(k);
     {
       const Vec dp_ = seg_deriv(p, l, s2H);
       const Vec fz = load(2);
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (dp_.v[j] - fz.v[j]);
     }
-    W = seg_solve(q, r, (0.5 / eta) * pH, (0.5 / eta) * p0, H, kappa, N, l);
+    W = seg_solve(q, r, (0.5 * ie) * pH, (0.5 * ie) * p0, H, kappa, N, l);
     {
       const Vec fx = body_x();
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(kx, p.v[j]) - fx.v[j]);
     }
-    U = seg_solve(q, r, imul(-kx / (2.0 * k * eta), pH),
-                  imul(kx / (2.0 * k * eta), p0), H, kappa, N, l);
+    const double ax = 0.5 * kx * ik * ie, ay = 0.5 * ky * ik * ie;
+    U = seg_solve(q, r, imul(-ax, pH), imul(ax, p0), H, kappa, N, l);
     {
       const Vec fy = body_y();
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(ky, p.v[j]) - fy.v[j]);
     }
-    V = seg_solve(q, r, imul(-ky / (2.0 * k * eta), pH),
-                  imul(ky / (2.0 * k * eta), p0), H, kappa, N, l);
+    V = seg_solve(q, r, imul(-ay, pH), imul(ay, p0), H, kappa, N, l);
 
     // wall correction, evaluated on all nodes and transformed
     const Z2 u0 = -1.0 * bsum_bottom(U), v0 = -1.0 * bsum_bottom(V),
@@ -543,7 +552,7 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     if constexpr (GEOM == 0) {
       const Z2 Ac = imul(k, w0) + kx * u0 + ky * v0;
       const Z2 Bc = k * w0 - imul(kx, u0) - imul(ky, v0);
-      const double rx = kx / k, ry = ky / k;
+      const double rx = kx * ik, ry = ky * ik;
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) {
         U.v[j] = U.v[j] + (-rx * ZE[j]) * Ac + E[j] * u0;
@@ -554,11 +563,11 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
       const Z2 uH = -1.0 * bsum_top(U), vH = -1.0 * bsum_top(V),
                wH = -1.0 * bsum_top(W);
       const double Ex = exp(-k * H);
-      const double hh = H / (2.0 * eta), e2 = 1.0 / (2.0 * eta);
-      const Z2 uL0 = (1.0 / k) * (kx * u0 + ky * v0);
-      const Z2 uT0 = (1.0 / k) * (kx * v0 - ky * u0);
-      const Z2 uLH = (1.0 / k) * (kx * uH + ky * vH);
-      const Z2 uTH = (1.0 / k) * (kx * vH - ky * uH);
+      const double hh = 0.5 * H * ie, e2 = 0.5 * ie;
+      const Z2 uL0 = ik * (kx * u0 + ky * v0);
+      const Z2 uT0 = ik * (kx * v0 - ky * u0);
+      const Z2 uLH = ik * (kx * uH + ky * vH);
+      const Z2 uTH = ik * (kx * vH - ky * uH);
       // longitudinal 6x6 system, one row per lane (unknowns C0, D0~,
       // i C_L, i D_L~, C_z, D_z~; D~ = D e^{kH})
       double row6[6] = {0, 0, 0, 0, 0, 0};
@@ -580,16 +589,15 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
       const Z2 C0 = shz(x6, 0), D0 = shz(x6, 1);
       const Z2 CL = imul(-1.0, shz(x6, 2)), DL = imul(-1.0, shz(x6, 3));
       const Z2 Cz = shz(x6, 4), Dz = shz(x6, 5);
-      const double det = 1.0 - Ex * Ex;
-      const Z2 CT = zdiv(uT0 - Ex * uTH, det);
-      const Z2 DT = zdiv(uTH - Ex * uT0, det);
-      const double rx = kx / k, ry = ky / k;
+      const double idet = frcp(1.0 - Ex * Ex);
+      const Z2 CT = idet * (uT0 - Ex * uTH);
+      const Z2 DT = idet * (uTH - Ex * uT0);
+      const double rx = kx * ik, ry = ky * ik;
       const Z2 Cx = rx * CL - ry * CT, Cy = ry * CL + rx * CT;
       const Z2 Dx = rx * DL - ry * DT, Dy = ry * DL + rx * DT;
       double Ep[kNpl], ZEp[kNpl];
       basis(2, Ep);
       basis(3, ZEp);
-      const double ax = kx / (2.0 * eta * k), ay = ky / (2.0 * eta * k);
       const Z2 pu0 = imul(-ax, C0), pu1 = imul(ax, D0);
       const Z2 pv0 = imul(-ay, C0), pv1 = imul(ay, D0);
 #pragma unroll
