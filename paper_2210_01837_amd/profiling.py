@@ -35,6 +35,7 @@ KERNEL_SOURCES = {
     "k_interp_tiled": ["spread_interp.hip", "es.h", "fcmdp_internal.h"],
     "k_fftw_x_r2c": ["fft.hip", "fcmdp_internal.h"],
     "k_fftw_y": ["fft.hip", "fcmdp_internal.h"],
+    "k_fftw_y_pipe": ["fft.hip", "fcmdp_internal.h"],
     "k_fftw_x_c2r": ["fft.hip", "fcmdp_internal.h"],
     "k_records": ["prep.hip", "es.h", "fcmdp_internal.h"],
 }
