@@ -679,10 +679,26 @@ k_fftw_x_r2c(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   }
   __syncthreads();
   const size_t pbase = (size_t)p * dp.Nkx * dp.Ny;
-  for (int idx = threadIdx.x; idx < (M + 1) * ROWS; idx += ROWS * TPR) {
-    const int k = idx / ROWS;
-    const int r = idx % ROWS;
-    if (r < nr) spec[pbase + (size_t)k * dp.Ny + y0 + r] = lds[r * S + k];
+  if constexpr (ROWS % 2 == 0 && sizeof(T) == 4) {
+    // two consecutive rows per thread: one 16-byte store (y0 and Ny even)
+    for (int idx = threadIdx.x; idx < (M + 1) * (ROWS / 2); idx += ROWS * TPR) {
+      const int k = idx / (ROWS / 2);
+      const int r = 2 * (idx % (ROWS / 2));
+      C* dst = spec + pbase + (size_t)k * dp.Ny + y0 + r;
+      const C a = lds[r * S + k], b = lds[(r + 1) * S + k];
+      if (r + 1 < nr && (dp.Ny & 1) == 0) {
+        *reinterpret_cast<float4*>(dst) = make_float4(a.x, a.y, b.x, b.y);
+      } else {
+        if (r < nr) dst[0] = a;
+        if (r + 1 < nr) dst[1] = b;
+      }
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < (M + 1) * ROWS; idx += ROWS * TPR) {
+      const int k = idx / ROWS;
+      const int r = idx % ROWS;
+      if (r < nr) spec[pbase + (size_t)k * dp.Ny + y0 + r] = lds[r * S + k];
+    }
   }
 }
 
@@ -796,11 +812,31 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   const int y0 = blockIdx.x * ROWS;
   const int nr = min(ROWS, dp.Ny - y0);
   const size_t pbase = (size_t)p * dp.Nkx * dp.Ny;
-  for (int idx = threadIdx.x; idx < (M + 1) * ROWS; idx += ROWS * TPR) {
-    const int k = idx / ROWS;
-    const int r = idx % ROWS;
-    // rows past the grid edge transform a copy of row y0
-    lds[r * S + k] = spec[pbase + (size_t)k * dp.Ny + y0 + (r < nr ? r : 0)];
+  if constexpr (ROWS % 2 == 0 && sizeof(T) == 4) {
+    // two consecutive rows per thread: one 16-byte load (y0 and Ny even)
+    for (int idx = threadIdx.x; idx < (M + 1) * (ROWS / 2); idx += ROWS * TPR) {
+      const int k = idx / (ROWS / 2);
+      const int r = 2 * (idx % (ROWS / 2));
+      const C* src = spec + pbase + (size_t)k * dp.Ny + y0;
+      C a, b;
+      if (r + 1 < nr && (dp.Ny & 1) == 0) {
+        const float4 v = *reinterpret_cast<const float4*>(src + r);
+        a.x = v.x; a.y = v.y; b.x = v.z; b.y = v.w;
+      } else {
+        // rows past the grid edge transform a copy of row y0
+        a = src[r < nr ? r : 0];
+        b = src[r + 1 < nr ? r + 1 : 0];
+      }
+      lds[r * S + k] = a;
+      lds[(r + 1) * S + k] = b;
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < (M + 1) * ROWS; idx += ROWS * TPR) {
+      const int k = idx / ROWS;
+      const int r = idx % ROWS;
+      // rows past the grid edge transform a copy of row y0
+      lds[r * S + k] = spec[pbase + (size_t)k * dp.Ny + y0 + (r < nr ? r : 0)];
+    }
   }
   __syncthreads();
   const int wr = __builtin_amdgcn_readfirstlane(threadIdx.x / TPR);
