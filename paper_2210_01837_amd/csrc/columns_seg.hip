@@ -831,42 +831,59 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
 
   // --- A: band node values of the body-force combinations, and the
   //     correction's node functions at all nodes --------------------------
+  // each thread takes a pair of adjacent columns (one 16-byte access per
+  // channel; K and the group start are even, so a pair is either inside
+  // the spectrum or past its end)
+  static_assert(kMCols % 2 == 0, "column pairs");
 #pragma unroll
-  for (int i = 0; i < 32 * kMCols / kMThreads; ++i) {
+  for (int i = 0; i < 32 * (kMCols / 2) / kMThreads; ++i) {
     const int it = tid + i * kMThreads;
-    const int c = it / kMCols, col = it % kMCols;      // band-relative row
+    const int c = it / (kMCols / 2), col = 2 * (it % (kMCols / 2));  // band-relative row
     const int idx = idx0 + col;
-    int kxi, kyi;
-    col_index(kx0, ky0, col, dp.Ny, kxi, kyi);
-    const float kx = kxs * (float)kxi;
-    const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
-    const float ky = kys * (float)nyi;
-    float* xr = XC + c * kMV + col * 10;
-    {
-      if (c < P && idx < K) {
-        float2 v[6];
+    float kxv[2], kyv[2];
 #pragma unroll
-        for (int ch = 0; ch < 6; ++ch) v[ch] = in[(ch * N + lo + c) * PS + idx];
+    for (int h = 0; h < 2; ++h) {
+      int kxi, kyi;
+      col_index(kx0, ky0, col + h, dp.Ny, kxi, kyi);
+      kxv[h] = kxs * (float)kxi;
+      const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
+      kyv[h] = kys * (float)nyi;
+    }
+    if (c < P && idx < K) {
+      float4 v[6];
+#pragma unroll
+      for (int ch = 0; ch < 6; ++ch)
+        v[ch] = *reinterpret_cast<const float4*>(in + (ch * N + lo + c) * PS + idx);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float2 w[6];
+#pragma unroll
+        for (int ch = 0; ch < 6; ++ch)
+          w[ch] = h == 0 ? make_float2(v[ch].x, v[ch].y) : make_float2(v[ch].z, v[ch].w);
+        const float kx = kxv[h], ky = kyv[h];
+        float* xr = XC + c * kMV + (col + h) * 10;
         // f~x = Fx + (1/2) i ky Gz ; f~y = Fy - (1/2) i kx Gz ;
         // f~z = Fz + (1/2)(i kx Gy - i ky Gx)
-        xr[0] = v[0].x - 0.5f * ky * v[5].y;
-        xr[1] = v[0].y + 0.5f * ky * v[5].x;
-        xr[2] = v[1].x + 0.5f * kx * v[5].y;
-        xr[3] = v[1].y - 0.5f * kx * v[5].x;
-        xr[4] = v[2].x - 0.5f * kx * v[4].y + 0.5f * ky * v[3].y;
-        xr[5] = v[2].y + 0.5f * kx * v[4].x - 0.5f * ky * v[3].x;
-        xr[6] = v[3].x; xr[7] = v[3].y;
-        xr[8] = v[4].x; xr[9] = v[4].y;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 10; ++e) xr[e] = 0.f;
+        xr[0] = w[0].x - 0.5f * ky * w[5].y;
+        xr[1] = w[0].y + 0.5f * ky * w[5].x;
+        xr[2] = w[1].x + 0.5f * kx * w[5].y;
+        xr[3] = w[1].y - 0.5f * kx * w[5].x;
+        xr[4] = w[2].x - 0.5f * kx * w[4].y + 0.5f * ky * w[3].y;
+        xr[5] = w[2].y + 0.5f * kx * w[4].x - 0.5f * ky * w[3].x;
+        xr[6] = w[3].x; xr[7] = w[3].y;
+        xr[8] = w[4].x; xr[9] = w[4].y;
       }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 20; ++e) XC[c * kMV + col * 10 + e] = 0.f;
     }
     // c is also the absolute node of the correction functions
-    float* br = XC + c * kMV + kSpec + col * NB;
-    {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float* br = XC + c * kMV + kSpec + (col + h) * NB;
       float eb = 0.f, ezb = 0.f, et = 0.f, ezt = 0.f;
       if (c < N && idx < K) {
+        const float kx = kxv[h], ky = kyv[h];
         const float k = sqrtf(kx * kx + ky * ky);
         const float z = (float)zc[c];
         eb = expf(-k * z);
@@ -1016,29 +1033,34 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
 
   // --- E: omega = (1/2) curl u at the nodes, scale, store ----------------------
   const float sc = (float)cp.scale;
-  for (int it = tid; it < P * kMCols; it += kMThreads) {
-    const int c = it / kMCols, col = it % kMCols;
+  for (int it = tid; it < P * (kMCols / 2); it += kMThreads) {
+    const int c = it / (kMCols / 2), col = 2 * (it % (kMCols / 2));
     const int idx = idx0 + col;
     if (idx >= K) continue;
-    int kxi, kyi;
-    col_index(kx0, ky0, col, dp.Ny, kxi, kyi);
-    const float kx = kxs * (float)kxi;
-    const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
-    const float ky = kys * (float)nyi;
-    float* d = XC + c * kMV + col * 10;
-    const float ur = d[0], ui = d[1], vr = d[2], vi = d[3], wr = d[4], wi = d[5];
-    const float dur = d[6], dui = d[7], dvr = d[8], dvi = d[9];
-    float2 o[6];
-    o[0] = make_float2(sc * ur, sc * ui);
-    o[1] = make_float2(sc * vr, sc * vi);
-    o[2] = make_float2(sc * wr, sc * wi);
-    // ox = (i ky w - dv/dz)/2, oy = (du/dz - i kx w)/2, oz = (i kx v - i ky u)/2
-    o[3] = make_float2(0.5f * sc * (-ky * wi - dvr), 0.5f * sc * (ky * wr - dvi));
-    o[4] = make_float2(0.5f * sc * (dur + kx * wi), 0.5f * sc * (dui - kx * wr));
-    o[5] = make_float2(0.5f * sc * (-kx * vi + ky * ui),
-                       0.5f * sc * (kx * vr - ky * ur));
+    float2 o[2][6];
 #pragma unroll
-    for (int ch = 0; ch < 6; ++ch) out[(ch * N + lo + c) * PS + idx] = o[ch];
+    for (int h = 0; h < 2; ++h) {
+      int kxi, kyi;
+      col_index(kx0, ky0, col + h, dp.Ny, kxi, kyi);
+      const float kx = kxs * (float)kxi;
+      const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
+      const float ky = kys * (float)nyi;
+      float* d = XC + c * kMV + (col + h) * 10;
+      const float ur = d[0], ui = d[1], vr = d[2], vi = d[3], wr = d[4], wi = d[5];
+      const float dur = d[6], dui = d[7], dvr = d[8], dvi = d[9];
+      o[h][0] = make_float2(sc * ur, sc * ui);
+      o[h][1] = make_float2(sc * vr, sc * vi);
+      o[h][2] = make_float2(sc * wr, sc * wi);
+      // ox = (i ky w - dv/dz)/2, oy = (du/dz - i kx w)/2, oz = (i kx v - i ky u)/2
+      o[h][3] = make_float2(0.5f * sc * (-ky * wi - dvr), 0.5f * sc * (ky * wr - dvi));
+      o[h][4] = make_float2(0.5f * sc * (dur + kx * wi), 0.5f * sc * (dui - kx * wr));
+      o[h][5] = make_float2(0.5f * sc * (-kx * vi + ky * ui),
+                            0.5f * sc * (kx * vr - ky * ur));
+    }
+#pragma unroll
+    for (int ch = 0; ch < 6; ++ch)
+      *reinterpret_cast<float4*>(out + (ch * N + lo + c) * PS + idx) =
+          make_float4(o[0][ch].x, o[0][ch].y, o[1][ch].x, o[1][ch].y);
   }
 }
 
