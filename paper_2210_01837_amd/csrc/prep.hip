@@ -291,94 +291,112 @@ hipError_t launch_sort(const fcmdp_solver* s, int n, hipStream_t st) {
 // ----------------------------------------------------------------------------
 // per-particle records in sorted order
 // ----------------------------------------------------------------------------
-// A workgroup of B threads builds the records of B consecutive sorted
-// particles in LDS (rows padded by one word against bank conflicts) and then
-// copies them out as contiguous, coalesced blocks.  The folded z weights are
-// stored densely over all Nz nodes (zero outside the particle's window), so
-// readers index them by node without window arithmetic.
-template <typename Tin, typename T, int B>
-__global__ void __launch_bounds__(B)
+// One thread builds the records of one sorted particle and writes each as
+// whole 16-byte vectors (no LDS staging, so occupancy is limited by registers
+// only and the scattered reads of the unsorted inputs overlap across many
+// wavefronts).  The folded z weights are stored densely over all Nz nodes
+// (zero outside the particle's window), so readers index them by node
+// without window arithmetic.
+__device__ __forceinline__ void store4(float* p, float a, float b, float c, float d) {
+  *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+}
+__device__ __forceinline__ void store4(double* p, double a, double b, double c,
+                                       double d) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(a, b);
+  reinterpret_cast<double2*>(p)[1] = make_double2(c, d);
+}
+
+template <typename Tin, typename T>
+__global__ void __launch_bounds__(256)
 k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
           const int* __restrict__ perm, const Tin* __restrict__ pos,
           const Tin* __restrict__ F, const Tin* __restrict__ Tq,
           const double* __restrict__ zc, int4* __restrict__ pinfo,
           T* __restrict__ pw, T* __restrict__ pf, T* __restrict__ psi) {
-  extern __shared__ unsigned char lds_raw[];
-  const int NZ2 = 2 * dp.Nz;
-  T* rw = reinterpret_cast<T*>(lds_raw);       // [B][33]
-  T* rf = rw + B * 33;                          // [B][9]
-  T* rz = rf + B * 9;                           // [B][NZ2 + 1]
-  const int t = threadIdx.x;
-  const int i0 = blockIdx.x * B;
-  const int i = i0 + t;
-  T* w = rw + t * 33;
-  T* f = rf + t * 9;
-  T* ps = rz + t * (NZ2 + 1);
-  for (int e = 0; e < NZ2; ++e) ps[e] = T(0);
-  if (i < n && skeys[i] < (uint32_t)dp.ncells) {
-    const int j = perm[i];
-    const double x = wrap_coord((double)pos[3 * (size_t)j + 0], dp.Lx);
-    const double y = wrap_coord((double)pos[3 * (size_t)j + 1], dp.Ly);
-    const double z = (double)pos[3 * (size_t)j + 2];
-    int ix, iy;
-    double fx, fy;
-    cell_of(x, dp.h, dp.Nx, &ix, &fx);
-    cell_of(y, dp.h, dp.Ny, &iy, &fy);
-    int cA, cB;
-    z_window(dp, zc, z, &cA, &cB);
-    pinfo[i] = make_int4(ix, iy, cA, cB);
-#pragma unroll
-    for (int d = 0; d < kWin; ++d) {
-      const double tx = ((double)(d - 3) - fx) * dp.h;
-      const double ty = ((double)(d - 3) - fy) * dp.h;
-      w[d] = es_eval<T>(tx, dp.alpha, dp.beta_m, dp.inv_norm_m);
-      w[8 + d] = es_eval<T>(ty, dp.alpha, dp.beta_m, dp.inv_norm_m);
-      w[16 + d] = es_eval<T>(tx, dp.alpha, dp.beta_d, dp.inv_norm_d);
-      w[24 + d] = es_eval<T>(ty, dp.alpha, dp.beta_d, dp.inv_norm_d);
-    }
-    w[7] = w[15] = w[23] = w[31] = T(0);
-    const double zim_top = 2.0 * dp.H - z;
-    for (int c = cA; c <= cB; ++c) {
-      const double zcv = zc[c];
-      T pm = es_eval<T>(zcv - z, dp.alpha, dp.beta_m, dp.inv_norm_m) -
-             es_eval<T>(zcv + z, dp.alpha, dp.beta_m, dp.inv_norm_m);
-      T pd = es_eval<T>(zcv - z, dp.alpha, dp.beta_d, dp.inv_norm_d) -
-             es_eval<T>(zcv + z, dp.alpha, dp.beta_d, dp.inv_norm_d);
-      if (dp.geometry == 1) {
-        pm -= es_eval<T>(zcv - zim_top, dp.alpha, dp.beta_m, dp.inv_norm_m);
-        pd -= es_eval<T>(zcv - zim_top, dp.alpha, dp.beta_d, dp.inv_norm_d);
-      }
-      ps[c] = pm;
-      ps[dp.Nz + c] = pd;
-    }
-    f[0] = F ? (T)F[3 * (size_t)j + 0] : T(0);
-    f[1] = F ? (T)F[3 * (size_t)j + 1] : T(0);
-    f[2] = F ? (T)F[3 * (size_t)j + 2] : T(0);
-    f[3] = T(0);
-    f[4] = Tq ? (T)Tq[3 * (size_t)j + 0] : T(0);
-    f[5] = Tq ? (T)Tq[3 * (size_t)j + 1] : T(0);
-    f[6] = Tq ? (T)Tq[3 * (size_t)j + 2] : T(0);
-    f[7] = T(0);
-  } else {
-    for (int e = 0; e < 32; ++e) w[e] = T(0);
-    for (int e = 0; e < 8; ++e) f[e] = T(0);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int Nz = dp.Nz;
+  T* w = pw + (size_t)i * 32;
+  T* f = pf + (size_t)i * 8;
+  T* ps = psi + (size_t)i * 2 * Nz;
+  if (skeys[i] >= (uint32_t)dp.ncells) {
+    // outside the domain: zero records (never read by the grid kernels)
+    for (int e = 0; e < 32; e += 4) store4(w + e, T(0), T(0), T(0), T(0));
+    store4(f, T(0), T(0), T(0), T(0));
+    store4(f + 4, T(0), T(0), T(0), T(0));
+    for (int e = 0; e < 2 * Nz; ++e) ps[e] = T(0);
+    return;
   }
-  __syncthreads();
-  const int nb = min(B, n - i0);
-  for (int e = t; e < nb * 32; e += B) pw[(size_t)i0 * 32 + e] = rw[(e >> 5) * 33 + (e & 31)];
-  for (int e = t; e < nb * 8; e += B) pf[(size_t)i0 * 8 + e] = rf[(e >> 3) * 9 + (e & 7)];
-  for (int e = t; e < nb * NZ2; e += B) {
-    const int r = e / NZ2;
-    psi[(size_t)i0 * NZ2 + e] = rz[r * (NZ2 + 1) + (e - r * NZ2)];
+  const int j = perm[i];
+  const double x = wrap_coord((double)pos[3 * (size_t)j + 0], dp.Lx);
+  const double y = wrap_coord((double)pos[3 * (size_t)j + 1], dp.Ly);
+  const double z = (double)pos[3 * (size_t)j + 2];
+  T fv[8];
+  fv[0] = F ? (T)F[3 * (size_t)j + 0] : T(0);
+  fv[1] = F ? (T)F[3 * (size_t)j + 1] : T(0);
+  fv[2] = F ? (T)F[3 * (size_t)j + 2] : T(0);
+  fv[3] = T(0);
+  fv[4] = Tq ? (T)Tq[3 * (size_t)j + 0] : T(0);
+  fv[5] = Tq ? (T)Tq[3 * (size_t)j + 1] : T(0);
+  fv[6] = Tq ? (T)Tq[3 * (size_t)j + 2] : T(0);
+  fv[7] = T(0);
+  int ix, iy;
+  double fx, fy;
+  cell_of(x, dp.h, dp.Nx, &ix, &fx);
+  cell_of(y, dp.h, dp.Ny, &iy, &fy);
+  int cA, cB;
+  z_window(dp, zc, z, &cA, &cB);
+  pinfo[i] = make_int4(ix, iy, cA, cB);
+  // x and y weights of the M and D kernels, 7 each (eighth slot zero)
+#pragma unroll
+  for (int part = 0; part < 4; ++part) {
+    const double off = part & 1 ? fy : fx;
+    const double beta = part < 2 ? dp.beta_m : dp.beta_d;
+    const double inv = part < 2 ? dp.inv_norm_m : dp.inv_norm_d;
+    T v[8];
+#pragma unroll
+    for (int d = 0; d < kWin; ++d)
+      v[d] = es_eval<T>(((double)(d - 3) - off) * dp.h, dp.alpha, beta, inv);
+    v[7] = T(0);
+    store4(w + 8 * part, v[0], v[1], v[2], v[3]);
+    store4(w + 8 * part + 4, v[4], v[5], v[6], v[7]);
+  }
+  store4(f, fv[0], fv[1], fv[2], fv[3]);
+  store4(f + 4, fv[4], fv[5], fv[6], fv[7]);
+  // folded z weights, four nodes at a time
+  const double zim_top = 2.0 * dp.H - z;
+  auto zw = [&](int c, T& pm, T& pd) {
+    pm = T(0);
+    pd = T(0);
+    if (c < cA || c > cB) return;
+    const double zcv = zc[c];
+    pm = es_eval<T>(zcv - z, dp.alpha, dp.beta_m, dp.inv_norm_m) -
+         es_eval<T>(zcv + z, dp.alpha, dp.beta_m, dp.inv_norm_m);
+    pd = es_eval<T>(zcv - z, dp.alpha, dp.beta_d, dp.inv_norm_d) -
+         es_eval<T>(zcv + z, dp.alpha, dp.beta_d, dp.inv_norm_d);
+    if (dp.geometry == 1) {
+      pm -= es_eval<T>(zcv - zim_top, dp.alpha, dp.beta_m, dp.inv_norm_m);
+      pd -= es_eval<T>(zcv - zim_top, dp.alpha, dp.beta_d, dp.inv_norm_d);
+    }
+  };
+  if (Nz % 4 == 0) {
+    for (int c = 0; c < Nz; c += 4) {
+      T pm[4], pd[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) zw(c + e, pm[e], pd[e]);
+      store4(ps + c, pm[0], pm[1], pm[2], pm[3]);
+      store4(ps + Nz + c, pd[0], pd[1], pd[2], pd[3]);
+    }
+  } else {
+    for (int c = 0; c < Nz; ++c) zw(c, ps[c], ps[Nz + c]);
   }
 }
 
-template <typename Tin, typename T, int B>
+template <typename Tin, typename T>
 static void records_impl(const fcmdp_solver* s, int n, const void* pos,
                          const void* F, const void* Tq, hipStream_t st) {
-  const size_t lds = (size_t)B * (33 + 9 + 2 * s->dp.Nz + 1) * sizeof(T);
-  hipLaunchKernelGGL((k_records<Tin, T, B>), dim3((n + B - 1) / B), dim3(B),
-                     lds, st, s->dp, n, s->keyA, s->valA, (const Tin*)pos,
+  hipLaunchKernelGGL((k_records<Tin, T>), dim3((n + 255) / 256), dim3(256), 0,
+                     st, s->dp, n, s->keyA, s->valA, (const Tin*)pos,
                      (const Tin*)F, (const Tin*)Tq, s->zc, s->pinfo,
                      (T*)s->pw, (T*)s->pf, (T*)s->psi);
 }
@@ -387,9 +405,9 @@ hipError_t launch_records(const fcmdp_solver* s, int n, const void* pos,
                           const void* F, const void* T, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (s->mixed)
-    records_impl<float, float, 128>(s, n, pos, F, T, st);
+    records_impl<float, float>(s, n, pos, F, T, st);
   else
-    records_impl<double, double, 64>(s, n, pos, F, T, st);
+    records_impl<double, double>(s, n, pos, F, T, st);
   return hipGetLastError();
 }
 
