@@ -51,9 +51,13 @@ k_prep(DevParams dp, int n, const Tin* __restrict__ pos,
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    // the band only widens, so a workgroup whose planes are already inside
+    // it skips the (contended) atomics
     if (s_hi >= 0) {
-      atomicMin(&band[0], s_lo);
-      atomicMax(&band[1], s_hi);
+      const int glo = __atomic_load_n(&band[0], __ATOMIC_RELAXED);
+      const int ghi = __atomic_load_n(&band[1], __ATOMIC_RELAXED);
+      if (s_lo < glo) atomicMin(&band[0], s_lo);
+      if (s_hi > ghi) atomicMax(&band[1], s_hi);
     }
     if (s_bad) atomicAdd(nbad, (unsigned)s_bad);
   }
