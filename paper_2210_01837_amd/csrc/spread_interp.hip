@@ -467,7 +467,7 @@ k_interp(DevParams dp, int n, const uint32_t* __restrict__ skeys,
   }
 }
 
-// Tiled interpolation: a workgroup owns a 16 x 16 block of xy cells and
+// Tiled interpolation: a workgroup owns a 26 x 26 block of xy cells and
 // interpolates the particles whose cell lies in it ("home" particles, at most
 // `cap` per pass).  Their weights are cached in LDS; the z-nodes they touch
 // give the tile's z range, and only those planes of the block plus its 3-cell
@@ -475,12 +475,14 @@ k_interp(DevParams dp, int n, const uint32_t* __restrict__ skeys,
 // particle (lane = x offset of the 7-point window) and reduces its partial
 // sums with shuffles in a fixed order, so results are deterministic.  The LDS
 // footprint is kept small enough for several workgroups per CU.
-constexpr int kTile = 16;
+constexpr int kTile = 26;
 constexpr int kRX = kTile + 6;
+constexpr int kIThreads = 512;   // threads per interpolation workgroup
 constexpr int kRec = 28;     // wxM[7] wyM[7] wxD[7] wyD[7]
 
 template <typename T, int ZC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(kIThreads)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2, 8)))
 k_interp_tiled(DevParams dp, const int* __restrict__ band,
                const int* __restrict__ cell_start,
                const int4* __restrict__ pinfo, const T* __restrict__ pw,
@@ -527,8 +529,8 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
   const size_t plane = (size_t)dp.Nx * dp.Ny;
   const size_t chstride = plane * dp.Nz;
   const int g = tid / 8, l = tid % 8;
-  constexpr int NG = 256 / 8;
-  constexpr int kRG = 256 / kRX;              // row groups in the staging loop
+  constexpr int NG = kIThreads / 8;
+  constexpr int kRG = kIThreads / kRX;        // row groups in the staging loop
   const int rx = tid % kRX, rg = tid / kRX;
   const int xa = wrap_index(tx0 - 3 + rx, dp.Nx);
 
@@ -537,7 +539,7 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
     if (tid == 0) { zr[0] = dp.Nz; zr[1] = -1; }
     __syncthreads();
     int zlo = dp.Nz, zhi = -1;
-    for (int h = tid; h < np; h += 256) {
+    for (int h = tid; h < np; h += kIThreads) {
       const int hp = base + h;
       int r = 0;
       while (r + 1 < kTile && rowoff[r + 1] <= hp) ++r;
@@ -657,7 +659,7 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
       }
       __syncthreads();
     }
-    for (int h = tid; h < np; h += 256) {
+    for (int h = tid; h < np; h += kIThreads) {
       const int j = pcj[h];
       const T* ac = acc + h * 6;
       U[3 * (size_t)j + 0] = ac[0];
@@ -700,12 +702,12 @@ static hipError_t interp_tiled(const fcmdp_solver* s, int n, const T* grid,
                      st, n, dp.ncells, s->keyA, s->valA, U, Om);
   dim3 g(((dp.Nx + kTile - 1) / kTile) * ((dp.Ny + kTile - 1) / kTile));
   // home particles cached per pass: a monolayer at area fraction 0.5 with
-  // R_h = 1.731 h has ~0.22 particles per xy cell, ~56 per tile; denser
-  // tiles take several passes.  64 keeps four workgroups per CU.
-  const int cap = 64;
+  // R_h = 1.731 h has ~0.22 particles per xy cell, ~150 per 26 x 26 tile;
+  // denser tiles take several passes.  192 keeps two workgroups per CU.
+  const int cap = sizeof(T) == 4 ? 192 : 96;
   constexpr int ZC = sizeof(T) == 4 ? 2 : 1;
   const size_t lds = interp_lds<T, ZC>(cap);
-  hipLaunchKernelGGL((k_interp_tiled<T, ZC>), g, dim3(256), lds, st, dp,
+  hipLaunchKernelGGL((k_interp_tiled<T, ZC>), g, dim3(kIThreads), lds, st, dp,
                      s->band, s->cell_start, s->pinfo, (const T*)s->pw,
                      (const T*)s->psi, (const T*)s->quad, grid, s->valA, U, Om,
                      cap);
