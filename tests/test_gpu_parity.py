@@ -188,6 +188,30 @@ def test_apply_deterministic_and_edge_cases():
         s.apply(big, big, big)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_apply_dense_cluster(precision):
+    """Hundreds of particles in a few cells: spread regions beyond the staged
+    capacity (the global-memory path) and interpolation tiles with more home
+    particles than one pass holds (several passes)."""
+    box = BOXES["bw48"]
+    pos, F, T = _particles(box, 420, 12)
+    rng = np.random.default_rng(1234)
+    # 400 of them in a 4 x 4-cell patch next to the periodic seam
+    pos[20:, 0] = (box.Lx - 2 * box.h) + 4 * box.h * rng.random(400)
+    pos[20:, 0] %= box.Lx
+    pos[20:, 1] = 10.0 + 4 * box.h * rng.random(400)
+    if precision == "mixed":
+        pos, F, T = (a.astype(np.float32).astype(np.float64) for a in (pos, F, T))
+    print(f"[dense cluster] {precision}", flush=True)
+    s = _solver(box, precision)
+    U, Om = s.apply(_dev(pos, precision), _dev(F, precision), _dev(T, precision))
+    rU, rO = oracle_apply(box, pos, F, T)
+    eU, eO = rel_err(_np(U), rU), rel_err(_np(Om), rO)
+    print(f"  rel err U {eU:.3e} Omega {eO:.3e}", flush=True)
+    tol = 1e-5 if precision == "mixed" else 1e-10
+    assert eU < tol and eO < tol
+
+
 def test_domain_errors_give_nan_and_status():
     box = BOXES["bw48"]
     pos, F, T = _particles(box, 30, 10)
