@@ -461,6 +461,303 @@ __device__ inline void seg_basis(const double fb[kNpl], const double* __restrict
   }
 }
 
+// ---- parity-split layout ----------------------------------------------------
+// The even and odd coefficient systems are independent except through the
+// derivative, so the eight lanes of a column split by parity: lane l has
+// parity p = l / 4 and position q = l % 4 in its group, and slot s (0..3)
+// holds unknown i = 4 q + s of that parity, coefficient m = 2 i + p = 8 q +
+// 2 s + p.  Every scan then runs over four lanes (two steps) for one parity
+// instead of over eight lanes (three steps) for both.
+__device__ __forceinline__ int ps_m(int l, int s) { return 8 * (l & 3) + 2 * s + (l >> 2); }
+
+// sum over the four lanes of a parity group (one quad)
+__device__ __forceinline__ double red4(double a) {
+  a += dpp_d<0xB1>(a);
+  a += dpp_d<0x4E>(a);
+  return a;
+}
+__device__ inline Z2 red4(Z2 a) { return zmk(red4(a.x), red4(a.y)); }
+// value of the same slot in the other parity group (lane l xor 4)
+// (ds_swizzle bit mode: and-mask 31, or-mask 0, xor-mask 4)
+__device__ __forceinline__ double swz_xor4(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_ds_swizzle(hi, 0x101F),
+                          __builtin_amdgcn_ds_swizzle(lo, 0x101F));
+}
+__device__ __forceinline__ Z2 other_group(Z2 a) {
+  return zmk(swz_xor4(a.x), swz_xor4(a.y));
+}
+
+struct Par4 {
+  double alpha[kNpl];
+  double P[kNpl];
+  double invD[kNpl];
+  double invEP;        // 1 / sum_i e_i P_i (dense boundary row)
+};
+
+// Operator data of this lane's parity for the Robin BVP (kappa only); see
+// seg_prepare for the two-slot form of the same recurrences.
+__device__ __forceinline__ Par4 ps_prepare(double kappa, int N, int l) {
+  Par4 q;
+  const int g = l & 3;
+  const double k2 = kappa * kappa;
+  double T[kNpl][4];
+  double Dd[kNpl], Uu[kNpl], e[kNpl];
+  bool act[kNpl], row[kNpl];
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) {
+    const int m = ps_m(l, s);
+    act[s] = m < N;
+    const Row rw = row_of(m, N);
+    row[s] = rw.row;
+    e[s] = act[s] ? (double)m * m + kappa : 0.0;
+    if (row[s]) {
+      Dd[s] = 1.0 + k2 * rw.di;
+      Uu[s] = -k2 * rw.up;
+      T[s][0] = 0.0; T[s][1] = k2 * rw.lo; T[s][2] = Uu[s]; T[s][3] = Dd[s];
+    } else {
+      Dd[s] = 1.0;
+      Uu[s] = 0.0;
+      T[s][0] = 1.0; T[s][1] = 0.0; T[s][2] = 0.0; T[s][3] = 1.0;
+    }
+  }
+  auto norm = [](double* Z) {
+    const double sc = fmax(fmax(fabs(Z[0]), fabs(Z[1])), fmax(fabs(Z[2]), fabs(Z[3])));
+    const int ex = sc > 0.0 ? -ilogb(sc) : 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Z[c] = ldexp(Z[c], ex);
+  };
+  // product of this lane's four Moebius matrices, then suffix products over
+  // the lanes of the group (rescaled by powers of two; only ratios matter)
+  double Y[4], Z[4];
+  m2mul(T[2], T[3], Z);
+  m2mul(T[1], Z, Y);
+  m2mul(T[0], Y, Z);
+  norm(Z);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Y[c] = Z[c];
+  {
+    double Yk[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Yk[c] = from_up<1>(Y[c]);
+    if (g + 1 < 4) { m2mul(Y, Yk, Z); norm(Z); for (int c = 0; c < 4; ++c) Y[c] = Z[c]; }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Yk[c] = from_up<2>(Y[c]);
+    if (g + 2 < 4) { m2mul(Y, Yk, Z); norm(Z); for (int c = 0; c < 4; ++c) Y[c] = Z[c]; }
+  }
+  double X[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) X[c] = from_up<1>(Y[c]);
+  if (g == 3) { X[0] = 1.0; X[1] = 0.0; X[2] = 0.0; X[3] = 1.0; }
+  double Sx[4];
+#pragma unroll
+  for (int s = kNpl - 1; s >= 0; --s) {
+    m2mul(T[s], X, Sx);
+    q.alpha[s] = Sx[1] * frcp(Sx[3]);
+    norm(Sx);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) X[c] = Sx[c];
+  }
+  if (g == 0) q.alpha[0] = 1.0;                // i = 0: P_0 = 1
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s)
+    if (!act[s]) q.alpha[s] = 0.0;
+  // Delta_i = D_i + U_i alpha_{i+1}
+  double anext[kNpl];
+#pragma unroll
+  for (int s = 0; s + 1 < kNpl; ++s) anext[s] = q.alpha[s + 1];
+  {
+    const double t = from_up<1>(q.alpha[0]);
+    anext[kNpl - 1] = (g + 1 < 4) ? t : 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s)
+    q.invD[s] = row[s] ? frcp(Dd[s] + Uu[s] * anext[s]) : 0.0;
+  // prefix products P_i = alpha_i P_{i-1}
+  double Yp = q.alpha[0] * q.alpha[1] * q.alpha[2] * q.alpha[3];
+  {
+    double t = from_down<1>(Yp);
+    if (g >= 1) Yp *= t;
+    t = from_down<2>(Yp);
+    if (g >= 2) Yp *= t;
+  }
+  double Pin = from_down<1>(Yp);
+  if (g == 0) Pin = 1.0;
+  q.P[0] = q.alpha[0] * Pin;
+#pragma unroll
+  for (int s = 1; s < kNpl; ++s) q.P[s] = q.alpha[s] * q.P[s - 1];
+  double ep = 0.0;
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) ep += e[s] * q.P[s];
+  q.invEP = frcp(red4(ep));
+  return q;
+}
+
+// Robin BVP y'' - k^2 y = r, (d/dz + k) y(H) = gH, (d/dz - k) y(0) = g0, for
+// this lane's parity (same recurrences as seg_solve, four slots per lane).
+__device__ __forceinline__ Vec ps_solve(const Par4& Q, const Vec& r, Z2 gH, Z2 g0,
+                                        double H, double kappa, int N, int l) {
+  const int g = l & 3, p = l >> 2;
+  const double h2 = 0.25 * H * H;
+  const double k2 = kappa * kappa;
+  const Z2 rm2 = from_down<1>(r.v[kNpl - 1]);        // r_{m-2} of slot 0
+  const Z2 rp2 = from_up<1>(r.v[0]);                 // r_{m+2} of slot 3
+  Z2 b[kNpl];
+  double a[kNpl];
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) {
+    const Row w = row_of(ps_m(l, s), N);
+    const Z2 rm = s == 0 ? rm2 : r.v[s - 1];
+    const Z2 rp = s == kNpl - 1 ? rp2 : r.v[s + 1];
+    const Z2 R = h2 * (w.lo * rm - w.di * r.v[s] + w.up * rp);
+    b[s] = Q.invD[s] * R;
+    a[s] = k2 * w.up * Q.invD[s];                    // -U_i / Delta_i
+  }
+  // beta: suffix affine recurrence beta_i = a_i beta_{i+1} + b_i
+  double A = a[kNpl - 1];
+  Z2 B = b[kNpl - 1];
+#pragma unroll
+  for (int s = kNpl - 2; s >= 0; --s) {
+    B = a[s] * B + b[s];
+    A = a[s] * A;
+  }
+  {
+    double Ak = from_up<1>(A);
+    Z2 Bk = from_up<1>(B);
+    if (g + 1 < 4) { B = A * Bk + B; A = A * Ak; }
+    Ak = from_up<2>(A);
+    Bk = from_up<2>(B);
+    if (g + 2 < 4) { B = A * Bk + B; A = A * Ak; }
+  }
+  Z2 bin = from_up<1>(B);
+  if (g == 3) bin = zmk(0, 0);
+  Z2 be[kNpl];
+  be[kNpl - 1] = a[kNpl - 1] * bin + b[kNpl - 1];
+#pragma unroll
+  for (int s = kNpl - 2; s >= 0; --s) be[s] = a[s] * be[s + 1] + b[s];
+  if (g == 0) be[0] = zmk(0, 0);
+  // Q_i = alpha_i Q_{i-1} + beta_i (prefix), Q_0 = 0
+  double Aq = Q.alpha[0];
+  Z2 Bq = be[0];
+#pragma unroll
+  for (int s = 1; s < kNpl; ++s) {
+    Bq = Q.alpha[s] * Bq + be[s];
+    Aq = Q.alpha[s] * Aq;
+  }
+  {
+    double Ak = from_down<1>(Aq);
+    Z2 Bk = from_down<1>(Bq);
+    if (g >= 1) { Bq = Aq * Bk + Bq; Aq = Aq * Ak; }
+    Ak = from_down<2>(Aq);
+    Bk = from_down<2>(Bq);
+    if (g >= 2) { Bq = Aq * Bk + Bq; Aq = Aq * Ak; }
+  }
+  Z2 qin = from_down<1>(Bq);
+  if (g == 0) qin = zmk(0, 0);
+  Z2 Qv[kNpl];
+  Qv[0] = Q.alpha[0] * qin + be[0];
+#pragma unroll
+  for (int s = 1; s < kNpl; ++s) Qv[s] = Q.alpha[s] * Qv[s - 1] + be[s];
+  Z2 eq = zmk(0, 0);
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) {
+    const int m = ps_m(l, s);
+    const double e = m < N ? (double)m * m + kappa : 0.0;
+    eq = eq + e * Qv[s];
+  }
+  const Z2 eQ = red4(eq);
+  const Z2 gg = p == 0 ? (0.25 * H) * (gH - g0) : (0.25 * H) * (gH + g0);
+  const Z2 y0 = Q.invEP * (gg - eQ);
+  Vec y;
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) y.v[s] = Q.P[s] * y0 + Qv[s];
+  return y;
+}
+
+// d/dz of a Chebyshev series (times 2/H): b_m = c_m (2/H) sum over n > m of
+// opposite parity of 2 n a_n (c_0 = 1/2, else 1).  Each group sums its own
+// weighted coefficients from the top; the even outputs take the odd group's
+// inclusive sums, the odd outputs the even group's sums from the next
+// unknown on.
+__device__ inline Vec ps_deriv(const Vec& a, int l, double s2H) {
+  const int g = l & 3, p = l >> 2;
+  Z2 w[kNpl];
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) w[s] = (double)ps_m(l, s) * a.v[s];
+  // inclusive suffix sums over this group's unknowns
+  Z2 tot = w[0] + w[1] + w[2] + w[3];
+  Z2 suf = tot;                                      // sum over lanes >= g
+  {
+    Z2 t = from_up<1>(suf);
+    if (g + 1 < 4) suf = suf + t;
+    t = from_up<2>(suf);
+    if (g + 2 < 4) suf = suf + t;
+  }
+  Z2 after = from_up<1>(suf);                        // sum over lanes > g
+  if (g == 3) after = zmk(0, 0);
+  Z2 S[kNpl];                                        // inclusive, per slot
+  S[kNpl - 1] = w[kNpl - 1] + after;
+#pragma unroll
+  for (int s = kNpl - 2; s >= 0; --s) S[s] = w[s] + S[s + 1];
+  // even group: sums from the next unknown on (for the odd outputs)
+  Z2 X[kNpl];
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) X[s] = p == 1 ? S[s] : (s + 1 < kNpl ? S[s + 1] : after);
+  Vec b;
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) {
+    const Z2 v = other_group(X[s]);
+    const double c = (p == 0 && g == 0 && s == 0) ? 1.0 : 2.0;
+    b.v[s] = (c * s2H) * v;
+  }
+  return b;
+}
+
+__device__ inline Z2 ps_bsum_bottom(const Vec& a, int l) {   // sum (-1)^n a_n
+  const Z2 t = a.v[0] + a.v[1] + a.v[2] + a.v[3];
+  return red((l >> 2) ? -1.0 * t : t);
+}
+__device__ inline Z2 ps_bsum_top(const Vec& a) {             // sum a_n
+  return red(a.v[0] + a.v[1] + a.v[2] + a.v[3]);
+}
+
+// k = 0: y'' = r with y(0) = 0 and y'(H) = 0 (bottom wall) or y(H) = 0.
+__device__ __forceinline__ Vec ps_zero_mode(const Vec& r, double H, int N, int geometry,
+                                            int l) {
+  const double h2 = 0.25 * H * H;
+  const Z2 rm2 = from_down<1>(r.v[kNpl - 1]);
+  const Z2 rp2 = from_up<1>(r.v[0]);
+  Vec y = vzero();
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) {
+    const Row w = row_of(ps_m(l, s), N);
+    const Z2 rm = s == 0 ? rm2 : r.v[s - 1];
+    const Z2 rp = s == kNpl - 1 ? rp2 : r.v[s + 1];
+    if (w.row) y.v[s] = h2 * (w.lo * rm - w.di * r.v[s] + w.up * rp);
+  }
+  Z2 sp = zmk(0, 0), sm = zmk(0, 0), sn2 = zmk(0, 0);
+  const double sgn = (l >> 2) ? -1.0 : 1.0;
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) {
+    const double n = ps_m(l, s);
+    sp = sp + y.v[s];
+    sm = sm + sgn * y.v[s];
+    sn2 = sn2 + (n * n) * y.v[s];
+  }
+  sp = red(sp);
+  sm = red(sm);
+  sn2 = red(sn2);
+  if ((l & 3) == 0) {                                // slot 0 holds m = 0 or 1
+    const bool odd = l >> 2;
+    if (geometry == 0) {
+      y.v[0] = odd ? -1.0 * sn2 : -1.0 * sn2 - sm;
+    } else {
+      y.v[0] = odd ? -0.5 * (sp - sm) : -0.5 * (sp + sm);
+    }
+  }
+  return y;
+}
+
 // Steps 2 (derivative part) to 6 for one column, from the Chebyshev
 // coefficients A[0..2] of f + (1/2)(ik_y g_z, -ik_x g_z, ik_x g_y - ik_y g_x)
 // and A[3], A[4] of g_x, g_y: body force, DP solve, wall correction, k = 0.
@@ -471,7 +768,9 @@ __device__ inline void seg_basis(const double fb[kNpl], const double* __restrict
 // `basis(which, out)` returns this lane's four Chebyshev coefficients of the
 // correction's node functions: which = 0: e^{-k z}, 1: z e^{-k z},
 // 2: e^{k (z - H)}, 3: z e^{k (z - H)} (the last two for the slit channel).
-template <int GEOM, typename Load, typename Basis>
+// SPLIT selects the parity-split coefficient layout (ps_*) instead of four
+// consecutive coefficients per lane.
+template <int GEOM, bool SPLIT = false, typename Load, typename Basis>
 __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& basis,
                                  const DevParams& dp, int N, int l,
                                  double kx, double ky, double k, Vec& U,
@@ -480,15 +779,23 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
   U = vzero();
   V = vzero();
   W = vzero();
+  auto deriv = [&](const Vec& a) {
+    if constexpr (SPLIT) return ps_deriv(a, l, s2H);
+    else return seg_deriv(a, l, s2H);
+  };
+  auto bot = [&](const Vec& a) {
+    if constexpr (SPLIT) return ps_bsum_bottom(a, l);
+    else return bsum_bottom(a);
+  };
   auto body_x = [&]() {
-    const Vec dgy = seg_deriv(load(4), l, s2H);
+    const Vec dgy = deriv(load(4));
     Vec f = load(0);
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) f.v[j] = f.v[j] - 0.5 * dgy.v[j];
     return f;
   };
   auto body_y = [&]() {
-    const Vec dgx = seg_deriv(load(3), l, s2H);
+    const Vec dgx = deriv(load(3));
     Vec f = load(1);
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) f.v[j] = f.v[j] + 0.5 * dgx.v[j];
@@ -498,17 +805,28 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     Vec r = body_x();
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
-    U = seg_zero_mode(r, H, N, GEOM, l);
+    if constexpr (SPLIT) U = ps_zero_mode(r, H, N, GEOM, l);
+    else U = seg_zero_mode(r, H, N, GEOM, l);
     r = body_y();
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
-    V = seg_zero_mode(r, H, N, GEOM, l);
+    if constexpr (SPLIT) V = ps_zero_mode(r, H, N, GEOM, l);
+    else V = seg_zero_mode(r, H, N, GEOM, l);
   } else {
     const double kappa = 0.5 * k * H;
     Par q[2];
-    q[0] = seg_prepare(kappa, N, l, 0);
-    q[1] = seg_prepare(kappa, N, l, 1);
-    Vec r = seg_deriv(load(2), l, s2H);
+    Par4 q4;
+    if constexpr (SPLIT) {
+      q4 = ps_prepare(kappa, N, l);
+    } else {
+      q[0] = seg_prepare(kappa, N, l, 0);
+      q[1] = seg_prepare(kappa, N, l, 1);
+    }
+    auto solve = [&](const Vec& rr, Z2 gH, Z2 g0) {
+      if constexpr (SPLIT) return ps_solve(q4, rr, gH, g0, H, kappa, N, l);
+      else return seg_solve(q, rr, gH, g0, H, kappa, N, l);
+    };
+    Vec r = deriv(load(2));
     {
       const Vec fx = body_x();
 #pragma unroll
@@ -519,33 +837,32 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) r.v[j] = r.v[j] + imul(ky, fy.v[j]);
     }
-    const Vec p = seg_solve(q, r, zmk(0, 0), zmk(0, 0), H, kappa, N, l);
-    const Z2 pH = bsum_top(p), p0 = bsum_bottom(p);
+    const Vec p = solve(r, zmk(0, 0), zmk(0, 0));
+    const Z2 pH = bsum_top(p), p0 = bot(p);
     const double ie = frcp(eta), ik = frcp(k);
     {
-      const Vec dp_ = seg_deriv(p, l, s2H);
+      const Vec dp_ = deriv(p);
       const Vec fz = load(2);
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (dp_.v[j] - fz.v[j]);
     }
-    W = seg_solve(q, r, (0.5 * ie) * pH, (0.5 * ie) * p0, H, kappa, N, l);
+    W = solve(r, (0.5 * ie) * pH, (0.5 * ie) * p0);
     {
       const Vec fx = body_x();
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(kx, p.v[j]) - fx.v[j]);
     }
     const double ax = 0.5 * kx * ik * ie, ay = 0.5 * ky * ik * ie;
-    U = seg_solve(q, r, imul(-ax, pH), imul(ax, p0), H, kappa, N, l);
+    U = solve(r, imul(-ax, pH), imul(ax, p0));
     {
       const Vec fy = body_y();
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) r.v[j] = ie * (imul(ky, p.v[j]) - fy.v[j]);
     }
-    V = seg_solve(q, r, imul(-ay, pH), imul(ay, p0), H, kappa, N, l);
+    V = solve(r, imul(-ay, pH), imul(ay, p0));
 
     // wall correction, evaluated on all nodes and transformed
-    const Z2 u0 = -1.0 * bsum_bottom(U), v0 = -1.0 * bsum_bottom(V),
-             w0 = -1.0 * bsum_bottom(W);
+    const Z2 u0 = -1.0 * bot(U), v0 = -1.0 * bot(V), w0 = -1.0 * bot(W);
     double E[kNpl], ZE[kNpl];
     basis(0, E);
     basis(1, ZE);
@@ -763,7 +1080,7 @@ template <int GEOM> struct MfmaLayout {
   static constexpr int kBasis = GEOM == 0 ? 2 : 4;     // correction node functions
   static constexpr int kSpec = kMCols * 10;            // spectral reals per row
   // reals per row; the odd pad spreads the eight lanes of a column (rows
-  // 4l + j) over different LDS banks
+  // 8 (l % 4) + 2 j + l / 4) over different LDS banks
   static constexpr int kMV = kSpec + kMCols * kBasis + 1;
   static constexpr int kSpecTiles = 2 * (kSpec / 16);  // forward, band rows
   static constexpr int kBasisTiles = 2 * kBasis;       // forward, all nodes
@@ -957,31 +1274,34 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const double ky = cp.kys * nyi;
     const double k = sqrt(kx * kx + ky * ky);
     const double s2H = 2.0 / dp.H;
-    float* cbase = XC + 4 * l * kMV + cl * 10;
-    float* bbase = XC + 4 * l * kMV + kSpec + cl * NB;
+    // parity-split layout: slot j of lane l is coefficient 8 (l % 4) + 2 j
+    // + l / 4
+    const int m0 = ps_m(l, 0);
+    float* cbase = XC + m0 * kMV + cl * 10;
+    float* bbase = XC + m0 * kMV + kSpec + cl * NB;
     Vec U = vzero(), V = vzero(), W = vzero();
     if (!nyq) {
       auto load = [&](int v) {
         Vec a;
 #pragma unroll
         for (int j = 0; j < kNpl; ++j) {
-          float* cr = cbase + j * kMV + 2 * v;
+          float* cr = cbase + 2 * j * kMV + 2 * v;
           a.v[j] = zmk((double)cr[0], (double)cr[1]);
         }
         return a;
       };
       auto basis = [&](int which, double o[kNpl]) {
 #pragma unroll
-        for (int j = 0; j < kNpl; ++j) o[j] = (double)bbase[j * kMV + which];
+        for (int j = 0; j < kNpl; ++j) o[j] = (double)bbase[2 * j * kMV + which];
       };
-      seg_column_solve<GEOM>(load, basis, dp, N, l, kx, ky, k, U, V, W);
+      seg_column_solve<GEOM, true>(load, basis, dp, N, l, kx, ky, k, U, V, W);
     }
     // the column's coefficients are read only by its own eight lanes (one
     // wavefront, in lockstep): overwrite them in place
     auto store = [&](int v, const Vec& a) {
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) {
-        float* cr = cbase + j * kMV + 2 * v;
+        float* cr = cbase + 2 * j * kMV + 2 * v;
         cr[0] = (float)a.v[j].x;
         cr[1] = (float)a.v[j].y;
       }
@@ -989,8 +1309,8 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     store(0, U);
     store(1, V);
     store(2, W);
-    store(3, seg_deriv(U, l, s2H));
-    store(4, seg_deriv(V, l, s2H));
+    store(3, ps_deriv(U, l, s2H));
+    store(4, ps_deriv(V, l, s2H));
   }
   __syncthreads();
 
