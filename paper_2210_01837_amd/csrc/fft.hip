@@ -814,21 +814,48 @@ k_fftw_x_c2r(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   const size_t pbase = (size_t)p * dp.Nkx * dp.Ny;
   if constexpr (ROWS % 2 == 0 && sizeof(T) == 4) {
     // two consecutive rows per thread: one 16-byte load (y0 and Ny even)
-    for (int idx = threadIdx.x; idx < (M + 1) * (ROWS / 2); idx += ROWS * TPR) {
-      const int k = idx / (ROWS / 2);
-      const int r = 2 * (idx % (ROWS / 2));
-      const C* src = spec + pbase + (size_t)k * dp.Ny + y0;
-      C a, b;
-      if (r + 1 < nr && (dp.Ny & 1) == 0) {
-        const float4 v = *reinterpret_cast<const float4*>(src + r);
-        a.x = v.x; a.y = v.y; b.x = v.z; b.y = v.w;
-      } else {
-        // rows past the grid edge transform a copy of row y0
-        a = src[r < nr ? r : 0];
-        b = src[r + 1 < nr ? r + 1 : 0];
+    const int total = (M + 1) * (ROWS / 2);
+    if (nr == ROWS && (dp.Ny & 1) == 0) {
+      // whole workgroup: a thread issues all of its loads (nine cover the
+      // half spectrum of 2176-point rows) before the first LDS store
+      constexpr int kB = 9;
+      for (int base = threadIdx.x; base < total; base += kB * ROWS * TPR) {
+        float4 v[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int idx = min(base + u * ROWS * TPR, total - 1);   // in bounds
+          const int k = idx / (ROWS / 2);
+          const int r = 2 * (idx % (ROWS / 2));
+          v[u] = *reinterpret_cast<const float4*>(spec + pbase + (size_t)k * dp.Ny + y0 + r);
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int idx = base + u * ROWS * TPR;
+          if (idx < total) {
+            const int k = idx / (ROWS / 2);
+            const int r = 2 * (idx % (ROWS / 2));
+            lds[r * S + k] = make_float2(v[u].x, v[u].y);
+            lds[(r + 1) * S + k] = make_float2(v[u].z, v[u].w);
+          }
+        }
       }
-      lds[r * S + k] = a;
-      lds[(r + 1) * S + k] = b;
+    } else {
+      for (int idx = threadIdx.x; idx < total; idx += ROWS * TPR) {
+        const int k = idx / (ROWS / 2);
+        const int r = 2 * (idx % (ROWS / 2));
+        const C* src = spec + pbase + (size_t)k * dp.Ny + y0;
+        C a, b;
+        if (r + 1 < nr && (dp.Ny & 1) == 0) {
+          const float4 v = *reinterpret_cast<const float4*>(src + r);
+          a.x = v.x; a.y = v.y; b.x = v.z; b.y = v.w;
+        } else {
+          // rows past the grid edge transform a copy of row y0
+          a = src[r < nr ? r : 0];
+          b = src[r + 1 < nr ? r + 1 : 0];
+        }
+        lds[r * S + k] = a;
+        lds[(r + 1) * S + k] = b;
+      }
     }
   } else {
     for (int idx = threadIdx.x; idx < (M + 1) * ROWS; idx += ROWS * TPR) {
