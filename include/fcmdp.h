@@ -64,7 +64,8 @@ typedef struct {
   double Lx, Ly, H;    /* periods and channel height / domain top */
   int Nx, Ny, Nz;      /* grid; Nx, Ny even, >= 8, factors in {2,3,5,7,11,13,17};
                           8 <= Nz <= 64 */
-  int w;               /* ES support in grid cells (even, 4..8) */
+  int w;               /* ES support in grid cells: 4 or 6 (the kernels hold a
+                          7-point window) */
   double beta_m, beta_d; /* ES shape parameters, monopole and dipole */
   double eta;          /* viscosity > 0 */
   int precision;       /* FCMDP_FP64 or FCMDP_MIXED */
@@ -86,9 +87,13 @@ int fcmdp_workspace_bytes(const fcmdp_params* p, int64_t n, size_t* bytes);
 /*
  * The mobility apply (F, T) -> (U, Omega) for n particles.
  *   pos, F: [n][3] device arrays (double in FP64 mode, float in MIXED mode).
- *   T:      torques, or NULL for none.
+ *   T:      torques, or NULL for none: the torque (dipole) channels are then
+ *           neither spread, transformed nor read by the solve (the
+ *           forces-only apply of Sec. 5 carries three channels).
  *   U:      output velocities [n][3].
- *   Omega:  output angular velocities [n][3], or NULL to skip.
+ *   Omega:  output angular velocities [n][3], or NULL to skip: the solve
+ *           then returns the three velocity channels only and the inverse
+ *           transform and interpolation carry three channels.
  * x and y are wrapped periodically.  Particles with z < 0, z > H (slit
  * channel) or z + alpha > H (bottom wall; the forcing must vanish above the
  * computational top) are skipped: their outputs are NaN and fcmdp_status()

@@ -161,7 +161,8 @@ int validate(const fcmdp_params* p) {
   if (!(p->beta_m > 0) || !(p->beta_d > 0)) return FCMDP_EINVAL;
   if (p->Nx < 8 || p->Ny < 8 || (p->Nx & 1) || (p->Ny & 1)) return FCMDP_EINVAL;
   if (p->Nz < 8 || p->Nz > fcmdp::kMaxNz) return FCMDP_EINVAL;
-  if (p->w != 6) return FCMDP_EINVAL;   // the kernels hold a 7-point window
+  // the kernels hold a 7-point window (|offset| <= 3 cells)
+  if (p->w != 4 && p->w != 6) return FCMDP_EINVAL;
   if (p->max_particles < 0 || p->max_particles > (int64_t)1 << 30)
     return FCMDP_EINVAL;
   const double hx = p->Lx / p->Nx, hy = p->Ly / p->Ny;
@@ -307,6 +308,8 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
   dp.Nkx = p->Nx / 2 + 1;
   dp.ncells = p->Nx * p->Ny;
   dp.half_w = p->w / 2;
+  dp.nch_in = 6;
+  dp.nch_out = 6;
   dp.Lx = p->Lx;
   dp.Ly = p->Ly;
   dp.H = p->H;
@@ -508,6 +511,10 @@ int fcmdp_apply_mobility(fcmdp_solver* s, int64_t n, const void* pos,
                                                                : FCMDP_EHIP;
   }
   const int ni = (int)n;
+  // without torques the grid and spectrum carry the three force channels;
+  // without angular velocities the solve returns the three velocity channels
+  s->dp.nch_in = T ? 6 : 3;
+  s->dp.nch_out = Omega ? 6 : 3;
   hipEvent_t ev[7] = {};
   const bool prof = s->profiling;
   if (prof) {
@@ -641,12 +648,19 @@ static bool band_ok(const fcmdp_solver* s, int lo, int hi) {
   return lo >= 0 && hi < s->dp.Nz && lo <= hi;
 }
 
+// the stage entry points work on the full six-channel layouts
+static void all_channels(fcmdp_solver* s) {
+  s->dp.nch_in = 6;
+  s->dp.nch_out = 6;
+}
+
 int fcmdp_stage_spread(fcmdp_solver* s, int64_t n, const void* pos,
                        const void* F, const void* T, void* grid,
                        void* hip_stream) {
   int v = check_particles(s, n);
   if (v != FCMDP_OK) return v;
   if (!grid || (n > 0 && (!pos || !F))) return FCMDP_EINVAL;
+  all_channels(s);
   hipStream_t st = (hipStream_t)hip_stream;
   if (fcmdp::launch_fill(grid, grid_bytes(s), st) != hipSuccess)
     return FCMDP_EHIP;
@@ -661,6 +675,7 @@ int fcmdp_stage_fft_forward(fcmdp_solver* s, const void* grid, void* spectrum,
                             int c_lo, int c_hi, void* hip_stream) {
   if (!s || !grid || !spectrum || !band_ok(s, c_lo, c_hi)) return FCMDP_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  all_channels(s);
   hipStream_t st = (hipStream_t)hip_stream;
   if (fcmdp::launch_set_band(s, c_lo, c_hi, st) != hipSuccess) return FCMDP_EHIP;
   return fcmdp::launch_fft_forward(s, grid, spectrum, st) == hipSuccess
@@ -674,6 +689,7 @@ int fcmdp_stage_solve(fcmdp_solver* s, const void* spectrum_in,
   if (!s || !spectrum_in || !spectrum_out || !band_ok(s, c_lo, c_hi))
     return FCMDP_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  all_channels(s);
   hipStream_t st = (hipStream_t)hip_stream;
   if (fcmdp::launch_set_band(s, c_lo, c_hi, st) != hipSuccess) return FCMDP_EHIP;
   return fcmdp::launch_columns(s, spectrum_in, spectrum_out, st) == hipSuccess
@@ -685,6 +701,7 @@ int fcmdp_stage_fft_inverse(fcmdp_solver* s, const void* spectrum, void* grid,
                             int c_lo, int c_hi, void* hip_stream) {
   if (!s || !grid || !spectrum || !band_ok(s, c_lo, c_hi)) return FCMDP_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  all_channels(s);
   hipStream_t st = (hipStream_t)hip_stream;
   if (fcmdp::launch_set_band(s, c_lo, c_hi, st) != hipSuccess) return FCMDP_EHIP;
   // the y-pass works in place: run it on the solver's own spectrum buffer
@@ -703,6 +720,7 @@ int fcmdp_stage_interp(fcmdp_solver* s, int64_t n, const void* pos,
   if (v != FCMDP_OK) return v;
   if (!grid || (n > 0 && (!pos || !U))) return FCMDP_EINVAL;
   if (n == 0) return FCMDP_OK;
+  all_channels(s);
   hipStream_t st = (hipStream_t)hip_stream;
   v = particle_front(s, (int)n, pos, nullptr, nullptr, st);
   if (v != FCMDP_OK) return v;

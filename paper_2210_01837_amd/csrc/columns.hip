@@ -149,7 +149,7 @@ k_columns(ColParams cp, const int* __restrict__ band,
   using C = cplx_t<T>;
   if (kxi == dp.Nx / 2 || kyi == dp.Ny / 2) {
     C zero; zero.x = T(0); zero.y = T(0);
-    for (int ch = 0; ch < 6; ++ch)
+    for (int ch = 0; ch < dp.nch_out; ++ch)
       for (int c = lo; c <= hi; ++c) out[(ch * N + c) * PS + idx] = zero;
     return;
   }
@@ -167,6 +167,7 @@ k_columns(ColParams cp, const int* __restrict__ band,
   // 1. Chebyshev transform of the band node values
   for (int ch = 0; ch < 6; ++ch) {
     for (int n = 0; n < N; ++n) A[ch][n] = zmk(0, 0);
+    if (ch >= dp.nch_in) continue;                // no torques: g = 0
     for (int c = lo; c <= hi; ++c) {
       const C v = in[(ch * N + c) * PS + idx];
       const Z2 z = zmk((double)v.x, (double)v.y);
@@ -290,8 +291,8 @@ k_columns(ColParams cp, const int* __restrict__ band,
     A[4][n] = 0.5 * (tmp2[n] - imul(kx, A[2][n]));
     A[5][n] = 0.5 * (imul(kx, A[1][n]) - imul(ky, A[0][n]));
   }
-  // inverse transform to the band nodes
-  for (int ch = 0; ch < 6; ++ch) {
+  // inverse transform to the band nodes (vorticity only when wanted)
+  for (int ch = 0; ch < dp.nch_out; ++ch) {
     for (int c = lo; c <= hi; ++c) {
       const double* row = Pi + c * N;
       Z2 s = zmk(0, 0);

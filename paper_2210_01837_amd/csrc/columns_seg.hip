@@ -971,7 +971,8 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
       Z2 val[6];
 #pragma unroll
       for (int ch = 0; ch < 6; ++ch) {
-        const C t = in[(ch * N + ca) * PS + idx];
+        // without torques the dipole channels are zero and not read
+        const C t = (ch < 3 || dp.nch_in == 6) ? in[(ch * N + ca) * PS + idx] : C{};
         val[ch] = zmk((double)t.x, (double)t.y);
       }
       Z2 comb[5];
@@ -1046,6 +1047,7 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
     o[5] = 0.5 * (imul(kx, s[1]) - imul(ky, s[0]));
 #pragma unroll
     for (int ch = 0; ch < 6; ++ch) {
+      if (ch >= dp.nch_out) break;               // vorticity only when wanted
       C t;
       t.x = (T)(sc * o[ch].x);
       t.y = (T)(sc * o[ch].y);
@@ -1167,10 +1169,14 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
       kyv[h] = kys * (float)nyi;
     }
     if (c < P && idx < K) {
+      // without torques the dipole channels are zero and not read
+      const bool dip = dp.nch_in == 6;
       float4 v[6];
 #pragma unroll
       for (int ch = 0; ch < 6; ++ch)
-        v[ch] = *reinterpret_cast<const float4*>(in + (ch * N + lo + c) * PS + idx);
+        v[ch] = (ch < 3 || dip)
+                    ? *reinterpret_cast<const float4*>(in + (ch * N + lo + c) * PS + idx)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         float2 w[6];
@@ -1377,10 +1383,13 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
       o[h][5] = make_float2(0.5f * sc * (-kx * vi + ky * ui),
                             0.5f * sc * (kx * vr - ky * ur));
     }
+    // the vorticity channels only when angular velocities are wanted
+    const int nch = dp.nch_out;
 #pragma unroll
     for (int ch = 0; ch < 6; ++ch)
-      *reinterpret_cast<float4*>(out + (ch * N + lo + c) * PS + idx) =
-          make_float4(o[0][ch].x, o[0][ch].y, o[1][ch].x, o[1][ch].y);
+      if (ch < nch)
+        *reinterpret_cast<float4*>(out + (ch * N + lo + c) * PS + idx) =
+            make_float4(o[0][ch].x, o[0][ch].y, o[1][ch].x, o[1][ch].y);
   }
 }
 

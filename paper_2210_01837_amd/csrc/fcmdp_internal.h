@@ -24,7 +24,7 @@ namespace fcmdp {
 constexpr int kMaxNz = 64;
 constexpr int kMaxStages = 24;
 constexpr size_t kLdsBudget = 160 * 1024;   // LDS per workgroup on gfx950
-constexpr int kWin = 7;        // ES window per axis: offsets -3..3 (w = 6)
+constexpr int kWin = 7;        // ES window per axis: offsets -3..3 (w = 4, 6)
 
 template <typename T> struct Cplx;
 template <> struct Cplx<float> { using type = float2; };
@@ -52,6 +52,9 @@ struct DevParams {
   int ncells;                   // Nx*Ny
   int ZW;                       // z-window slots per particle
   int half_w;                   // w/2 (3 for w = 6)
+  // channels carried by the grid and spectrum of the current apply: 6 with
+  // torques (in) or angular velocities (out), 3 for forces / velocities only
+  int nch_in, nch_out;
   double Lx, Ly, H, h, alpha, eta;
   double beta_m, beta_d, inv_norm_m, inv_norm_d;
 };

@@ -739,7 +739,7 @@ template <typename T, typename Run>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_fftw_y_pipe(DevParams dp, FFTPlan plan, const int* __restrict__ band,
               cplx_t<T>* __restrict__ spec, const cplx_t<T>* __restrict__ tw,
-              const T* __restrict__ dftc, DftOff doff, T sign) {
+              const T* __restrict__ dftc, DftOff doff, T sign, int nch) {
   using C = cplx_t<T>;
   constexpr int N = Run::kN;                        // == dp.Ny
   constexpr int PER = (N + 63) / 64;
@@ -748,7 +748,7 @@ k_fftw_y_pipe(DevParams dp, FFTPlan plan, const int* __restrict__ band,
   const int lo = band[0], hi = band[1];
   if (lo > hi) return;
   const int P = hi - lo + 1;
-  const int total = 6 * P * dp.Nkx;                 // band rows
+  const int total = nch * P * dp.Nkx;               // band rows
   const int t = threadIdx.x;
   int r = blockIdx.x;
   if (r >= total) return;
@@ -897,7 +897,7 @@ static void launch_wave_x(bool fwd, const fcmdp_solver* s, const void* in,
   const DevParams& dp = s->dp;
   const int M = dp.Nx / 2;
   const size_t lds = (size_t)ROWS * x_stride<Run>(M) * sizeof(C);
-  dim3 g((dp.Ny + ROWS - 1) / ROWS, 6 * dp.Nz);
+  dim3 g((dp.Ny + ROWS - 1) / ROWS, (fwd ? dp.nch_in : dp.nch_out) * dp.Nz);
   const T* cs = (const T*)s->dftc_t;
   if (fwd)
     hipLaunchKernelGGL((k_fftw_x_r2c<T, ROWS, TPR, Run>), g, dim3(ROWS * TPR),
@@ -929,7 +929,7 @@ static void launch_wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
   using C = cplx_t<T>;
   const DevParams& dp = s->dp;
   const size_t lds = (size_t)ROWS * Run::span(dp.Ny) * sizeof(C);
-  dim3 g((dp.Nkx + ROWS - 1) / ROWS, 6 * dp.Nz);
+  dim3 g((dp.Nkx + ROWS - 1) / ROWS, (sign < 0 ? dp.nch_in : dp.nch_out) * dp.Nz);
   hipLaunchKernelGGL((k_fftw_y<T, ROWS, TPR, Run>), g, dim3(ROWS * TPR), lds, st,
                      dp, s->wplan_y, s->band, (C*)spec, (const C*)s->tw_y,
                      (const T*)s->dftc_t, doff, sign);
@@ -959,7 +959,8 @@ static void wave_y_pipe(const fcmdp_solver* s, void* spec, const DftOff& doff,
   const int g = std::max(1, s->num_cu) * std::max(1, per_cu);
   hipLaunchKernelGGL((k_fftw_y_pipe<T, Run>), dim3(g), dim3(64), lds, st, dp,
                      s->wplan_y, s->band, (C*)spec, (const C*)s->tw_y,
-                     (const T*)s->dftc_t, doff, sign);
+                     (const T*)s->dftc_t, doff, sign,
+                     sign < 0 ? dp.nch_in : dp.nch_out);
 }
 
 // Codelets compiled for the transform lengths of the large workloads (single
@@ -1061,7 +1062,7 @@ static hipError_t fwd_impl(const fcmdp_solver* s, const T* grid, void* spec,
   DftOff doff;
   for (int i = 0; i < 32; ++i) doff.off[i] = s->dft_off[i];
   const int M = dp.Nx / 2;
-  const int planes = 6 * dp.Nz;
+  const int planes = dp.nch_in * dp.Nz;
   constexpr bool kRowOwned = sizeof(T) == 4;       // single precision only
   if (kRowOwned && s->wave_x && !s->force_generic_fft) {
     if constexpr (kRowOwned) wave_x<T>(true, s, grid, spec, doff, st);
@@ -1094,7 +1095,7 @@ static hipError_t inv_impl(const fcmdp_solver* s, void* spec, T* grid,
   DftOff doff;
   for (int i = 0; i < 32; ++i) doff.off[i] = s->dft_off[i];
   const int M = dp.Nx / 2;
-  const int planes = 6 * dp.Nz;
+  const int planes = dp.nch_out * dp.Nz;
   constexpr bool kRowOwned = sizeof(T) == 4;       // single precision only
   if (kRowOwned && s->wave_y && !s->force_generic_fft) {
     if constexpr (kRowOwned) wave_y<T>(s, spec, doff, T(1), st);

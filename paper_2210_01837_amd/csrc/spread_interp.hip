@@ -143,13 +143,14 @@ template <int ZC> struct SpreadRec {
   static constexpr int kLen = 28 + 2 * ZC + 1;     // odd stride
 };
 
-// One z-chunk of K planes (K <= ZC) over the staged particles.
-template <typename T, int ZC, int K>
+// One z-chunk of K planes (K <= ZC) over the staged particles; NCH = 3
+// spreads the forces only (no torques), NCH = 6 forces and torques.
+template <typename T, int ZC, int K, int NCH>
 __device__ __forceinline__ void spread_chunk(const T* __restrict__ recw, int total,
                                              int c0, int a, int b, bool inside,
                                              const DevParams& dp, const int4& inf,
                                              T F0, T F1, T F2, T G0, T G1, T G2,
-                                             T (&acc)[ZC][6]) {
+                                             T (&acc)[ZC][NCH]) {
   using Rec = SpreadRec<ZC>;
   for (int v = 0; v < total; ++v) {
     const int iz = rdlane_i(inf.z, v), iw = rdlane_i(inf.w, v);
@@ -159,24 +160,33 @@ __device__ __forceinline__ void spread_chunk(const T* __restrict__ recw, int tot
     int dy = b - rdlane_i(inf.y, v) + 3;
     if (dy < 0) dy += dp.Ny; else if (dy >= dp.Ny) dy -= dp.Ny;
     const T f0v = rdlane(F0, v), f1v = rdlane(F1, v), f2v = rdlane(F2, v);
-    const T g0v = rdlane(G0, v), g1v = rdlane(G1, v), g2v = rdlane(G2, v);
+    T g0v = T(0), g1v = T(0), g2v = T(0);
+    if constexpr (NCH == 6) {
+      g0v = rdlane(G0, v); g1v = rdlane(G1, v); g2v = rdlane(G2, v);
+    }
     if (inside && dx >= 0 && dx <= 6 && dy >= 0 && dy <= 6) {
       const T* r = recw + v * Rec::kLen;
       const T wm = r[dx] * r[7 + dy];
-      const T wd = r[14 + dx] * r[21 + dy];
       const T f0 = f0v * wm, f1 = f1v * wm, f2 = f2v * wm;
-      const T t0 = g0v * wd, t1 = g1v * wd, t2 = g2v * wd;
 #pragma unroll
       for (int s = 0; s < K; ++s) {
-        const T pm = r[Rec::kPM + s], pd = r[Rec::kPD + s];
+        const T pm = r[Rec::kPM + s];
         acc[s][0] += f0 * pm; acc[s][1] += f1 * pm; acc[s][2] += f2 * pm;
-        acc[s][3] += t0 * pd; acc[s][4] += t1 * pd; acc[s][5] += t2 * pd;
+      }
+      if constexpr (NCH == 6) {
+        const T wd = r[14 + dx] * r[21 + dy];
+        const T t0 = g0v * wd, t1 = g1v * wd, t2 = g2v * wd;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+          const T pd = r[Rec::kPD + s];
+          acc[s][3] += t0 * pd; acc[s][4] += t1 * pd; acc[s][5] += t2 * pd;
+        }
       }
     }
   }
 }
 
-template <typename T, int ZC>
+template <typename T, int ZC, int NCH>
 __global__ void __launch_bounds__(256)
 k_spread_wave(DevParams dp, const int* __restrict__ band,
               const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
@@ -232,17 +242,17 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
     for (int c = lo; c <= hi; ++c) {
       if (c >= zmin && c <= zmax) continue;
 #pragma unroll
-      for (int ch = 0; ch < 6; ++ch) grid[ch * chstride + c * plane + col] = T(0);
+      for (int ch = 0; ch < NCH; ++ch) grid[ch * chstride + c * plane + col] = T(0);
     }
   };
-  auto store_chunk = [&](int c0, int zmax, T (&acc)[ZC][6]) {
+  auto store_chunk = [&](int c0, int zmax, T (&acc)[ZC][NCH]) {
     if (!inside) return;
 #pragma unroll
     for (int s = 0; s < ZC; ++s) {
       const int c = c0 + s;
       if (c <= zmax) {
 #pragma unroll
-        for (int ch = 0; ch < 6; ++ch)
+        for (int ch = 0; ch < NCH; ++ch)
           grid[ch * chstride + c * plane + col] = acc[s][ch];
       }
     }
@@ -264,14 +274,16 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
       inf = pinfo[p];
       const T* f = pf + (size_t)p * 8;
       F0 = f[0]; F1 = f[1]; F2 = f[2];
-      G0 = f[4]; G1 = f[5]; G2 = f[6];
+      if constexpr (NCH == 6) { G0 = f[4]; G1 = f[5]; G2 = f[6]; }
       const T* w = pw + (size_t)p * 32;
 #pragma unroll
       for (int d = 0; d < 7; ++d) {
         mine[d] = w[d];
         mine[7 + d] = w[8 + d];
-        mine[14 + d] = w[16 + d];
-        mine[21 + d] = w[24 + d];
+        if constexpr (NCH == 6) {
+          mine[14 + d] = w[16 + d];
+          mine[21 + d] = w[24 + d];
+        }
       }
     }
     int zmin = inf.z, zmax = inf.w;
@@ -296,7 +308,7 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
         for (int s = 0; s < ZC; ++s) {
           if (s < zc) {
             mine[Rec::kPM + s] = ps[c0 + s];
-            mine[Rec::kPD + s] = ps[Nz + c0 + s];
+            if constexpr (NCH == 6) mine[Rec::kPD + s] = ps[Nz + c0 + s];
           }
         }
       }
@@ -304,16 +316,16 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      T acc[ZC][6];
+      T acc[ZC][NCH];
 #pragma unroll
       for (int s = 0; s < ZC; ++s)
 #pragma unroll
-        for (int ch = 0; ch < 6; ++ch) acc[s][ch] = T(0);
+        for (int ch = 0; ch < NCH; ++ch) acc[s][ch] = T(0);
 #define FCMDP_CHUNK(K)                                                         \
   case K:                                                                      \
     if constexpr (K <= ZC)                                                     \
-      spread_chunk<T, ZC, K>(recw, total, c0, a, b, inside, dp, inf, F0, F1,   \
-                             F2, G0, G1, G2, acc);                             \
+      spread_chunk<T, ZC, K, NCH>(recw, total, c0, a, b, inside, dp, inf, F0,  \
+                                  F1, F2, G0, G1, G2, acc);                    \
     break;
       switch (zc) {
         FCMDP_CHUNK(1) FCMDP_CHUNK(2) FCMDP_CHUNK(3) FCMDP_CHUNK(4) FCMDP_CHUNK(5)
@@ -340,11 +352,11 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
   }
   zero_outside(zmin, zmax);
   for (int c0 = zmin; c0 <= zmax; c0 += ZC) {
-    T acc[ZC][6];
+    T acc[ZC][NCH];
 #pragma unroll
     for (int s = 0; s < ZC; ++s)
 #pragma unroll
-      for (int ch = 0; ch < 6; ++ch) acc[s][ch] = T(0);
+      for (int ch = 0; ch < NCH; ++ch) acc[s][ch] = T(0);
     for (int r = 0; r < 2 * nrows; ++r) {
       const int p0 = rdlane_i(sstart, r), p1 = p0 + rdlane_i(scnt, r);
       for (int q = p0; q < p1; ++q) {
@@ -353,7 +365,10 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
         const T* ps = psi + (size_t)q * 2 * Nz;
         T pm[ZC], pd[ZC];
 #pragma unroll
-        for (int s = 0; s < ZC; ++s) { pm[s] = ps[c0 + s]; pd[s] = ps[Nz + c0 + s]; }
+        for (int s = 0; s < ZC; ++s) {
+          pm[s] = ps[c0 + s];
+          pd[s] = NCH == 6 ? ps[Nz + c0 + s] : T(0);
+        }
         int dx = a - inf.x + 3;
         if (dx < 0) dx += dp.Nx; else if (dx >= dp.Nx) dx -= dp.Nx;
         int dy = b - inf.y + 3;
@@ -370,7 +385,9 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
 #pragma unroll
           for (int s = 0; s < ZC; ++s) {
             acc[s][0] += f0 * pm[s]; acc[s][1] += f1 * pm[s]; acc[s][2] += f2 * pm[s];
-            acc[s][3] += t0 * pd[s]; acc[s][4] += t1 * pd[s]; acc[s][5] += t2 * pd[s];
+            if constexpr (NCH == 6) {
+              acc[s][3] += t0 * pd[s]; acc[s][4] += t1 * pd[s]; acc[s][5] += t2 * pd[s];
+            }
           }
         }
       }
@@ -379,19 +396,22 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
   }
 }
 
+template <typename T, int NCH>
+static void spread_wave(const fcmdp_solver* s, void* grid, hipStream_t st) {
+  dim3 g(((s->dp.Nx + 4 * kPW - 1) / (4 * kPW)) * ((s->dp.Ny + kPW - 1) / kPW));
+  hipLaunchKernelGGL((k_spread_wave<T, kSpreadZC, NCH>), g, dim3(256), 0, st,
+                     s->dp, s->band, s->cell_start, s->pinfo, (const T*)s->pw,
+                     (const T*)s->pf, (const T*)s->psi, (T*)grid);
+}
+
 hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st) {
   if (!s->force_simple_spread) {
-    dim3 g(((s->dp.Nx + 4 * kPW - 1) / (4 * kPW)) * ((s->dp.Ny + kPW - 1) / kPW));
+    // without torques only the three force channels are spread
+    const bool dip = s->dp.nch_in == 6;
     if (s->mixed)
-      hipLaunchKernelGGL((k_spread_wave<float, kSpreadZC>), g, dim3(256), 0, st,
-                         s->dp, s->band, s->cell_start, s->pinfo,
-                         (const float*)s->pw, (const float*)s->pf,
-                         (const float*)s->psi, (float*)grid);
+      dip ? spread_wave<float, 6>(s, grid, st) : spread_wave<float, 3>(s, grid, st);
     else
-      hipLaunchKernelGGL((k_spread_wave<double, kSpreadZC>), g, dim3(256), 0, st,
-                         s->dp, s->band, s->cell_start, s->pinfo,
-                         (const double*)s->pw, (const double*)s->pf,
-                         (const double*)s->psi, (double*)grid);
+      dip ? spread_wave<double, 6>(s, grid, st) : spread_wave<double, 3>(s, grid, st);
     return hipGetLastError();
   }
   dim3 block(128);
@@ -480,7 +500,9 @@ constexpr int kRX = kTile + 6;
 constexpr int kIThreads = 512;   // threads per interpolation workgroup
 constexpr int kRec = 28;     // wxM[7] wyM[7] wxD[7] wyD[7]
 
-template <typename T, int ZC>
+// NCH = 6 interpolates velocities and angular velocities, NCH = 3 the
+// velocities only (the grid's vorticity channels are then not read).
+template <typename T, int ZC, int NCH>
 __global__ void __launch_bounds__(kIThreads)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2, 8)))
 k_interp_tiled(DevParams dp, const int* __restrict__ band,
@@ -490,10 +512,10 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
                const T* __restrict__ grid, const int* __restrict__ perm,
                T* __restrict__ U, T* __restrict__ Om, int cap) {
   extern __shared__ unsigned char lds_raw[];
-  T* G = reinterpret_cast<T*>(lds_raw);                 // [ZC][6][kRX][kRX]
-  T* pcw = G + ZC * 6 * kRX * kRX;                      // [cap][kRec]
-  T* acc = pcw + cap * kRec;                            // [cap][6]
-  int4* pci = reinterpret_cast<int4*>(acc + cap * 6);   // [cap]
+  T* G = reinterpret_cast<T*>(lds_raw);                 // [ZC][NCH][kRX][kRX]
+  T* pcw = G + ZC * NCH * kRX * kRX;                    // [cap][kRec]
+  T* acc = pcw + cap * kRec;                            // [cap][NCH]
+  int4* pci = reinterpret_cast<int4*>(acc + cap * NCH); // [cap]
   int* pcj = reinterpret_cast<int*>(pci + cap);         // [cap] output index
   int* pcp = pcj + cap;                                 // [cap] sorted index
   __shared__ int rowoff[kTile + 1];
@@ -560,7 +582,7 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
         d[21 + e] = w[24 + e];
       }
 #pragma unroll
-      for (int e = 0; e < 6; ++e) acc[h * 6 + e] = T(0);
+      for (int e = 0; e < NCH; ++e) acc[h * NCH + e] = T(0);
     }
     if (zhi >= 0) {
       atomicMin(&zr[0], zlo);
@@ -575,7 +597,7 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
     // plane-channel e / 2, so every address is a compile-time offset from
     // two per-thread row bases.
     static_assert(kRX == 2 * kRG, "staging layout");
-    constexpr int kPer = 2 * 6 * ZC;
+    constexpr int kPer = 2 * NCH * ZC;
     T pre[kPer];
     const bool stager = tid < kRG * kRX;
     const size_t yrow0 = stager ? (size_t)ytab[rg] * dp.Nx + xa : 0;
@@ -585,7 +607,7 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
       const T* gb = grid + (size_t)c0 * plane;
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
-        const int t = e >> 1, ch = t % 6, sidx = t / 6;
+        const int t = e >> 1, ch = t % NCH, sidx = t / NCH;
         if (stager && sidx < nz)
           pre[e] = gb[ch * chstride + (size_t)sidx * plane + ((e & 1) ? yrow1 : yrow0)];
       }
@@ -595,7 +617,7 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
       const int nz = min(ZC, c_last - c0 + 1);
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
-        const int sidx = (e >> 1) / 6;
+        const int sidx = (e >> 1) / NCH;
         if (stager && sidx < nz) G[(rg + kRG * e) * kRX + rx] = pre[e];
       }
       T q[ZC];
@@ -630,14 +652,16 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
               if (sidx < nz) {
                 const T qm = pm[sidx] * wm;
                 const T qd = pd[sidx] * wd;
-                const T* gp = G + (sidx * 6 * kRX + ry) * kRX + px;
+                const T* gp = G + (sidx * NCH * kRX + ry) * kRX + px;
                 constexpr int CS = kRX * kRX;
                 a0 += qm * gp[0];
                 a1 += qm * gp[CS];
                 a2 += qm * gp[2 * CS];
-                a3 += qd * gp[3 * CS];
-                a4 += qd * gp[4 * CS];
-                a5 += qd * gp[5 * CS];
+                if constexpr (NCH == 6) {
+                  a3 += qd * gp[3 * CS];
+                  a4 += qd * gp[4 * CS];
+                  a5 += qd * gp[5 * CS];
+                }
               }
             }
           }
@@ -652,20 +676,20 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
           a5 += __shfl_xor(a5, m, 8);
         }
         if (l == 0) {
-          T* ac = acc + h * 6;
+          T* ac = acc + h * NCH;
           ac[0] += a0; ac[1] += a1; ac[2] += a2;
-          ac[3] += a3; ac[4] += a4; ac[5] += a5;
+          if constexpr (NCH == 6) { ac[3] += a3; ac[4] += a4; ac[5] += a5; }
         }
       }
       __syncthreads();
     }
     for (int h = tid; h < np; h += kIThreads) {
       const int j = pcj[h];
-      const T* ac = acc + h * 6;
+      const T* ac = acc + h * NCH;
       U[3 * (size_t)j + 0] = ac[0];
       U[3 * (size_t)j + 1] = ac[1];
       U[3 * (size_t)j + 2] = ac[2];
-      if (Om) {
+      if constexpr (NCH == 6) {
         Om[3 * (size_t)j + 0] = ac[3];
         Om[3 * (size_t)j + 1] = ac[4];
         Om[3 * (size_t)j + 2] = ac[5];
@@ -688,10 +712,10 @@ __global__ void k_interp_invalid(int n, int ncells, const uint32_t* __restrict__
   if (Om) Om[3 * (size_t)j + 0] = Om[3 * (size_t)j + 1] = Om[3 * (size_t)j + 2] = nan;
 }
 
-template <typename T, int ZC>
+template <typename T, int ZC, int NCH>
 static size_t interp_lds(int cap) {
-  return (size_t)ZC * 6 * kRX * kRX * sizeof(T) +
-         (size_t)cap * (kRec + 6) * sizeof(T) + (size_t)cap * (16 + 4 + 4);
+  return (size_t)ZC * NCH * kRX * kRX * sizeof(T) +
+         (size_t)cap * (kRec + NCH) * sizeof(T) + (size_t)cap * (16 + 4 + 4);
 }
 
 template <typename T>
@@ -705,12 +729,22 @@ static hipError_t interp_tiled(const fcmdp_solver* s, int n, const T* grid,
   // R_h = 1.731 h has ~0.22 particles per xy cell, ~150 per 26 x 26 tile;
   // denser tiles take several passes.  192 keeps two workgroups per CU.
   const int cap = sizeof(T) == 4 ? 192 : 96;
+  // planes staged per chunk: as many for three channels as for six, so that
+  // the velocities are the same bits whether or not Omega is wanted
   constexpr int ZC = sizeof(T) == 4 ? 2 : 1;
-  const size_t lds = interp_lds<T, ZC>(cap);
-  hipLaunchKernelGGL((k_interp_tiled<T, ZC>), g, dim3(kIThreads), lds, st, dp,
-                     s->band, s->cell_start, s->pinfo, (const T*)s->pw,
-                     (const T*)s->psi, (const T*)s->quad, grid, s->valA, U, Om,
-                     cap);
+  if (Om && dp.nch_out == 6) {
+    const size_t lds = interp_lds<T, ZC, 6>(cap);
+    hipLaunchKernelGGL((k_interp_tiled<T, ZC, 6>), g, dim3(kIThreads), lds, st,
+                       dp, s->band, s->cell_start, s->pinfo, (const T*)s->pw,
+                       (const T*)s->psi, (const T*)s->quad, grid, s->valA, U,
+                       Om, cap);
+  } else {
+    const size_t lds = interp_lds<T, ZC, 3>(cap);
+    hipLaunchKernelGGL((k_interp_tiled<T, ZC, 3>), g, dim3(kIThreads), lds, st,
+                       dp, s->band, s->cell_start, s->pinfo, (const T*)s->pw,
+                       (const T*)s->psi, (const T*)s->quad, grid, s->valA, U,
+                       nullptr, cap);
+  }
   return hipGetLastError();
 }
 

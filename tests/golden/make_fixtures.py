@@ -1,12 +1,18 @@
 """Write the stored oracle values used by the large-scale GPU parity tests.
 
-    python tests/golden/make_fixtures.py [bw131k] [bw1m] [sc1m]
+    python tests/golden/make_fixtures.py [bw131k] [bw1m] [sc1m] [m2048]
 
 For each workload this draws the seeded inputs (workloads.particles), runs
 the CPU oracle's full apply -- every particle is spread and the whole grid is
 solved -- and interpolates only the seeded 1% sample (workloads.subsample).
 It stores <name>_oracle_sample.npz with the sample indices and the oracle's
 U and Omega (float64).  Only oracle/ and workloads/ are used.
+
+Forces-only workloads (no torques) store U only.  ``m2048`` is one replica
+of the tiled ``m663k`` layer; every particle is interpolated.  Its values
+also serve the tiled layer: there the forcing is periodic with the replica's
+period on a grid of the same spacing, so the discrete solution is the
+replica's solution repeated (checked on a small tiling in the oracle tests).
 """
 from __future__ import annotations
 
@@ -28,7 +34,7 @@ from oracle import fcm, stokes  # noqa: E402
 def make(name: str) -> str:
     wl = workloads.WORKLOADS[name]
     pos, F, T = workloads.particles(name)
-    idx = workloads.subsample(name)
+    idx = workloads.subsample(name) if wl.n > 4096 else np.arange(wl.n)
     s = fcm.Solver(wl.box)
     t0 = time.time()
     p = s.wrap(pos)
@@ -47,7 +53,10 @@ def make(name: str) -> str:
     del omh
     U, Om = s.interp(p[idx], u, om)
     out = os.path.join(HERE, f"{name}_oracle_sample.npz")
-    np.savez_compressed(out, index=idx, U=U, Omega=Om)
+    if wl.torques:
+        np.savez_compressed(out, index=idx, U=U, Omega=Om)
+    else:
+        np.savez_compressed(out, index=idx, U=U)
     print(f"{name}: wrote {out} ({len(idx)} particles) in {time.time() - t0:.0f} s",
           flush=True)
     return out

@@ -47,7 +47,7 @@ def _params(**kw):
 
 @pytest.mark.parametrize("bad", [
     dict(Nx=47), dict(Ny=6), dict(Nz=7), dict(Nz=65), dict(Nx=38),  # 19 prime
-    dict(Ly=31.0), dict(H=1.9), dict(w=4), dict(eta=0.0),
+    dict(Ly=31.0), dict(H=1.9), dict(w=8), dict(w=5), dict(w=2), dict(eta=0.0),
     dict(geometry="sc", H=3.9), dict(max_particles=-1), dict(beta_m=-1.0),
 ])
 def test_invalid_parameters_rejected(L, bad):

@@ -377,3 +377,62 @@ def test_apply_fp64_full_size_golden(name):
     assert rel_err(Ug, g["U"]) < 1e-6
     assert rel_err(Og, g["Omega"]) < 1e-6
     s.close()
+
+
+# --- forces-only apply (no torques, no angular velocities) at m = 4 ----------
+# The paper's timed configuration (Sec. 5): monopole kernel of width 4,
+# beta/m = 1.87; the apply then carries three channels through every stage.
+M_BOXES = {
+    "bw30x36_m4": Box("bw", 30.0, 36.0, 9.0, 30, 36, 19, w=4, beta_m=7.48,
+                      beta_d=7.48),
+    "sc40_m4": Box("sc", 40.0, 40.0, 8.0, 40, 40, 20, w=4, beta_m=7.48,
+                   beta_d=7.48),
+}
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("name", list(M_BOXES))
+def test_apply_forces_only_m4(name, precision):
+    box = M_BOXES[name]
+    pos, F, _ = _particles(box, 60, 13)
+    if precision == "mixed":
+        pos, F = (a.astype(np.float32).astype(np.float64) for a in (pos, F))
+    print(f"[forces only m=4] {name} {precision}", flush=True)
+    s = _solver(box, precision)
+    P, Fd = _dev(pos, precision), _dev(F, precision)
+    U, Om = s.apply(P, Fd, None, want_omega=False)
+    assert Om is None
+    zero = np.zeros_like(F)
+    rU, _ = oracle_apply(box, pos, F, zero)
+    eU = rel_err(_np(U), rU)
+    print(f"  rel err U {eU:.3e}", flush=True)
+    assert eU < (1e-5 if precision == "mixed" else 1e-10)
+    # three channels give the same bits as six with zero torques
+    U6, _ = s.apply(P, Fd, torch.zeros_like(Fd))
+    assert torch.equal(U, U6)
+    assert s.status() == (0, 0)
+
+
+def test_apply_forces_only_replicated_layer():
+    """The paper's forces-only layer: 663,552 particles (18 x 18 copies of a
+    2048-particle replica) on 2700 x 2700 x 19.  Its solution is the
+    replica's solution repeated, so every particle is checked against the
+    oracle's apply of one replica (stored values)."""
+    g = _golden("m2048")
+    assert np.array_equal(g["index"], np.arange(2048))
+    rU = g["U"]
+    for name in ("m2048", "m663k"):
+        wl = workloads.WORKLOADS[name]
+        pos, F, _ = workloads.particles(name)
+        print(f"[forces only layer] {name} N={wl.n}", flush=True)
+        s = _solver(wl.box, "mixed", cap=wl.n)
+        U, Om = s.apply(_dev(pos, "mixed"), _dev(F, "mixed"), None,
+                        want_omega=False)
+        got = _np(U).reshape(-1, len(rU), 3)
+        e = rel_err(got, np.broadcast_to(rU, got.shape))
+        worst = max(rel_err(got[r], rU) for r in range(got.shape[0]))
+        print(f"  rel err U {e:.3e} (worst replica {worst:.3e})", flush=True)
+        assert e < 1e-5 and worst < 1e-5
+        assert s.status() == (0, 0)
+        s.close()
+        del U

@@ -19,6 +19,20 @@ workload ``i``; draw order x, y, z, then F, then T):
 * ``bw1m`` / ``sc1m`` -- the same monolayer at N=1,048,576 on a 1448x1448
                   box, grid 2176x2176, Nz=32, H=12, positions stored as FP32;
                   a seeded 1% subsample is used for oracle comparison.
+* ``m2048`` / ``m663k`` -- the forces-only (monopole, kernel width m = 4)
+                  performance test of Sec. 5 and its parameter table: one
+                  replica of 2048 particles with L = 128.8 R_h, 150 x 150 grid
+                  cells, Nz = 19, H = 9.1 R_h, beta/m = 1.87, area fraction
+                  N pi R_h^2 / L^2 = 0.39; ``m663k`` tiles that replica
+                  18 x 18 times (663,552 particles on 2700 x 2700 x 19).
+                  Lengths are in units of the grid spacing h (R_h = 150/128.8
+                  h), and x, y are multiples of 2^-11 so that the tiled
+                  positions are exact in FP32: the tiled apply then equals the
+                  one-replica apply replicated.  Heights (the paper shows a
+                  two-layer distribution only as a figure): half the
+                  particles at z/R_h = 1.1 + Exp(0.3), half at z/R_h = 3.3 +
+                  N(0, 0.3^2) clipped to [2.4, 5]; F = (0,0,-1) + N(0,0.1^2)
+                  (in units of the monolayer's gravity), no torques.
 * ``serve``    -- 512 requests, N log-uniform in [1024, 262144], geometry
                   bottom wall or slit channel with equal odds, box side set for
                   N/L^2 = 0.4, grid spacing h = 1/1.731 (so the ES radius
@@ -39,6 +53,13 @@ W = 6
 BETA_M = 1.327 * W   # Table 1, m = 6, monopole
 BETA_D = 2.216 * W   # Table 1, m = 6, dipole
 RH_OVER_H = 1.731    # Table 1, m = 6
+
+# forces-only test of Sec. 5 (lengths in units of h)
+M_W = 4
+M_BETA = 1.87 * M_W          # beta/m of the monopole-only performance test
+M_RH = 150.0 / 128.8         # R_h in units of h (L = 128.8 R_h = 150 h)
+M_H = 9.1 * M_RH
+M_REPLICAS = 18
 
 
 @dataclass(frozen=True)
@@ -71,8 +92,11 @@ class Workload:
     heights: str           # "uniform" or "monolayer"
     zlo: float = 0.0
     zhi: float = 0.0
-    forces: str = "normal"  # "normal" or "roller"
+    forces: str = "normal"  # "normal", "roller" or "gravity" (no torques)
     pos_fp32: bool = False
+    torques: bool = True    # False: forces-only apply (T = None, no Omega)
+    replicas: int = 1       # tile a base replica replicas x replicas times
+    unit: float = 1.0       # particle radius in length units (heights)
 
 
 WORKLOADS = {
@@ -86,25 +110,55 @@ WORKLOADS = {
                      1048576, "mixed", "monolayer", forces="roller", pos_fp32=True),
     "sc1m": Workload("sc1m", 4, Box("sc", 1448.0, 1448.0, 12.0, 2176, 2176, 32),
                      1048576, "mixed", "monolayer", forces="roller", pos_fp32=True),
+    "m2048": Workload("m2048", 7, Box("bw", 150.0, 150.0, M_H, 150, 150, 19,
+                                      w=M_W, beta_m=M_BETA, beta_d=M_BETA),
+                      2048, "mixed", "bimodal", forces="gravity", torques=False,
+                      unit=M_RH),
+    "m663k": Workload("m663k", 7, Box("bw", 150.0 * M_REPLICAS, 150.0 * M_REPLICAS,
+                                      M_H, 150 * M_REPLICAS, 150 * M_REPLICAS, 19,
+                                      w=M_W, beta_m=M_BETA, beta_d=M_BETA),
+                      2048 * M_REPLICAS ** 2, "mixed", "bimodal",
+                      forces="gravity", torques=False, replicas=M_REPLICAS,
+                      unit=M_RH),
 }
 
 
 def _draw(rng: np.random.Generator, n: int, L_x: float, L_y: float,
-          heights: str, zlo: float, zhi: float, forces: str):
+          heights: str, zlo: float, zhi: float, forces: str, unit: float = 1.0):
     x = rng.uniform(0.0, L_x, n)
     y = rng.uniform(0.0, L_y, n)
     if heights == "uniform":
         z = rng.uniform(zlo, zhi, n)
+    elif heights == "bimodal":
+        # two equally weighted layers (in units of the particle radius)
+        low = 1.1 + rng.exponential(0.3, n)
+        high = np.clip(3.3 + 0.3 * rng.standard_normal(n), 2.4, 5.0)
+        z = unit * np.where(rng.uniform(size=n) < 0.5, low, high)
+        # x, y on a 2^-11 lattice: exact in FP32 after tiling (|x| < 4096)
+        x = np.round(x * 2048.0) / 2048.0
+        y = np.round(y * 2048.0) / 2048.0
     else:
         z = 1.1 + rng.exponential(0.3, n)
     if forces == "normal":
         F = rng.standard_normal((n, 3))
         T = rng.standard_normal((n, 3))
+    elif forces == "gravity":
+        F = np.array([0.0, 0.0, -1.0]) + 0.1 * rng.standard_normal((n, 3))
+        T = np.zeros((n, 3))
     else:
         F = np.array([0.0, 0.0, -1.0]) + 0.1 * rng.standard_normal((n, 3))
         T = np.array([0.0, 1.0, 0.0]) + 0.1 * rng.standard_normal((n, 3))
     pos = np.stack([x, y, z], axis=1)
     return pos, F, T
+
+
+def _tile(pos, F, T, L_x, L_y, reps):
+    """reps x reps periodic copies of one replica of side (L_x, L_y)."""
+    a, b = np.meshgrid(np.arange(reps), np.arange(reps), indexing="ij")
+    shift = np.stack([a.ravel() * L_x, b.ravel() * L_y,
+                      np.zeros(reps * reps)], axis=1)
+    pos_t = (pos[None, :, :] + shift[:, None, :]).reshape(-1, 3)
+    return (pos_t, np.tile(F, (reps * reps, 1)), np.tile(T, (reps * reps, 1)))
 
 
 def particles(name: str):
@@ -116,8 +170,12 @@ def particles(name: str):
     """
     wl = WORKLOADS[name]
     rng = np.random.default_rng(SEED_BASE + wl.index)
-    pos, F, T = _draw(rng, wl.n, wl.box.Lx, wl.box.Ly, wl.heights, wl.zlo,
-                      wl.zhi, wl.forces)
+    r = wl.replicas
+    Lx, Ly = wl.box.Lx / r, wl.box.Ly / r
+    pos, F, T = _draw(rng, wl.n // (r * r), Lx, Ly, wl.heights, wl.zlo,
+                      wl.zhi, wl.forces, wl.unit)
+    if r > 1:
+        pos, F, T = _tile(pos, F, T, Lx, Ly, r)
     if wl.precision == "mixed":
         pos = pos.astype(np.float32).astype(np.float64)
         F = F.astype(np.float32).astype(np.float64)
@@ -147,7 +205,7 @@ def sub_box(name: str, factor: int):
     n = int(round(wl.n * (box.Lx * box.Ly) / (b.Lx * b.Ly)))
     rng = np.random.default_rng(SEED_BASE + 200 + wl.index)
     pos, F, T = _draw(rng, n, box.Lx, box.Ly, wl.heights, wl.zlo, wl.zhi,
-                      wl.forces)
+                      wl.forces, wl.unit)
     if wl.precision == "mixed":
         pos = pos.astype(np.float32).astype(np.float64)
         F = F.astype(np.float32).astype(np.float64)
