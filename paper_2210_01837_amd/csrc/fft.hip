@@ -972,11 +972,19 @@ static const CodeletDesc kCodelets[] = {
     {2176, 64, 3, {16 * 16 + 3, 8 * 16 + 5, 17 * 16 + 2}},          // 2176
     {384, 64, 3, {16 * 16 + 1, 8 * 16 + 1, 3 * 16 + 2}},            // 768 / 2
     {768, 64, 4, {4 * 16 + 3, 8 * 16 + 2, 8 * 16 + 2, 3 * 16 + 4}},  // 768
+    {1350, 64, 6, {2 * 16 + 11, 3 * 16 + 8, 3 * 16 + 8, 3 * 16 + 8,   // 2700 / 2
+                   5 * 16 + 5, 5 * 16 + 5}},
+    {2700, 64, 6, {4 * 16 + 11, 3 * 16 + 15, 3 * 16 + 15, 3 * 16 + 15,  // 2700
+                   5 * 16 + 9, 5 * 16 + 9}},
 };
 using Codelet0 = FixedRows<8 * 16 + 3, 8 * 16 + 3, 17 * 16 + 1>;
 using Codelet1 = FixedRows<16 * 16 + 3, 8 * 16 + 5, 17 * 16 + 2>;
 using Codelet2 = FixedRows<16 * 16 + 1, 8 * 16 + 1, 3 * 16 + 2>;
 using Codelet3 = FixedRows<4 * 16 + 3, 8 * 16 + 2, 8 * 16 + 2, 3 * 16 + 4>;
+using Codelet4 = FixedRows<2 * 16 + 11, 3 * 16 + 8, 3 * 16 + 8, 3 * 16 + 8,
+                           5 * 16 + 5, 5 * 16 + 5>;
+using Codelet5 = FixedRows<4 * 16 + 11, 3 * 16 + 15, 3 * 16 + 15, 3 * 16 + 15,
+                           5 * 16 + 9, 5 * 16 + 9>;
 
 template <typename T>
 static void wave_x(bool fwd, const fcmdp_solver* s, const void* in, void* out,
@@ -986,6 +994,8 @@ static void wave_x(bool fwd, const fcmdp_solver* s, const void* in, void* out,
     case 1: wave_x_rows<T, 64, Codelet1>(fwd, s, in, out, doff, st); return;
     case 2: wave_x_rows<T, 64, Codelet2>(fwd, s, in, out, doff, st); return;
     case 3: wave_x_rows<T, 64, Codelet3>(fwd, s, in, out, doff, st); return;
+    case 4: wave_x_rows<T, 64, Codelet4>(fwd, s, in, out, doff, st); return;
+    case 5: wave_x_rows<T, 64, Codelet5>(fwd, s, in, out, doff, st); return;
     default: break;
   }
   switch (s->tpr_x) {
@@ -1004,6 +1014,8 @@ static void wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
       case 1: wave_y_pipe<T, Codelet1>(s, spec, doff, sign, st); return;
       case 2: wave_y_pipe<T, Codelet2>(s, spec, doff, sign, st); return;
       case 3: wave_y_pipe<T, Codelet3>(s, spec, doff, sign, st); return;
+      case 4: wave_y_pipe<T, Codelet4>(s, spec, doff, sign, st); return;
+      case 5: wave_y_pipe<T, Codelet5>(s, spec, doff, sign, st); return;
       default: break;
     }
   }
@@ -1012,6 +1024,8 @@ static void wave_y(const fcmdp_solver* s, void* spec, const DftOff& doff,
     case 1: wave_y_rows<T, 64, Codelet1>(s, spec, doff, sign, st); return;
     case 2: wave_y_rows<T, 64, Codelet2>(s, spec, doff, sign, st); return;
     case 3: wave_y_rows<T, 64, Codelet3>(s, spec, doff, sign, st); return;
+    case 4: wave_y_rows<T, 64, Codelet4>(s, spec, doff, sign, st); return;
+    case 5: wave_y_rows<T, 64, Codelet5>(s, spec, doff, sign, st); return;
     default: break;
   }
   switch (s->tpr_y) {
@@ -1027,6 +1041,8 @@ int fft_lds_row(int codelet, int n, bool x) {
     case 1: return x ? x_stride<Codelet1>(n) : Codelet1::span(n);
     case 2: return x ? x_stride<Codelet2>(n) : Codelet2::span(n);
     case 3: return x ? x_stride<Codelet3>(n) : Codelet3::span(n);
+    case 4: return x ? x_stride<Codelet4>(n) : Codelet4::span(n);
+    case 5: return x ? x_stride<Codelet5>(n) : Codelet5::span(n);
     default: return x ? x_stride<GenericRows>(n) : GenericRows::span(n);
   }
 }

@@ -248,7 +248,7 @@ def test_periodic_wrapping_of_inputs():
 # "generic_fft" variant); one band plane, compared with numpy's FFT in FP64 on
 # the same float32-rounded input.
 FFT_SIZES = [(48, 48), (40, 56), (96, 26), (90, 1000), (1536, 1000),
-             (768, 768), (2176, 2176)]
+             (768, 768), (2176, 2176), (2700, 2700)]
 
 
 def _fft_box(nx, ny, nz=8):
