@@ -769,8 +769,10 @@ __device__ __forceinline__ Vec ps_zero_mode(const Vec& r, double H, int N, int g
 // correction's node functions: which = 0: e^{-k z}, 1: z e^{-k z},
 // 2: e^{k (z - H)}, 3: z e^{k (z - H)} (the last two for the slit channel).
 // SPLIT selects the parity-split coefficient layout (ps_*) instead of four
-// consecutive coefficients per lane.
-template <int GEOM, bool SPLIT = false, typename Load, typename Basis>
+// consecutive coefficients per lane.  FO (forces only): there is no dipole
+// density, `load` provides v = 0..2 only and f is A0, A1, A2 itself.
+template <int GEOM, bool SPLIT = false, bool FO = false, typename Load,
+          typename Basis>
 __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& basis,
                                  const DevParams& dp, int N, int l,
                                  double kx, double ky, double k, Vec& U,
@@ -788,17 +790,21 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     else return bsum_bottom(a);
   };
   auto body_x = [&]() {
-    const Vec dgy = deriv(load(4));
     Vec f = load(0);
+    if constexpr (!FO) {
+      const Vec dgy = deriv(load(4));
 #pragma unroll
-    for (int j = 0; j < kNpl; ++j) f.v[j] = f.v[j] - 0.5 * dgy.v[j];
+      for (int j = 0; j < kNpl; ++j) f.v[j] = f.v[j] - 0.5 * dgy.v[j];
+    }
     return f;
   };
   auto body_y = [&]() {
-    const Vec dgx = deriv(load(3));
     Vec f = load(1);
+    if constexpr (!FO) {
+      const Vec dgx = deriv(load(3));
 #pragma unroll
-    for (int j = 0; j < kNpl; ++j) f.v[j] = f.v[j] + 0.5 * dgx.v[j];
+      for (int j = 0; j < kNpl; ++j) f.v[j] = f.v[j] + 0.5 * dgx.v[j];
+    }
     return f;
   };
   if (k == 0.0) {
@@ -1075,12 +1081,15 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kMCols = 16;                 // columns per workgroup
 constexpr int kMThreads = kMCols * kSeg;   // 128
-// XC columns: [0, 160) the five complex node vectors of the 16 columns
-// (col * 10 + component; rows = band nodes c - lo), then [160, 160 + 16 NB)
-// the NB correction node functions (col * NB + b; rows = all nodes c).
-template <int GEOM> struct MfmaLayout {
+// XC columns: [0, 16 VR) the complex node vectors of the 16 columns
+// (col * VR + component; rows = band nodes c - lo; VR = 10 reals for the five
+// vectors, 6 for the three force components of a forces-only apply), then
+// [16 VR, 16 VR + 16 NB) the NB correction node functions (col * NB + b; rows
+// = all nodes c).
+template <int GEOM, bool FO> struct MfmaLayout {
   static constexpr int kBasis = GEOM == 0 ? 2 : 4;     // correction node functions
-  static constexpr int kSpec = kMCols * 10;            // spectral reals per row
+  static constexpr int kVR = FO ? 6 : 10;              // reals per column
+  static constexpr int kSpec = kMCols * kVR;           // spectral reals per row
   // reals per row; the odd pad spreads the eight lanes of a column (rows
   // 8 (l % 4) + 2 j + l / 4) over different LDS banks
   static constexpr int kMV = kSpec + kMCols * kBasis + 1;
@@ -1098,14 +1107,17 @@ __device__ __forceinline__ void col_index(int kx0, int ky0, int col, int Ny,
   while (kyi >= Ny) { kyi -= Ny; ++kxi; }
 }
 
-template <int GEOM>
+// FO: forces only (no torques in, no vorticity out): three node vectors per
+// column instead of five and three output channels.
+template <int GEOM, bool FO>
 __global__ void __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_columns_mfma(ColParams cp, const int* __restrict__ band,
                const float2* __restrict__ in, float2* __restrict__ out,
                const double* __restrict__ zc, const float* __restrict__ Mf32,
                const float* __restrict__ Pi32) {
-  using Lay = MfmaLayout<GEOM>;
+  using Lay = MfmaLayout<GEOM, FO>;
   constexpr int kMV = Lay::kMV, kSpec = Lay::kSpec, NB = Lay::kBasis;
+  constexpr int VR = Lay::kVR;
   // one buffer: node values (A), then coefficients (B, C), then band node
   // values (D, E); each transform keeps its output tiles in registers until
   // every wave has finished reading its input
@@ -1170,7 +1182,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     }
     if (c < P && idx < K) {
       // without torques the dipole channels are zero and not read
-      const bool dip = dp.nch_in == 6;
+      const bool dip = !FO && dp.nch_in == 6;
       float4 v[6];
 #pragma unroll
       for (int ch = 0; ch < 6; ++ch)
@@ -1184,7 +1196,13 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
         for (int ch = 0; ch < 6; ++ch)
           w[ch] = h == 0 ? make_float2(v[ch].x, v[ch].y) : make_float2(v[ch].z, v[ch].w);
         const float kx = kxv[h], ky = kyv[h];
-        float* xr = XC + c * kMV + (col + h) * 10;
+        float* xr = XC + c * kMV + (col + h) * VR;
+        if constexpr (FO) {
+          xr[0] = w[0].x; xr[1] = w[0].y;
+          xr[2] = w[1].x; xr[3] = w[1].y;
+          xr[4] = w[2].x; xr[5] = w[2].y;
+          continue;
+        }
         // f~x = Fx + (1/2) i ky Gz ; f~y = Fy - (1/2) i kx Gz ;
         // f~z = Fz + (1/2)(i kx Gy - i ky Gx)
         xr[0] = w[0].x - 0.5f * ky * w[5].y;
@@ -1198,7 +1216,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 20; ++e) XC[c * kMV + col * 10 + e] = 0.f;
+      for (int e = 0; e < 2 * VR; ++e) XC[c * kMV + col * VR + e] = 0.f;
     }
     // c is also the absolute node of the correction functions
 #pragma unroll
@@ -1283,7 +1301,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     // parity-split layout: slot j of lane l is coefficient 8 (l % 4) + 2 j
     // + l / 4
     const int m0 = ps_m(l, 0);
-    float* cbase = XC + m0 * kMV + cl * 10;
+    float* cbase = XC + m0 * kMV + cl * VR;
     float* bbase = XC + m0 * kMV + kSpec + cl * NB;
     Vec U = vzero(), V = vzero(), W = vzero();
     if (!nyq) {
@@ -1300,7 +1318,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
 #pragma unroll
         for (int j = 0; j < kNpl; ++j) o[j] = (double)bbase[2 * j * kMV + which];
       };
-      seg_column_solve<GEOM, true>(load, basis, dp, N, l, kx, ky, k, U, V, W);
+      seg_column_solve<GEOM, true, FO>(load, basis, dp, N, l, kx, ky, k, U, V, W);
     }
     // the column's coefficients are read only by its own eight lanes (one
     // wavefront, in lockstep): overwrite them in place
@@ -1315,8 +1333,10 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     store(0, U);
     store(1, V);
     store(2, W);
-    store(3, ps_deriv(U, l, s2H));
-    store(4, ps_deriv(V, l, s2H));
+    if constexpr (!FO) {
+      store(3, ps_deriv(U, l, s2H));
+      store(4, ps_deriv(V, l, s2H));
+    }
   }
   __syncthreads();
 
@@ -1371,12 +1391,13 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
       const float kx = kxs * (float)kxi;
       const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
       const float ky = kys * (float)nyi;
-      float* d = XC + c * kMV + (col + h) * 10;
+      float* d = XC + c * kMV + (col + h) * VR;
       const float ur = d[0], ui = d[1], vr = d[2], vi = d[3], wr = d[4], wi = d[5];
-      const float dur = d[6], dui = d[7], dvr = d[8], dvi = d[9];
       o[h][0] = make_float2(sc * ur, sc * ui);
       o[h][1] = make_float2(sc * vr, sc * vi);
       o[h][2] = make_float2(sc * wr, sc * wi);
+      if constexpr (FO) continue;
+      const float dur = d[6], dui = d[7], dvr = d[8], dvi = d[9];
       // ox = (i ky w - dv/dz)/2, oy = (du/dz - i kx w)/2, oz = (i kx v - i ky u)/2
       o[h][3] = make_float2(0.5f * sc * (-ky * wi - dvr), 0.5f * sc * (ky * wr - dvi));
       o[h][4] = make_float2(0.5f * sc * (dur + kx * wi), 0.5f * sc * (dui - kx * wr));
@@ -1384,7 +1405,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
                             0.5f * sc * (kx * vr - ky * ur));
     }
     // the vorticity channels only when angular velocities are wanted
-    const int nch = dp.nch_out;
+    const int nch = FO ? 3 : dp.nch_out;
 #pragma unroll
     for (int ch = 0; ch < 6; ++ch)
       if (ch < nch)
@@ -1398,10 +1419,15 @@ static void launch_seg_geom(const fcmdp_solver* s, const ColParams& cp,
                             const void* spec_in, void* spec_out, hipStream_t st) {
   const int K = s->dp.Nkx * s->dp.Ny;
   if (s->mixed && s->dct_f32 && !s->force_vector_dct) {
-    hipLaunchKernelGGL((k_columns_mfma<GEOM>), dim3((K + kMCols - 1) / kMCols),
-                       dim3(kMThreads), 0, st, cp, s->band,
-                       (const float2*)spec_in, (float2*)spec_out, s->zc,
-                       s->dct_f32, s->dct_i32);
+    const dim3 g((K + kMCols - 1) / kMCols);
+    if (s->dp.nch_in == 3 && s->dp.nch_out == 3)
+      hipLaunchKernelGGL((k_columns_mfma<GEOM, true>), g, dim3(kMThreads), 0, st,
+                         cp, s->band, (const float2*)spec_in, (float2*)spec_out,
+                         s->zc, s->dct_f32, s->dct_i32);
+    else
+      hipLaunchKernelGGL((k_columns_mfma<GEOM, false>), g, dim3(kMThreads), 0, st,
+                         cp, s->band, (const float2*)spec_in, (float2*)spec_out,
+                         s->zc, s->dct_f32, s->dct_i32);
   } else if (s->mixed) {
     constexpr int cols = ColsPerBlock<float>::value;
     hipLaunchKernelGGL((k_columns_seg<float, GEOM>), dim3((K + cols - 1) / cols),
