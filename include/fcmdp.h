@@ -113,6 +113,30 @@ void fcmdp_destroy_solver(fcmdp_solver* s);
 
 const char* fcmdp_strerror(int code);
 
+/*
+ * Brownian displacements g = M^{1/2} W (Sec. 5.2) by the Lanczos process in
+ * the Krylov space of the translational mobility M, i.e. the forces-only
+ * apply F -> U of fcmdp_apply_mobility (T = NULL, Omega = NULL), which is
+ * symmetric positive definite up to discretisation error.
+ *   pos, W, g:  [n][3] device arrays of the solver's element type; W holds
+ *               the random vector (e.g. i.i.d. N(0, 1)), g receives
+ *               |W| V_k T_k^{1/2} e_1 (V_k the orthonormal Krylov basis, T_k
+ *               the Lanczos tridiagonal matrix).  g must not alias W.
+ *   max_iter:   1..64 iterations (one mobility apply each).
+ *   tol:        stop once |g_k - g_{k-1}| / |g_{k-1}| < tol (k >= 2); 0 runs
+ *               all max_iter iterations.
+ *   iters, rel_change (optional): iterations used and the last relative
+ *               change.
+ * Blocking on the host (a few synchronisations of the stream per iteration);
+ * the Krylov basis ((max_iter + 1) * 3n words) is allocated on first use and
+ * kept with the solver.  W = 0 gives g = 0 and *iters = 0.
+ * Returns EINVAL for bad arguments, ECAPACITY if n > max_particles, ENOMEM,
+ * EHIP, or an error of the mobility apply.
+ */
+int fcmdp_lanczos_sqrt(fcmdp_solver* s, int64_t n, const void* pos,
+                       const void* W, void* g, int max_iter, double tol,
+                       int* iters, double* rel_change, void* hip_stream);
+
 /* Derived quantities of a solver (host only): out[0] = h, out[1] = alpha,
  * out[2] = ES normalisation integral of the monopole kernel, out[3] = of the
  * dipole kernel (the integral in eq. es-scalar). */

@@ -17,6 +17,8 @@ linear time" (arXiv 2210.01837), written from the paper:
   k = 0 mode (Sec. 3.3, App. A.2), vorticity by a spectral curl.
 * ``fcm``     -- spreading with wall images (eqs. fcm, kernelnearwall),
   interpolation (eqs. getpartvel, getpartvort) and the whole apply.
+* ``lanczos`` -- Brownian displacements M^{1/2} W by the Lanczos process
+  (Sec. 5.2) on top of the forces-only apply.
 
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the GPU library and never calls
@@ -28,5 +30,5 @@ mobility values against the paper's figures are "parity unpinned" because the
 figures' data are not part of the paper's text.
 """
 from .kernel import ESKernel, es_normalization, phi  # noqa: F401
-from . import cheb, bvp, stokes, fcm  # noqa: F401
+from . import cheb, bvp, stokes, fcm, lanczos  # noqa: F401
 from .fcm import Solver, apply_mobility  # noqa: F401

@@ -61,6 +61,10 @@ def lib() -> ctypes.CDLL:
         L.fcmdp_workspace_bytes.restype = ci
         L.fcmdp_apply_mobility.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
         L.fcmdp_apply_mobility.restype = ci
+        L.fcmdp_lanczos_sqrt.argtypes = [vp, i64, vp, vp, vp, ci,
+                                         ctypes.c_double, ctypes.POINTER(ci),
+                                         ctypes.POINTER(ctypes.c_double), vp]
+        L.fcmdp_lanczos_sqrt.restype = ci
         L.fcmdp_status.argtypes = [vp, ctypes.POINTER(i64)]
         L.fcmdp_status.restype = ci
         L.fcmdp_destroy_solver.argtypes = [vp]

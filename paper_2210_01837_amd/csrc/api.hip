@@ -252,7 +252,8 @@ void free_all(fcmdp_solver* s) {
                   s->hist, s->cell_start, s->pinfo, s->pw, s->pf, s->psi,
                   s->band, s->nbad, s->zc, s->quad, s->dct_f, s->dct_i,
                   s->dct_f32, s->dct_i32,
-                  s->dftc, s->dftc_t, s->tw_x, s->tw_y, s->tw_r};
+                  s->dftc, s->dftc_t, s->tw_x, s->tw_y, s->tw_r,
+                  s->lz_basis, s->lz_red};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }

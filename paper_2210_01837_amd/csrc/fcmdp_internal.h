@@ -123,6 +123,12 @@ struct fcmdp_solver {
   bool force_no_pipeline = false;
   int num_cu = 0;               // compute units of the device
 
+  // Lanczos square root: Krylov basis [kmax + 1][3 n] (T) and the partial
+  // sums of its reductions (double), grown on demand
+  void* lz_basis = nullptr;
+  size_t lz_bytes = 0;
+  double* lz_red = nullptr;
+
   // tracing: events of applies not yet summed, 7 per apply
   bool profiling = false;
   std::vector<hipEvent_t> events;

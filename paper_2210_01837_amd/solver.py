@@ -111,6 +111,23 @@ class Solver:
             _stream(stream)), "fcmdp_apply_mobility")
         return U, Omega
 
+    def lanczos_sqrt(self, pos, W, max_iter=32, tol=1e-3, g=None, stream=None):
+        """g = M^{1/2} W for the translational mobility (fcmdp_lanczos_sqrt).
+
+        Returns (g, iterations, last relative change)."""
+        import torch
+        n = pos.shape[0]
+        if g is None:
+            g = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
+        self._check_particles(pos, W, None, g, None)
+        it = ctypes.c_int(0)
+        ch = ctypes.c_double(0.0)
+        L.check(L.lib().fcmdp_lanczos_sqrt(
+            self._h, n, _ptr(pos), _ptr(W), _ptr(g), int(max_iter), float(tol),
+            ctypes.byref(it), ctypes.byref(ch), _stream(stream)),
+            "fcmdp_lanczos_sqrt")
+        return g, it.value, ch.value
+
     STAGES = ("particles", "spread", "fft_forward", "columns", "fft_inverse",
               "interp")
 
