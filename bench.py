@@ -324,6 +324,21 @@ def main():
         "paper_context": "663,552 particles (forces only, m=4) in 370 ms on a "
                          "V100, i.e. ~1.79e6 particle-applies/s (Sec. 5.1)",
     }
+    if forces_only:
+        # Brownian displacements M^{1/2} W on the same layer (Sec. 5.2):
+        # three digits (relative change below 1e-3), a fresh N(0,1) vector
+        W = torch.tensor(workloads.random_array((wl.n, 3), 40), dtype=dt,
+                         device="cuda")
+        g, it, ch = s.lanczos_sqrt(P, W, max_iter=32, tol=1e-3)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g, it, ch = s.lanczos_sqrt(P, W, max_iter=32, tol=1e-3, g=g)
+        torch.cuda.synchronize()
+        line["lanczos"] = {"iterations": it, "rel_change": ch, "tol": 1e-3,
+                           "ms": (time.perf_counter() - t2) * 1e3,
+                           "ms_per_iteration": (time.perf_counter() - t2) * 1e3 / max(1, it)}
+        print(f"[bench] lanczos: {line['lanczos']}", file=sys.stderr, flush=True)
+        del W, g
     del P, Fd, Td, U, Om
     s.close()
     if not args.no_fp64_comparison:
