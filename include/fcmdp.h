@@ -159,10 +159,10 @@ int fcmdp_stage_times(fcmdp_solver* s, double ms[8], int64_t* napplies);
  * Kernel variants.  Every step has a default kernel chosen at creation from
  * the sizes; the alternatives below compute the same quantities with a
  * different parallel decomposition and exist for cross-checks and tuning.
- * value: 0/1 for the switches; for the FFT row counts a power of two (rows
- * per workgroup of the wave-per-row x and y passes, 0 = default), rejected
- * with FCMDP_EINVAL if the rows do not fit in LDS.  Not thread safe with
- * respect to applies on the same solver.
+ * value: 0/1 for the switches; for the FFT row counts a power of two, or 12
+ * for the x pass (rows per workgroup of the wave-per-row x and y passes,
+ * 0 = default), rejected with FCMDP_EINVAL if the rows do not fit in LDS.
+ * Not thread safe with respect to applies on the same solver.
  */
 enum {
   FCMDP_VARIANT_GENERIC_FFT = 0,     /* workgroup-per-row-batch transforms */

@@ -150,6 +150,14 @@ int rows_fitting(size_t row_bytes, int maxrows) {
   return (size_t)r * row_bytes <= fcmdp::kLdsBudget ? r : 0;
 }
 
+// rows per workgroup of the x passes: the most (up to 16) that fit, and
+// twelve when sixteen do not fit but twelve do (1350-point rows): more
+// wavefronts and longer transposed runs than eight
+int default_rows_x(size_t row_bytes) {
+  const int r = rows_fitting(row_bytes, 16);
+  return r == 8 && 12 * row_bytes <= fcmdp::kLdsBudget ? 12 : r;
+}
+
 int validate(const fcmdp_params* p) {
   if (!p) return FCMDP_EINVAL;
   if (p->geometry != FCMDP_BOTTOM_WALL && p->geometry != FCMDP_SLIT_CHANNEL)
@@ -346,7 +354,7 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
     if (s->codelet_y >= 0) s->wave_y = true;
     const size_t row_x = (size_t)fcmdp::fft_lds_row(s->codelet_x, p->Nx / 2, true) * csz;
     const size_t row_y = (size_t)fcmdp::fft_lds_row(s->codelet_y, p->Ny, false) * csz;
-    s->rows_x = rows_fitting(row_x, 16);
+    s->rows_x = default_rows_x(row_x);
     // rows of the y pass are independent; one per workgroup packs LDS best
     s->rows_y = s->codelet_y >= 0 ? 1 : rows_fitting(row_y, 8);
     if (s->rows_x == 0) s->wave_x = false;
@@ -570,8 +578,9 @@ int fcmdp_set_variant(fcmdp_solver* s, int key, int value) {
                                      x ? s->p.Nx / 2 : s->p.Ny, x) * csz;
       const int maxr = x ? 16 : 8;   // capped at 1024 threads per workgroup
       int r = value;
-      if (r == 0) r = rows_fitting(row, maxr);
-      if (r < 1 || r > maxr || (r & (r - 1)) || (size_t)r * row > fcmdp::kLdsBudget)
+      if (r == 0) r = x ? default_rows_x(row) : rows_fitting(row, maxr);
+      if (r < 1 || r > maxr || ((r & (r - 1)) && r != 12) ||
+          (size_t)r * row > fcmdp::kLdsBudget)
         return FCMDP_EINVAL;
       (x ? s->rows_x : s->rows_y) = r;
       return FCMDP_OK;

@@ -916,6 +916,7 @@ static void wave_x_rows(bool fwd, const fcmdp_solver* s, const void* in,
   const int r = s->rows_x * TPR > 1024 ? 1024 / TPR : s->rows_x;
   switch (r) {
     case 16: launch_wave_x<T, 16, 64, Run>(fwd, s, in, out, doff, st); break;
+    case 12: launch_wave_x<T, 12, 64, Run>(fwd, s, in, out, doff, st); break;
     case 8: launch_wave_x<T, 8, TPR, Run>(fwd, s, in, out, doff, st); break;
     case 4: launch_wave_x<T, 4, TPR, Run>(fwd, s, in, out, doff, st); break;
     case 2: launch_wave_x<T, 2, TPR, Run>(fwd, s, in, out, doff, st); break;

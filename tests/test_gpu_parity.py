@@ -436,3 +436,33 @@ def test_apply_forces_only_replicated_layer():
         assert s.status() == (0, 0)
         s.close()
         del U
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("name", ["bw48", "sc192"])
+def test_channel_modes_give_the_same_bits(name, precision):
+    """Without torques (T = None) the spread, transforms and solve carry the
+    three force channels; without Omega the solve returns three channels.
+    Every combination gives the velocities (and, where asked, angular
+    velocities) of the six-channel apply with zero torques bit for bit.
+    sc192 (Nz = 48) runs the one-thread-per-column solve, bw48 the
+    eight-lane one."""
+    box = BOXES[name]
+    pos, F, T = _particles(box, 50, 14)
+    if precision == "mixed":
+        pos, F, T = (a.astype(np.float32).astype(np.float64) for a in (pos, F, T))
+    print(f"[channel modes] {name} {precision}", flush=True)
+    s = _solver(box, precision)
+    P, Fd, Td = _dev(pos, precision), _dev(F, precision), _dev(T, precision)
+    Z = torch.zeros_like(Td)
+    U0, O0 = s.apply(P, Fd, Z)                            # 6 in, 6 out
+    U1, O1 = s.apply(P, Fd, None)                         # 3 in, 6 out
+    U2, O2 = s.apply(P, Fd, None, want_omega=False)       # 3 in, 3 out
+    assert torch.equal(U1, U0) and torch.equal(O1, O0)
+    assert O2 is None and torch.equal(U2, U0)
+    U3, O3 = s.apply(P, Fd, Td)                           # 6 in, 6 out
+    U4, O4 = s.apply(P, Fd, Td, want_omega=False)         # 6 in, 3 out
+    assert O4 is None and torch.equal(U4, U3)
+    rU, rO = oracle_apply(box, pos, F, T)
+    tol = 1e-5 if precision == "mixed" else 1e-10
+    assert rel_err(_np(U4), rU) < tol and rel_err(_np(O3), rO) < tol
