@@ -114,6 +114,52 @@ def fp64_comparison(name="bw131k", steps=5):
     return out
 
 
+def forces_only_summary(steps=10, warmup=2):
+    """The paper's timed case (Sec. 5.1): the forces-only apply (m = 4) of
+    the 663,552-particle replicated layer, its accuracy against the oracle's
+    one-replica values, and a Lanczos square root to three digits."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2210_01837_amd import Solver
+    wl = workloads.WORKLOADS["m663k"]
+    pos, F, _ = workloads.particles("m663k")
+    P = torch.tensor(pos, dtype=torch.float32, device="cuda")
+    Fd = torch.tensor(F, dtype=torch.float32, device="cuda")
+    U = torch.empty_like(P)
+    s = Solver.from_box(wl.box, precision="mixed", max_particles=wl.n)
+    for _ in range(warmup):
+        s.apply(P, Fd, None, U=U, want_omega=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.apply(P, Fd, None, U=U, want_omega=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    out = {"workload": "m663k", "N": wl.n, "grid": [wl.box.Nx, wl.box.Ny, wl.box.Nz],
+           "w": wl.box.w, "ms_per_apply": ms, "value": wl.n / (ms * 1e-3),
+           "unit": "particle-applies/s",
+           "vs_paper_v100": wl.n / (ms * 1e-3) / PAPER_FORCES_ONLY_RATE}
+    gold = os.path.join(ROOT, "tests", "golden", "m2048_oracle_sample.npz")
+    if os.path.exists(gold):
+        gU = np.load(gold)["U"]
+        Uh = U.double().cpu().numpy().reshape(-1, len(gU), 3)
+        out["rel_err_U"] = float(np.linalg.norm(Uh - gU[None]) /
+                                 (np.linalg.norm(gU) * np.sqrt(Uh.shape[0])))
+    W = torch.tensor(workloads.random_array((wl.n, 3), 40), dtype=torch.float32,
+                     device="cuda")
+    g, it, ch = s.lanczos_sqrt(P, W, max_iter=32, tol=1e-3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g, it, ch = s.lanczos_sqrt(P, W, max_iter=32, tol=1e-3, g=g)
+    torch.cuda.synchronize()
+    out["lanczos"] = {"iterations": it, "rel_change": ch, "tol": 1e-3,
+                      "ms": (time.perf_counter() - t1) * 1e3}
+    s.close()
+    return out
+
+
 def cpu_baseline(name, factor=4):
     """Time the oracle on a 1/factor x 1/factor sub-box of the workload."""
     import numpy as np  # noqa: F401
@@ -186,6 +232,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-fp64-comparison", action="store_true")
+    ap.add_argument("--no-forces-only", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for "
@@ -345,6 +392,10 @@ def main():
         line["fp64_comparison"] = fp64_comparison()
         print(f"[bench] fp64 comparison: {line['fp64_comparison']}",
               file=sys.stderr, flush=True)
+    if not args.no_forces_only and name != "m663k":
+        line["forces_only"] = forces_only_summary()
+        print(f"[bench] forces only: {line['forces_only']}", file=sys.stderr,
+              flush=True)
     if not args.no_serving:
         sv = serving_bench(args.serving_requests)
         line["serving"] = sv
