@@ -466,3 +466,22 @@ def test_channel_modes_give_the_same_bits(name, precision):
     rU, rO = oracle_apply(box, pos, F, T)
     tol = 1e-5 if precision == "mixed" else 1e-10
     assert rel_err(_np(U4), rU) < tol and rel_err(_np(O3), rO) < tol
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("nz,geometry", [(8, "bw"), (64, "bw"), (64, "sc")])
+def test_apply_smallest_and_largest_nz(nz, geometry, precision):
+    """Nz = 8 and Nz = 64, the limits the library accepts (Nz > 32 runs the
+    one-thread-per-column solve)."""
+    box = Box(geometry, 16.0, 16.0, 6.0, 24, 24, nz)
+    pos, F, T = _particles(box, 30, 15)
+    if precision == "mixed":
+        pos, F, T = (a.astype(np.float32).astype(np.float64) for a in (pos, F, T))
+    print(f"[nz limits] {geometry} Nz={nz} {precision}", flush=True)
+    s = _solver(box, precision)
+    U, Om = s.apply(_dev(pos, precision), _dev(F, precision), _dev(T, precision))
+    rU, rO = oracle_apply(box, pos, F, T)
+    eU, eO = rel_err(_np(U), rU), rel_err(_np(Om), rO)
+    print(f"  rel err U {eU:.3e} Omega {eO:.3e}", flush=True)
+    tol = 1e-5 if precision == "mixed" else 1e-10
+    assert eU < tol and eO < tol
