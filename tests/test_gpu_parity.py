@@ -296,7 +296,7 @@ def test_stage_fft_mixed_sizes(nx, ny):
     assert rel_err(results["default"][1][sl], results["no_pipeline"][1][sl]) < 1e-6
 
 
-@pytest.mark.parametrize("rows", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("rows", [1, 2, 4, 8, 12, 16])
 def test_stage_fft_mixed_rows_per_workgroup(rows):
     nx, ny = 1536, 1000
     box = _fft_box(nx, ny)
