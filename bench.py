@@ -313,6 +313,14 @@ def main():
                 "traffic": measured_traffic(name, kname),
                 "algorithmic_bytes": nbytes[dom], "avg_ms": avg[dom]}
     stage_gbs = {k: nbytes[k] / (avg[k] * 1e-3) / 1e9 for k in nbytes}
+    # the same accounting with every plane transformed (P = Nz), for
+    # comparison with a full-grid implementation
+    full = stage_bytes(box, wl.n, (0, box.Nz - 1),
+                       complex_bytes=8 if wl.precision == "mixed" else 16,
+                       real_bytes=4 if wl.precision == "mixed" else 8,
+                       torques=wl.torques)
+    full_grid = {"bytes": full,
+                 "gbs": {k: full[k] / (avg[k] * 1e-3) / 1e9 for k in full}}
 
     # accuracy on the seeded 1% sample, against stored oracle values
     # (a tiled layer is compared in full with its replica's stored values:
@@ -365,6 +373,7 @@ def main():
         "roofline": roofline,
         "stages_ms": avg,
         "stages_gbs": stage_gbs,
+        "full_grid_accounting": full_grid,
         "band_planes": [band[0], band[1]],
         "domain_status": [code, bad],
         "accuracy": acc,
