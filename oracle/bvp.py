@@ -67,26 +67,35 @@ def solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:
     return x[..., 0] + 1j * x[..., 1]
 
 
-def zero_mode_matrix(N: int, geometry: str) -> np.ndarray:
+def zero_mode_matrix(N: int, geometry: str, H: float = 1.0, slip0: float = 0.0,
+                     slipH: float = 0.0) -> np.ndarray:
     """System for y'' = rhs at k = 0.
 
-    Rows m >= 2: y_m = (H^2/4)(B^2 rhs)_m.  Row 1: y(0) = 0.  Row 0: bottom
-    wall y'(H) = 0, i.e. sum n^2 y_n = 0; slit channel y(H) = 0, i.e.
-    sum y_n = 0.
+    Rows m >= 2: y_m = (H^2/4)(B^2 rhs)_m.  Row 1: y(0) = 0, or for a slit
+    channel with slip length l_0 at z = 0, y(0) - l_0 y'(0) = 0 (eq.
+    bvp-uv-k0-sc).  Row 0: bottom wall y'(H) = 0, i.e. sum n^2 y_n = 0; slit
+    channel y(H) + l_H y'(H) = 0.  With T_n(+-1) = (+-1)^n and
+    T_n'(+-1) = (+-1)^(n+1) n^2, d/dz = (2/H) d/ds.
     """
     n = np.arange(N, dtype=np.float64)
+    sgn = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
     A = np.eye(N)
-    A[0, :] = n ** 2 if geometry == "bw" else 1.0
-    A[1, :] = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    if geometry == "bw":
+        A[0, :] = n ** 2
+        A[1, :] = sgn
+    else:
+        A[0, :] = 1.0 + slipH * (2.0 / H) * n ** 2
+        A[1, :] = sgn - slip0 * (2.0 / H) * (-sgn) * n ** 2
     return A
 
 
-def zero_mode_solve(rhs_coeffs: np.ndarray, H: float, geometry: str) -> np.ndarray:
+def zero_mode_solve(rhs_coeffs: np.ndarray, H: float, geometry: str,
+                    slip0: float = 0.0, slipH: float = 0.0) -> np.ndarray:
     """Coefficients y of y'' = rhs (rhs given as Chebyshev coefficients)."""
     N = rhs_coeffs.shape[-1]
     B2 = cheb.b2_matrix(N)
     b = (H * H / 4.0) * (B2 @ rhs_coeffs)
     b[0] = 0.0
     b[1] = 0.0
-    A = zero_mode_matrix(N, geometry)
+    A = zero_mode_matrix(N, geometry, H, slip0, slipH)
     return solve(A[None], b[None])[0]

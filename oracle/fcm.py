@@ -36,6 +36,9 @@ class Solver:
         self.box = box
         if abs(box.Lx / box.Nx - box.Ly / box.Ny) > 1e-12 * box.Lx / box.Nx:
             raise ValueError("the oracle requires hx == hy")
+        if box.slip0 < 0 or box.slipH < 0 or (
+                box.geometry == "bw" and (box.slip0 or box.slipH)):
+            raise ValueError("slip lengths are >= 0 and for the slit channel")
         self.h = box.Lx / box.Nx
         self.alpha = 0.5 * box.w * self.h        # alpha = m h / 2 (Sec. 3.5)
         self.kernel = ESKernel(self.alpha, box.beta_m, box.beta_d)

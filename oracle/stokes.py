@@ -119,35 +119,51 @@ def _dp_and_correction(box, kx, ky, fx, fy, fz, chunk=16384):
 
 
 def _slit_correction(box, kx, ky, k, uu, vv, ww, zc, alt):
-    """Slit-channel correction with no slip at both walls (App. A, l = 0).
+    """Slit-channel correction with slip lengths l_0, l_H (App. A; no slip
+    when both are zero) and zero wall velocity.
 
     Unknowns (C0, D0, Cx, Dx, Cy, Dy, Cz, Dz) of eqs. psolfs-corr-sc ..
-    wsolfs-corr-sc from the six boundary conditions (eq. 6eqs-for-constants
-    with l_0 = l_H = 0 and zero wall velocity) and the two continuity
-    conditions (eq. 2eqs-for-constants).  Reading: the D-coefficients are
-    rescaled, D~ = D e^{kH}, so every matrix entry carries at most e^{-kH} <= 1.
+    wsolfs-corr-sc from the six boundary conditions (eq. 6eqs-for-constants)
+    and the two continuity conditions (eq. 2eqs-for-constants).  The boundary
+    data are eq. u0uHformula: u_0 = -u_DP(0) + l_0 du_DP/dz(0), u_H = -u_DP(H)
+    - l_H du_DP/dz(H), w_0 = -w_DP(0), w_H = -w_DP(H).  Reading: the
+    D-coefficients are rescaled, D~ = D e^{kH}, so every matrix entry carries
+    at most e^{-kH} <= 1 (rows scaled by e^{-kH} where needed).
     """
     H, eta = box.H, box.eta
+    l0, lH = box.slip0, box.slipH
     Kc = k.size
     E = np.exp(-k * H)
-    # boundary data: u_corr = -u_DP at z = 0 and z = H
-    u0, v0, w0 = -(uu * alt).sum(-1), -(vv * alt).sum(-1), -(ww * alt).sum(-1)
-    uH, vH, wH = -uu.sum(-1), -vv.sum(-1), -ww.sum(-1)
+    # z-derivatives at the walls: T_n'(+-1) = (+-1)^(n+1) n^2, d/dz = (2/H) d/ds
+    n2 = np.arange(uu.shape[-1], dtype=float) ** 2
+    d0 = lambda a: (2.0 / H) * (a * (-alt) * n2).sum(-1)   # noqa: E731
+    dH = lambda a: (2.0 / H) * (a * n2).sum(-1)            # noqa: E731
+    u0 = -(uu * alt).sum(-1) + l0 * d0(uu)
+    v0 = -(vv * alt).sum(-1) + l0 * d0(vv)
+    w0 = -(ww * alt).sum(-1)
+    uH = -uu.sum(-1) - lH * dH(uu)
+    vH = -vv.sum(-1) - lH * dH(vv)
+    wH = -ww.sum(-1)
     M = np.zeros((Kc, 8, 8), complex)
     b = np.zeros((Kc, 8), complex)
     C0, D0, CX, DX, CY, DY, CZ, DZ = range(8)
     one = np.ones(Kc)
-    # u(0) = u0, v(0) = v0, w(0) = w0
-    M[:, 0, CX], M[:, 0, DX], b[:, 0] = one, E, u0
-    M[:, 1, CY], M[:, 1, DY], b[:, 1] = one, E, v0
+    # u(0) - l_0 u'(0) = u0, v likewise; w(0) = w0
+    for row, kk, rhs, Cc, Dc in ((0, kx, u0, CX, DX), (1, ky, v0, CY, DY)):
+        c = 1j * kk * l0 / (2.0 * eta * k)
+        M[:, row, C0] = c
+        M[:, row, D0] = -c * E
+        M[:, row, Cc] = 1.0 + k * l0
+        M[:, row, Dc] = (1.0 - k * l0) * E
+        b[:, row] = rhs
     M[:, 2, CZ], M[:, 2, DZ], b[:, 2] = one, E, w0
-    # u(H) = uH, v(H) = vH
+    # u(H) + l_H u'(H) = uH, v likewise
     for row, kk, rhs, Cc, Dc in ((3, kx, uH, CX, DX), (4, ky, vH, CY, DY)):
         c = 1j * kk * H / (2.0 * eta * k)
-        M[:, row, C0] = -c * E
-        M[:, row, D0] = c
-        M[:, row, Cc] = E
-        M[:, row, Dc] = one
+        M[:, row, C0] = c * E * (k * lH - lH / H - 1.0)
+        M[:, row, D0] = c * (k * lH + lH / H + 1.0)
+        M[:, row, Cc] = E * (1.0 - k * lH)
+        M[:, row, Dc] = 1.0 + k * lH
         b[:, row] = rhs
     # w(H) = wH
     M[:, 5, C0] = H * E / (2.0 * eta)
@@ -209,8 +225,10 @@ def solve_coefficients(box, Fh, Gh):
     # Step 5: k = 0 mode (Sec. 3.3; App. A.2 for the slit channel); w = 0.
     k0 = np.nonzero(k2 == 0)[0]
     for j in k0:
-        U[0][j] = bvp.zero_mode_solve(-cx[j] / box.eta, H, box.geometry)
-        U[1][j] = bvp.zero_mode_solve(-cy[j] / box.eta, H, box.geometry)
+        U[0][j] = bvp.zero_mode_solve(-cx[j] / box.eta, H, box.geometry,
+                                      box.slip0, box.slipH)
+        U[1][j] = bvp.zero_mode_solve(-cy[j] / box.eta, H, box.geometry,
+                                      box.slip0, box.slipH)
     uh = np.stack([U[i].T.reshape(shape) for i in range(3)])
     # vorticity: omega = (1/2) curl u in Fourier-Chebyshev space
     cu = curl(uh[0], uh[1], uh[2], ikx, iky, D)

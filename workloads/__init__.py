@@ -76,6 +76,8 @@ class Box:
     beta_m: float = BETA_M
     beta_d: float = BETA_D
     eta: float = 1.0
+    slip0: float = 0.0     # slip lengths of the slit channel's walls at
+    slipH: float = 0.0     # z = 0 and z = H (App. A); 0 = no slip
 
     @property
     def h(self) -> float:
