@@ -70,6 +70,10 @@ typedef struct {
   double eta;          /* viscosity > 0 */
   int precision;       /* FCMDP_FP64 or FCMDP_MIXED */
   int64_t max_particles; /* capacity of the particle workspace */
+  double slip0, slipH; /* slip lengths of the walls at z = 0 and z = H (App. A,
+                          partial slip u - l0 du/dz = 0 at z = 0, u + lH du/dz
+                          = 0 at z = H, zero wall velocity): slit channel
+                          with Nz <= 32 only; 0 = no slip */
 } fcmdp_params;
 
 /*

@@ -32,6 +32,8 @@ class Params(ctypes.Structure):
         ("eta", ctypes.c_double),
         ("precision", ctypes.c_int),
         ("max_particles", ctypes.c_int64),
+        ("slip0", ctypes.c_double),
+        ("slipH", ctypes.c_double),
     ]
 
 

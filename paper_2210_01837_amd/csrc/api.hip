@@ -173,6 +173,13 @@ int validate(const fcmdp_params* p) {
   if (p->w != 4 && p->w != 6) return FCMDP_EINVAL;
   if (p->max_particles < 0 || p->max_particles > (int64_t)1 << 30)
     return FCMDP_EINVAL;
+  // partial slip: slit channel, solved by the eight-lane column kernels
+  if (!(p->slip0 >= 0) || !(p->slipH >= 0) || !std::isfinite(p->slip0) ||
+      !std::isfinite(p->slipH))
+    return FCMDP_EINVAL;
+  if ((p->slip0 != 0 || p->slipH != 0) &&
+      (p->geometry != FCMDP_SLIT_CHANNEL || p->Nz > 32))
+    return FCMDP_EINVAL;
   const double hx = p->Lx / p->Nx, hy = p->Ly / p->Ny;
   if (std::fabs(hx - hy) > 1e-12 * hx) return FCMDP_EINVAL;
   const double alpha = 0.5 * p->w * hx;
@@ -319,6 +326,8 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
   dp.half_w = p->w / 2;
   dp.nch_in = 6;
   dp.nch_out = 6;
+  dp.slip0 = p->slip0;
+  dp.slipH = p->slipH;
   dp.Lx = p->Lx;
   dp.Ly = p->Ly;
   dp.H = p->H;

@@ -384,7 +384,7 @@ __device__ __forceinline__ Z2 seg_solve6(double a[6], Z2 b, int l) {
 
 // k = 0: y'' = r with y(0) = 0 and y'(H) = 0 (bottom wall) or y(H) = 0.
 __device__ __forceinline__ Vec seg_zero_mode(const Vec& r, double H, int N, int geometry,
-                             int l) {
+                             int l, double a0 = 0.0, double aH = 0.0) {
   const double h2 = 0.25 * H * H;
   Vec y = vzero();
 #pragma unroll
@@ -417,16 +417,47 @@ __device__ __forceinline__ Vec seg_zero_mode(const Vec& r, double H, int N, int 
   sp = red(sp);
   sm = red(sm);
   sn2 = red(sn2);
+  const bool slip = geometry == 1 && (a0 != 0.0 || aH != 0.0);
+  Z2 y0s = zmk(0, 0), y1s = zmk(0, 0);
+  if (slip) {                    // Robin conditions, as in ps_zero_mode
+    Z2 sdm = zmk(0, 0);
+#pragma unroll
+    for (int j = 0; j < kNpl; ++j) {
+      const double n = 4.0 * l + j;
+      sdm = sdm + (((j & 1) ? 1.0 : -1.0) * n * n) * y.v[j];
+    }
+    sdm = red(sdm);
+    y1s = frcp(2.0 + a0 + aH) * (sm - sp - a0 * sdm - aH * sn2);
+    y0s = -1.0 * sp - aH * sn2 - (1.0 + aH) * y1s;
+  }
   if (l == 0) {
     if (geometry == 0) {
       y.v[1] = -1.0 * sn2;
       y.v[0] = y.v[1] - sm;
+    } else if (slip) {
+      y.v[0] = y0s;
+      y.v[1] = y1s;
     } else {
       y.v[0] = -0.5 * (sp + sm);
       y.v[1] = -0.5 * (sp - sm);
     }
   }
   return y;
+}
+
+// z-derivative sums at the walls, in units of 2/H: top = sum n^2 a_n
+// (T_n'(1) = n^2), bot = sum (-1)^(n+1) n^2 a_n (T_n'(-1)); four consecutive
+// coefficients per lane (n = 4 l + j)
+__device__ inline void seg_dsums(const Vec& a, int l, Z2& top, Z2& bot) {
+  Z2 t = zmk(0, 0), b = zmk(0, 0);
+#pragma unroll
+  for (int j = 0; j < kNpl; ++j) {
+    const double n = 4.0 * l + j;
+    t = t + (n * n) * a.v[j];
+    b = b + (((j & 1) ? 1.0 : -1.0) * n * n) * a.v[j];
+  }
+  top = red(t);
+  bot = red(b);
 }
 
 __device__ inline Z2 bsum_bottom(const Vec& a) {   // sum (-1)^n a_n
@@ -720,10 +751,21 @@ __device__ inline Z2 ps_bsum_bottom(const Vec& a, int l) {   // sum (-1)^n a_n
 __device__ inline Z2 ps_bsum_top(const Vec& a) {             // sum a_n
   return red(a.v[0] + a.v[1] + a.v[2] + a.v[3]);
 }
+// the derivative sums of seg_dsums in the parity-split layout
+__device__ inline void ps_dsums(const Vec& a, int l, Z2& top, Z2& bot) {
+  Z2 t = zmk(0, 0);
+#pragma unroll
+  for (int s = 0; s < kNpl; ++s) {
+    const double n = ps_m(l, s);
+    t = t + (n * n) * a.v[s];
+  }
+  top = red(t);
+  bot = red((l >> 2) ? t : -1.0 * t);                 // (-1)^(n+1)
+}
 
 // k = 0: y'' = r with y(0) = 0 and y'(H) = 0 (bottom wall) or y(H) = 0.
 __device__ __forceinline__ Vec ps_zero_mode(const Vec& r, double H, int N, int geometry,
-                                            int l) {
+                                            int l, double a0 = 0.0, double aH = 0.0) {
   const double h2 = 0.25 * H * H;
   const Z2 rm2 = from_down<1>(r.v[kNpl - 1]);
   const Z2 rp2 = from_up<1>(r.v[0]);
@@ -747,10 +789,28 @@ __device__ __forceinline__ Vec ps_zero_mode(const Vec& r, double H, int N, int g
   sp = red(sp);
   sm = red(sm);
   sn2 = red(sn2);
+  const bool slip = geometry == 1 && (a0 != 0.0 || aH != 0.0);
+  Z2 y0s = zmk(0, 0), y1s = zmk(0, 0);
+  if (slip) {
+    // y(0) - l_0 y'(0) = 0, y(H) + l_H y'(H) = 0 with a = 2 l / H:
+    // y0 - (1 + a0) y1 = -sm + a0 sdm, y0 + (1 + aH) y1 = -sp - aH sn2,
+    // sdm = sum_{n >= 2} (-1)^{n+1} n^2 y_n
+    Z2 sdm = zmk(0, 0);
+#pragma unroll
+    for (int s = 0; s < kNpl; ++s) {
+      const double n = ps_m(l, s);
+      sdm = sdm + (-sgn * n * n) * y.v[s];
+    }
+    sdm = red(sdm);
+    y1s = frcp(2.0 + a0 + aH) * (sm - sp - a0 * sdm - aH * sn2);
+    y0s = -1.0 * sp - aH * sn2 - (1.0 + aH) * y1s;
+  }
   if ((l & 3) == 0) {                                // slot 0 holds m = 0 or 1
     const bool odd = l >> 2;
     if (geometry == 0) {
       y.v[0] = odd ? -1.0 * sn2 : -1.0 * sn2 - sm;
+    } else if (slip) {
+      y.v[0] = odd ? y1s : y0s;
     } else {
       y.v[0] = odd ? -0.5 * (sp - sm) : -0.5 * (sp + sm);
     }
@@ -789,6 +849,9 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     if constexpr (SPLIT) return ps_bsum_bottom(a, l);
     else return bsum_bottom(a);
   };
+  // slit channel slip lengths (App. A) as a = 2 l / H; zero for no slip
+  const double a0s = GEOM == 1 ? 2.0 * dp.slip0 / H : 0.0;
+  const double aHs = GEOM == 1 ? 2.0 * dp.slipH / H : 0.0;
   auto body_x = [&]() {
     Vec f = load(0);
     if constexpr (!FO) {
@@ -811,13 +874,13 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     Vec r = body_x();
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
-    if constexpr (SPLIT) U = ps_zero_mode(r, H, N, GEOM, l);
-    else U = seg_zero_mode(r, H, N, GEOM, l);
+    if constexpr (SPLIT) U = ps_zero_mode(r, H, N, GEOM, l, a0s, aHs);
+    else U = seg_zero_mode(r, H, N, GEOM, l, a0s, aHs);
     r = body_y();
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
-    if constexpr (SPLIT) V = ps_zero_mode(r, H, N, GEOM, l);
-    else V = seg_zero_mode(r, H, N, GEOM, l);
+    if constexpr (SPLIT) V = ps_zero_mode(r, H, N, GEOM, l, a0s, aHs);
+    else V = seg_zero_mode(r, H, N, GEOM, l, a0s, aHs);
   } else {
     const double kappa = 0.5 * k * H;
     Par q[2];
@@ -883,12 +946,27 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
         W.v[j] = W.v[j] + ZE[j] * Bc + E[j] * w0;
       }
     } else {
-      const Z2 uH = -1.0 * bsum_top(U), vH = -1.0 * bsum_top(V),
-               wH = -1.0 * bsum_top(W);
+      Z2 uH = -1.0 * bsum_top(U), vH = -1.0 * bsum_top(V);
+      const Z2 wH = -1.0 * bsum_top(W);
       const double Ex = exp(-k * H);
       const double hh = 0.5 * H * ie, e2 = 0.5 * ie;
-      const Z2 uL0 = ik * (kx * u0 + ky * v0);
-      const Z2 uT0 = ik * (kx * v0 - ky * u0);
+      // partial slip (App. A): boundary data u_0 = -u_DP(0) + l_0 u_DP'(0),
+      // u_H = -u_DP(H) - l_H u_DP'(H) (v likewise), Robin rows below
+      const double l0 = dp.slip0, lH = dp.slipH;
+      const bool slip = l0 != 0.0 || lH != 0.0;
+      Z2 us0 = u0, vs0 = v0;
+      if (slip) {
+        Z2 tu, bu, tv, bv;
+        if constexpr (SPLIT) { ps_dsums(U, l, tu, bu); ps_dsums(V, l, tv, bv); }
+        else { seg_dsums(U, l, tu, bu); seg_dsums(V, l, tv, bv); }
+        us0 = us0 + (l0 * s2H) * bu;
+        vs0 = vs0 + (l0 * s2H) * bv;
+        uH = uH - (lH * s2H) * tu;
+        vH = vH - (lH * s2H) * tv;
+      }
+      const double kl0 = k * l0, klH = k * lH;
+      const Z2 uL0 = ik * (kx * us0 + ky * vs0);
+      const Z2 uT0 = ik * (kx * vs0 - ky * us0);
       const Z2 uLH = ik * (kx * uH + ky * vH);
       const Z2 uTH = ik * (kx * vH - ky * uH);
       // longitudinal 6x6 system, one row per lane (unknowns C0, D0~,
@@ -896,10 +974,21 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
       double row6[6] = {0, 0, 0, 0, 0, 0};
       Z2 rhs6 = zmk(0, 0);
       switch (l) {
-        case 0: row6[2] = 1; row6[3] = Ex; rhs6 = imul(1.0, uL0); break;
+        case 0: row6[2] = 1; row6[3] = Ex; rhs6 = imul(1.0, uL0);
+                if (slip) {
+                  row6[0] = -l0 * e2; row6[1] = l0 * e2 * Ex;
+                  row6[2] = 1.0 + kl0; row6[3] = (1.0 - kl0) * Ex;
+                }
+                break;
         case 1: row6[4] = 1; row6[5] = Ex; rhs6 = w0; break;
         case 2: row6[0] = hh * Ex; row6[1] = -hh; row6[2] = Ex; row6[3] = 1;
-                rhs6 = imul(1.0, uLH); break;
+                rhs6 = imul(1.0, uLH);
+                if (slip) {
+                  row6[0] = hh * Ex * (1.0 + lH / H - klH);
+                  row6[1] = -hh * (1.0 + lH / H + klH);
+                  row6[2] = Ex * (1.0 - klH); row6[3] = 1.0 + klH;
+                }
+                break;
         case 3: row6[0] = hh * Ex; row6[1] = hh; row6[4] = Ex; row6[5] = 1;
                 rhs6 = wH; break;
         case 4: row6[0] = e2; row6[1] = e2 * Ex; row6[2] = k; row6[3] = k * Ex;
@@ -912,9 +1001,19 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
       const Z2 C0 = shz(x6, 0), D0 = shz(x6, 1);
       const Z2 CL = imul(-1.0, shz(x6, 2)), DL = imul(-1.0, shz(x6, 3));
       const Z2 Cz = shz(x6, 4), Dz = shz(x6, 5);
-      const double idet = frcp(1.0 - Ex * Ex);
-      const Z2 CT = idet * (uT0 - Ex * uTH);
-      const Z2 DT = idet * (uTH - Ex * uT0);
+      Z2 CT, DT;
+      if (!slip) {
+        const double idet = frcp(1.0 - Ex * Ex);
+        CT = idet * (uT0 - Ex * uTH);
+        DT = idet * (uTH - Ex * uT0);
+      } else {
+        // (1 + k l0) C_T + (1 - k l0) e^{-kH} D~_T = u_T0,
+        // e^{-kH} (1 - k lH) C_T + (1 + k lH) D~_T = u_TH
+        const double idet = frcp((1.0 + kl0) * (1.0 + klH) -
+                                 (1.0 - kl0) * (1.0 - klH) * Ex * Ex);
+        CT = idet * ((1.0 + klH) * uT0 - ((1.0 - kl0) * Ex) * uTH);
+        DT = idet * ((1.0 + kl0) * uTH - (Ex * (1.0 - klH)) * uT0);
+      }
       const double rx = kx * ik, ry = ky * ik;
       const Z2 Cx = rx * CL - ry * CT, Cy = ry * CL + rx * CT;
       const Z2 Dx = rx * DL - ry * DT, Dy = ry * DL + rx * DT;

@@ -57,6 +57,7 @@ struct DevParams {
   int nch_in, nch_out;
   double Lx, Ly, H, h, alpha, eta;
   double beta_m, beta_d, inv_norm_m, inv_norm_d;
+  double slip0, slipH;          // slit channel slip lengths (0 = no slip)
 };
 
 }  // namespace fcmdp

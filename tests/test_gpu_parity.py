@@ -485,3 +485,27 @@ def test_apply_smallest_and_largest_nz(nz, geometry, precision):
     print(f"  rel err U {eU:.3e} Omega {eO:.3e}", flush=True)
     tol = 1e-5 if precision == "mixed" else 1e-10
     assert eU < tol and eO < tol
+
+
+# --- slit channel with partial slip (App. A) ----------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("slip", [(0.5, 2.0), (3.0, 0.0), (0.0, 0.7)])
+def test_apply_slit_channel_partial_slip(slip, precision):
+    from dataclasses import replace
+    box = replace(BOXES["sc40x56"], slip0=slip[0], slipH=slip[1])
+    pos, F, T = _particles(box, 40, 16)
+    if precision == "mixed":
+        pos, F, T = (a.astype(np.float32).astype(np.float64) for a in (pos, F, T))
+    print(f"[slip] {slip} {precision}", flush=True)
+    s = _solver(box, precision)
+    U, Om = s.apply(_dev(pos, precision), _dev(F, precision), _dev(T, precision))
+    rU, rO = oracle_apply(box, pos, F, T)
+    eU, eO = rel_err(_np(U), rU), rel_err(_np(Om), rO)
+    print(f"  rel err U {eU:.3e} Omega {eO:.3e}", flush=True)
+    tol = 1e-5 if precision == "mixed" else 1e-10
+    assert eU < tol and eO < tol
+    # the forces-only kernel and the FP64 eight-lane kernel take the same rows
+    U2, _ = s.apply(_dev(pos, precision), _dev(F, precision), None,
+                    want_omega=False)
+    rU2, _ = oracle_apply(box, pos, F, np.zeros_like(T))
+    assert rel_err(_np(U2), rU2) < tol
