@@ -82,3 +82,27 @@ def test_null_arguments(L):
     assert L.fcmdp_apply_mobility(None, 1, None, None, None, None, None, None) == _lib.EINVAL
     assert L.fcmdp_status(None, None) == _lib.EINVAL
     L.fcmdp_destroy_solver(None)
+
+
+def test_params_struct_matches_the_header():
+    """The ctypes mirror of fcmdp_params has the header's fields, in order,
+    with the header's C types (an ABI drift would misread every field after
+    it)."""
+    from paper_2210_01837_amd import _lib
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\} fcmdp_params;", src, re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        for nm in names.split(","):
+            fields.append((nm.strip(), ctype))
+    ctypes_of = {"int": ctypes.c_int, "double": ctypes.c_double,
+                 "int64_t": ctypes.c_int64}
+    got = [(n, t) for n, t in _lib.Params._fields_]
+    assert [n for n, _ in got] == [n for n, _ in fields]
+    for (n, t), (_, c) in zip(got, fields):
+        assert t is ctypes_of[c], n
