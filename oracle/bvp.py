@@ -90,12 +90,16 @@ def zero_mode_matrix(N: int, geometry: str, H: float = 1.0, slip0: float = 0.0,
 
 
 def zero_mode_solve(rhs_coeffs: np.ndarray, H: float, geometry: str,
-                    slip0: float = 0.0, slipH: float = 0.0) -> np.ndarray:
-    """Coefficients y of y'' = rhs (rhs given as Chebyshev coefficients)."""
+                    slip0: float = 0.0, slipH: float = 0.0, g0: complex = 0.0,
+                    gH: complex = 0.0) -> np.ndarray:
+    """Coefficients y of y'' = rhs (rhs given as Chebyshev coefficients);
+    g0 and gH are the right-hand sides of the wall conditions (the wall
+    velocities of eqs. bcnoslip0fs and bvp-uv-k0-sc; gH = 0 for a bottom
+    wall, whose top condition is y'(H) = 0)."""
     N = rhs_coeffs.shape[-1]
     B2 = cheb.b2_matrix(N)
     b = (H * H / 4.0) * (B2 @ rhs_coeffs)
-    b[0] = 0.0
-    b[1] = 0.0
+    b[0] = gH
+    b[1] = g0
     A = zero_mode_matrix(N, geometry, H, slip0, slipH)
     return solve(A[None], b[None])[0]

@@ -39,6 +39,8 @@ class Solver:
         if box.slip0 < 0 or box.slipH < 0 or (
                 box.geometry == "bw" and (box.slip0 or box.slipH)):
             raise ValueError("slip lengths are >= 0 and for the slit channel")
+        if box.geometry == "bw" and any(box.wallH):
+            raise ValueError("a bottom wall has no wall at z = H")
         self.h = box.Lx / box.Nx
         self.alpha = 0.5 * box.w * self.h        # alpha = m h / 2 (Sec. 3.5)
         self.kernel = ESKernel(self.alpha, box.beta_m, box.beta_d)

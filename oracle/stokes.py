@@ -223,12 +223,15 @@ def solve_coefficients(box, Fh, Gh):
                                     cz[idx])
     U[0][idx], U[1][idx], U[2][idx] = uu, vv, ww
     # Step 5: k = 0 mode (Sec. 3.3; App. A.2 for the slit channel); w = 0.
+    # Uniform wall velocities enter only here: the unnormalised xy DFT of a
+    # constant c is c Nx Ny at k = 0.
     k0 = np.nonzero(k2 == 0)[0]
+    nxy = box.Nx * box.Ny
     for j in k0:
-        U[0][j] = bvp.zero_mode_solve(-cx[j] / box.eta, H, box.geometry,
-                                      box.slip0, box.slipH)
-        U[1][j] = bvp.zero_mode_solve(-cy[j] / box.eta, H, box.geometry,
-                                      box.slip0, box.slipH)
+        for c, cc in ((0, cx), (1, cy)):
+            U[c][j] = bvp.zero_mode_solve(-cc[j] / box.eta, H, box.geometry,
+                                          box.slip0, box.slipH,
+                                          nxy * box.wall0[c], nxy * box.wallH[c])
     uh = np.stack([U[i].T.reshape(shape) for i in range(3)])
     # vorticity: omega = (1/2) curl u in Fourier-Chebyshev space
     cu = curl(uh[0], uh[1], uh[2], ikx, iky, D)

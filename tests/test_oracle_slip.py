@@ -94,3 +94,46 @@ def test_slip_mobility_symmetric_positive_and_faster():
     U_ns, _ = oracle.Solver(BOX).apply(pos, e, z)
     U_sl, _ = s.apply(pos, e, z)
     assert U_sl[0, 0] > U_ns[0, 0] * 1.01
+
+
+def test_couette_flow_between_moving_walls():
+    """No particles forcing (F = T = 0), walls moving at U0 and UH: the grid
+    velocity is the linear profile (exactly, at the nodes) and a particle
+    away from the walls moves with the fluid at its height (to the kernel's
+    quadrature accuracy); with slip the profile is u(z) = a z + b with
+    b - l0 a = U0 and a H + b + lH a = UH."""
+    for l0, lH in ((0.0, 0.0), (0.8, 1.5)):
+        box = replace(BOX, wall0=(0.3, -0.2), wallH=(1.0, 0.5), slip0=l0,
+                      slipH=lH)
+        s = oracle.Solver(box)
+        pos = np.array([[5.1, 6.2, 3.5], [11.3, 2.4, 2.9], [8.8, 13.1, 4.2]])
+        z = np.zeros((3, 3))
+        f, g = s.spread(s.wrap(pos), z, z)
+        uh, _ = stokes.solve_coefficients(box, stokes.forward_transform(box, f),
+                                          stokes.forward_transform(box, g))
+        u = stokes.inverse_transform(box, uh)
+        for c in (0, 1):
+            U0, UH = box.wall0[c], box.wallH[c]
+            a = (UH - U0) / (box.H + l0 + lH)
+            b = U0 + l0 * a
+            prof = a * s.zc + b
+            np.testing.assert_allclose(u[c], prof[:, None, None] + 0 * u[c],
+                                       atol=1e-12)
+        U, _ = s.apply(pos, z, z)
+        for c in (0, 1):
+            U0, UH = box.wall0[c], box.wallH[c]
+            a = (UH - U0) / (box.H + l0 + lH)
+            np.testing.assert_allclose(U[:, c], a * pos[:, 2] + U0 + l0 * a,
+                                       rtol=2e-3, atol=2e-3)
+        assert np.abs(U[:, 2]).max() < 1e-12
+
+
+def test_bottom_wall_moving():
+    """A bottom wall moving at U0 under an open top drags the whole fluid:
+    u = U0 everywhere (y'' = 0, y(0) = U0, y'(H) = 0)."""
+    box = Box("bw", 16.0, 16.0, 8.0, 24, 24, 24, wall0=(0.7, 0.0))
+    s = oracle.Solver(box)
+    pos = np.array([[5.1, 6.2, 3.5]])
+    z = np.zeros((1, 3))
+    U, _ = s.apply(pos, z, z)
+    assert U[0, 0] == pytest.approx(0.7, rel=2e-3) and abs(U[0, 1]) < 1e-12

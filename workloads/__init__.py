@@ -78,6 +78,8 @@ class Box:
     eta: float = 1.0
     slip0: float = 0.0     # slip lengths of the slit channel's walls at
     slipH: float = 0.0     # z = 0 and z = H (App. A); 0 = no slip
+    wall0: tuple = (0.0, 0.0)   # uniform (x, y) velocity of the wall at z = 0
+    wallH: tuple = (0.0, 0.0)   # and of the slit channel's wall at z = H
 
     @property
     def h(self) -> float:
