@@ -74,6 +74,10 @@ typedef struct {
                           partial slip u - l0 du/dz = 0 at z = 0, u + lH du/dz
                           = 0 at z = H, zero wall velocity): slit channel
                           with Nz <= 32 only; 0 = no slip */
+  double wall0[2];     /* uniform (x, y) velocity of the wall at z = 0 */
+  double wallH[2];     /* ... of the slit channel's wall at z = H (zero for a
+                          bottom wall); nonzero wall velocities need
+                          Nz <= 32 */
 } fcmdp_params;
 
 /*

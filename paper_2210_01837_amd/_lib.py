@@ -34,6 +34,8 @@ class Params(ctypes.Structure):
         ("max_particles", ctypes.c_int64),
         ("slip0", ctypes.c_double),
         ("slipH", ctypes.c_double),
+        ("wall0", ctypes.c_double * 2),
+        ("wallH", ctypes.c_double * 2),
     ]
 
 

@@ -180,6 +180,13 @@ int validate(const fcmdp_params* p) {
   if ((p->slip0 != 0 || p->slipH != 0) &&
       (p->geometry != FCMDP_SLIT_CHANNEL || p->Nz > 32))
     return FCMDP_EINVAL;
+  // uniform wall velocities: finite; a bottom wall has no wall at z = H
+  for (int c = 0; c < 2; ++c) {
+    if (!std::isfinite(p->wall0[c]) || !std::isfinite(p->wallH[c]))
+      return FCMDP_EINVAL;
+    if (p->geometry == FCMDP_BOTTOM_WALL && p->wallH[c] != 0) return FCMDP_EINVAL;
+    if ((p->wall0[c] != 0 || p->wallH[c] != 0) && p->Nz > 32) return FCMDP_EINVAL;
+  }
   const double hx = p->Lx / p->Nx, hy = p->Ly / p->Ny;
   if (std::fabs(hx - hy) > 1e-12 * hx) return FCMDP_EINVAL;
   const double alpha = 0.5 * p->w * hx;
@@ -328,6 +335,10 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
   dp.nch_out = 6;
   dp.slip0 = p->slip0;
   dp.slipH = p->slipH;
+  for (int c = 0; c < 2; ++c) {
+    dp.wall0[c] = p->wall0[c];
+    dp.wallH[c] = p->wallH[c];
+  }
   dp.Lx = p->Lx;
   dp.Ly = p->Ly;
   dp.H = p->H;

@@ -384,7 +384,8 @@ __device__ __forceinline__ Z2 seg_solve6(double a[6], Z2 b, int l) {
 
 // k = 0: y'' = r with y(0) = 0 and y'(H) = 0 (bottom wall) or y(H) = 0.
 __device__ __forceinline__ Vec seg_zero_mode(const Vec& r, double H, int N, int geometry,
-                             int l, double a0 = 0.0, double aH = 0.0) {
+                             int l, double a0 = 0.0, double aH = 0.0,
+                             double g0 = 0.0, double gH = 0.0) {
   const double h2 = 0.25 * H * H;
   Vec y = vzero();
 #pragma unroll
@@ -417,7 +418,7 @@ __device__ __forceinline__ Vec seg_zero_mode(const Vec& r, double H, int N, int 
   sp = red(sp);
   sm = red(sm);
   sn2 = red(sn2);
-  const bool slip = geometry == 1 && (a0 != 0.0 || aH != 0.0);
+  const bool slip = geometry == 1 && (a0 != 0.0 || aH != 0.0 || g0 != 0.0 || gH != 0.0);
   Z2 y0s = zmk(0, 0), y1s = zmk(0, 0);
   if (slip) {                    // Robin conditions, as in ps_zero_mode
     Z2 sdm = zmk(0, 0);
@@ -427,13 +428,14 @@ __device__ __forceinline__ Vec seg_zero_mode(const Vec& r, double H, int N, int 
       sdm = sdm + (((j & 1) ? 1.0 : -1.0) * n * n) * y.v[j];
     }
     sdm = red(sdm);
-    y1s = frcp(2.0 + a0 + aH) * (sm - sp - a0 * sdm - aH * sn2);
-    y0s = -1.0 * sp - aH * sn2 - (1.0 + aH) * y1s;
+    y1s = frcp(2.0 + a0 + aH) * (zmk(gH - g0, 0) + sm - sp - a0 * sdm - aH * sn2);
+    y0s = zmk(gH, 0) - sp - aH * sn2 - (1.0 + aH) * y1s;
   }
   if (l == 0) {
     if (geometry == 0) {
       y.v[1] = -1.0 * sn2;
       y.v[0] = y.v[1] - sm;
+      if (g0 != 0.0) y.v[0] = y.v[0] + zmk(g0, 0);
     } else if (slip) {
       y.v[0] = y0s;
       y.v[1] = y1s;
@@ -765,7 +767,8 @@ __device__ inline void ps_dsums(const Vec& a, int l, Z2& top, Z2& bot) {
 
 // k = 0: y'' = r with y(0) = 0 and y'(H) = 0 (bottom wall) or y(H) = 0.
 __device__ __forceinline__ Vec ps_zero_mode(const Vec& r, double H, int N, int geometry,
-                                            int l, double a0 = 0.0, double aH = 0.0) {
+                                            int l, double a0 = 0.0, double aH = 0.0,
+                                            double g0 = 0.0, double gH = 0.0) {
   const double h2 = 0.25 * H * H;
   const Z2 rm2 = from_down<1>(r.v[kNpl - 1]);
   const Z2 rp2 = from_up<1>(r.v[0]);
@@ -789,11 +792,12 @@ __device__ __forceinline__ Vec ps_zero_mode(const Vec& r, double H, int N, int g
   sp = red(sp);
   sm = red(sm);
   sn2 = red(sn2);
-  const bool slip = geometry == 1 && (a0 != 0.0 || aH != 0.0);
+  // slip lengths or wall velocities: the general Robin rows
+  const bool slip = geometry == 1 && (a0 != 0.0 || aH != 0.0 || g0 != 0.0 || gH != 0.0);
   Z2 y0s = zmk(0, 0), y1s = zmk(0, 0);
   if (slip) {
-    // y(0) - l_0 y'(0) = 0, y(H) + l_H y'(H) = 0 with a = 2 l / H:
-    // y0 - (1 + a0) y1 = -sm + a0 sdm, y0 + (1 + aH) y1 = -sp - aH sn2,
+    // y(0) - l_0 y'(0) = g0, y(H) + l_H y'(H) = gH with a = 2 l / H:
+    // y0 - (1 + a0) y1 = g0 - sm + a0 sdm, y0 + (1 + aH) y1 = gH - sp - aH sn2,
     // sdm = sum_{n >= 2} (-1)^{n+1} n^2 y_n
     Z2 sdm = zmk(0, 0);
 #pragma unroll
@@ -802,13 +806,15 @@ __device__ __forceinline__ Vec ps_zero_mode(const Vec& r, double H, int N, int g
       sdm = sdm + (-sgn * n * n) * y.v[s];
     }
     sdm = red(sdm);
-    y1s = frcp(2.0 + a0 + aH) * (sm - sp - a0 * sdm - aH * sn2);
-    y0s = -1.0 * sp - aH * sn2 - (1.0 + aH) * y1s;
+    y1s = frcp(2.0 + a0 + aH) * (zmk(gH - g0, 0) + sm - sp - a0 * sdm - aH * sn2);
+    y0s = zmk(gH, 0) - sp - aH * sn2 - (1.0 + aH) * y1s;
   }
   if ((l & 3) == 0) {                                // slot 0 holds m = 0 or 1
     const bool odd = l >> 2;
     if (geometry == 0) {
+      // y(0) = g0 (wall velocity), y'(H) = 0
       y.v[0] = odd ? -1.0 * sn2 : -1.0 * sn2 - sm;
+      if (!odd && g0 != 0.0) y.v[0] = y.v[0] + zmk(g0, 0);
     } else if (slip) {
       y.v[0] = odd ? y1s : y0s;
     } else {
@@ -852,6 +858,12 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
   // slit channel slip lengths (App. A) as a = 2 l / H; zero for no slip
   const double a0s = GEOM == 1 ? 2.0 * dp.slip0 / H : 0.0;
   const double aHs = GEOM == 1 ? 2.0 * dp.slipH / H : 0.0;
+  // uniform wall velocities: the k = 0 wall data in the unnormalised xy DFT
+  // (a constant c transforms to c Nx Ny)
+  const double nxy = (double)dp.Nx * (double)dp.Ny;
+  const double g0x = nxy * dp.wall0[0], g0y = nxy * dp.wall0[1];
+  const double gHx = GEOM == 1 ? nxy * dp.wallH[0] : 0.0;
+  const double gHy = GEOM == 1 ? nxy * dp.wallH[1] : 0.0;
   auto body_x = [&]() {
     Vec f = load(0);
     if constexpr (!FO) {
@@ -874,13 +886,13 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     Vec r = body_x();
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
-    if constexpr (SPLIT) U = ps_zero_mode(r, H, N, GEOM, l, a0s, aHs);
-    else U = seg_zero_mode(r, H, N, GEOM, l, a0s, aHs);
+    if constexpr (SPLIT) U = ps_zero_mode(r, H, N, GEOM, l, a0s, aHs, g0x, gHx);
+    else U = seg_zero_mode(r, H, N, GEOM, l, a0s, aHs, g0x, gHx);
     r = body_y();
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
-    if constexpr (SPLIT) V = ps_zero_mode(r, H, N, GEOM, l, a0s, aHs);
-    else V = seg_zero_mode(r, H, N, GEOM, l, a0s, aHs);
+    if constexpr (SPLIT) V = ps_zero_mode(r, H, N, GEOM, l, a0s, aHs, g0y, gHy);
+    else V = seg_zero_mode(r, H, N, GEOM, l, a0s, aHs, g0y, gHy);
   } else {
     const double kappa = 0.5 * k * H;
     Par q[2];

@@ -58,6 +58,7 @@ struct DevParams {
   double Lx, Ly, H, h, alpha, eta;
   double beta_m, beta_d, inv_norm_m, inv_norm_d;
   double slip0, slipH;          // slit channel slip lengths (0 = no slip)
+  double wall0[2], wallH[2];    // uniform wall velocities (x, y)
 };
 
 }  // namespace fcmdp

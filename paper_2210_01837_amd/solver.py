@@ -27,11 +27,14 @@ def _stream(stream):
 
 def make_params(geometry, Lx, Ly, H, Nx, Ny, Nz, w=6, beta_m=1.327 * 6,
                 beta_d=2.216 * 6, eta=1.0, precision="mixed",
-                max_particles=0, slip0=0.0, slipH=0.0) -> L.Params:
+                max_particles=0, slip0=0.0, slipH=0.0, wall0=(0.0, 0.0),
+                wallH=(0.0, 0.0)) -> L.Params:
+    arr = ctypes.c_double * 2
     return L.Params(GEOMETRY[geometry], float(Lx), float(Ly), float(H),
                     int(Nx), int(Ny), int(Nz), int(w), float(beta_m),
                     float(beta_d), float(eta), PRECISION[precision],
-                    int(max_particles), float(slip0), float(slipH))
+                    int(max_particles), float(slip0), float(slipH),
+                    arr(*map(float, wall0)), arr(*map(float, wallH)))
 
 
 def workspace_bytes(n, **kw) -> int:
@@ -48,10 +51,11 @@ class Solver:
 
     def __init__(self, geometry, Lx, Ly, H, Nx, Ny, Nz, w=6, beta_m=1.327 * 6,
                  beta_d=2.216 * 6, eta=1.0, precision="mixed",
-                 max_particles=1 << 20, slip0=0.0, slipH=0.0):
+                 max_particles=1 << 20, slip0=0.0, slipH=0.0, wall0=(0.0, 0.0),
+                 wallH=(0.0, 0.0)):
         self.params = make_params(geometry, Lx, Ly, H, Nx, Ny, Nz, w, beta_m,
                                   beta_d, eta, precision, max_particles, slip0,
-                                  slipH)
+                                  slipH, wall0, wallH)
         self.precision = precision
         self.Nx, self.Ny, self.Nz = int(Nx), int(Ny), int(Nz)
         self._h = ctypes.c_void_p(0)
@@ -64,7 +68,8 @@ class Solver:
         return cls(box.geometry, box.Lx, box.Ly, box.H, box.Nx, box.Ny, box.Nz,
                    box.w, box.beta_m, box.beta_d, box.eta, precision,
                    max_particles, getattr(box, "slip0", 0.0),
-                   getattr(box, "slipH", 0.0))
+                   getattr(box, "slipH", 0.0), getattr(box, "wall0", (0.0, 0.0)),
+                   getattr(box, "wallH", (0.0, 0.0)))
 
     @property
     def dtype(self):

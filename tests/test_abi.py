@@ -52,6 +52,9 @@ def _params(**kw):
     # partial slip: slit channel only, non-negative, Nz <= 32
     dict(slip0=0.5), dict(geometry="sc", slipH=-1.0),
     dict(geometry="sc", Nz=48, slip0=1.0), dict(geometry="sc", slip0=float("inf")),
+    # uniform wall velocities: no top wall for a bottom wall, Nz <= 32
+    dict(wallH=(1.0, 0.0)), dict(Nz=48, wall0=(0.5, 0.0)),
+    dict(geometry="sc", wallH=(float("nan"), 0.0)),
 ])
 def test_invalid_parameters_rejected(L, bad):
     from paper_2210_01837_amd import _lib
@@ -99,10 +102,15 @@ def test_params_struct_matches_the_header():
             continue
         ctype, names = decl.split(None, 1)
         for nm in names.split(","):
-            fields.append((nm.strip(), ctype))
+            m = re.match(r"(\w+)(?:\[(\d+)\])?$", nm.strip())
+            fields.append((m.group(1), ctype, int(m.group(2) or 0)))
     ctypes_of = {"int": ctypes.c_int, "double": ctypes.c_double,
                  "int64_t": ctypes.c_int64}
     got = [(n, t) for n, t in _lib.Params._fields_]
-    assert [n for n, _ in got] == [n for n, _ in fields]
-    for (n, t), (_, c) in zip(got, fields):
-        assert t is ctypes_of[c], n
+    assert [n for n, _ in got] == [n for n, _, _ in fields]
+    for (n, t), (_, c, dim) in zip(got, fields):
+        if dim:
+            assert issubclass(t, ctypes.Array) and t._length_ == dim, n
+            assert t._type_ is ctypes_of[c], n
+        else:
+            assert t is ctypes_of[c], n
