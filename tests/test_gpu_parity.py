@@ -533,3 +533,21 @@ def test_apply_moving_walls(case, precision):
     print(f"  rel err U {eU:.3e} Omega {eO:.3e}", flush=True)
     tol = 1e-5 if precision == "mixed" else 1e-10
     assert eU < tol and eO < tol
+
+
+def test_apply_forces_only_replicated_layer_fp64():
+    """The 663,552-particle forces-only layer on the all-FP64 path: every
+    particle against the oracle's one-replica apply."""
+    g = _golden("m2048")
+    rU = g["U"]
+    wl = workloads.WORKLOADS["m663k"]
+    pos, F, _ = workloads.particles("m663k")
+    print("[forces only layer fp64] m663k", flush=True)
+    s = _solver(wl.box, "fp64", cap=wl.n)
+    U, _ = s.apply(_dev(pos, "fp64"), _dev(F, "fp64"), None, want_omega=False)
+    got = _np(U).reshape(-1, len(rU), 3)
+    e = rel_err(got, np.broadcast_to(rU, got.shape))
+    print(f"  rel err U {e:.3e}", flush=True)
+    assert e < 1e-9
+    assert s.status() == (0, 0)
+    s.close()
