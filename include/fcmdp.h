@@ -137,7 +137,8 @@ const char* fcmdp_strerror(int code);
  *               change.
  * Blocking on the host (a few synchronisations of the stream per iteration);
  * the Krylov basis ((max_iter + 1) * 3n words) is allocated on first use and
- * kept with the solver.  W = 0 gives g = 0 and *iters = 0.
+ * kept with the solver.  W = 0 gives g = 0 and *iters = 0.  Particles outside
+ * the domain make the applies, and so g, NaN (fcmdp_status reports them).
  * Returns EINVAL for bad arguments, ECAPACITY if n > max_particles, ENOMEM,
  * EHIP, or an error of the mobility apply.
  */
