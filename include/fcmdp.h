@@ -83,11 +83,16 @@ typedef struct {
 /*
  * Create a solver: validates p, derives h, alpha, the ES normalisations, the
  * Chebyshev tables and FFT plans, and allocates all device workspace on the
- * current HIP device.  Blocking (host side); ~ (2*6*Nz*Ny*Nx real words +
- * particle buffers) of device memory, see fcmdp_workspace_bytes.
+ * current HIP device, ~ (2*6*Nz*Ny*Nx real words + particle buffers), see
+ * fcmdp_workspace_bytes.  The workspace is allocated and the tables are
+ * uploaded in stream order on hip_stream (NULL = the default stream), and
+ * the call returns once hip_stream has completed them: it waits for that
+ * stream only, never for the whole device, so applies in flight on other
+ * streams keep running.  The solver may then be used on any stream.
  * Returns EINVAL for invalid parameters, ENOMEM/EHIP on allocation failure.
  */
-int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out);
+int fcmdp_create_solver(const fcmdp_params* p, void* hip_stream,
+                        fcmdp_solver** out);
 
 /* Device bytes a solver with parameters p needs for n particles (host only). */
 int fcmdp_workspace_bytes(const fcmdp_params* p, int64_t n, size_t* bytes);
@@ -116,8 +121,11 @@ int fcmdp_apply_mobility(fcmdp_solver* s, int64_t n, const void* pos,
  * with *n_bad (if non-NULL) set to the number of skipped particles. */
 int fcmdp_status(fcmdp_solver* s, int64_t* n_bad);
 
-/* Release all device memory of s (synchronises the device first). */
-void fcmdp_destroy_solver(fcmdp_solver* s);
+/* Release all device memory of s in stream order on hip_stream (NULL = the
+ * default stream); does not block the host or the device.  The caller
+ * orders every apply on s before hip_stream (same stream, or an event wait)
+ * and does not use s afterwards. */
+void fcmdp_destroy_solver(fcmdp_solver* s, void* hip_stream);
 
 const char* fcmdp_strerror(int code);
 
@@ -183,9 +191,12 @@ enum {
   FCMDP_VARIANT_VECTOR_DCT = 6,      /* FP64 Chebyshev transforms in MIXED */
   FCMDP_VARIANT_NO_CODELET = 7,      /* run-time-plan row transforms even
                                         where a fixed-plan kernel exists */
-  FCMDP_VARIANT_NO_PIPELINE = 8      /* one workgroup per y row instead of
+  FCMDP_VARIANT_NO_PIPELINE = 8,     /* one workgroup per y row instead of
                                         the persistent row loop that loads
                                         the next row during a transform */
+  FCMDP_VARIANT_NO_LOWK = 9          /* MIXED slit channel: take the vertical
+                                        force of the kH < 1 columns from the
+                                        FP32 path too (no FP64 route) */
 };
 int fcmdp_set_variant(fcmdp_solver* s, int key, int value);
 

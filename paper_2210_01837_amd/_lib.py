@@ -57,7 +57,7 @@ def lib() -> ctypes.CDLL:
                 "`python -m paper_2210_01837_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
-        L.fcmdp_create_solver.argtypes = [ctypes.POINTER(Params),
+        L.fcmdp_create_solver.argtypes = [ctypes.POINTER(Params), vp,
                                           ctypes.POINTER(vp)]
         L.fcmdp_create_solver.restype = ci
         L.fcmdp_workspace_bytes.argtypes = [ctypes.POINTER(Params), i64,
@@ -71,7 +71,7 @@ def lib() -> ctypes.CDLL:
         L.fcmdp_lanczos_sqrt.restype = ci
         L.fcmdp_status.argtypes = [vp, ctypes.POINTER(i64)]
         L.fcmdp_status.restype = ci
-        L.fcmdp_destroy_solver.argtypes = [vp]
+        L.fcmdp_destroy_solver.argtypes = [vp, vp]
         L.fcmdp_destroy_solver.restype = None
         L.fcmdp_strerror.argtypes = [ci]
         L.fcmdp_strerror.restype = ctypes.c_char_p

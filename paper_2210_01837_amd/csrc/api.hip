@@ -222,7 +222,25 @@ int z_window_slots(int Nz, double H, double alpha) {
 
 struct Sizes {
   size_t grid, spec, keys, vals, hist, cells, pinfo, pw, pf, psi;
+  // exact low-wavenumber vertical force (mixed slit channel), 0 when off
+  size_t psi64, fzlo, lowk_part, lowk_coef, lowk_ex, lowk_ey;
 };
+
+// Half-width ns of the square |nx|, |ny| <= ns of wavenumbers whose vertical
+// force takes the FP64 route (mixed slit channel; 0 = none): every column
+// with kH < 1 (ns = ceil(L / (2 pi H)) for the longer period L), capped so
+// that the square stays clear of the Nyquist modes.
+int lowk_half_width(const fcmdp_params* p) {
+  if (p->precision != FCMDP_MIXED || p->geometry != FCMDP_SLIT_CHANNEL ||
+      p->Nz > 32)
+    return 0;
+  const double L = p->Lx > p->Ly ? p->Lx : p->Ly;
+  int ns = (int)std::ceil(L / (2.0 * kPi * p->H) - 1e-12);
+  const int nmax = (p->Nx < p->Ny ? p->Nx : p->Ny) / 2 - 1;
+  if (ns > nmax) ns = nmax;
+  if (ns > fcmdp::kLowkMaxNs) ns = fcmdp::kLowkMaxNs;
+  return ns < 1 ? 0 : ns;
+}
 
 Sizes sizes_for(const fcmdp_params* p, int64_t cap, int ZW) {
   const size_t T = p->precision == FCMDP_MIXED ? 4 : 8;
@@ -242,42 +260,65 @@ Sizes sizes_for(const fcmdp_params* p, int64_t cap, int ZW) {
   // dense folded z weights [cap][2][Nz], padded for chunked readers that may
   // run past the last node
   s.psi = (c * 2 * (size_t)p->Nz + 64) * T;
+  const int ns = lowk_half_width(p);
+  s.psi64 = s.fzlo = s.lowk_part = s.lowk_coef = s.lowk_ex = s.lowk_ey = 0;
+  if (ns > 0) {
+    const size_t ncols = (size_t)(ns + 1) * (2 * ns + 1);
+    s.psi64 = (c * (size_t)p->Nz + 64) * 8;
+    s.fzlo = (size_t)p->Nz * p->Ny * p->Nx * 4;
+    s.lowk_part = ((size_t)p->Nz * p->Ny * (ns + 1) + ncols * p->Nz) * 16;
+    s.lowk_coef = ncols * p->Nz * 16;
+    s.lowk_ex = (size_t)p->Nx * (ns + 1) * 16;
+    s.lowk_ey = (size_t)p->Ny * 16;
+  }
   (void)ZW;
   return s;
 }
 
-template <typename T>
-void* upload(const std::vector<T>& v, int* err) {
-  void* d = nullptr;
-  if (hipMalloc(&d, sizeof(T) * v.size()) != hipSuccess) {
-    *err = FCMDP_ENOMEM;
-    return nullptr;
+// Device tables are uploaded in stream order on the creation stream; the host
+// copies stay alive (in `keep`) until that stream has been synchronised.
+struct Uploader {
+  hipStream_t st;
+  std::vector<std::vector<unsigned char>> keep;
+  int* err;
+  template <typename T>
+  void* operator()(const std::vector<T>& v) {
+    if (*err != FCMDP_OK) return nullptr;
+    void* d = nullptr;
+    const size_t bytes = sizeof(T) * v.size();
+    if (hipMallocAsync(&d, bytes ? bytes : 16, st) != hipSuccess) {
+      *err = FCMDP_ENOMEM;
+      return nullptr;
+    }
+    keep.emplace_back(reinterpret_cast<const unsigned char*>(v.data()),
+                      reinterpret_cast<const unsigned char*>(v.data()) + bytes);
+    if (bytes && hipMemcpyAsync(d, keep.back().data(), bytes,
+                                hipMemcpyHostToDevice, st) != hipSuccess)
+      *err = FCMDP_EHIP;
+    return d;
   }
-  if (hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) !=
-      hipSuccess)
-    *err = FCMDP_EHIP;
-  return d;
-}
-
-template <typename T>
-void* upload_twiddles(int n, int count, int* err) {
-  std::vector<T> v(2 * (size_t)count);
-  for (int m = 0; m < count; ++m) {
-    v[2 * m] = (T)cospi_frac(2L * m, n);
-    v[2 * m + 1] = (T)(-sinpi_frac(2L * m, n));
+  template <typename T>
+  void* twiddles(int n, int count) {
+    std::vector<T> v(2 * (size_t)count);
+    for (int m = 0; m < count; ++m) {
+      v[2 * m] = (T)cospi_frac(2L * m, n);
+      v[2 * m + 1] = (T)(-sinpi_frac(2L * m, n));
+    }
+    return (*this)(v);
   }
-  return upload(v, err);
-}
+};
 
-void free_all(fcmdp_solver* s) {
+void free_all(fcmdp_solver* s, hipStream_t st) {
   void* ptrs[] = {s->grid, s->spec, s->keyA, s->keyB, s->valA, s->valB,
                   s->hist, s->cell_start, s->pinfo, s->pw, s->pf, s->psi,
                   s->band, s->nbad, s->zc, s->quad, s->dct_f, s->dct_i,
                   s->dct_f32, s->dct_i32,
                   s->dftc, s->dftc_t, s->tw_x, s->tw_y, s->tw_r,
-                  s->lz_basis, s->lz_red};
+                  s->lz_basis, s->lz_red, s->psi64, s->fzlo, s->lowk_part,
+                  s->lowk_coef, s->lowk_ex, s->lowk_ey};
+  // stream-ordered frees: no device-wide synchronisation
   for (void* q : ptrs)
-    if (q) (void)hipFree(q);
+    if (q) (void)hipFreeAsync(q, st);
 }
 
 }  // namespace
@@ -303,12 +344,16 @@ int fcmdp_workspace_bytes(const fcmdp_params* p, int64_t n, size_t* bytes) {
   const double alpha = 0.5 * p->w * (p->Lx / p->Nx);
   const Sizes s = sizes_for(p, n, z_window_slots(p->Nz, p->H, alpha));
   *bytes = s.grid + s.spec + 2 * s.keys + 2 * s.vals + s.hist + s.cells +
-           s.pinfo + s.pw + s.pf + s.psi + (size_t)p->Nz * p->Nz * 16 + 65536;
+           s.pinfo + s.pw + s.pf + s.psi + s.psi64 + s.fzlo + s.lowk_part +
+           s.lowk_coef + s.lowk_ex + s.lowk_ey + (size_t)p->Nz * p->Nz * 16 +
+           65536;
   return FCMDP_OK;
 }
 
-int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
+int fcmdp_create_solver(const fcmdp_params* p, void* hip_stream,
+                        fcmdp_solver** out) {
   if (!out) return FCMDP_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
   *out = nullptr;
   int v = validate(p);
   if (v != FCMDP_OK) return v;
@@ -352,6 +397,9 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
   dp.inv_norm_m = 1.0 / s->norm_m;
   dp.inv_norm_d = 1.0 / s->norm_d;
   dp.ZW = z_window_slots(Nz, p->H, dp.alpha);
+  dp.lowk_ns = -1;
+  dp.lowk_coef = nullptr;
+  s->lowk_ns = lowk_half_width(p);
   s->cap = p->max_particles;
   s->nblk_cap = (int)((s->cap > 0 ? s->cap : 1) + 2047) / 2048;
   {
@@ -383,13 +431,16 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
 
   int err = FCMDP_OK;
   const Sizes z = sizes_for(p, s->cap, dp.ZW);
+  // stream-ordered allocations on the creation stream (no device-wide
+  // synchronisation, so applies in flight on other streams keep running)
   auto alloc = [&](void** ptr, size_t bytes) {
     if (err != FCMDP_OK) return;
-    if (hipMalloc(ptr, bytes ? bytes : 16) != hipSuccess) {
+    if (hipMallocAsync(ptr, bytes ? bytes : 16, st) != hipSuccess) {
       *ptr = nullptr;
       err = FCMDP_ENOMEM;
     }
   };
+  Uploader upload{st, {}, &err};
   alloc(&s->grid, z.grid);
   alloc(&s->spec, z.spec);
   alloc((void**)&s->keyA, z.keys);
@@ -402,6 +453,12 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
   alloc(&s->pw, z.pw);
   alloc(&s->pf, z.pf);
   alloc(&s->psi, z.psi);
+  if (s->lowk_ns > 0) {
+    alloc((void**)&s->psi64, z.psi64);
+    alloc((void**)&s->fzlo, z.fzlo);
+    alloc((void**)&s->lowk_part, z.lowk_part);
+    alloc((void**)&s->lowk_coef, z.lowk_coef);
+  }
   alloc((void**)&s->band, 2 * sizeof(int));
   alloc((void**)&s->nbad, sizeof(unsigned int));
 
@@ -421,22 +478,22 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
       }
     const std::vector<double> w = clenshaw_curtis(Nz);
     const double h2 = dp.h * dp.h;
-    s->zc = (double*)upload(zc, &err);
-    s->dct_f = (double*)upload(Mf, &err);
-    s->dct_i = (double*)upload(Pi, &err);
+    s->zc = (double*)upload(zc);
+    s->dct_f = (double*)upload(Mf);
+    s->dct_i = (double*)upload(Pi);
     if (s->mixed) {
       std::vector<float> mf(Mf.begin(), Mf.end()), pf(Pi.begin(), Pi.end());
-      s->dct_f32 = (float*)upload(mf, &err);
-      s->dct_i32 = (float*)upload(pf, &err);
+      s->dct_f32 = (float*)upload(mf);
+      s->dct_i32 = (float*)upload(pf);
     }
     if (s->mixed) {
       std::vector<float> q(Nz);
       for (int c = 0; c < Nz; ++c) q[c] = (float)(h2 * 0.5 * p->H * w[c]);
-      s->quad = upload(q, &err);
+      s->quad = upload(q);
     } else {
       std::vector<double> q(Nz);
       for (int c = 0; c < Nz; ++c) q[c] = h2 * 0.5 * p->H * w[c];
-      s->quad = upload(q, &err);
+      s->quad = upload(q);
     }
     // small prime DFT constants
     std::vector<double> cs;
@@ -449,32 +506,52 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
         cs.push_back(sinpi_frac(2L * m, P));
       }
     }
-    s->dftc = (double*)upload(cs, &err);
+    s->dftc = (double*)upload(cs);
     if (s->mixed) {
       std::vector<float> c32(cs.begin(), cs.end());
-      s->dftc_t = upload(c32, &err);
+      s->dftc_t = upload(c32);
     } else {
-      s->dftc_t = upload(cs, &err);
+      s->dftc_t = upload(cs);
+    }
+    if (s->lowk_ns > 0) {
+      // e^{-2 pi i nx a / Nx} for nx = 0..ns ([a][nx]) and e^{-2 pi i m / Ny}
+      const int nk = s->lowk_ns + 1;
+      std::vector<double> ex(2 * (size_t)p->Nx * nk), ey(2 * (size_t)p->Ny);
+      for (int a = 0; a < p->Nx; ++a)
+        for (int n = 0; n < nk; ++n) {
+          const long m = ((long)n * a) % p->Nx;
+          ex[2 * ((size_t)a * nk + n)] = cospi_frac(2L * m, p->Nx);
+          ex[2 * ((size_t)a * nk + n) + 1] = -sinpi_frac(2L * m, p->Nx);
+        }
+      for (int m = 0; m < p->Ny; ++m) {
+        ey[2 * (size_t)m] = cospi_frac(2L * m, p->Ny);
+        ey[2 * (size_t)m + 1] = -sinpi_frac(2L * m, p->Ny);
+      }
+      s->lowk_ex = (double2*)upload(ex);
+      s->lowk_ey = (double2*)upload(ey);
     }
     const int M = p->Nx / 2;
     if (s->mixed) {
-      s->tw_x = upload_twiddles<float>(M, M, &err);
-      s->tw_y = upload_twiddles<float>(p->Ny, p->Ny, &err);
-      s->tw_r = upload_twiddles<float>(p->Nx, M + 1, &err);
+      s->tw_x = upload.twiddles<float>(M, M);
+      s->tw_y = upload.twiddles<float>(p->Ny, p->Ny);
+      s->tw_r = upload.twiddles<float>(p->Nx, M + 1);
     } else {
-      s->tw_x = upload_twiddles<double>(M, M, &err);
-      s->tw_y = upload_twiddles<double>(p->Ny, p->Ny, &err);
-      s->tw_r = upload_twiddles<double>(p->Nx, M + 1, &err);
+      s->tw_x = upload.twiddles<double>(M, M);
+      s->tw_y = upload.twiddles<double>(p->Ny, p->Ny);
+      s->tw_r = upload.twiddles<double>(p->Nx, M + 1);
     }
   }
   if (err == FCMDP_OK) {
-    if (fcmdp::launch_set_band(s, Nz, -1, 0) != hipSuccess ||
-        hipMemset(s->nbad, 0, sizeof(unsigned int)) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess)
+    if (fcmdp::launch_set_band(s, Nz, -1, st) != hipSuccess ||
+        fcmdp::launch_fill(s->nbad, sizeof(unsigned int), st) != hipSuccess)
       err = FCMDP_EHIP;
   }
+  // the creation stream only: the uploads are complete (and the host copies
+  // may go) and the buffers are usable from any stream afterwards
+  if (hipStreamSynchronize(st) != hipSuccess && err == FCMDP_OK) err = FCMDP_EHIP;
   if (err != FCMDP_OK) {
-    free_all(s);
+    free_all(s, st);
+    (void)hipStreamSynchronize(st);
     delete s;
     return err;
   }
@@ -482,13 +559,12 @@ int fcmdp_create_solver(const fcmdp_params* p, fcmdp_solver** out) {
   return FCMDP_OK;
 }
 
-void fcmdp_destroy_solver(fcmdp_solver* s) {
+void fcmdp_destroy_solver(fcmdp_solver* s, void* hip_stream) {
   if (!s) return;
   (void)hipSetDevice(s->device);
-  (void)hipDeviceSynchronize();
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
   s->events.clear();
-  free_all(s);
+  free_all(s, (hipStream_t)hip_stream);
   delete s;
 }
 
@@ -544,6 +620,9 @@ int fcmdp_apply_mobility(fcmdp_solver* s, int64_t n, const void* pos,
   // without angular velocities the solve returns the three velocity channels
   s->dp.nch_in = T ? 6 : 3;
   s->dp.nch_out = Omega ? 6 : 3;
+  const bool lowk = fcmdp::lowk_active(s);
+  s->dp.lowk_ns = lowk ? s->lowk_ns : -1;
+  s->dp.lowk_coef = lowk ? s->lowk_coef : nullptr;
   hipEvent_t ev[7] = {};
   const bool prof = s->profiling;
   if (prof) {
@@ -560,6 +639,8 @@ int fcmdp_apply_mobility(fcmdp_solver* s, int64_t n, const void* pos,
   if (fcmdp::launch_spread(s, s->grid, st) != hipSuccess) return FCMDP_EHIP;
   mark(2);
   if (fcmdp::launch_fft_forward(s, s->grid, s->spec, st) != hipSuccess)
+    return FCMDP_EHIP;
+  if (lowk && fcmdp::launch_lowk(s, s->grid, st) != hipSuccess)
     return FCMDP_EHIP;
   mark(3);
   if (fcmdp::launch_columns(s, s->spec, s->spec, st) != hipSuccess)
@@ -634,6 +715,9 @@ int fcmdp_set_variant(fcmdp_solver* s, int key, int value) {
     case FCMDP_VARIANT_NO_PIPELINE:
       s->force_no_pipeline = on;
       return FCMDP_OK;
+    case FCMDP_VARIANT_NO_LOWK:
+      s->no_lowk = on;
+      return FCMDP_OK;
     default:
       return FCMDP_EINVAL;
   }
@@ -679,9 +763,13 @@ static bool band_ok(const fcmdp_solver* s, int lo, int hi) {
 }
 
 // the stage entry points work on the full six-channel layouts
+// (and without the exact low-wavenumber vertical force, which needs the
+// spread's FP64 residual plane)
 static void all_channels(fcmdp_solver* s) {
   s->dp.nch_in = 6;
   s->dp.nch_out = 6;
+  s->dp.lowk_ns = -1;
+  s->dp.lowk_coef = nullptr;
 }
 
 int fcmdp_stage_spread(fcmdp_solver* s, int64_t n, const void* pos,
@@ -720,6 +808,10 @@ int fcmdp_stage_solve(fcmdp_solver* s, const void* spectrum_in,
     return FCMDP_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
   all_channels(s);
+  // the mixed slit channel's kH < 1 columns transform f_z and the
+  // correction's node functions in FP64 (from the FP32 input spectrum: the
+  // spread's FP64 route is not part of this stage)
+  if (fcmdp::lowk_active(s)) s->dp.lowk_ns = s->lowk_ns;
   hipStream_t st = (hipStream_t)hip_stream;
   if (fcmdp::launch_set_band(s, c_lo, c_hi, st) != hipSuccess) return FCMDP_EHIP;
   return fcmdp::launch_columns(s, spectrum_in, spectrum_out, st) == hipSuccess

@@ -26,7 +26,16 @@ struct ColParams {
   DevParams dp;
   double scale;       // 1 / (Nx Ny)
   double kxs, kys;    // 2 pi / Lx, 2 pi / Ly
+  const double* dctf; // forward Chebyshev transform [c][n] in FP64
 };
+
+// Column (kxi, nyi) of the exact low-wavenumber square |nx|, |ny| <= ns
+// (index into lowk_coef), or -1.
+__device__ inline int lowk_col(const DevParams& dp, int kxi, int nyi) {
+  const int ns = dp.lowk_ns;
+  if (ns < 0 || kxi > ns || nyi > ns || nyi < -ns) return -1;
+  return kxi * (2 * ns + 1) + nyi + ns;
+}
 
 // 6x6 real Gaussian elimination with partial pivoting, complex RHS.
 __device__ inline void solve6(double A[6][6], Z2 b[6]) {

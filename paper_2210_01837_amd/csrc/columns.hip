@@ -133,7 +133,7 @@ __device__ void dct_real(const double* v, const double* __restrict__ Mf,
 template <typename T, int NZ>
 __global__ void __launch_bounds__(64)
 k_columns(ColParams cp, const int* __restrict__ band,
-          const cplx_t<T>* __restrict__ in, cplx_t<T>* __restrict__ out,
+          const cplx_t<T>* in, cplx_t<T>* out,
           const double* __restrict__ zc, const double* __restrict__ Mf,
           const double* __restrict__ Pi) {
   const DevParams& dp = cp.dp;
@@ -318,6 +318,7 @@ hipError_t launch_columns(const fcmdp_solver* s, const void* spec_in,
   cp.scale = 1.0 / ((double)s->dp.Nx * (double)s->dp.Ny);
   cp.kxs = 2.0 * M_PI / s->dp.Lx;
   cp.kys = 2.0 * M_PI / s->dp.Ly;
+  cp.dctf = s->dct_f;
   const int K = s->dp.Nkx * s->dp.Ny;
   dim3 g((K + 63) / 64);
   const bool small = s->dp.Nz <= 32;

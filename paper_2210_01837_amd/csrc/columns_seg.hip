@@ -1048,7 +1048,7 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
 template <typename T, int GEOM>
 __global__ void __launch_bounds__(256)
 k_columns_seg(ColParams cp, const int* __restrict__ band,
-              const cplx_t<T>* __restrict__ in, cplx_t<T>* __restrict__ out,
+              const cplx_t<T>* in, cplx_t<T>* out,
               const double* __restrict__ zc, const double* __restrict__ Mf,
               const double* __restrict__ Pi) {
   using C = cplx_t<T>;
@@ -1076,6 +1076,10 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
   const double H = dp.H, eta = dp.eta, s2H = 2.0 / H;
 
   Vec U = vzero(), V = vzero(), W = vzero(), DU, DV;
+  // exact low-wavenumber vertical force (mixed slit channel): f_z's
+  // coefficients come from the FP64 route, only the torque part of the third
+  // combination is transformed here
+  const int lcol = nyq ? -1 : lowk_col(dp, kxi, nyi);
   if (!nyq) {
     // Chebyshev transform of f + (1/2)(ik_y g_z, -ik_x g_z, ik_x g_y - ik_y g_x)
     // and of g_x, g_y (their z-derivatives enter the curl below)
@@ -1095,7 +1099,8 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
       Z2 comb[5];
       comb[0] = val[0] + imul(0.5 * ky, val[5]);
       comb[1] = val[1] - imul(0.5 * kx, val[5]);
-      comb[2] = val[2] + imul(0.5 * kx, val[4]) - imul(0.5 * ky, val[3]);
+      comb[2] = (lcol >= 0 && dp.lowk_coef ? zmk(0, 0) : val[2]) +
+                imul(0.5 * kx, val[4]) - imul(0.5 * ky, val[3]);
       comb[3] = val[3];
       comb[4] = val[4];
       const double* row = Mf + ca * N + 4 * l;
@@ -1104,6 +1109,16 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
         const double m = (4 * l + j < N) ? row[j] : 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) A[v].v[j] = A[v].v[j] + m * comb[v];
+      }
+    }
+    if (lcol >= 0 && dp.lowk_coef) {
+#pragma unroll
+      for (int j = 0; j < kNpl; ++j) {
+        const int n = 4 * l + j;
+        if (n < N) {
+          const double2 e = dp.lowk_coef[(size_t)lcol * N + n];
+          A[2].v[j] = A[2].v[j] + zmk(e.x, e.y);
+        }
       }
     }
     auto basis = [&](int which, double out[kNpl]) {
@@ -1223,7 +1238,7 @@ __device__ __forceinline__ void col_index(int kx0, int ky0, int col, int Ny,
 template <int GEOM, bool FO>
 __global__ void __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_columns_mfma(ColParams cp, const int* __restrict__ band,
-               const float2* __restrict__ in, float2* __restrict__ out,
+               const float2* in, float2* out,
                const double* __restrict__ zc, const float* __restrict__ Mf32,
                const float* __restrict__ Pi32) {
   using Lay = MfmaLayout<GEOM, FO>;
@@ -1283,6 +1298,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     const int c = it / (kMCols / 2), col = 2 * (it % (kMCols / 2));  // band-relative row
     const int idx = idx0 + col;
     float kxv[2], kyv[2];
+    bool lkv[2];   // column of the exact low-wavenumber square (f_z via FP64)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       int kxi, kyi;
@@ -1290,6 +1306,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
       kxv[h] = kxs * (float)kxi;
       const int nyi = kyi <= dp.Ny / 2 ? kyi : kyi - dp.Ny;
       kyv[h] = kys * (float)nyi;
+      lkv[h] = lowk_col(dp, kxi, nyi) >= 0;
     }
     if (c < P && idx < K) {
       // without torques the dipole channels are zero and not read
@@ -1308,10 +1325,12 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
           w[ch] = h == 0 ? make_float2(v[ch].x, v[ch].y) : make_float2(v[ch].z, v[ch].w);
         const float kx = kxv[h], ky = kyv[h];
         float* xr = XC + c * kMV + (col + h) * VR;
+        // in the low-wavenumber square f_z is added after the transform
+        const float2 fz = lkv[h] ? make_float2(0.f, 0.f) : w[2];
         if constexpr (FO) {
           xr[0] = w[0].x; xr[1] = w[0].y;
           xr[2] = w[1].x; xr[3] = w[1].y;
-          xr[4] = w[2].x; xr[5] = w[2].y;
+          xr[4] = fz.x; xr[5] = fz.y;
           continue;
         }
         // f~x = Fx + (1/2) i ky Gz ; f~y = Fy - (1/2) i kx Gz ;
@@ -1320,8 +1339,8 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
         xr[1] = w[0].y + 0.5f * ky * w[5].x;
         xr[2] = w[1].x + 0.5f * kx * w[5].y;
         xr[3] = w[1].y - 0.5f * kx * w[5].x;
-        xr[4] = w[2].x - 0.5f * kx * w[4].y + 0.5f * ky * w[3].y;
-        xr[5] = w[2].y + 0.5f * kx * w[4].x - 0.5f * ky * w[3].x;
+        xr[4] = fz.x - 0.5f * kx * w[4].y + 0.5f * ky * w[3].y;
+        xr[5] = fz.y + 0.5f * kx * w[4].x - 0.5f * ky * w[3].x;
         xr[6] = w[3].x; xr[7] = w[3].y;
         xr[8] = w[4].x; xr[9] = w[4].y;
       }
@@ -1415,6 +1434,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
     float* cbase = XC + m0 * kMV + cl * VR;
     float* bbase = XC + m0 * kMV + kSpec + cl * NB;
     Vec U = vzero(), V = vzero(), W = vzero();
+    const int lcol = nyq ? -1 : lowk_col(dp, kxi, nyi);
     if (!nyq) {
       auto load = [&](int v) {
         Vec a;
@@ -1423,9 +1443,51 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
           float* cr = cbase + 2 * j * kMV + 2 * v;
           a.v[j] = zmk((double)cr[0], (double)cr[1]);
         }
+        // low-wavenumber square: f_z's coefficients in FP64, from the FP64
+        // route of the apply, or (stage entry point, no such route) from an
+        // FP64 transform of the input's f_z band values
+        if (v == 2 && lcol >= 0) {
+          if (dp.lowk_coef) {
+#pragma unroll
+            for (int j = 0; j < kNpl; ++j) {
+              const int m = m0 + 2 * j;
+              if (m < N) {
+                const double2 e = dp.lowk_coef[(size_t)lcol * N + m];
+                a.v[j] = a.v[j] + zmk(e.x, e.y);
+              }
+            }
+          } else {
+            for (int c = 0; c < P; ++c) {
+              const float2 t = in[(2 * N + lo + c) * PS + idx];
+              const Z2 fz = zmk((double)t.x, (double)t.y);
+#pragma unroll
+              for (int j = 0; j < kNpl; ++j) {
+                const int m = m0 + 2 * j;
+                if (m < N) a.v[j] = a.v[j] + cp.dctf[(lo + c) * N + m] * fz;
+              }
+            }
+          }
+        }
         return a;
       };
       auto basis = [&](int which, double o[kNpl]) {
+        if (lcol >= 0) {
+          // low-wavenumber square: node functions and transform in FP64
+          // (their combination cancels strongly as kH -> 0)
+#pragma unroll
+          for (int j = 0; j < kNpl; ++j) o[j] = 0.0;
+          for (int c = 0; c < N; ++c) {
+            const double z = zc[c];
+            const double e = which < 2 ? exp(-k * z) : exp(k * (z - dp.H));
+            const double f = (which & 1) ? z * e : e;
+#pragma unroll
+            for (int j = 0; j < kNpl; ++j) {
+              const int m = m0 + 2 * j;
+              if (m < N) o[j] = fma(cp.dctf[c * N + m], f, o[j]);
+            }
+          }
+          return;
+        }
 #pragma unroll
         for (int j = 0; j < kNpl; ++j) o[j] = (double)bbase[2 * j * kMV + which];
       };
@@ -1561,6 +1623,7 @@ hipError_t launch_columns_seg(const fcmdp_solver* s, const void* spec_in,
   cp.scale = 1.0 / ((double)s->dp.Nx * (double)s->dp.Ny);
   cp.kxs = 2.0 * M_PI / s->dp.Lx;
   cp.kys = 2.0 * M_PI / s->dp.Ly;
+  cp.dctf = s->dct_f;
   if (s->dp.geometry == 0)
     launch_seg_geom<0>(s, cp, spec_in, spec_out, st);
   else

@@ -9,6 +9,14 @@
 //     pf      T       [cap][8]                F (3), pad, torque (3), pad
 //     psi     T       [cap][2][Nz]            folded z weights, M then D,
 //                                             zero outside the z window
+//   exact low-wavenumber vertical force (mixed slit channel only):
+//     psi64   double  [cap][Nz]               folded M z weights in FP64
+//     fzlo    float   [Nz][Ny][Nx]            f_z - (float)f_z of the FP64
+//                                             accumulated vertical force
+//     lowk_part double2 [Nz][G][ns+1][2ns+1]  DFT of f_z over x (nx = 0..ns)
+//                                             and over the 64-row group g of
+//                                             y (ny = -ns..ns)
+//     lowk_coef double2 [(ns+1)(2ns+1)][Nz]   its Chebyshev coefficients
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -59,7 +67,17 @@ struct DevParams {
   double beta_m, beta_d, inv_norm_m, inv_norm_d;
   double slip0, slipH;          // slit channel slip lengths (0 = no slip)
   double wall0[2], wallH[2];    // uniform wall velocities (x, y)
+  // exact low-wavenumber vertical force: columns with |nx|, |ny| <= lowk_ns
+  // take the FP64 Chebyshev coefficients of f_z from lowk_coef and FP64
+  // correction node functions; -1 = off for this launch
+  int lowk_ns;
+  const double2* lowk_coef;
 };
+
+// rows of y per workgroup of the low-wavenumber x transform
+constexpr int kLowkRows = 64;
+// largest low-wavenumber square half-width
+constexpr int kLowkMaxNs = 48;
 
 }  // namespace fcmdp
 
@@ -87,6 +105,15 @@ struct fcmdp_solver {
   void* pf = nullptr;
   void* psi = nullptr;
   int* band = nullptr;          // [2]: first and last z-node touched
+  // exact low-wavenumber vertical force (layouts above); lowk_ns = 0: off
+  int lowk_ns = 0;
+  bool no_lowk = false;         // variant switch (tests, measurement)
+  double* psi64 = nullptr;
+  float* fzlo = nullptr;
+  double2* lowk_part = nullptr;
+  double2* lowk_coef = nullptr;
+  double2* lowk_ex = nullptr;   // e^{-2 pi i nx a / Nx}, [Nx][ns+1]
+  double2* lowk_ey = nullptr;   // e^{-2 pi i m / Ny}, [Ny]
   unsigned int* nbad = nullptr;
 
   // tables (device)
@@ -152,6 +179,11 @@ hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t st);
 hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st);
 hipError_t launch_interp(const fcmdp_solver* s, int n, const void* grid,
                          void* U, void* Omega, hipStream_t st);
+// lowk.hip: exact FP64 Chebyshev coefficients of the vertical force density
+// at the low wavenumbers (from the spread's f_z and fzlo planes)
+hipError_t launch_lowk(const fcmdp_solver* s, const void* grid, hipStream_t st);
+// whether the apply's launches use the exact low-wavenumber vertical force
+bool lowk_active(const fcmdp_solver* s);
 // fft.hip
 hipError_t launch_fft_forward(const fcmdp_solver* s, const void* grid,
                               void* spec, hipStream_t st);

@@ -146,16 +146,17 @@ static int lanczos_impl(fcmdp_solver* s, int64_t n, const void* pos,
   const size_t m = 3 * (size_t)n;
   const size_t stride = (m + 63) & ~(size_t)63;
   const size_t need = (size_t)(max_iter + 1) * stride * sizeof(T);
+  // stream-ordered (like the rest of the solver's workspace)
   if (need > s->lz_bytes) {
-    if (s->lz_basis) (void)hipFree(s->lz_basis);
+    if (s->lz_basis) (void)hipFreeAsync(s->lz_basis, st);
     s->lz_basis = nullptr;
     s->lz_bytes = 0;
-    if (hipMalloc(&s->lz_basis, need) != hipSuccess) return FCMDP_ENOMEM;
+    if (hipMallocAsync(&s->lz_basis, need, st) != hipSuccess) return FCMDP_ENOMEM;
     s->lz_bytes = need;
   }
   if (!s->lz_red &&
-      hipMalloc((void**)&s->lz_red, sizeof(double) * (kLzMax + 1) * (kLzBlocks + 1)) !=
-          hipSuccess)
+      hipMallocAsync((void**)&s->lz_red,
+                     sizeof(double) * (kLzMax + 1) * (kLzBlocks + 1), st) != hipSuccess)
     return FCMDP_ENOMEM;
   T* V = (T*)s->lz_basis;
   double* part = s->lz_red;

@@ -316,19 +316,23 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
           const int* __restrict__ perm, const Tin* __restrict__ pos,
           const Tin* __restrict__ F, const Tin* __restrict__ Tq,
           const double* __restrict__ zc, int4* __restrict__ pinfo,
-          T* __restrict__ pw, T* __restrict__ pf, T* __restrict__ psi) {
+          T* __restrict__ pw, T* __restrict__ pf, T* __restrict__ psi,
+          double* __restrict__ psi64) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int Nz = dp.Nz;
   T* w = pw + (size_t)i * 32;
   T* f = pf + (size_t)i * 8;
   T* ps = psi + (size_t)i * 2 * Nz;
+  double* ps64 = psi64 ? psi64 + (size_t)i * Nz : nullptr;
   if (skeys[i] >= (uint32_t)dp.ncells) {
     // outside the domain: zero records (never read by the grid kernels)
     for (int e = 0; e < 32; e += 4) store4(w + e, T(0), T(0), T(0), T(0));
     store4(f, T(0), T(0), T(0), T(0));
     store4(f + 4, T(0), T(0), T(0), T(0));
     for (int e = 0; e < 2 * Nz; ++e) ps[e] = T(0);
+    if (ps64)
+      for (int e = 0; e < Nz; ++e) ps64[e] = 0.0;
     return;
   }
   const int j = perm[i];
@@ -394,6 +398,21 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
   } else {
     for (int c = 0; c < Nz; ++c) zw(c, ps[c], ps[Nz + c]);
   }
+  // the monopole z weights once more in FP64 (the exact low-wavenumber
+  // vertical force of the mixed slit channel)
+  if (ps64) {
+    for (int c = 0; c < Nz; ++c) {
+      double pm = 0.0;
+      if (c >= cA && c <= cB) {
+        const double zcv = zc[c];
+        pm = es_eval<double>(zcv - z, dp.alpha, dp.beta_m, dp.inv_norm_m) -
+             es_eval<double>(zcv + z, dp.alpha, dp.beta_m, dp.inv_norm_m);
+        if (dp.geometry == 1)
+          pm -= es_eval<double>(zcv - zim_top, dp.alpha, dp.beta_m, dp.inv_norm_m);
+      }
+      ps64[c] = pm;
+    }
+  }
 }
 
 template <typename Tin, typename T>
@@ -402,7 +421,8 @@ static void records_impl(const fcmdp_solver* s, int n, const void* pos,
   hipLaunchKernelGGL((k_records<Tin, T>), dim3((n + 255) / 256), dim3(256), 0,
                      st, s->dp, n, s->keyA, s->valA, (const Tin*)pos,
                      (const Tin*)F, (const Tin*)Tq, s->zc, s->pinfo,
-                     (T*)s->pw, (T*)s->pf, (T*)s->psi);
+                     (T*)s->pw, (T*)s->pf, (T*)s->psi,
+                     s->dp.lowk_ns >= 0 ? s->psi64 : nullptr);
 }
 
 hipError_t launch_records(const fcmdp_solver* s, int n, const void* pos,

@@ -145,12 +145,14 @@ template <int ZC> struct SpreadRec {
 
 // One z-chunk of K planes (K <= ZC) over the staged particles; NCH = 3
 // spreads the forces only (no torques), NCH = 6 forces and torques.
-template <typename T, int ZC, int K, int NCH>
-__device__ __forceinline__ void spread_chunk(const T* __restrict__ recw, int total,
-                                             int c0, int a, int b, bool inside,
-                                             const DevParams& dp, const int4& inf,
-                                             T F0, T F1, T F2, T G0, T G1, T G2,
-                                             T (&acc)[ZC][NCH]) {
+template <typename T, int ZC, int K, int NCH, bool FZ>
+__device__ __forceinline__ void spread_chunk(const T* __restrict__ recw,
+                                             const double* __restrict__ rec64w,
+                                             int total, int c0, int a, int b,
+                                             bool inside, const DevParams& dp,
+                                             const int4& inf, T F0, T F1, T F2,
+                                             T G0, T G1, T G2, T (&acc)[ZC][NCH],
+                                             double (&acc64)[ZC]) {
   using Rec = SpreadRec<ZC>;
   for (int v = 0; v < total; ++v) {
     const int iz = rdlane_i(inf.z, v), iw = rdlane_i(inf.w, v);
@@ -168,10 +170,22 @@ __device__ __forceinline__ void spread_chunk(const T* __restrict__ recw, int tot
       const T* r = recw + v * Rec::kLen;
       const T wm = r[dx] * r[7 + dy];
       const T f0 = f0v * wm, f1 = f1v * wm, f2 = f2v * wm;
+      if constexpr (FZ) {
+        // vertical force in FP64 with the FP64 z weights
+        const double f2d = (double)f2v * ((double)r[dx] * (double)r[7 + dy]);
+        const double* r64 = rec64w + v * ZC;
 #pragma unroll
-      for (int s = 0; s < K; ++s) {
-        const T pm = r[Rec::kPM + s];
-        acc[s][0] += f0 * pm; acc[s][1] += f1 * pm; acc[s][2] += f2 * pm;
+        for (int s = 0; s < K; ++s) {
+          const T pm = r[Rec::kPM + s];
+          acc[s][0] += f0 * pm; acc[s][1] += f1 * pm;
+          acc64[s] = fma(f2d, r64[s], acc64[s]);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+          const T pm = r[Rec::kPM + s];
+          acc[s][0] += f0 * pm; acc[s][1] += f1 * pm; acc[s][2] += f2 * pm;
+        }
       }
       if constexpr (NCH == 6) {
         const T wd = r[14 + dx] * r[21 + dy];
@@ -186,15 +200,20 @@ __device__ __forceinline__ void spread_chunk(const T* __restrict__ recw, int tot
   }
 }
 
-template <typename T, int ZC, int NCH>
+// FZ (mixed slit channel): the vertical force f_z is accumulated in FP64
+// with the FP64 z weights psi64 and stored as the FP32 grid value plus its
+// residual in fzlo (the exact low-wavenumber route of lowk.hip).
+template <typename T, int ZC, int NCH, bool FZ>
 __global__ void __launch_bounds__(256)
 k_spread_wave(DevParams dp, const int* __restrict__ band,
               const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
               const T* __restrict__ pw, const T* __restrict__ pf,
-              const T* __restrict__ psi, T* __restrict__ grid) {
+              const T* __restrict__ psi, const double* __restrict__ psi64,
+              T* __restrict__ grid, float* __restrict__ fzlo) {
   using Rec = SpreadRec<ZC>;
   constexpr int kS = SpreadStage<T>::n;
   __shared__ T rec[4][kS][Rec::kLen];       // staged particle records per wavefront
+  __shared__ double rec64[FZ ? 4 : 1][FZ ? kS : 1][ZC];   // their FP64 z weights
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gx = (dp.Nx + 4 * kPW - 1) / (4 * kPW);
@@ -243,17 +262,25 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
       if (c >= zmin && c <= zmax) continue;
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) grid[ch * chstride + c * plane + col] = T(0);
+      if constexpr (FZ) fzlo[c * plane + col] = 0.f;
     }
   };
-  auto store_chunk = [&](int c0, int zmax, T (&acc)[ZC][NCH]) {
+  auto store_chunk = [&](int c0, int zmax, T (&acc)[ZC][NCH], double (&acc64)[ZC]) {
     if (!inside) return;
 #pragma unroll
     for (int s = 0; s < ZC; ++s) {
       const int c = c0 + s;
       if (c <= zmax) {
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-          grid[ch * chstride + c * plane + col] = acc[s][ch];
+        for (int ch = 0; ch < NCH; ++ch) {
+          if (FZ && ch == 2) {
+            const float h = (float)acc64[s];
+            grid[ch * chstride + c * plane + col] = h;
+            fzlo[c * plane + col] = (float)(acc64[s] - (double)h);
+          } else {
+            grid[ch * chstride + c * plane + col] = acc[s][ch];
+          }
+        }
       }
     }
   };
@@ -309,6 +336,7 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
           if (s < zc) {
             mine[Rec::kPM + s] = ps[c0 + s];
             if constexpr (NCH == 6) mine[Rec::kPD + s] = ps[Nz + c0 + s];
+            if constexpr (FZ) rec64[wv][lane][s] = psi64[(size_t)p * Nz + c0 + s];
           }
         }
       }
@@ -317,15 +345,19 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       T acc[ZC][NCH];
+      double acc64[ZC];
 #pragma unroll
-      for (int s = 0; s < ZC; ++s)
+      for (int s = 0; s < ZC; ++s) {
+        acc64[s] = 0.0;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) acc[s][ch] = T(0);
+      }
 #define FCMDP_CHUNK(K)                                                         \
   case K:                                                                      \
     if constexpr (K <= ZC)                                                     \
-      spread_chunk<T, ZC, K, NCH>(recw, total, c0, a, b, inside, dp, inf, F0,  \
-                                  F1, F2, G0, G1, G2, acc);                    \
+      spread_chunk<T, ZC, K, NCH, FZ>(recw, &rec64[FZ ? wv : 0][0][0], total, \
+                                      c0, a, b, inside, dp, inf, F0, F1, F2,   \
+                                      G0, G1, G2, acc, acc64);                 \
     break;
       switch (zc) {
         FCMDP_CHUNK(1) FCMDP_CHUNK(2) FCMDP_CHUNK(3) FCMDP_CHUNK(4) FCMDP_CHUNK(5)
@@ -334,7 +366,7 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
         default: break;
       }
 #undef FCMDP_CHUNK
-      store_chunk(c0, min(zmax, c0 + zc - 1), acc);
+      store_chunk(c0, min(zmax, c0 + zc - 1), acc, acc64);
       __builtin_amdgcn_wave_barrier();
     }
     return;
@@ -353,10 +385,13 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
   zero_outside(zmin, zmax);
   for (int c0 = zmin; c0 <= zmax; c0 += ZC) {
     T acc[ZC][NCH];
+    double acc64[ZC];
 #pragma unroll
-    for (int s = 0; s < ZC; ++s)
+    for (int s = 0; s < ZC; ++s) {
+      acc64[s] = 0.0;
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) acc[s][ch] = T(0);
+    }
     for (int r = 0; r < 2 * nrows; ++r) {
       const int p0 = rdlane_i(sstart, r), p1 = p0 + rdlane_i(scnt, r);
       for (int q = p0; q < p1; ++q) {
@@ -382,9 +417,15 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
           const T wd = w[16 + dx] * w[24 + dy];
           const T f0 = F0 * wm, f1 = F1 * wm, f2 = F2 * wm;
           const T t0 = G0 * wd, t1 = G1 * wd, t2 = G2 * wd;
+          double f2d = 0.0;
+          if constexpr (FZ) f2d = (double)F2 * ((double)w[dx] * (double)w[8 + dy]);
 #pragma unroll
           for (int s = 0; s < ZC; ++s) {
-            acc[s][0] += f0 * pm[s]; acc[s][1] += f1 * pm[s]; acc[s][2] += f2 * pm[s];
+            acc[s][0] += f0 * pm[s]; acc[s][1] += f1 * pm[s];
+            if constexpr (FZ)
+              acc64[s] = fma(f2d, psi64[(size_t)q * Nz + c0 + s], acc64[s]);
+            else
+              acc[s][2] += f2 * pm[s];
             if constexpr (NCH == 6) {
               acc[s][3] += t0 * pd[s]; acc[s][4] += t1 * pd[s]; acc[s][5] += t2 * pd[s];
             }
@@ -392,23 +433,28 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
         }
       }
     }
-    store_chunk(c0, zmax, acc);
+    store_chunk(c0, zmax, acc, acc64);
   }
 }
 
-template <typename T, int NCH>
+template <typename T, int NCH, bool FZ = false>
 static void spread_wave(const fcmdp_solver* s, void* grid, hipStream_t st) {
   dim3 g(((s->dp.Nx + 4 * kPW - 1) / (4 * kPW)) * ((s->dp.Ny + kPW - 1) / kPW));
-  hipLaunchKernelGGL((k_spread_wave<T, kSpreadZC, NCH>), g, dim3(256), 0, st,
+  hipLaunchKernelGGL((k_spread_wave<T, kSpreadZC, NCH, FZ>), g, dim3(256), 0, st,
                      s->dp, s->band, s->cell_start, s->pinfo, (const T*)s->pw,
-                     (const T*)s->pf, (const T*)s->psi, (T*)grid);
+                     (const T*)s->pf, (const T*)s->psi,
+                     FZ ? (const double*)s->psi64 : nullptr, (T*)grid,
+                     FZ ? s->fzlo : nullptr);
 }
 
 hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st) {
   if (!s->force_simple_spread) {
     // without torques only the three force channels are spread
     const bool dip = s->dp.nch_in == 6;
-    if (s->mixed)
+    if (s->mixed && s->dp.lowk_ns >= 0)
+      dip ? spread_wave<float, 6, true>(s, grid, st)
+          : spread_wave<float, 3, true>(s, grid, st);
+    else if (s->mixed)
       dip ? spread_wave<float, 6>(s, grid, st) : spread_wave<float, 3>(s, grid, st);
     else
       dip ? spread_wave<double, 6>(s, grid, st) : spread_wave<double, 3>(s, grid, st);

@@ -3,9 +3,13 @@
 A request is one mobility apply (F, T) -> (U, Omega) for its own particle set
 and periodic box (geometry, L, grid).  The server
 
-* keeps a pool of solvers keyed by (geometry, box, grid, particle capacity):
-  a solver owns the grid, spectrum, sort buffers and FFT plans of one shape,
-  so a repeated shape reuses them (the plan cache);
+* keeps a pool of solvers keyed by every parameter of the discrete operator
+  (geometry, box, grid, kernel width and shapes, viscosity, slip lengths and
+  wall velocities), the precision and the particle capacity: a solver owns
+  the grid, spectrum, sort buffers and FFT plans of one shape, so a repeated
+  shape reuses them (the plan cache); solvers are created and released in
+  stream order on the pool's own stream, so neither stalls the requests in
+  flight;
 * admits requests first-in first-out while the device workspace of everything
   in flight plus the next request fits the HBM budget (fcmdp_workspace_bytes,
   the admission-control query of the C ABI), and evicts idle solvers, least
@@ -34,15 +38,45 @@ def capacity_bucket(n: int, minimum: int = 1024) -> int:
     return c
 
 
+# every parameter of the discrete operator (fcmdp_params), so that requests
+# differing in any of them never share a solver
+_KEY_FIELDS = ("geometry", "Lx", "Ly", "H", "Nx", "Ny", "Nz", "w", "beta_m",
+               "beta_d", "eta", "slip0", "slipH", "wall0", "wallH")
+_DEFAULTS = {"w": 6, "beta_m": 1.327 * 6, "beta_d": 2.216 * 6, "eta": 1.0,
+             "slip0": 0.0, "slipH": 0.0, "wall0": (0.0, 0.0),
+             "wallH": (0.0, 0.0)}
+
+
+def _field(box, name):
+    v = getattr(box, name, _DEFAULTS.get(name))
+    if name == "geometry":
+        return v
+    if name in ("Nx", "Ny", "Nz", "w"):
+        return int(v)
+    if name in ("wall0", "wallH"):
+        return tuple(float(x) for x in v)
+    return float(v)
+
+
 def solver_key(box, n: int, precision: str):
-    return (box.geometry, float(box.Lx), float(box.Ly), float(box.H),
-            int(box.Nx), int(box.Ny), int(box.Nz), precision, capacity_bucket(n))
+    """(box and operator parameters, precision, particle capacity)."""
+    return tuple(_field(box, f) for f in _KEY_FIELDS) + (precision,
+                                                          capacity_bucket(n))
+
+
+def key_params(key) -> dict:
+    """Keyword arguments of Solver / workspace_bytes for a solver key."""
+    kw = dict(zip(_KEY_FIELDS, key[:len(_KEY_FIELDS)]))
+    kw["precision"] = key[len(_KEY_FIELDS)]
+    return kw
+
+
+def key_capacity(key) -> int:
+    return key[len(_KEY_FIELDS) + 1]
 
 
 def key_bytes(key) -> int:
-    geometry, Lx, Ly, H, Nx, Ny, Nz, precision, cap = key
-    return workspace_bytes(cap, geometry=geometry, Lx=Lx, Ly=Ly, H=H, Nx=Nx,
-                           Ny=Ny, Nz=Nz, precision=precision)
+    return workspace_bytes(key_capacity(key), **key_params(key))
 
 
 class AdmissionQueue:
@@ -87,12 +121,28 @@ class SolverPool:
         self._idle = collections.OrderedDict()     # id -> (key, solver, bytes)
         self._factory = factory or self._make
         self._sizer = sizer
+        self._setup = None          # stream of solver creation and release
 
-    @staticmethod
-    def _make(key):
-        geometry, Lx, Ly, H, Nx, Ny, Nz, precision, cap = key
-        return Solver(geometry, Lx, Ly, H, Nx, Ny, Nz, precision=precision,
-                      max_particles=cap)
+    def _stream(self):
+        if self._setup is None:
+            import torch
+            self._setup = torch.cuda.Stream()
+        return self._setup
+
+    def _make(self, key):
+        # stream-ordered allocation on the pool's own stream: creating a
+        # solver waits for that stream only, not for requests in flight
+        return Solver(max_particles=key_capacity(key), stream=self._stream(),
+                      **key_params(key))
+
+    def _release(self, s):
+        # stream-ordered release after the solver's last apply; no
+        # synchronisation of the device or the host
+        if hasattr(s, "close"):
+            if self._factory == self._make:
+                s.close(stream=self._stream())
+            else:
+                s.close()
 
     def get(self, key):
         """An idle solver for key (reused or newly created) and its bytes."""
@@ -103,8 +153,7 @@ class SolverPool:
         need = self._sizer(key)
         while self.allocated + need > self.budget and self._idle:
             _, (k, s, b) = self._idle.popitem(last=False)
-            if hasattr(s, "close"):
-                s.close()
+            self._release(s)
             self.allocated -= b
             self.evicted += 1
         if self.allocated + need > self.budget:
@@ -119,8 +168,7 @@ class SolverPool:
 
     def close(self):
         for _, s, b in self._idle.values():
-            if hasattr(s, "close"):
-                s.close()
+            self._release(s)
             self.allocated -= b
         self._idle.clear()
 

@@ -52,34 +52,54 @@ class Solver:
     def __init__(self, geometry, Lx, Ly, H, Nx, Ny, Nz, w=6, beta_m=1.327 * 6,
                  beta_d=2.216 * 6, eta=1.0, precision="mixed",
                  max_particles=1 << 20, slip0=0.0, slipH=0.0, wall0=(0.0, 0.0),
-                 wallH=(0.0, 0.0)):
+                 wallH=(0.0, 0.0), stream=None):
         self.params = make_params(geometry, Lx, Ly, H, Nx, Ny, Nz, w, beta_m,
                                   beta_d, eta, precision, max_particles, slip0,
                                   slipH, wall0, wallH)
         self.precision = precision
         self.Nx, self.Ny, self.Nz = int(Nx), int(Ny), int(Nz)
         self._h = ctypes.c_void_p(0)
+        self._last = None          # event after the last call's device work
         L.check(L.lib().fcmdp_create_solver(ctypes.byref(self.params),
+                                            _stream(stream),
                                             ctypes.byref(self._h)),
                 "fcmdp_create_solver")
 
     @classmethod
-    def from_box(cls, box, precision="mixed", max_particles=1 << 20):
+    def from_box(cls, box, precision="mixed", max_particles=1 << 20,
+                 stream=None):
         return cls(box.geometry, box.Lx, box.Ly, box.H, box.Nx, box.Ny, box.Nz,
                    box.w, box.beta_m, box.beta_d, box.eta, precision,
                    max_particles, getattr(box, "slip0", 0.0),
                    getattr(box, "slipH", 0.0), getattr(box, "wall0", (0.0, 0.0)),
-                   getattr(box, "wallH", (0.0, 0.0)))
+                   getattr(box, "wallH", (0.0, 0.0)), stream=stream)
+
+    def _mark(self, stream):
+        """Record the end of this call's device work (close() orders the
+        release of the workspace after it)."""
+        import torch
+        st = torch.cuda.current_stream() if stream is None else stream
+        ev = torch.cuda.Event()
+        ev.record(st)
+        self._last = ev
 
     @property
     def dtype(self):
         import torch
         return torch.float64 if self.precision == "fp64" else torch.float32
 
-    def close(self):
+    def close(self, stream=None):
+        """Release the device workspace in stream order on `stream` (default:
+        the current stream), after the last call's work; no device-wide
+        synchronisation."""
         if self._h and self._h.value:
-            L.lib().fcmdp_destroy_solver(self._h)
+            import torch
+            st = torch.cuda.current_stream() if stream is None else stream
+            if self._last is not None:
+                st.wait_event(self._last)
+            L.lib().fcmdp_destroy_solver(self._h, ctypes.c_void_p(st.cuda_stream))
             self._h = ctypes.c_void_p(0)
+            self._last = None
 
     def __del__(self):
         try:
@@ -116,6 +136,7 @@ class Solver:
         L.check(L.lib().fcmdp_apply_mobility(
             self._h, n, _ptr(pos), _ptr(F), _ptr(T), _ptr(U), _ptr(Omega),
             _stream(stream)), "fcmdp_apply_mobility")
+        self._mark(stream)
         return U, Omega
 
     def lanczos_sqrt(self, pos, W, max_iter=32, tol=1e-3, g=None, stream=None):
@@ -133,6 +154,7 @@ class Solver:
             self._h, n, _ptr(pos), _ptr(W), _ptr(g), int(max_iter), float(tol),
             ctypes.byref(it), ctypes.byref(ch), _stream(stream)),
             "fcmdp_lanczos_sqrt")
+        self._mark(stream)
         return g, it.value, ch.value
 
     STAGES = ("particles", "spread", "fft_forward", "columns", "fft_inverse",
@@ -140,7 +162,8 @@ class Solver:
 
     VARIANTS = {"generic_fft": 0, "fft_rows_x": 1, "fft_rows_y": 2,
                 "simple_spread": 3, "simple_interp": 4, "generic_columns": 5,
-                "vector_dct": 6, "no_codelet": 7, "no_pipeline": 8}
+                "vector_dct": 6, "no_codelet": 7, "no_pipeline": 8,
+                "no_lowk": 9}
 
     def set_variant(self, name, value):
         """Select an alternative kernel (see fcmdp_set_variant)."""
@@ -184,36 +207,53 @@ class Solver:
                                            _ptr(F), _ptr(T), _ptr(grid),
                                            _stream(stream)),
                 "fcmdp_stage_spread")
+        self._mark(stream)
         return grid
 
     def _cplx(self):
         import torch
         return torch.complex128 if self.precision == "fp64" else torch.complex64
 
+    @staticmethod
+    def _check_buffer(t, shape, dtype, what):
+        """Grids and spectra cross the ABI as raw pointers in the layouts of
+        fcmdp.h: they must be contiguous device tensors of that shape."""
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{what} must be a contiguous device tensor of dtype "
+                            f"{dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{what} must have shape {tuple(shape)}")
+
     def stage_fft_forward(self, grid, c_lo, c_hi, stream=None):
         import torch
+        self._check_buffer(grid, self.grid_shape(), self.dtype, "grid")
         spec = torch.zeros(self.spectrum_shape(), dtype=self._cplx(),
                            device=grid.device)
         L.check(L.lib().fcmdp_stage_fft_forward(self._h, _ptr(grid), _ptr(spec),
                                                 c_lo, c_hi, _stream(stream)),
                 "fcmdp_stage_fft_forward")
+        self._mark(stream)
         return spec
 
     def stage_solve(self, spec, c_lo, c_hi, stream=None):
         import torch
+        self._check_buffer(spec, self.spectrum_shape(), self._cplx(), "spectrum")
         out = torch.zeros_like(spec)
         L.check(L.lib().fcmdp_stage_solve(self._h, _ptr(spec), _ptr(out), c_lo,
                                           c_hi, _stream(stream)),
                 "fcmdp_stage_solve")
+        self._mark(stream)
         return out
 
     def stage_fft_inverse(self, spec, c_lo, c_hi, stream=None):
         import torch
+        self._check_buffer(spec, self.spectrum_shape(), self._cplx(), "spectrum")
         grid = torch.zeros(self.grid_shape(), dtype=self.dtype,
                            device=spec.device)
         L.check(L.lib().fcmdp_stage_fft_inverse(self._h, _ptr(spec), _ptr(grid),
                                                 c_lo, c_hi, _stream(stream)),
                 "fcmdp_stage_fft_inverse")
+        self._mark(stream)
         return grid
 
     def stage_interp(self, pos, grid, stream=None):
@@ -222,7 +262,9 @@ class Solver:
         U = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
         Om = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
         self._check_particles(pos)
+        self._check_buffer(grid, self.grid_shape(), self.dtype, "grid")
         L.check(L.lib().fcmdp_stage_interp(self._h, n, _ptr(pos), _ptr(grid),
                                            _ptr(U), _ptr(Om), _stream(stream)),
                 "fcmdp_stage_interp")
+        self._mark(stream)
         return U, Om

@@ -19,6 +19,18 @@ def rel_err(a, b):
     return float(np.linalg.norm((a - b).ravel()) / den)
 
 
+def particle_err(a, b):
+    """Largest error of one particle's vector, relative to the RMS particle
+    vector of the reference: max_j |a_j - b_j| / sqrt(mean_j |b_j|^2) for
+    (N, 3) arrays (a single particle far off shows here even when the
+    norm-wise error is small)."""
+    a = np.asarray(a, dtype=np.float64).reshape(-1, 3)
+    b = np.asarray(b, dtype=np.float64).reshape(-1, 3)
+    rms = np.sqrt(np.mean(np.sum(b * b, axis=1)))
+    d = np.sqrt(np.max(np.sum((a - b) ** 2, axis=1)))
+    return float(d / rms) if rms > 0 else float(d)
+
+
 def max_rel(a, b):
     den = np.max(np.abs(b))
     return float(np.max(np.abs(np.asarray(a) - b)) / (den if den > 0 else 1.0))

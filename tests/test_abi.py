@@ -60,7 +60,7 @@ def test_invalid_parameters_rejected(L, bad):
     from paper_2210_01837_amd import _lib
     p = _params(**bad)
     h = ctypes.c_void_p(0)
-    assert L.fcmdp_create_solver(ctypes.byref(p), ctypes.byref(h)) == _lib.EINVAL
+    assert L.fcmdp_create_solver(ctypes.byref(p), None, ctypes.byref(h)) == _lib.EINVAL
     assert not h.value
     nb = ctypes.c_size_t(0)
     assert L.fcmdp_workspace_bytes(ctypes.byref(p), 10, ctypes.byref(nb)) == _lib.EINVAL
@@ -81,10 +81,10 @@ def test_workspace_bytes_scales(L):
 
 def test_null_arguments(L):
     from paper_2210_01837_amd import _lib
-    assert L.fcmdp_create_solver(None, None) == _lib.EINVAL
+    assert L.fcmdp_create_solver(None, None, None) == _lib.EINVAL
     assert L.fcmdp_apply_mobility(None, 1, None, None, None, None, None, None) == _lib.EINVAL
     assert L.fcmdp_status(None, None) == _lib.EINVAL
-    L.fcmdp_destroy_solver(None)
+    L.fcmdp_destroy_solver(None, None)
 
 
 def test_params_struct_matches_the_header():

@@ -14,7 +14,7 @@ from workloads import Box
 
 from _parity import (band_of, max_rel, oracle_apply, oracle_fft_forward,
                      oracle_fft_inverse, oracle_interp, oracle_solve,
-                     oracle_spread, rel_err)
+                     oracle_spread, particle_err, rel_err)
 from oracle import fcm
 
 pytestmark = pytest.mark.gpu
@@ -322,16 +322,13 @@ def test_stage_fft_mixed_rows_per_workgroup(rows):
 # runs only the oracle).  The GPU runs the whole apply in the launch
 # configuration the benchmark times and is compared on that sample.
 #
-# Mixed-precision tolerance: the grids are FP32, so every grid value carries a
-# relative rounding error ~6e-8 of its own size.  In these monolayers every
-# particle sediments with F_z ~ -1, so the grid is dominated by the uniform
-# layer while the velocities come from its fluctuations, about sqrt(N) times
-# smaller: the relative error grows like 6e-8 * sqrt(N) * c.  Above one wall
-# (bw1m) c is small (measured 1.8e-6); between two walls the flow driven by
-# the fluctuations is screened beyond the gap H and c is large (measured
-# 7.8e-5 at N = 1M, insensitive to the FFT, DCT, spread and interpolation
-# variants; the FP64 path gives 3.6e-8).  Hence 2e-4 for sc1m.
-GOLDEN = {"bw131k": 1e-5, "bw1m": 1e-5, "sc1m": 2e-4}
+# Mixed-precision tolerance: 1e-5 norm-wise in U and Omega.  The slit
+# channel reaches it through the FP64 route for the vertical force of its
+# kH < 1 columns (without it the FP32 rounding of f_z, amplified by the
+# small-kH response of the slit channel, gives ~8e-5 at N = 1M).  The largest
+# single-particle error (relative to the RMS particle velocity) must stay
+# within ten times that.
+GOLDEN = {"bw131k": 1e-5, "bw1m": 1e-5, "sc1m": 1e-5}
 
 
 def _golden(name):
@@ -356,8 +353,12 @@ def test_apply_mixed_full_size_golden(name):
     idx = g["index"]
     assert np.array_equal(idx, workloads.subsample(name))
     Ug, Og = _np(U)[idx], _np(Om)[idx]
-    assert rel_err(Ug, g["U"]) < GOLDEN[name]
-    assert rel_err(Og, g["Omega"]) < GOLDEN[name]
+    eU, eO = rel_err(Ug, g["U"]), rel_err(Og, g["Omega"])
+    pU, pO = particle_err(Ug, g["U"]), particle_err(Og, g["Omega"])
+    print(f"  rel err U {eU:.2e} Omega {eO:.2e}; max particle {pU:.2e} "
+          f"{pO:.2e}", flush=True)
+    assert eU < GOLDEN[name] and eO < GOLDEN[name]
+    assert pU < 10 * GOLDEN[name] and pO < 10 * GOLDEN[name]
     s.close()
 
 
@@ -374,8 +375,11 @@ def test_apply_fp64_full_size_golden(name):
     assert s.status() == (0, 0)
     idx = g["index"]
     Ug, Og = _np(U)[idx], _np(Om)[idx]
-    assert rel_err(Ug, g["U"]) < 1e-6
-    assert rel_err(Og, g["Omega"]) < 1e-6
+    eU, eO = rel_err(Ug, g["U"]), rel_err(Og, g["Omega"])
+    pU, pO = particle_err(Ug, g["U"]), particle_err(Og, g["Omega"])
+    print(f"  rel err U {eU:.2e} Omega {eO:.2e}; max particle {pU:.2e} "
+          f"{pO:.2e}", flush=True)
+    assert eU < 1e-6 and eO < 1e-6
     s.close()
 
 

@@ -85,3 +85,22 @@ def test_pool_evicts_only_what_it_needs():
     pool.get("l")
     assert b.closed and not a.closed and pool.evicted == 1
     assert pool.allocated == 70
+
+
+def test_keys_separate_every_operator_parameter():
+    from dataclasses import replace
+    from paper_2210_01837_amd.serving import key_capacity, key_params
+    base = workloads.Box("sc", 64.0, 64.0, 10.0, 96, 96, 32)
+    variants = [replace(base, w=4, beta_m=7.48, beta_d=7.48),
+                replace(base, beta_m=7.0), replace(base, beta_d=12.0),
+                replace(base, eta=2.0), replace(base, slip0=0.5),
+                replace(base, slipH=0.5), replace(base, wall0=(0.1, 0.0)),
+                replace(base, wallH=(0.0, 0.1)), replace(base, geometry="bw"),
+                replace(base, Nz=24)]
+    keys = {solver_key(b, 1000, "mixed") for b in [base] + variants}
+    assert len(keys) == len(variants) + 1
+    assert solver_key(base, 1000, "mixed") != solver_key(base, 1000, "fp64")
+    k = solver_key(variants[0], 3000, "mixed")
+    kw = key_params(k)
+    assert kw["w"] == 4 and kw["beta_m"] == 7.48 and kw["precision"] == "mixed"
+    assert key_capacity(k) == 4096

@@ -195,16 +195,19 @@ def subsample(name: str, fraction: float = 0.01) -> np.ndarray:
     return np.sort(rng.choice(wl.n, size=k, replace=False))
 
 
-def sub_box(name: str, factor: int):
-    """A box 1/factor as wide in x and y with the same particle density.
+def sub_box(name: str, factor: int, factor_y: int | None = None):
+    """A box 1/factor as wide in x (1/factor_y in y, default the same) with
+    the same particle density, grid spacing and height.
 
-    Used to time the CPU oracle on a bounded sample of a large workload; the
-    sample is the first particles of a fresh seeded draw with the same recipe.
+    Used to time the CPU oracle on a bounded sample of a large workload and
+    for small-box error studies; the sample is a fresh seeded draw with the
+    same recipe.
     """
     wl = WORKLOADS[name]
     b = wl.box
-    box = replace(b, Lx=b.Lx / factor, Ly=b.Ly / factor, Nx=b.Nx // factor,
-                  Ny=b.Ny // factor)
+    fy = factor if factor_y is None else factor_y
+    box = replace(b, Lx=b.Lx / factor, Ly=b.Ly / fy, Nx=b.Nx // factor,
+                  Ny=b.Ny // fy)
     box = replace(box, Lx=box.Nx * b.h, Ly=box.Ny * b.h)
     n = int(round(wl.n * (box.Lx * box.Ly) / (b.Lx * b.Ly)))
     rng = np.random.default_rng(SEED_BASE + 200 + wl.index)
@@ -261,6 +264,13 @@ def serving_requests(count: int = 512, nmin: int = 1024, nmax: int = 262144,
         reqs.append(Request(r, n, Box(geom, Lb, Lb, H, nx, nx, Nz),
                             SEED_BASE + 1000 + r))
     return reqs
+
+
+def largest_request(geometry: str, count: int = 512) -> Request:
+    """The request of the given geometry with the most particles in the
+    serving stream of `count` requests."""
+    reqs = [r for r in serving_requests(count) if r.box.geometry == geometry]
+    return max(reqs, key=lambda r: r.n)
 
 
 def request_particles(req: Request):
