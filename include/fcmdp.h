@@ -154,6 +154,25 @@ int fcmdp_lanczos_sqrt(fcmdp_solver* s, int64_t n, const void* pos,
                        const void* W, void* g, int max_iter, double tol,
                        int* iters, double* rel_change, void* hip_stream);
 
+/*
+ * fcmdp_lanczos_sqrt without any device allocation, for callers that cannot
+ * allocate (tight serving loops, code that must not call hipMalloc): the
+ * Krylov basis and the reduction partial sums live in a fixed 64 MiB device
+ * array of the library, one per GPU, held until the process ends, instead of
+ * the solver's on-demand buffers.  Same arguments, results and errors as
+ * fcmdp_lanczos_sqrt (its arithmetic, bit for bit), plus ECAPACITY when the
+ * basis ((max_iter + 1) * 3n words, rounded up to 64 per vector) and the
+ * partial sums (~260 KiB) do not fit in that array: about 64 iterations at
+ * n = 86,000 or 8 iterations at n = 660,000 in MIXED mode, half of that in
+ * FP64.  Every call on a GPU shares that GPU's array: calls that overlap on
+ * one GPU (different streams or host threads) race and must be serialised
+ * by the caller.  The mobility applies inside use the solver's own
+ * workspace, allocated when the solver was created.
+ */
+int fcmdp_lanczos_sqrt_noalloc(fcmdp_solver* s, int64_t n, const void* pos,
+                               const void* W, void* g, int max_iter, double tol,
+                               int* iters, double* rel_change, void* hip_stream);
+
 /* Derived quantities of a solver (host only): out[0] = h, out[1] = alpha,
  * out[2] = ES normalisation integral of the monopole kernel, out[3] = of the
  * dipole kernel (the integral in eq. es-scalar). */

@@ -69,6 +69,8 @@ def lib() -> ctypes.CDLL:
                                          ctypes.c_double, ctypes.POINTER(ci),
                                          ctypes.POINTER(ctypes.c_double), vp]
         L.fcmdp_lanczos_sqrt.restype = ci
+        L.fcmdp_lanczos_sqrt_noalloc.argtypes = L.fcmdp_lanczos_sqrt.argtypes
+        L.fcmdp_lanczos_sqrt_noalloc.restype = ci
         L.fcmdp_status.argtypes = [vp, ctypes.POINTER(i64)]
         L.fcmdp_status.restype = ci
         L.fcmdp_destroy_solver.argtypes = [vp, vp]

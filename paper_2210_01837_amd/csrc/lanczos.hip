@@ -16,6 +16,7 @@
 #include "fcmdp_internal.h"
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 namespace fcmdp {
@@ -139,28 +140,26 @@ static void sqrt_e1(int k, const double* alpha, const double* beta, double nrm,
   for (int i = 0; i < k; ++i) y[i] *= nrm;
 }
 
+// Krylov basis and reduction scratch of one call
+constexpr size_t kLzRedBytes = sizeof(double) * (kLzMax + 1) * (kLzBlocks + 1);
+inline size_t lz_stride(int64_t n) { return (3 * (size_t)n + 63) & ~(size_t)63; }
 template <typename T>
-static int lanczos_impl(fcmdp_solver* s, int64_t n, const void* pos,
+size_t lz_basis_bytes(int64_t n, int max_iter) {
+  return (size_t)(max_iter + 1) * lz_stride(n) * sizeof(T);
+}
+
+// The Lanczos steps on caller-provided scratch: V the basis
+// ((max_iter + 1) x stride words), red the reduction partial sums.  Every
+// word of both is written before it is read.
+template <typename T>
+static int lanczos_core(fcmdp_solver* s, int64_t n, const void* pos,
                         const void* W, void* g, int max_iter, double tol,
-                        int* iters_out, double* change_out, hipStream_t st) {
+                        int* iters_out, double* change_out, hipStream_t st,
+                        T* V, double* red) {
   const size_t m = 3 * (size_t)n;
-  const size_t stride = (m + 63) & ~(size_t)63;
-  const size_t need = (size_t)(max_iter + 1) * stride * sizeof(T);
-  // stream-ordered (like the rest of the solver's workspace)
-  if (need > s->lz_bytes) {
-    if (s->lz_basis) (void)hipFreeAsync(s->lz_basis, st);
-    s->lz_basis = nullptr;
-    s->lz_bytes = 0;
-    if (hipMallocAsync(&s->lz_basis, need, st) != hipSuccess) return FCMDP_ENOMEM;
-    s->lz_bytes = need;
-  }
-  if (!s->lz_red &&
-      hipMallocAsync((void**)&s->lz_red,
-                     sizeof(double) * (kLzMax + 1) * (kLzBlocks + 1), st) != hipSuccess)
-    return FCMDP_ENOMEM;
-  T* V = (T*)s->lz_basis;
-  double* part = s->lz_red;
-  double* sums = s->lz_red + (size_t)(kLzMax + 1) * kLzBlocks;
+  const size_t stride = lz_stride(n);
+  double* part = red;
+  double* sums = red + (size_t)(kLzMax + 1) * kLzBlocks;
   const int gb = (int)std::min<size_t>(kLzBlocks, (m + kLzThreads - 1) / kLzThreads);
 
   // <basis_v, w> for v < nvec, returned on the host
@@ -242,7 +241,94 @@ static int lanczos_impl(fcmdp_solver* s, int64_t n, const void* pos,
   return FCMDP_OK;
 }
 
+template <typename T>
+static int lanczos_impl(fcmdp_solver* s, int64_t n, const void* pos,
+                        const void* W, void* g, int max_iter, double tol,
+                        int* iters_out, double* change_out, hipStream_t st) {
+  const size_t need = lz_basis_bytes<T>(n, max_iter);
+  // stream-ordered (like the rest of the solver's workspace)
+  if (need > s->lz_bytes) {
+    if (s->lz_basis) (void)hipFreeAsync(s->lz_basis, st);
+    s->lz_basis = nullptr;
+    s->lz_bytes = 0;
+    if (hipMallocAsync(&s->lz_basis, need, st) != hipSuccess) return FCMDP_ENOMEM;
+    s->lz_bytes = need;
+  }
+  if (!s->lz_red && hipMallocAsync((void**)&s->lz_red, kLzRedBytes, st) != hipSuccess)
+    return FCMDP_ENOMEM;
+  return lanczos_core<T>(s, n, pos, W, g, max_iter, tol, iters_out, change_out,
+                         st, (T*)s->lz_basis, s->lz_red);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the Krylov basis and the reduction partial sums
+// live in one file-scope device array per GPU (kept until the process ends).
+// Its host-side name is not a device address; the address each device gives
+// it is looked up once per device (hipGetSymbolAddress, with that device
+// current) and only that pointer is handed to kernels.
+constexpr size_t kLzScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kLzScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices] = {};
+
+// this device's address of `scratch` (the device must be current), or null
+static void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+      return nullptr;
+    g_scratch[device] = p;
+  }
+  return g_scratch[device];
+}
+
+template <typename T>
+static int lanczos_noalloc_impl(fcmdp_solver* s, int64_t n, const void* pos,
+                                const void* W, void* g, int max_iter, double tol,
+                                int* iters_out, double* change_out,
+                                hipStream_t st) {
+  unsigned char* base = (unsigned char*)scratch_ptr(s->device);
+  if (!base) return FCMDP_EHIP;
+  // partial sums first (256-byte aligned), then the basis
+  const size_t red_bytes = (kLzRedBytes + 255) & ~(size_t)255;
+  return lanczos_core<T>(s, n, pos, W, g, max_iter, tol, iters_out, change_out,
+                         st, (T*)(base + red_bytes), (double*)base);
+}
+
+static bool lanczos_noalloc_fits(const fcmdp_solver* s, int64_t n, int max_iter) {
+  const size_t red_bytes = (kLzRedBytes + 255) & ~(size_t)255;
+  const size_t basis = s->mixed ? lz_basis_bytes<float>(n, max_iter)
+                                : lz_basis_bytes<double>(n, max_iter);
+  return red_bytes + basis <= kLzScratchBytes;
+}
+
 }  // namespace fcmdp
+
+extern "C" int fcmdp_lanczos_sqrt_noalloc(fcmdp_solver* s, int64_t n,
+                                          const void* pos, const void* W,
+                                          void* g, int max_iter, double tol,
+                                          int* iters, double* rel_change,
+                                          void* hip_stream) {
+  if (!s || n < 0 || max_iter < 1 || max_iter > fcmdp::kLzMax || !(tol >= 0))
+    return FCMDP_EINVAL;
+  if (n > s->cap) return FCMDP_ECAPACITY;
+  if (n > 0 && (!pos || !W || !g)) return FCMDP_EINVAL;
+  if (!fcmdp::lanczos_noalloc_fits(s, n, max_iter)) return FCMDP_ECAPACITY;
+  if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  if (iters) *iters = 0;
+  if (rel_change) *rel_change = 0.0;
+  if (n == 0) return FCMDP_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  return s->mixed
+             ? fcmdp::lanczos_noalloc_impl<float>(s, n, pos, W, g, max_iter, tol,
+                                                  iters, rel_change, st)
+             : fcmdp::lanczos_noalloc_impl<double>(s, n, pos, W, g, max_iter, tol,
+                                                   iters, rel_change, st);
+}
 
 extern "C" int fcmdp_lanczos_sqrt(fcmdp_solver* s, int64_t n, const void* pos,
                                   const void* W, void* g, int max_iter,
