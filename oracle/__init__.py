@@ -19,6 +19,10 @@ linear time" (arXiv 2210.01837), written from the paper:
   interpolation (eqs. getpartvel, getpartvort) and the whole apply.
 * ``lanczos`` -- Brownian displacements M^{1/2} W by the Lanczos process
   (Sec. 5.2) on top of the forces-only apply.
+* ``torque_deriv`` -- the second torque route of Sec. 3.4 (last paragraph
+  and its footnotes): torques spread, and angular velocities interpolated,
+  through the truncated derivative of the dipole ES kernel instead of a
+  spectral curl.
 
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the GPU library and never calls
@@ -30,5 +34,5 @@ mobility values against the paper's figures are "parity unpinned" because the
 figures' data are not part of the paper's text.
 """
 from .kernel import ESKernel, es_normalization, phi  # noqa: F401
-from . import cheb, bvp, stokes, fcm, lanczos  # noqa: F401
+from . import cheb, bvp, stokes, fcm, lanczos, torque_deriv  # noqa: F401
 from .fcm import Solver, apply_mobility  # noqa: F401
