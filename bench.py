@@ -29,24 +29,31 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def stage_bytes(box, n, band, complex_bytes=8, real_bytes=4, torques=True):
+def stage_bytes(box, n, band, complex_bytes=8, real_bytes=4, torques=True,
+                lowk=False, deriv=False):
     """Algorithmic HBM bytes of one launch of each stage (mixed precision).
 
     P = number of band planes; the real grid holds 6 channels (forces and
     torques in, velocities and angular velocities out), 3 in the
-    forces-only apply.
+    forces-only apply and with torques through the kernel derivative
+    (deriv: torques enter the spread, Omega the interpolation, through the
+    three force / velocity channels).  lowk: the mixed slit channel's FP64 route for the
+    vertical force of its kH < 1 columns (the spread also writes the FP32
+    residual plane of f_z, which the direct x transform reads back with f_z
+    itself; its small y and Chebyshev stages are negligible).
     """
     P = band[1] - band[0] + 1
     nxy = box.Nx * box.Ny
     nk = (box.Nx // 2 + 1) * box.Ny
-    nch = 6 if torques else 3
+    nch = 6 if torques and not deriv else 3
     grid = nch * P * nxy * real_bytes
     spec = nch * P * nk * complex_bytes
     particles_in = n * (36 if torques else 24)   # pos, F (, T) (float32)
     particles_out = n * (24 if torques else 12)  # U (, Omega)
+    lo_plane = P * nxy * 4 if lowk else 0
     return {
-        "spread": particles_in + grid,
-        "fft_forward": grid + spec + 2 * spec,    # x-pass r+w, y-pass r+w
+        "spread": particles_in + grid + lo_plane,
+        "fft_forward": grid + spec + 2 * spec + 2 * lo_plane,
         "columns": 2 * spec,
         "fft_inverse": 2 * spec + spec + grid,
         "interp": grid + n * 12 + particles_out,
@@ -161,28 +168,140 @@ def forces_only_summary(steps=10, warmup=2):
 
 
 def cpu_baseline(name, factor=4):
-    """Time the oracle on a 1/factor x 1/factor sub-box of the workload."""
+    """Time the oracle on a 1/factor x 1/factor sub-box of the workload, with
+    every host core available to NumPy's thread pools (BLAS / OpenMP).  The
+    oracle is not parallelised beyond that: NumPy's FFT and its per-particle
+    loops run on one thread, so `cores` reports the threads it actually kept
+    busy (process CPU time over wall time)."""
     import numpy as np  # noqa: F401
-    from threadpoolctl import threadpool_limits
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import workloads
     from oracle import fcm
     box, pos, F, T = workloads.sub_box(name, factor)
-    with threadpool_limits(1):
+    avail = len(os.sched_getaffinity(0))
+    with threadpool_limits(avail):
+        pools = {p.get("internal_api", "?"): p.get("num_threads")
+                 for p in threadpool_info()}
+        c0 = time.process_time()
         t0 = time.perf_counter()
         fcm.Solver(box).apply(pos, F, T)
         dt = time.perf_counter() - t0
+        busy = (time.process_time() - c0) / dt
     return {
         "value": len(pos) / dt,
         "unit": "particle-applies/s",
-        "cores": 1,
+        "cores": round(busy, 2),
         "kind": "oracle",
-        "sample": (f"one oracle apply (float64 NumPy, 1 thread) of a "
+        "sample": (f"one oracle apply (float64 NumPy) of a "
                    f"{box.Nx}x{box.Ny}x{box.Nz} sub-box with {len(pos)} "
                    f"particles at the same density and grid spacing as "
                    f"{name}; {dt:.1f} s"),
-        "host_cores_available": len(os.sched_getaffinity(0)),
+        "host_cores_available": avail,
+        "thread_pools": pools,
     }
+
+
+def slit_channel_summary(steps=10, warmup=2):
+    """The slit channel at N = 1M (mixed): per-apply time and stages with the
+    FP64 route for the vertical force of the kH < 1 columns (the default)
+    and without it, and the accuracy of both against the stored oracle
+    sample."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2210_01837_amd import Solver
+    name = "sc1m"
+    wl = workloads.WORKLOADS[name]
+    pos, F, T = workloads.particles(name)
+    P, Fd, Td = (torch.tensor(a, dtype=torch.float32, device="cuda")
+                 for a in (pos, F, T))
+    U = torch.empty_like(P)
+    Om = torch.empty_like(P)
+    s = Solver.from_box(wl.box, precision="mixed", max_particles=wl.n)
+    gold = os.path.join(ROOT, "tests", "golden", f"{name}_oracle_sample.npz")
+    g = np.load(gold) if os.path.exists(gold) else None
+    out = {"workload": name, "N": wl.n}
+    for label, off in (("fp64_route", 0), ("fp32_only", 1)):
+        s.set_variant("no_lowk", off)
+        for _ in range(warmup):
+            s.apply(P, Fd, Td, U=U, Omega=Om)
+        torch.cuda.synchronize()
+        s.stage_times()
+        s.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.apply(P, Fd, Td, U=U, Omega=Om)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        s.set_profiling(False)
+        stages, na, band = s.stage_times()
+        r = {"ms_per_apply": ms, "value": wl.n / (ms * 1e-3),
+             "stages_ms": {k: v / max(1, na) for k, v in stages.items()}}
+        if g is not None:
+            idx = g["index"]
+            Uh = U.double().cpu().numpy()[idx]
+            Oh = Om.double().cpu().numpy()[idx]
+            r["rel_err_U"] = float(np.linalg.norm(Uh - g["U"]) /
+                                   np.linalg.norm(g["U"]))
+            r["rel_err_Omega"] = float(np.linalg.norm(Oh - g["Omega"]) /
+                                       np.linalg.norm(g["Omega"]))
+        out[label] = r
+    s.close()
+    return out
+
+
+def torque_derivative_summary(name="bw1m", steps=10, warmup=2):
+    """Torques through the derivative of the dipole kernel (three channels
+    through the transforms and the solve) against the spectral-curl route
+    (six) on the same inputs: per-apply time, stages, algorithmic bytes and
+    the difference between the two discrete operators."""
+    from dataclasses import replace
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2210_01837_amd import Solver
+    wl = workloads.WORKLOADS[name]
+    pos, F, T = workloads.particles(name)
+    P, Fd, Td = (torch.tensor(a, dtype=torch.float32, device="cuda")
+                 for a in (pos, F, T))
+    out = {"workload": name, "N": wl.n}
+    res = {}
+    for route in ("curl", "derivative"):
+        box = replace(wl.box, torque_route=route)
+        s = Solver.from_box(box, precision="mixed", max_particles=wl.n)
+        U = torch.empty_like(P)
+        Om = torch.empty_like(P)
+        for _ in range(warmup):
+            s.apply(P, Fd, Td, U=U, Omega=Om)
+        torch.cuda.synchronize()
+        s.stage_times()
+        s.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.apply(P, Fd, Td, U=U, Omega=Om)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        s.set_profiling(False)
+        stages, na, band = s.stage_times()
+        nb = stage_bytes(wl.box, wl.n, band, deriv=route == "derivative",
+                         lowk=wl.box.geometry == "sc")
+        out[route] = {"ms_per_apply": ms, "value": wl.n / (ms * 1e-3),
+                      "stages_ms": {k: v / max(1, na) for k, v in stages.items()},
+                      "algorithmic_bytes": sum(nb.values())}
+        res[route] = (U.double().cpu().numpy(), Om.double().cpu().numpy())
+        s.close()
+    out["byte_ratio"] = (out["derivative"]["algorithmic_bytes"] /
+                         out["curl"]["algorithmic_bytes"])
+    out["speedup"] = out["curl"]["ms_per_apply"] / out["derivative"]["ms_per_apply"]
+    (Uc, Oc), (Ud, Od) = res["curl"], res["derivative"]
+    out["rel_diff_U_vs_curl"] = float(np.linalg.norm(Ud - Uc) / np.linalg.norm(Uc))
+    out["rel_diff_Omega_vs_curl"] = float(np.linalg.norm(Od - Oc) /
+                                          np.linalg.norm(Oc))
+    return out
 
 
 def serving_bench(count=512, loads=(0.5, 0.8, 0.95), streams=4):
@@ -220,6 +339,20 @@ def serving_bench(count=512, loads=(0.5, 0.8, 0.95), streams=4):
         print(f"[bench] serving load {f}: {res}", file=sys.stderr, flush=True)
         out["poisson"][str(f)] = res
     pool.close()
+    # a budget a fifth of the stream's distinct-solver total: the pool keeps
+    # evicting (stream-ordered releases) and creating (stream-ordered
+    # allocations) solvers while requests run
+    small = max(int(budget * 0.2), 8 << 30)
+    pool = serving.SolverPool(small)
+    arr = workloads.poisson_arrivals(count, 0.8 * sat["requests_per_s"]) * 1e3
+    res = serving.latency_summary(
+        serving.serve(jobs, list(arr), budget=small, streams=streams, pool=pool))
+    res.update({"budget_bytes": small, "solvers_created": pool.created,
+                "solvers_evicted": pool.evicted})
+    print(f"[bench] serving load 0.8, evicting pool: {res}", file=sys.stderr,
+          flush=True)
+    out["poisson_evicting"] = res
+    pool.close()
     return out
 
 
@@ -233,6 +366,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-fp64-comparison", action="store_true")
     ap.add_argument("--no-forces-only", action="store_true")
+    ap.add_argument("--no-slit-channel", action="store_true")
+    ap.add_argument("--no-torque-derivative", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for "
@@ -298,10 +433,11 @@ def main():
     print(f"[bench] {ms_per_step:.3f} ms/apply, stages {avg}, band {band}",
           file=sys.stderr, flush=True)
 
+    lowk = wl.precision == "mixed" and box.geometry == "sc"
     nbytes = stage_bytes(box, wl.n, band,
                          complex_bytes=8 if wl.precision == "mixed" else 16,
                          real_bytes=4 if wl.precision == "mixed" else 8,
-                         torques=wl.torques)
+                         torques=wl.torques, lowk=lowk)
     # dominant stage; its kernel (one launch per apply for the columns,
     # spread and interp stages) is what the roofline describes
     dom = max((k for k in nbytes), key=lambda k: avg[k])
@@ -400,6 +536,14 @@ def main():
     if not args.no_fp64_comparison:
         line["fp64_comparison"] = fp64_comparison()
         print(f"[bench] fp64 comparison: {line['fp64_comparison']}",
+              file=sys.stderr, flush=True)
+    if not args.no_slit_channel and name == "bw1m":
+        line["slit_channel"] = slit_channel_summary()
+        print(f"[bench] slit channel: {line['slit_channel']}", file=sys.stderr,
+              flush=True)
+    if not args.no_torque_derivative and name == "bw1m":
+        line["torque_derivative"] = torque_derivative_summary(name)
+        print(f"[bench] torque derivative: {line['torque_derivative']}",
               file=sys.stderr, flush=True)
     if not args.no_forces_only and name != "m663k":
         line["forces_only"] = forces_only_summary()

@@ -78,7 +78,19 @@ typedef struct {
   double wallH[2];     /* ... of the slit channel's wall at z = H (zero for a
                           bottom wall); nonzero wall velocities need
                           Nz <= 32 */
+  int torque_route;    /* FCMDP_TORQUE_CURL: torques spread as the dipole
+                          density g and Omega = (1/2) curl u, both curls taken
+                          spectrally (six channels through the transforms and
+                          the solve; the paper's GPU route).
+                          FCMDP_TORQUE_DERIVATIVE: the force density gets
+                          (1/2) grad Delta_D x tau and Omega = (1/2) sum
+                          u x grad Delta_D with the truncated derivative of
+                          the dipole ES kernel (Sec. 3.4, last paragraph and
+                          its footnotes; three channels through the
+                          transforms and the solve).  Nz <= 32. */
 } fcmdp_params;
+
+enum { FCMDP_TORQUE_CURL = 0, FCMDP_TORQUE_DERIVATIVE = 1 };
 
 /*
  * Create a solver: validates p, derives h, alpha, the ES normalisations, the
@@ -233,7 +245,10 @@ int fcmdp_set_variant(fcmdp_solver* s, int key, int value);
  */
 
 /* Step 1: spread (eq. fcm with the images of eq. kernelnearwall); writes the
- * whole grid (zero outside the particles' kernels). */
+ * whole grid (zero outside the particles' kernels).  The stage entry points
+ * use the six-channel (spectral-curl) layouts: a solver created with
+ * FCMDP_TORQUE_DERIVATIVE refuses fcmdp_stage_spread and fcmdp_stage_interp
+ * with EINVAL. */
 int fcmdp_stage_spread(fcmdp_solver* s, int64_t n, const void* pos,
                        const void* F, const void* T, void* grid,
                        void* hip_stream);

@@ -13,6 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FCMDP_LIBRARY") or os.path.join(_HERE, "libfcmdp.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ECAPACITY = 0, -1, -2, -3, -4, -5
+TORQUE_CURL, TORQUE_DERIVATIVE = 0, 1
 BOTTOM_WALL, SLIT_CHANNEL = 0, 1
 FP64, MIXED = 0, 1
 
@@ -36,6 +37,7 @@ class Params(ctypes.Structure):
         ("slipH", ctypes.c_double),
         ("wall0", ctypes.c_double * 2),
         ("wallH", ctypes.c_double * 2),
+        ("torque_route", ctypes.c_int),
     ]
 
 

@@ -187,6 +187,10 @@ int validate(const fcmdp_params* p) {
     if (p->geometry == FCMDP_BOTTOM_WALL && p->wallH[c] != 0) return FCMDP_EINVAL;
     if ((p->wall0[c] != 0 || p->wallH[c] != 0) && p->Nz > 32) return FCMDP_EINVAL;
   }
+  // torques through the kernel derivative: the three-channel kernels
+  if (p->torque_route != FCMDP_TORQUE_CURL && p->torque_route != FCMDP_TORQUE_DERIVATIVE)
+    return FCMDP_EINVAL;
+  if (p->torque_route == FCMDP_TORQUE_DERIVATIVE && p->Nz > 32) return FCMDP_EINVAL;
   const double hx = p->Lx / p->Nx, hy = p->Ly / p->Ny;
   if (std::fabs(hx - hy) > 1e-12 * hx) return FCMDP_EINVAL;
   const double alpha = 0.5 * p->w * hx;
@@ -224,7 +228,28 @@ struct Sizes {
   size_t grid, spec, keys, vals, hist, cells, pinfo, pw, pf, psi;
   // exact low-wavenumber vertical force (mixed slit channel), 0 when off
   size_t psi64, fzlo, lowk_part, lowk_coef, lowk_ex, lowk_ey;
+  // torques through the kernel derivative, 0 when off
+  size_t pdw, dpsi;
 };
+
+// Truncation point t* of the dipole kernel's derivative: with r = t/alpha
+// and s = sqrt(1 - r^2), |phi'| is proportional to r e^{beta (s - 1)} / s,
+// whose stationary points solve beta s^3 - beta s + 1 = 0; the smaller root
+// in (0, 1) is the minimum before |phi'| grows without bound at the edge of
+// the support (the larger one is its maximum).  Bisection on the
+// decreasing branch (the cubic falls on (0, 1/sqrt(3))); alpha when there
+// is no interior minimum.
+double derivative_cutoff(double alpha, double beta) {
+  auto f = [&](double x) { return beta * x * x * x - beta * x + 1.0; };
+  double a = 0.0, b = 1.0 / std::sqrt(3.0);
+  if (f(b) > 0.0) return alpha;
+  for (int it = 0; it < 200; ++it) {
+    const double m = 0.5 * (a + b);
+    (f(m) > 0.0 ? a : b) = m;
+  }
+  const double sv = 0.5 * (a + b);
+  return alpha * std::sqrt(1.0 - sv * sv);
+}
 
 // Half-width ns of the square |nx|, |ny| <= ns of wavenumbers whose vertical
 // force takes the FP64 route (mixed slit channel; 0 = none): every column
@@ -261,10 +286,13 @@ Sizes sizes_for(const fcmdp_params* p, int64_t cap, int ZW) {
   // run past the last node
   s.psi = (c * 2 * (size_t)p->Nz + 64) * T;
   const int ns = lowk_half_width(p);
+  const bool deriv = p->torque_route == FCMDP_TORQUE_DERIVATIVE;
   s.psi64 = s.fzlo = s.lowk_part = s.lowk_coef = s.lowk_ex = s.lowk_ey = 0;
+  s.pdw = deriv ? c * 16 * T : 0;
+  s.dpsi = deriv ? (c * (size_t)p->Nz + 64) * T : 0;
   if (ns > 0) {
     const size_t ncols = (size_t)(ns + 1) * (2 * ns + 1);
-    s.psi64 = (c * (size_t)p->Nz + 64) * 8;
+    s.psi64 = (c * (size_t)p->Nz * (deriv ? 2 : 1) + 64) * 8;
     s.fzlo = (size_t)p->Nz * p->Ny * p->Nx * 4;
     s.lowk_part = ((size_t)p->Nz * p->Ny * (ns + 1) + ncols * p->Nz) * 16;
     s.lowk_coef = ncols * p->Nz * 16;
@@ -315,7 +343,7 @@ void free_all(fcmdp_solver* s, hipStream_t st) {
                   s->dct_f32, s->dct_i32,
                   s->dftc, s->dftc_t, s->tw_x, s->tw_y, s->tw_r,
                   s->lz_basis, s->lz_red, s->psi64, s->fzlo, s->lowk_part,
-                  s->lowk_coef, s->lowk_ex, s->lowk_ey};
+                  s->lowk_coef, s->lowk_ex, s->lowk_ey, s->pdw, s->dpsi};
   // stream-ordered frees: no device-wide synchronisation
   for (void* q : ptrs)
     if (q) (void)hipFreeAsync(q, st);
@@ -345,8 +373,8 @@ int fcmdp_workspace_bytes(const fcmdp_params* p, int64_t n, size_t* bytes) {
   const Sizes s = sizes_for(p, n, z_window_slots(p->Nz, p->H, alpha));
   *bytes = s.grid + s.spec + 2 * s.keys + 2 * s.vals + s.hist + s.cells +
            s.pinfo + s.pw + s.pf + s.psi + s.psi64 + s.fzlo + s.lowk_part +
-           s.lowk_coef + s.lowk_ex + s.lowk_ey + (size_t)p->Nz * p->Nz * 16 +
-           65536;
+           s.lowk_coef + s.lowk_ex + s.lowk_ey + s.pdw + s.dpsi +
+           (size_t)p->Nz * p->Nz * 16 + 65536;
   return FCMDP_OK;
 }
 
@@ -399,6 +427,9 @@ int fcmdp_create_solver(const fcmdp_params* p, void* hip_stream,
   dp.ZW = z_window_slots(Nz, p->H, dp.alpha);
   dp.lowk_ns = -1;
   dp.lowk_coef = nullptr;
+  dp.torque_deriv = p->torque_route == FCMDP_TORQUE_DERIVATIVE;
+  dp.dt_torque = dp.dt_omega = 0;
+  dp.tstar_d = derivative_cutoff(dp.alpha, p->beta_d);
   s->lowk_ns = lowk_half_width(p);
   s->cap = p->max_particles;
   s->nblk_cap = (int)((s->cap > 0 ? s->cap : 1) + 2047) / 2048;
@@ -429,6 +460,17 @@ int fcmdp_create_solver(const fcmdp_params* p, void* hip_stream,
     if (s->rows_y == 0) s->wave_y = false;
   }
 
+  // Workspace comes from the device's default memory pool in stream order.
+  // Keep freed blocks in the pool (no release threshold), so that a solver
+  // created after another was released reuses its memory instead of mapping
+  // new pages (a serving pool creates and releases solvers continuously).
+  {
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess && pool) {
+      uint64_t keep = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+  }
   int err = FCMDP_OK;
   const Sizes z = sizes_for(p, s->cap, dp.ZW);
   // stream-ordered allocations on the creation stream (no device-wide
@@ -453,6 +495,10 @@ int fcmdp_create_solver(const fcmdp_params* p, void* hip_stream,
   alloc(&s->pw, z.pw);
   alloc(&s->pf, z.pf);
   alloc(&s->psi, z.psi);
+  if (dp.torque_deriv) {
+    alloc(&s->pdw, z.pdw);
+    alloc(&s->dpsi, z.dpsi);
+  }
   if (s->lowk_ns > 0) {
     alloc((void**)&s->psi64, z.psi64);
     alloc((void**)&s->fzlo, z.fzlo);
@@ -617,9 +663,14 @@ int fcmdp_apply_mobility(fcmdp_solver* s, int64_t n, const void* pos,
   }
   const int ni = (int)n;
   // without torques the grid and spectrum carry the three force channels;
-  // without angular velocities the solve returns the three velocity channels
-  s->dp.nch_in = T ? 6 : 3;
-  s->dp.nch_out = Omega ? 6 : 3;
+  // without angular velocities the solve returns the three velocity channels.
+  // Torques through the kernel derivative: three channels throughout, the
+  // torques enter the spread and Omega the interpolation.
+  const bool deriv = s->dp.torque_deriv != 0;
+  s->dp.nch_in = (T && !deriv) ? 6 : 3;
+  s->dp.nch_out = (Omega && !deriv) ? 6 : 3;
+  s->dp.dt_torque = deriv && T;
+  s->dp.dt_omega = deriv && Omega;
   const bool lowk = fcmdp::lowk_active(s);
   s->dp.lowk_ns = lowk ? s->lowk_ns : -1;
   s->dp.lowk_coef = lowk ? s->lowk_coef : nullptr;
@@ -770,6 +821,7 @@ static void all_channels(fcmdp_solver* s) {
   s->dp.nch_out = 6;
   s->dp.lowk_ns = -1;
   s->dp.lowk_coef = nullptr;
+  s->dp.dt_torque = s->dp.dt_omega = 0;
 }
 
 int fcmdp_stage_spread(fcmdp_solver* s, int64_t n, const void* pos,
@@ -777,6 +829,7 @@ int fcmdp_stage_spread(fcmdp_solver* s, int64_t n, const void* pos,
                        void* hip_stream) {
   int v = check_particles(s, n);
   if (v != FCMDP_OK) return v;
+  if (s->dp.torque_deriv) return FCMDP_EINVAL;   // six-channel layouts only
   if (!grid || (n > 0 && (!pos || !F))) return FCMDP_EINVAL;
   all_channels(s);
   hipStream_t st = (hipStream_t)hip_stream;
@@ -840,6 +893,7 @@ int fcmdp_stage_interp(fcmdp_solver* s, int64_t n, const void* pos,
                        void* hip_stream) {
   int v = check_particles(s, n);
   if (v != FCMDP_OK) return v;
+  if (s->dp.torque_deriv) return FCMDP_EINVAL;   // six-channel layouts only
   if (!grid || (n > 0 && (!pos || !U))) return FCMDP_EINVAL;
   if (n == 0) return FCMDP_OK;
   all_channels(s);

@@ -30,6 +30,33 @@ __device__ inline float es_eval<float>(double t, double alpha, double beta,
          (float)inv_norm;
 }
 
+// phi'(t), the derivative of the envelope, set to zero for |t| > tstar: the
+// point beyond its maximum where |phi'| is smallest before it grows without
+// bound at the edge of the support (torques through the kernel derivative,
+// Sec. 3.4).  tstar < alpha.
+template <typename T>
+__device__ inline T es_deval(double t, double alpha, double beta,
+                             double inv_norm, double tstar);
+
+template <>
+__device__ inline double es_deval<double>(double t, double alpha, double beta,
+                                          double inv_norm, double tstar) {
+  if (fabs(t) > tstar) return 0.0;
+  const double r = t / alpha;
+  const double s = sqrt((1.0 - r) * (1.0 + r));
+  return exp(beta * (s - 1.0)) * inv_norm * beta * (-r / alpha) / s;
+}
+
+template <>
+__device__ inline float es_deval<float>(double t, double alpha, double beta,
+                                        double inv_norm, double tstar) {
+  if (fabs(t) > tstar) return 0.0f;
+  const float r = (float)(t / alpha);
+  const float s = sqrtf((1.0f - r) * (1.0f + r));
+  return expf((float)beta * (s - 1.0f)) * (float)inv_norm * (float)beta *
+         (-r / (float)alpha) / s;
+}
+
 // x wrapped into [0, L)
 __device__ inline double wrap_coord(double x, double L) {
   double r = x - L * floor(x / L);

@@ -9,8 +9,12 @@
 //     pf      T       [cap][8]                F (3), pad, torque (3), pad
 //     psi     T       [cap][2][Nz]            folded z weights, M then D,
 //                                             zero outside the z window
+//   torques through the kernel derivative (torque_route DERIVATIVE):
+//     pdw     T       [cap][16]               phi_D' along x (7), along y (7)
+//     dpsi    T       [cap][Nz]               psi_D', the folded z derivative
 //   exact low-wavenumber vertical force (mixed slit channel only):
-//     psi64   double  [cap][Nz]               folded M z weights in FP64
+//     psi64   double  [cap][R][Nz]            folded M (and, with derivative
+//                                             torques, D) z weights in FP64
 //     fzlo    float   [Nz][Ny][Nx]            f_z - (float)f_z of the FP64
 //                                             accumulated vertical force
 //     lowk_part double2 [Nz][G][ns+1][2ns+1]  DFT of f_z over x (nx = 0..ns)
@@ -72,12 +76,19 @@ struct DevParams {
   // correction node functions; -1 = off for this launch
   int lowk_ns;
   const double2* lowk_coef;
+  // torques through the kernel derivative: route chosen at creation, and
+  // for the current apply whether torques are spread (dt_torque) and
+  // angular velocities interpolated (dt_omega) that way; tstar_d is the
+  // truncation point of the dipole kernel's derivative
+  int torque_deriv, dt_torque, dt_omega;
+  double tstar_d;
 };
 
 // rows of y per workgroup of the low-wavenumber x transform
 constexpr int kLowkRows = 64;
-// largest low-wavenumber square half-width
-constexpr int kLowkMaxNs = 48;
+// largest low-wavenumber square half-width (four 16-column tiles of the
+// x transform)
+constexpr int kLowkMaxNs = 31;
 
 }  // namespace fcmdp
 
@@ -109,6 +120,8 @@ struct fcmdp_solver {
   int lowk_ns = 0;
   bool no_lowk = false;         // variant switch (tests, measurement)
   double* psi64 = nullptr;
+  void* pdw = nullptr;          // derivative-route records (layouts above)
+  void* dpsi = nullptr;
   float* fzlo = nullptr;
   double2* lowk_part = nullptr;
   double2* lowk_coef = nullptr;

@@ -14,7 +14,7 @@
 //   spread  f_z accumulated in FP64 with FP64 z weights, stored as the FP32
 //           grid value hi = (float) f_z plus the residual lo = (float)(f_z - hi)
 //   x       T[c][b][nx]   = sum_a (hi + lo)[c][b][a] e^{-2 pi i nx a / Nx}
-//           for nx = 0..ns (direct partial DFT, FP64)
+//           for nx = 0..ns (direct partial DFT as an FP64 MFMA product)
 //   y       Y[nx][ny][c]  = sum_b T[c][b][nx] e^{-2 pi i ny b / Ny}
 //           for ny = -ns..ns
 //   z       coef[n]       = sum_{c in band} Mf[c][n] Y[c]  (DCT-I, Sec. 3.4
@@ -31,95 +31,106 @@ namespace fcmdp {
 
 namespace {
 
-constexpr int kNB = 24;          // nx values per pass (complex accumulators)
-constexpr int kChunk = 32;       // a values staged per step
 constexpr int kLowkThreads = 256;
+constexpr int kAChunk = 32;      // x values staged per step
+static_assert((2 * (kLowkMaxNs + 1) + 15) / 16 <= 4, "at most four column tiles");
+typedef double d4v __attribute__((ext_vector_type(4)));
 
-// x transform of the band planes of f_z: one workgroup per (row group g,
-// band plane c); wave w sums the quarter w of the x range for 64 rows (lane
-// = row), the quarters are added in a fixed order.
+// x transform of the band planes of f_z as an FP64 matrix product,
+//   T[row][j] = sum_a G[row][a] E[a][j],   row = (c, b), j = (nx, re|im),
+// G = hi + lo of the spread, E[a][2 nx] = cos(2 pi nx a / Nx) and
+// E[a][2 nx + 1] = -sin(...) (the table lowk_ex, NT column tiles of 16).
+// One workgroup per 64 rows of one band plane; wave w owns rows
+// 16 w .. 16 w + 15 and every column tile.  The x range is walked 32 values
+// at a time: the next chunk's G and E are loaded into registers while the
+// current chunk, staged in LDS, goes through v_mfma_f64_16x16x4f64 in
+// k-steps of four.  Operand layout (wave64): A[i][k] from lane i + 16 k,
+// B[k][j] from lane j + 16 k, and (unlike the FP32 16x16x4 product, whose
+// register r holds row 4 (l / 16) + r) D[l / 16 + 4 r][l % 16] in register
+// r of lane l.
+template <int NT>
 __global__ void __launch_bounds__(kLowkThreads)
 k_lowk_x(DevParams dp, const int* __restrict__ band,
          const float* __restrict__ fz, const float* __restrict__ fzlo,
-         const double2* __restrict__ ex, double2* __restrict__ T, int ns) {
+         const double* __restrict__ ex, double* __restrict__ T, int ns) {
+  constexpr int kCols = 16 * NT;
+  constexpr int kES = kCols + 1;                        // LDS row stride of E
+  constexpr int kRowsPer = kLowkRows * kAChunk / kLowkThreads;   // G per thread
+  constexpr int kEPer = (kAChunk * kCols + kLowkThreads - 1) / kLowkThreads;
+  static_assert(kAChunk % 4 == 0 && kLowkThreads % kAChunk == 0, "staging");
+  __shared__ double G[kLowkRows * (kAChunk + 1)];
+  __shared__ double E[kAChunk * kES];
   const int lo = band[0], hi = band[1];
   const int c = lo + blockIdx.y;
   if (lo > hi || c > hi) return;
   const int Nx = dp.Nx, Ny = dp.Ny;
-  const int nk = ns + 1;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ncol = 2 * (ns + 1);                        // real columns of T
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int b0 = blockIdx.x * kLowkRows;
-  const int b = b0 + lane;
   const size_t plane = (size_t)c * Ny * Nx;
-  // staging: [wave][a][row] (row stride 65 doubles: conflict-free writes of
-  // the transposed loads); reused for the quarter sums
-  constexpr int kStage = 4 * kChunk * 65, kRed = 3 * kNB * 64 * 2;
-  __shared__ double lds[kStage > kRed ? kStage : kRed];
-  double* X = lds + wave * kChunk * 65;
-  const int a_beg = (wave * Nx) / 4, a_end = ((wave + 1) * Nx) / 4;
-  for (int n0 = 0; n0 < nk; n0 += kNB) {
-    double ar[kNB], ai[kNB];
+  const int i16 = lane & 15, k4 = lane >> 4;
+  // this thread's staging slots: column tid % 32 of rows tid / 32 + 8 i
+  const int ga = tid % kAChunk, gr = tid / kAChunk;
+  float ph[kRowsPer], pl[kRowsPer];
+  double pe[kEPer];
+  auto fetch = [&](int a0) {
+    const int aa = a0 + ga;
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) { ar[j] = 0.0; ai[j] = 0.0; }
-    for (int a0 = a_beg; a0 < a_end; a0 += kChunk) {
-      // stage rows b0..b0+63, columns a0..a0+31 as doubles (hi + lo);
-      // lane l loads column a0 + l % 32 of rows l / 32, l / 32 + 2, ...
-      __builtin_amdgcn_wave_barrier();
-#pragma unroll 4
-      for (int k = 0; k < 32; ++k) {
-        const int r = lane / 32 + 2 * k, aa = a0 + (lane & 31);
-        double v = 0.0;
-        if (b0 + r < Ny && aa < a_end) {
-          const size_t o = plane + (size_t)(b0 + r) * Nx + aa;
-          v = (double)fz[o] + (double)fzlo[o];
-        }
-        X[(lane & 31) * 65 + r] = v;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int na = min(kChunk, a_end - a0);
-      for (int t = 0; t < na; ++t) {
-        const double v = X[t * 65 + lane];
-        const double2* e = ex + (size_t)(a0 + t) * nk + n0;
-#pragma unroll
-        for (int j = 0; j < kNB; ++j) {
-          if (n0 + j < nk) {
-            const double2 w = e[j];
-            ar[j] = fma(v, w.x, ar[j]);
-            ai[j] = fma(v, w.y, ai[j]);
-          }
-        }
+    for (int i = 0; i < kRowsPer; ++i) {
+      const int r = gr + (kLowkThreads / kAChunk) * i;
+      ph[i] = pl[i] = 0.f;
+      if (aa < Nx && b0 + r < Ny) {
+        const size_t o = plane + (size_t)(b0 + r) * Nx + aa;
+        ph[i] = fz[o];
+        pl[i] = fzlo[o];
       }
     }
-    // quarters 1..3 to LDS, quarter 0 adds them in order and stores
-    __syncthreads();
-    if (wave > 0) {
-      double* R = lds + (wave - 1) * kNB * 64 * 2;
 #pragma unroll
-      for (int j = 0; j < kNB; ++j) {
-        R[(2 * j) * 64 + lane] = ar[j];
-        R[(2 * j + 1) * 64 + lane] = ai[j];
-      }
+    for (int k = 0; k < kEPer; ++k) {
+      const int e = tid + kLowkThreads * k;
+      const int ar = e / kCols, j = e % kCols;
+      pe[k] = (e < kAChunk * kCols && a0 + ar < Nx && j < ncol)
+                  ? ex[(size_t)(a0 + ar) * ncol + j] : 0.0;
+    }
+  };
+  d4v acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  for (int a0 = 0; a0 < Nx; a0 += kAChunk) {
+#pragma unroll
+    for (int i = 0; i < kRowsPer; ++i)
+      G[(gr + (kLowkThreads / kAChunk) * i) * (kAChunk + 1) + ga] =
+          (double)ph[i] + (double)pl[i];
+#pragma unroll
+    for (int k = 0; k < kEPer; ++k) {
+      const int e = tid + kLowkThreads * k;
+      if (e < kAChunk * kCols) E[(e / kCols) * kES + e % kCols] = pe[k];
     }
     __syncthreads();
-    if (wave == 0 && b < Ny) {
+    if (a0 + kAChunk < Nx) fetch(a0 + kAChunk);    // in flight during the products
 #pragma unroll
-      for (int j = 0; j < kNB; ++j) {
-        if (n0 + j < nk) {
-          double sr = ar[j], si = ai[j];
+    for (int s4 = 0; s4 < kAChunk / 4; ++s4) {
+      const double av = G[(16 * wave + i16) * (kAChunk + 1) + 4 * s4 + k4];
 #pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            const double* R = lds + q * kNB * 64 * 2;
-            sr += R[(2 * j) * 64 + lane];
-            si += R[(2 * j + 1) * 64 + lane];
-          }
-          T[((size_t)(c - lo) * Ny + b) * nk + n0 + j] = make_double2(sr, si);
-        }
+      for (int t = 0; t < NT; ++t) {
+        const double bv = E[(4 * s4 + k4) * kES + 16 * t + i16];
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
       }
     }
     __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = 16 * t + i16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int b = b0 + 16 * wave + k4 + 4 * r;
+      if (b < Ny && j < ncol)
+        T[((size_t)(c - lo) * Ny + b) * ncol + j] = acc[t][r];
+    }
   }
 }
 
@@ -205,9 +216,20 @@ hipError_t launch_lowk(const fcmdp_solver* s, const void* grid, hipStream_t st) 
   // lowk_part holds T (band planes first) and then Y
   double2* T = s->lowk_part;
   double2* Y = s->lowk_part + (size_t)dp.Nz * dp.Ny * (ns + 1);
-  hipLaunchKernelGGL(k_lowk_x, dim3((dp.Ny + kLowkRows - 1) / kLowkRows, dp.Nz),
-                     dim3(kLowkThreads), 0, st, dp, s->band, fz, s->fzlo,
-                     s->lowk_ex, T, ns);
+  const int nt = (2 * (ns + 1) + 15) / 16;         // 1..4 (ns <= kLowkMaxNs)
+  const dim3 gx((dp.Ny + kLowkRows - 1) / kLowkRows, dp.Nz);
+  const double* exd = (const double*)s->lowk_ex;
+  double* Td = (double*)T;
+  switch (nt) {
+    case 1: hipLaunchKernelGGL(k_lowk_x<1>, gx, dim3(kLowkThreads), 0, st, dp,
+                               s->band, fz, s->fzlo, exd, Td, ns); break;
+    case 2: hipLaunchKernelGGL(k_lowk_x<2>, gx, dim3(kLowkThreads), 0, st, dp,
+                               s->band, fz, s->fzlo, exd, Td, ns); break;
+    case 3: hipLaunchKernelGGL(k_lowk_x<3>, gx, dim3(kLowkThreads), 0, st, dp,
+                               s->band, fz, s->fzlo, exd, Td, ns); break;
+    default: hipLaunchKernelGGL(k_lowk_x<4>, gx, dim3(kLowkThreads), 0, st, dp,
+                                s->band, fz, s->fzlo, exd, Td, ns); break;
+  }
   const size_t ylds = ((size_t)dp.Ny + (size_t)ny_n * kYParts) * sizeof(double2);
   hipLaunchKernelGGL(k_lowk_y, dim3(ns + 1, dp.Nz), dim3(kLowkThreads), ylds, st,
                      dp, s->band, T, s->lowk_ey, Y, ns);

@@ -317,14 +317,20 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
           const Tin* __restrict__ F, const Tin* __restrict__ Tq,
           const double* __restrict__ zc, int4* __restrict__ pinfo,
           T* __restrict__ pw, T* __restrict__ pf, T* __restrict__ psi,
-          double* __restrict__ psi64) {
+          double* __restrict__ psi64, T* __restrict__ pdw, T* __restrict__ dpsi) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int Nz = dp.Nz;
+  // FP64 z weights: the monopole's, and with torques spread through the
+  // kernel derivative also the dipole's (the spread's FP64 vertical force
+  // then carries their torque part)
+  const int rows64 = dp.dt_torque ? 2 : 1;
   T* w = pw + (size_t)i * 32;
   T* f = pf + (size_t)i * 8;
   T* ps = psi + (size_t)i * 2 * Nz;
-  double* ps64 = psi64 ? psi64 + (size_t)i * Nz : nullptr;
+  double* ps64 = psi64 ? psi64 + (size_t)i * rows64 * Nz : nullptr;
+  T* dw = pdw ? pdw + (size_t)i * 16 : nullptr;
+  T* dps = dpsi ? dpsi + (size_t)i * Nz : nullptr;
   if (skeys[i] >= (uint32_t)dp.ncells) {
     // outside the domain: zero records (never read by the grid kernels)
     for (int e = 0; e < 32; e += 4) store4(w + e, T(0), T(0), T(0), T(0));
@@ -332,7 +338,11 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
     store4(f + 4, T(0), T(0), T(0), T(0));
     for (int e = 0; e < 2 * Nz; ++e) ps[e] = T(0);
     if (ps64)
-      for (int e = 0; e < Nz; ++e) ps64[e] = 0.0;
+      for (int e = 0; e < rows64 * Nz; ++e) ps64[e] = 0.0;
+    if (dw)
+      for (int e = 0; e < 16; ++e) dw[e] = T(0);
+    if (dps)
+      for (int e = 0; e < Nz; ++e) dps[e] = T(0);
     return;
   }
   const int j = perm[i];
@@ -371,6 +381,21 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
   }
   store4(f, fv[0], fv[1], fv[2], fv[3]);
   store4(f + 4, fv[4], fv[5], fv[6], fv[7]);
+  // derivative of the dipole kernel along x and y (truncated), 7 each
+  if (dw) {
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      const double off = part ? fy : fx;
+      T v[8];
+#pragma unroll
+      for (int d = 0; d < kWin; ++d)
+        v[d] = es_deval<T>(((double)(d - 3) - off) * dp.h, dp.alpha, dp.beta_d,
+                           dp.inv_norm_d, dp.tstar_d);
+      v[7] = T(0);
+      store4(dw + 8 * part, v[0], v[1], v[2], v[3]);
+      store4(dw + 8 * part + 4, v[4], v[5], v[6], v[7]);
+    }
+  }
   // folded z weights, four nodes at a time
   const double zim_top = 2.0 * dp.H - z;
   auto zw = [&](int c, T& pm, T& pd) {
@@ -401,16 +426,42 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
   // the monopole z weights once more in FP64 (the exact low-wavenumber
   // vertical force of the mixed slit channel)
   if (ps64) {
+    for (int row = 0; row < rows64; ++row) {
+      const double beta = row ? dp.beta_d : dp.beta_m;
+      const double inv = row ? dp.inv_norm_d : dp.inv_norm_m;
+      auto p64 = [&](int c) {
+        if (c < cA || c > cB) return 0.0;
+        const double zcv = zc[c];
+        double pm = es_eval<double>(zcv - z, dp.alpha, beta, inv) -
+                    es_eval<double>(zcv + z, dp.alpha, beta, inv);
+        if (dp.geometry == 1) pm -= es_eval<double>(zcv - zim_top, dp.alpha, beta, inv);
+        return pm;
+      };
+      double* dst = ps64 + (size_t)row * Nz;
+      if (Nz % 2 == 0) {
+        // 16-byte stores (an even Nz keeps every row 16-byte aligned)
+        double2* r2 = reinterpret_cast<double2*>(dst);
+        for (int c = 0; c < Nz; c += 2) r2[c / 2] = make_double2(p64(c), p64(c + 1));
+      } else {
+        for (int c = 0; c < Nz; ++c) dst[c] = p64(c);
+      }
+    }
+  }
+  // z derivative of the folded dipole kernel: the direct term's derivative
+  // and the mirror images' (phi'(z_c - z) - phi'(z_c + z), minus
+  // phi'(z_c - (2H - z)) between two walls)
+  if (dps) {
     for (int c = 0; c < Nz; ++c) {
-      double pm = 0.0;
+      T d = T(0);
       if (c >= cA && c <= cB) {
         const double zcv = zc[c];
-        pm = es_eval<double>(zcv - z, dp.alpha, dp.beta_m, dp.inv_norm_m) -
-             es_eval<double>(zcv + z, dp.alpha, dp.beta_m, dp.inv_norm_m);
+        d = es_deval<T>(zcv - z, dp.alpha, dp.beta_d, dp.inv_norm_d, dp.tstar_d) -
+            es_deval<T>(zcv + z, dp.alpha, dp.beta_d, dp.inv_norm_d, dp.tstar_d);
         if (dp.geometry == 1)
-          pm -= es_eval<double>(zcv - zim_top, dp.alpha, dp.beta_m, dp.inv_norm_m);
+          d -= es_deval<T>(zcv - zim_top, dp.alpha, dp.beta_d, dp.inv_norm_d,
+                           dp.tstar_d);
       }
-      ps64[c] = pm;
+      dps[c] = d;
     }
   }
 }
@@ -422,7 +473,9 @@ static void records_impl(const fcmdp_solver* s, int n, const void* pos,
                      st, s->dp, n, s->keyA, s->valA, (const Tin*)pos,
                      (const Tin*)F, (const Tin*)Tq, s->zc, s->pinfo,
                      (T*)s->pw, (T*)s->pf, (T*)s->psi,
-                     s->dp.lowk_ns >= 0 ? s->psi64 : nullptr);
+                     s->dp.lowk_ns >= 0 ? s->psi64 : nullptr,
+                     (s->dp.dt_torque || s->dp.dt_omega) ? (T*)s->pdw : nullptr,
+                     (s->dp.dt_torque || s->dp.dt_omega) ? (T*)s->dpsi : nullptr);
 }
 
 hipError_t launch_records(const fcmdp_solver* s, int n, const void* pos,

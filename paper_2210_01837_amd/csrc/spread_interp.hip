@@ -137,15 +137,21 @@ __device__ __forceinline__ int rdlane_i(int x, int v) {
 }
 
 // LDS record of a staged particle: x/y weights of the M and D kernels
-// (4 x 7), then the folded z weights of the current chunk (ZC of each).
-template <int ZC> struct SpreadRec {
-  static constexpr int kPM = 28, kPD = 28 + ZC;
-  static constexpr int kLen = 28 + 2 * ZC + 1;     // odd stride
+// (4 x 7; with DT also the D kernel's derivative along x and y, 2 x 7), then
+// the folded z weights of the current chunk (ZC of each of M, D and, with
+// DT, the z derivative of D).
+template <int ZC, bool DT> struct SpreadRec {
+  static constexpr int kW = DT ? 42 : 28;
+  static constexpr int kPM = kW, kPD = kW + ZC, kPQ = kW + 2 * ZC;
+  static constexpr int kLen = kW + (DT ? 3 : 2) * ZC + 1;     // odd stride
 };
 
 // One z-chunk of K planes (K <= ZC) over the staged particles; NCH = 3
-// spreads the forces only (no torques), NCH = 6 forces and torques.
-template <typename T, int ZC, int K, int NCH, bool FZ>
+// spreads the forces only (no torques), NCH = 6 forces and torques (the
+// dipole density g).  DT (with NCH = 3): torques through the derivative of
+// the dipole kernel, f += (1/2) grad Delta_D x tau, with grad Delta_D =
+// (phi_D' phi_D psi_D, phi_D phi_D' psi_D, phi_D phi_D psi_D').
+template <typename T, int ZC, int K, int NCH, bool FZ, bool DT>
 __device__ __forceinline__ void spread_chunk(const T* __restrict__ recw,
                                              const double* __restrict__ rec64w,
                                              int total, int c0, int a, int b,
@@ -153,7 +159,8 @@ __device__ __forceinline__ void spread_chunk(const T* __restrict__ recw,
                                              const int4& inf, T F0, T F1, T F2,
                                              T G0, T G1, T G2, T (&acc)[ZC][NCH],
                                              double (&acc64)[ZC]) {
-  using Rec = SpreadRec<ZC>;
+  using Rec = SpreadRec<ZC, DT>;
+  constexpr int R64 = DT ? 2 : 1;      // FP64 z weights per node (M, D)
   for (int v = 0; v < total; ++v) {
     const int iz = rdlane_i(inf.z, v), iw = rdlane_i(inf.w, v);
     if (iw < c0 || iz >= c0 + K) continue;         // no overlap in z
@@ -163,13 +170,45 @@ __device__ __forceinline__ void spread_chunk(const T* __restrict__ recw,
     if (dy < 0) dy += dp.Ny; else if (dy >= dp.Ny) dy -= dp.Ny;
     const T f0v = rdlane(F0, v), f1v = rdlane(F1, v), f2v = rdlane(F2, v);
     T g0v = T(0), g1v = T(0), g2v = T(0);
-    if constexpr (NCH == 6) {
+    if constexpr (NCH == 6 || DT) {
       g0v = rdlane(G0, v); g1v = rdlane(G1, v); g2v = rdlane(G2, v);
     }
     if (inside && dx >= 0 && dx <= 6 && dy >= 0 && dy <= 6) {
       const T* r = recw + v * Rec::kLen;
       const T wm = r[dx] * r[7 + dy];
       const T f0 = f0v * wm, f1 = f1v * wm, f2 = f2v * wm;
+      if constexpr (DT) {
+        // grad Delta_D = (a psi_D, b psi_D, c psi_D') per node
+        const T ga = r[28 + dx] * r[21 + dy];      // phi_D'(x) phi_D(y)
+        const T gb = r[14 + dx] * r[35 + dy];      // phi_D(x) phi_D'(y)
+        const T gc = r[14 + dx] * r[21 + dy];      // phi_D(x) phi_D(y)
+        // (1/2) grad Delta_D x tau = (px pd + qx pq, py pd + qy pq, pz pd)
+        const T px = T(0.5) * g2v * gb, qx = T(-0.5) * g1v * gc;
+        const T py = T(-0.5) * g2v * ga, qy = T(0.5) * g0v * gc;
+        const T pz = T(0.5) * (g1v * ga - g0v * gb);
+        if constexpr (FZ) {
+          const double f2d = (double)f2v * ((double)r[dx] * (double)r[7 + dy]);
+          const double pzd = 0.5 * ((double)g1v * ((double)r[28 + dx] * (double)r[21 + dy]) -
+                                    (double)g0v * ((double)r[14 + dx] * (double)r[35 + dy]));
+          const double* r64 = rec64w + v * R64 * ZC;
+#pragma unroll
+          for (int s = 0; s < K; ++s) {
+            const T pm = r[Rec::kPM + s], pd = r[Rec::kPD + s], pq = r[Rec::kPQ + s];
+            acc[s][0] += f0 * pm + px * pd + qx * pq;
+            acc[s][1] += f1 * pm + py * pd + qy * pq;
+            acc64[s] = fma(f2d, r64[s], fma(pzd, r64[ZC + s], acc64[s]));
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < K; ++s) {
+            const T pm = r[Rec::kPM + s], pd = r[Rec::kPD + s], pq = r[Rec::kPQ + s];
+            acc[s][0] += f0 * pm + px * pd + qx * pq;
+            acc[s][1] += f1 * pm + py * pd + qy * pq;
+            acc[s][2] += f2 * pm + pz * pd;
+          }
+        }
+        continue;
+      }
       if constexpr (FZ) {
         // vertical force in FP64 with the FP64 z weights
         const double f2d = (double)f2v * ((double)r[dx] * (double)r[7 + dy]);
@@ -202,18 +241,23 @@ __device__ __forceinline__ void spread_chunk(const T* __restrict__ recw,
 
 // FZ (mixed slit channel): the vertical force f_z is accumulated in FP64
 // with the FP64 z weights psi64 and stored as the FP32 grid value plus its
-// residual in fzlo (the exact low-wavenumber route of lowk.hip).
-template <typename T, int ZC, int NCH, bool FZ>
+// residual in fzlo (the exact low-wavenumber route of lowk.hip).  DT: torques
+// through the derivative of the dipole kernel (three grid channels).
+template <typename T, int ZC, int NCH, bool FZ, bool DT>
 __global__ void __launch_bounds__(256)
 k_spread_wave(DevParams dp, const int* __restrict__ band,
               const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
               const T* __restrict__ pw, const T* __restrict__ pf,
               const T* __restrict__ psi, const double* __restrict__ psi64,
+              const T* __restrict__ pdw, const T* __restrict__ dpsi,
               T* __restrict__ grid, float* __restrict__ fzlo) {
-  using Rec = SpreadRec<ZC>;
+  static_assert(!DT || NCH == 3, "derivative torques spread three channels");
+  using Rec = SpreadRec<ZC, DT>;
+  constexpr int R64 = DT ? 2 : 1;
   constexpr int kS = SpreadStage<T>::n;
   __shared__ T rec[4][kS][Rec::kLen];       // staged particle records per wavefront
-  __shared__ double rec64[FZ ? 4 : 1][FZ ? kS : 1][ZC];   // their FP64 z weights
+  // their FP64 z weights (M, and with DT also D)
+  __shared__ double rec64[FZ ? 4 : 1][FZ ? kS : 1][R64 * ZC];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gx = (dp.Nx + 4 * kPW - 1) / (4 * kPW);
@@ -301,15 +345,19 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
       inf = pinfo[p];
       const T* f = pf + (size_t)p * 8;
       F0 = f[0]; F1 = f[1]; F2 = f[2];
-      if constexpr (NCH == 6) { G0 = f[4]; G1 = f[5]; G2 = f[6]; }
+      if constexpr (NCH == 6 || DT) { G0 = f[4]; G1 = f[5]; G2 = f[6]; }
       const T* w = pw + (size_t)p * 32;
 #pragma unroll
       for (int d = 0; d < 7; ++d) {
         mine[d] = w[d];
         mine[7 + d] = w[8 + d];
-        if constexpr (NCH == 6) {
+        if constexpr (NCH == 6 || DT) {
           mine[14 + d] = w[16 + d];
           mine[21 + d] = w[24 + d];
+        }
+        if constexpr (DT) {
+          mine[28 + d] = pdw[(size_t)p * 16 + d];
+          mine[35 + d] = pdw[(size_t)p * 16 + 8 + d];
         }
       }
     }
@@ -335,8 +383,13 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
         for (int s = 0; s < ZC; ++s) {
           if (s < zc) {
             mine[Rec::kPM + s] = ps[c0 + s];
-            if constexpr (NCH == 6) mine[Rec::kPD + s] = ps[Nz + c0 + s];
-            if constexpr (FZ) rec64[wv][lane][s] = psi64[(size_t)p * Nz + c0 + s];
+            if constexpr (NCH == 6 || DT) mine[Rec::kPD + s] = ps[Nz + c0 + s];
+            if constexpr (DT) mine[Rec::kPQ + s] = dpsi[(size_t)p * Nz + c0 + s];
+            if constexpr (FZ) {
+              const double* p64 = psi64 + (size_t)p * R64 * Nz;
+              rec64[wv][lane][s] = p64[c0 + s];
+              if constexpr (DT) rec64[wv][lane][ZC + s] = p64[Nz + c0 + s];
+            }
           }
         }
       }
@@ -355,7 +408,8 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
 #define FCMDP_CHUNK(K)                                                         \
   case K:                                                                      \
     if constexpr (K <= ZC)                                                     \
-      spread_chunk<T, ZC, K, NCH, FZ>(recw, &rec64[FZ ? wv : 0][0][0], total, \
+      spread_chunk<T, ZC, K, NCH, FZ, DT>(recw, &rec64[FZ ? wv : 0][0][0],    \
+                                          total,                               \
                                       c0, a, b, inside, dp, inf, F0, F1, F2,   \
                                       G0, G1, G2, acc, acc64);                 \
     break;
@@ -398,11 +452,12 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
         const int4 inf = pinfo[q];
         if (inf.w < c0 || inf.z >= c0 + ZC) continue;   // no overlap in z
         const T* ps = psi + (size_t)q * 2 * Nz;
-        T pm[ZC], pd[ZC];
+        T pm[ZC], pd[ZC], pq[ZC];
 #pragma unroll
         for (int s = 0; s < ZC; ++s) {
           pm[s] = ps[c0 + s];
-          pd[s] = NCH == 6 ? ps[Nz + c0 + s] : T(0);
+          pd[s] = (NCH == 6 || DT) ? ps[Nz + c0 + s] : T(0);
+          pq[s] = DT ? dpsi[(size_t)q * Nz + c0 + s] : T(0);
         }
         int dx = a - inf.x + 3;
         if (dx < 0) dx += dp.Nx; else if (dx >= dp.Nx) dx -= dp.Nx;
@@ -417,13 +472,40 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
           const T wd = w[16 + dx] * w[24 + dy];
           const T f0 = F0 * wm, f1 = F1 * wm, f2 = F2 * wm;
           const T t0 = G0 * wd, t1 = G1 * wd, t2 = G2 * wd;
+          if constexpr (DT) {
+            const T* dw = pdw + (size_t)q * 16;
+            const T ga = dw[dx] * w[24 + dy];
+            const T gb = w[16 + dx] * dw[8 + dy];
+            const T gc = w[16 + dx] * w[24 + dy];
+            const T px = T(0.5) * G2 * gb, qx = T(-0.5) * G1 * gc;
+            const T py = T(-0.5) * G2 * ga, qy = T(0.5) * G0 * gc;
+            const T pz = T(0.5) * (G1 * ga - G0 * gb);
+            double f2d = 0.0, pzd = 0.0;
+            const double* p64 = nullptr;
+            if constexpr (FZ) {
+              f2d = (double)F2 * ((double)w[dx] * (double)w[8 + dy]);
+              pzd = 0.5 * ((double)G1 * ((double)dw[dx] * (double)w[24 + dy]) -
+                           (double)G0 * ((double)w[16 + dx] * (double)dw[8 + dy]));
+              p64 = psi64 + (size_t)q * R64 * Nz;
+            }
+#pragma unroll
+            for (int s = 0; s < ZC; ++s) {
+              acc[s][0] += f0 * pm[s] + px * pd[s] + qx * pq[s];
+              acc[s][1] += f1 * pm[s] + py * pd[s] + qy * pq[s];
+              if constexpr (FZ)
+                acc64[s] = fma(f2d, p64[c0 + s], fma(pzd, p64[Nz + c0 + s], acc64[s]));
+              else
+                acc[s][2] += f2 * pm[s] + pz * pd[s];
+            }
+            continue;
+          }
           double f2d = 0.0;
           if constexpr (FZ) f2d = (double)F2 * ((double)w[dx] * (double)w[8 + dy]);
 #pragma unroll
           for (int s = 0; s < ZC; ++s) {
             acc[s][0] += f0 * pm[s]; acc[s][1] += f1 * pm[s];
             if constexpr (FZ)
-              acc64[s] = fma(f2d, psi64[(size_t)q * Nz + c0 + s], acc64[s]);
+              acc64[s] = fma(f2d, psi64[(size_t)q * R64 * Nz + c0 + s], acc64[s]);
             else
               acc[s][2] += f2 * pm[s];
             if constexpr (NCH == 6) {
@@ -437,17 +519,28 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
   }
 }
 
-template <typename T, int NCH, bool FZ = false>
+template <typename T, int NCH, bool FZ = false, bool DT = false>
 static void spread_wave(const fcmdp_solver* s, void* grid, hipStream_t st) {
   dim3 g(((s->dp.Nx + 4 * kPW - 1) / (4 * kPW)) * ((s->dp.Ny + kPW - 1) / kPW));
-  hipLaunchKernelGGL((k_spread_wave<T, kSpreadZC, NCH, FZ>), g, dim3(256), 0, st,
-                     s->dp, s->band, s->cell_start, s->pinfo, (const T*)s->pw,
+  hipLaunchKernelGGL((k_spread_wave<T, kSpreadZC, NCH, FZ, DT>), g, dim3(256), 0,
+                     st, s->dp, s->band, s->cell_start, s->pinfo, (const T*)s->pw,
                      (const T*)s->pf, (const T*)s->psi,
-                     FZ ? (const double*)s->psi64 : nullptr, (T*)grid,
-                     FZ ? s->fzlo : nullptr);
+                     FZ ? (const double*)s->psi64 : nullptr,
+                     DT ? (const T*)s->pdw : nullptr, DT ? (const T*)s->dpsi : nullptr,
+                     (T*)grid, FZ ? s->fzlo : nullptr);
 }
 
 hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st) {
+  if (s->dp.dt_torque) {
+    // torques through the derivative of the dipole kernel: three channels
+    if (s->mixed && s->dp.lowk_ns >= 0)
+      spread_wave<float, 3, true, true>(s, grid, st);
+    else if (s->mixed)
+      spread_wave<float, 3, false, true>(s, grid, st);
+    else
+      spread_wave<double, 3, false, true>(s, grid, st);
+    return hipGetLastError();
+  }
   if (!s->force_simple_spread) {
     // without torques only the three force channels are spread
     const bool dip = s->dp.nch_in == 6;
@@ -544,11 +637,14 @@ k_interp(DevParams dp, int n, const uint32_t* __restrict__ skeys,
 constexpr int kTile = 26;
 constexpr int kRX = kTile + 6;
 constexpr int kIThreads = 512;   // threads per interpolation workgroup
-constexpr int kRec = 28;     // wxM[7] wyM[7] wxD[7] wyD[7]
+// per particle: wxM[7] wyM[7] wxD[7] wyD[7] (and with DT wxD'[7] wyD'[7])
+template <bool DT> struct IRec { static constexpr int n = DT ? 42 : 28; };
 
-// NCH = 6 interpolates velocities and angular velocities, NCH = 3 the
-// velocities only (the grid's vorticity channels are then not read).
-template <typename T, int ZC, int NCH>
+// NCH = 6 interpolates velocities and angular velocities (Omega from the
+// grid's vorticity channels), NCH = 3 the velocities only (the vorticity
+// channels are then not read).  DT (with NCH = 3): Omega = (1/2) sum
+// u x grad Delta_D with the derivative of the dipole kernel.
+template <typename T, int ZC, int NCH, bool DT = false>
 __global__ void __launch_bounds__(kIThreads)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2, 8)))
 k_interp_tiled(DevParams dp, const int* __restrict__ band,
@@ -556,12 +652,16 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
                const int4* __restrict__ pinfo, const T* __restrict__ pw,
                const T* __restrict__ psi, const T* __restrict__ quad,
                const T* __restrict__ grid, const int* __restrict__ perm,
+               const T* __restrict__ pdw, const T* __restrict__ dpsi,
                T* __restrict__ U, T* __restrict__ Om, int cap) {
+  static_assert(!DT || NCH == 3, "derivative route reads the velocity channels");
+  constexpr int kRec = IRec<DT>::n;
+  constexpr int NOUT = (NCH == 6 || DT) ? 6 : 3;         // U (and Omega)
   extern __shared__ unsigned char lds_raw[];
   T* G = reinterpret_cast<T*>(lds_raw);                 // [ZC][NCH][kRX][kRX]
   T* pcw = G + ZC * NCH * kRX * kRX;                    // [cap][kRec]
-  T* acc = pcw + cap * kRec;                            // [cap][NCH]
-  int4* pci = reinterpret_cast<int4*>(acc + cap * NCH); // [cap]
+  T* acc = pcw + cap * kRec;                            // [cap][NOUT]
+  int4* pci = reinterpret_cast<int4*>(acc + cap * NOUT); // [cap]
   int* pcj = reinterpret_cast<int*>(pci + cap);         // [cap] output index
   int* pcp = pcj + cap;                                 // [cap] sorted index
   __shared__ int rowoff[kTile + 1];
@@ -626,9 +726,13 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
         d[7 + e] = w[8 + e];
         d[14 + e] = w[16 + e];
         d[21 + e] = w[24 + e];
+        if constexpr (DT) {
+          d[28 + e] = pdw[(size_t)p * 16 + e];
+          d[35 + e] = pdw[(size_t)p * 16 + 8 + e];
+        }
       }
 #pragma unroll
-      for (int e = 0; e < NCH; ++e) acc[h * NCH + e] = T(0);
+      for (int e = 0; e < NOUT; ++e) acc[h * NOUT + e] = T(0);
     }
     if (zhi >= 0) {
       atomicMin(&zr[0], zlo);
@@ -675,7 +779,46 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
         const int4 inf = pci[h];
         if (inf.w < c0 || inf.z > c0 + nz - 1) continue;   // no z overlap
         T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
-        if (l < 7) {
+        if (DT && l < 7) {
+          const T* w = pcw + h * kRec;
+          const T* ps = psi + (size_t)pcp[h] * 2 * dp.Nz;
+          const T* dps = dpsi + (size_t)pcp[h] * dp.Nz;
+          const T wxm = w[l], wxd = w[14 + l], wxq = w[28 + l];
+          const int px = inf.x - tx0 + l;
+          const int ry0 = inf.y - ty0;
+          T pm[ZC], pd[ZC], pq[ZC];
+#pragma unroll
+          for (int sidx = 0; sidx < ZC; ++sidx) {
+            const bool ok = sidx < nz;
+            pm[sidx] = ok ? q[sidx] * ps[c0 + sidx] : T(0);
+            pd[sidx] = ok ? q[sidx] * ps[dp.Nz + c0 + sidx] : T(0);
+            pq[sidx] = ok ? q[sidx] * dps[c0 + sidx] : T(0);
+          }
+          for (int dy = 0; dy < 7; ++dy) {
+            const T wm = wxm * w[7 + dy];
+            const T ga = wxq * w[21 + dy];          // phi_D'(x) phi_D(y)
+            const T gb = wxd * w[35 + dy];          // phi_D(x) phi_D'(y)
+            const T gc = wxd * w[21 + dy];          // phi_D(x) phi_D(y)
+            const int ry = ry0 + dy;
+#pragma unroll
+            for (int sidx = 0; sidx < ZC; ++sidx) {
+              if (sidx < nz) {
+                const T qm = pm[sidx] * wm;
+                const T gx = pd[sidx] * ga, gy = pd[sidx] * gb, gz = pq[sidx] * gc;
+                const T* gp = G + (sidx * NCH * kRX + ry) * kRX + px;
+                constexpr int CS = kRX * kRX;
+                const T u = gp[0], v = gp[CS], ww = gp[2 * CS];
+                a0 += qm * u;
+                a1 += qm * v;
+                a2 += qm * ww;
+                // u x grad Delta_D (the 1/2 is applied at the end)
+                a3 += v * gz - ww * gy;
+                a4 += ww * gx - u * gz;
+                a5 += u * gy - v * gx;
+              }
+            }
+          }
+        } else if (!DT && l < 7) {
           const T* w = pcw + h * kRec;
           // dense folded z weights of this particle (zero outside its window)
           const T* ps = psi + (size_t)pcp[h] * 2 * dp.Nz;
@@ -722,23 +865,24 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
           a5 += __shfl_xor(a5, m, 8);
         }
         if (l == 0) {
-          T* ac = acc + h * NCH;
+          T* ac = acc + h * NOUT;
           ac[0] += a0; ac[1] += a1; ac[2] += a2;
-          if constexpr (NCH == 6) { ac[3] += a3; ac[4] += a4; ac[5] += a5; }
+          if constexpr (NOUT == 6) { ac[3] += a3; ac[4] += a4; ac[5] += a5; }
         }
       }
       __syncthreads();
     }
     for (int h = tid; h < np; h += kIThreads) {
       const int j = pcj[h];
-      const T* ac = acc + h * NCH;
+      const T* ac = acc + h * NOUT;
       U[3 * (size_t)j + 0] = ac[0];
       U[3 * (size_t)j + 1] = ac[1];
       U[3 * (size_t)j + 2] = ac[2];
-      if constexpr (NCH == 6) {
-        Om[3 * (size_t)j + 0] = ac[3];
-        Om[3 * (size_t)j + 1] = ac[4];
-        Om[3 * (size_t)j + 2] = ac[5];
+      if constexpr (NOUT == 6) {
+        const T half = DT ? T(0.5) : T(1);
+        Om[3 * (size_t)j + 0] = half * ac[3];
+        Om[3 * (size_t)j + 1] = half * ac[4];
+        Om[3 * (size_t)j + 2] = half * ac[5];
       }
     }
     __syncthreads();
@@ -758,10 +902,11 @@ __global__ void k_interp_invalid(int n, int ncells, const uint32_t* __restrict__
   if (Om) Om[3 * (size_t)j + 0] = Om[3 * (size_t)j + 1] = Om[3 * (size_t)j + 2] = nan;
 }
 
-template <typename T, int ZC, int NCH>
+template <typename T, int ZC, int NCH, bool DT = false>
 static size_t interp_lds(int cap) {
+  constexpr int NOUT = (NCH == 6 || DT) ? 6 : 3;
   return (size_t)ZC * NCH * kRX * kRX * sizeof(T) +
-         (size_t)cap * (kRec + NCH) * sizeof(T) + (size_t)cap * (16 + 4 + 4);
+         (size_t)cap * (IRec<DT>::n + NOUT) * sizeof(T) + (size_t)cap * (16 + 4 + 4);
 }
 
 template <typename T>
@@ -778,18 +923,25 @@ static hipError_t interp_tiled(const fcmdp_solver* s, int n, const T* grid,
   // planes staged per chunk: as many for three channels as for six, so that
   // the velocities are the same bits whether or not Omega is wanted
   constexpr int ZC = sizeof(T) == 4 ? 2 : 1;
-  if (Om && dp.nch_out == 6) {
+  if (Om && dp.dt_omega) {
+    // angular velocities through the derivative of the dipole kernel
+    const size_t lds = interp_lds<T, ZC, 3, true>(cap);
+    hipLaunchKernelGGL((k_interp_tiled<T, ZC, 3, true>), g, dim3(kIThreads), lds,
+                       st, dp, s->band, s->cell_start, s->pinfo, (const T*)s->pw,
+                       (const T*)s->psi, (const T*)s->quad, grid, s->valA,
+                       (const T*)s->pdw, (const T*)s->dpsi, U, Om, cap);
+  } else if (Om && dp.nch_out == 6) {
     const size_t lds = interp_lds<T, ZC, 6>(cap);
     hipLaunchKernelGGL((k_interp_tiled<T, ZC, 6>), g, dim3(kIThreads), lds, st,
                        dp, s->band, s->cell_start, s->pinfo, (const T*)s->pw,
-                       (const T*)s->psi, (const T*)s->quad, grid, s->valA, U,
-                       Om, cap);
+                       (const T*)s->psi, (const T*)s->quad, grid, s->valA,
+                       nullptr, nullptr, U, Om, cap);
   } else {
     const size_t lds = interp_lds<T, ZC, 3>(cap);
     hipLaunchKernelGGL((k_interp_tiled<T, ZC, 3>), g, dim3(kIThreads), lds, st,
                        dp, s->band, s->cell_start, s->pinfo, (const T*)s->pw,
-                       (const T*)s->psi, (const T*)s->quad, grid, s->valA, U,
-                       nullptr, cap);
+                       (const T*)s->psi, (const T*)s->quad, grid, s->valA,
+                       nullptr, nullptr, U, nullptr, cap);
   }
   return hipGetLastError();
 }
@@ -797,7 +949,7 @@ static hipError_t interp_tiled(const fcmdp_solver* s, int n, const T* grid,
 hipError_t launch_interp(const fcmdp_solver* s, int n, const void* grid,
                          void* U, void* Omega, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  if (!s->force_simple_interp) {
+  if (!s->force_simple_interp || s->dp.dt_omega) {
     if (s->mixed)
       return interp_tiled<float>(s, n, (const float*)grid, (float*)U,
                                  (float*)Omega, st);

@@ -41,15 +41,16 @@ def capacity_bucket(n: int, minimum: int = 1024) -> int:
 # every parameter of the discrete operator (fcmdp_params), so that requests
 # differing in any of them never share a solver
 _KEY_FIELDS = ("geometry", "Lx", "Ly", "H", "Nx", "Ny", "Nz", "w", "beta_m",
-               "beta_d", "eta", "slip0", "slipH", "wall0", "wallH")
+               "beta_d", "eta", "slip0", "slipH", "wall0", "wallH",
+               "torque_route")
 _DEFAULTS = {"w": 6, "beta_m": 1.327 * 6, "beta_d": 2.216 * 6, "eta": 1.0,
              "slip0": 0.0, "slipH": 0.0, "wall0": (0.0, 0.0),
-             "wallH": (0.0, 0.0)}
+             "wallH": (0.0, 0.0), "torque_route": "curl"}
 
 
 def _field(box, name):
     v = getattr(box, name, _DEFAULTS.get(name))
-    if name == "geometry":
+    if name in ("geometry", "torque_route"):
         return v
     if name in ("Nx", "Ny", "Nz", "w"):
         return int(v)

@@ -25,16 +25,20 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+TORQUE_ROUTE = {"curl": L.TORQUE_CURL, "derivative": L.TORQUE_DERIVATIVE}
+
+
 def make_params(geometry, Lx, Ly, H, Nx, Ny, Nz, w=6, beta_m=1.327 * 6,
                 beta_d=2.216 * 6, eta=1.0, precision="mixed",
                 max_particles=0, slip0=0.0, slipH=0.0, wall0=(0.0, 0.0),
-                wallH=(0.0, 0.0)) -> L.Params:
+                wallH=(0.0, 0.0), torque_route="curl") -> L.Params:
     arr = ctypes.c_double * 2
     return L.Params(GEOMETRY[geometry], float(Lx), float(Ly), float(H),
                     int(Nx), int(Ny), int(Nz), int(w), float(beta_m),
                     float(beta_d), float(eta), PRECISION[precision],
                     int(max_particles), float(slip0), float(slipH),
-                    arr(*map(float, wall0)), arr(*map(float, wallH)))
+                    arr(*map(float, wall0)), arr(*map(float, wallH)),
+                    TORQUE_ROUTE[torque_route])
 
 
 def workspace_bytes(n, **kw) -> int:
@@ -52,10 +56,10 @@ class Solver:
     def __init__(self, geometry, Lx, Ly, H, Nx, Ny, Nz, w=6, beta_m=1.327 * 6,
                  beta_d=2.216 * 6, eta=1.0, precision="mixed",
                  max_particles=1 << 20, slip0=0.0, slipH=0.0, wall0=(0.0, 0.0),
-                 wallH=(0.0, 0.0), stream=None):
+                 wallH=(0.0, 0.0), torque_route="curl", stream=None):
         self.params = make_params(geometry, Lx, Ly, H, Nx, Ny, Nz, w, beta_m,
                                   beta_d, eta, precision, max_particles, slip0,
-                                  slipH, wall0, wallH)
+                                  slipH, wall0, wallH, torque_route)
         self.precision = precision
         self.Nx, self.Ny, self.Nz = int(Nx), int(Ny), int(Nz)
         self._h = ctypes.c_void_p(0)
@@ -72,7 +76,8 @@ class Solver:
                    box.w, box.beta_m, box.beta_d, box.eta, precision,
                    max_particles, getattr(box, "slip0", 0.0),
                    getattr(box, "slipH", 0.0), getattr(box, "wall0", (0.0, 0.0)),
-                   getattr(box, "wallH", (0.0, 0.0)), stream=stream)
+                   getattr(box, "wallH", (0.0, 0.0)),
+                   getattr(box, "torque_route", "curl"), stream=stream)
 
     def _mark(self, stream):
         """Record the end of this call's device work (close() orders the

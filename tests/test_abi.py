@@ -55,6 +55,8 @@ def _params(**kw):
     # uniform wall velocities: no top wall for a bottom wall, Nz <= 32
     dict(wallH=(1.0, 0.0)), dict(Nz=48, wall0=(0.5, 0.0)),
     dict(geometry="sc", wallH=(float("nan"), 0.0)),
+    # torques through the kernel derivative: three-channel kernels, Nz <= 32
+    dict(Nz=48, torque_route="derivative"),
 ])
 def test_invalid_parameters_rejected(L, bad):
     from paper_2210_01837_amd import _lib

@@ -80,6 +80,8 @@ class Box:
     slipH: float = 0.0     # z = 0 and z = H (App. A); 0 = no slip
     wall0: tuple = (0.0, 0.0)   # uniform (x, y) velocity of the wall at z = 0
     wallH: tuple = (0.0, 0.0)   # and of the slit channel's wall at z = H
+    torque_route: str = "curl"  # "curl" (spectral curl) or "derivative"
+                                # (derivative of the dipole kernel, Sec. 3.4)
 
     @property
     def h(self) -> float:
