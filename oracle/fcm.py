@@ -54,15 +54,19 @@ class Solver:
         """Indices (P, 9) and kernel values on a 9-point window around x.
 
         The support |t| <= alpha = 3h holds at most 7 grid points; the
-        9-point window contains it for any rounding of floor(x/h).
+        9-point window contains it for any rounding of floor(x/h).  The
+        node offset t = x_a - x is taken as (a - x/h) h: a - x/h is exact in
+        floating point (a and x/h agree to a few units), so a particle lying
+        exactly on a grid node keeps both edge nodes |t| = alpha of the
+        closed support (eq. es).  Periodicity acts on the index only.
         """
         h = self.h
-        i0 = np.floor(x / h).astype(np.int64)
+        u = x / h
+        i0 = np.floor(u)
         a = i0[:, None] + np.arange(-4, 5)[None, :]
-        t = a * h - x[:, None]
-        t = (t + 0.5 * L) % L - 0.5 * L           # minimum image
+        t = (a - u[:, None]) * h
         from .kernel import phi
-        return a % N, phi(t, self.alpha, beta, norm)
+        return a.astype(np.int64) % N, phi(t, self.alpha, beta, norm)
 
     def _z_weights(self, z, beta, norm):
         """Folded z kernel psi(z_c; z_j) on all nodes, shape (P, Nz)."""
@@ -132,15 +136,17 @@ class Solver:
         p[:, 1] = np.mod(p[:, 1], self.box.Ly)
         return p
 
-    def apply(self, pos, F, T, sample=None):
+    def apply(self, pos, F, T, sample=None, wall=None):
         """The mobility apply (F, T) -> (U, Omega) (eq. grandmob).
 
         ``sample``: optional index array; only those particles are
-        interpolated (every particle is still spread).
+        interpolated (every particle is still spread).  ``wall``: optional
+        tangential wall velocities at the walls' grid nodes, shape
+        (nw, 2, Ny, Nx) (eq. bcnoslip0; App. A, eq. u0uHformula).
         """
         pos = self.wrap(pos)
         f, g = self.spread(pos, np.asarray(F, float), np.asarray(T, float))
-        u, om = stokes.stokes_solve(self.box, f, g)
+        u, om = stokes.stokes_solve(self.box, f, g, wall)
         del f, g
         tgt = pos if sample is None else pos[sample]
         return self.interp(tgt, u, om)

@@ -72,25 +72,29 @@ def dp_solve(box, kx, ky, fx, fy, fz):
     return p, u, v, w
 
 
-def correction_nodes(box, kx, ky, u, v, w):
+def correction_nodes(box, kx, ky, u, v, w, wall=None):
     """Wall correction velocity at the Chebyshev nodes (step 4 of Sec. 3.4).
 
     u, v, w: (K, Nz) coefficients of the DP velocity.  Bottom wall: the
     closed form of Sec. 3.2 (eqs. usolfs-corr-final .. wsolfs-corr-final) with
-    boundary data u_corr(0) = -u_DP(0) (no slip, zero wall velocity).  Slit
-    channel: App. A with zero slip lengths and wall velocities.
+    boundary data u_corr(0) = u^W - u_DP(0) (eq. bcnoslip0: the wall moves
+    tangentially with u^W, w = 0).  Slit channel: App. A.  wall: None (walls
+    at rest) or (4, K) xy-DFT coefficients of u^W, v^W at z = 0 and z = H
+    (the last two unused for a bottom wall).
     """
     Nz = box.Nz
     _, zc = cheb.nodes(Nz, box.H)
     alt = (-1.0) ** np.arange(Nz)
     k = np.sqrt(kx ** 2 + ky ** 2)
     if box.geometry != "bw":
-        return _slit_correction(box, kx, ky, k, u, v, w, zc, alt)
+        return _slit_correction(box, kx, ky, k, u, v, w, zc, alt, wall)
     kk = k[:, None]
     em = np.exp(-kk * zc[None, :])            # e^{-kz}
     u0 = -(u * alt).sum(-1)
     v0 = -(v * alt).sum(-1)
     w0 = -(w * alt).sum(-1)
+    if wall is not None:
+        u0, v0 = u0 + wall[0], v0 + wall[1]
     Acoef = (1j * k * w0 + kx * u0 + ky * v0)[:, None]
     ze = zc[None, :] * em
     uc = -(kx / k)[:, None] * Acoef * ze + u0[:, None] * em
@@ -100,9 +104,11 @@ def correction_nodes(box, kx, ky, u, v, w):
     return uc, vc, wc
 
 
-def _dp_and_correction(box, kx, ky, fx, fy, fz, chunk=16384):
+def _dp_and_correction(box, kx, ky, fx, fy, fz, wall=None, chunk=16384):
     """k != 0 columns: DP solve plus wall correction, added in coefficient
-    space after a Chebyshev transform of the nodal correction (step 6)."""
+    space after a Chebyshev transform of the nodal correction (step 6).
+    wall: None or (4, K) xy-DFT coefficients of the wall velocities
+    (u^W, v^W at z = 0, then at z = H)."""
     K = kx.size
     Nz = box.Nz
     u = np.empty((K, Nz), complex)
@@ -111,22 +117,24 @@ def _dp_and_correction(box, kx, ky, fx, fy, fz, chunk=16384):
     for lo in range(0, K, chunk):
         sl = slice(lo, min(K, lo + chunk))
         _, uu, vv, ww = dp_solve(box, kx[sl], ky[sl], fx[sl], fy[sl], fz[sl])
-        uc, vc, wc = correction_nodes(box, kx[sl], ky[sl], uu, vv, ww)
+        uc, vc, wc = correction_nodes(box, kx[sl], ky[sl], uu, vv, ww,
+                                      None if wall is None else wall[:, sl])
         u[sl] = uu + cheb.dct1(uc, axis=-1)
         v[sl] = vv + cheb.dct1(vc, axis=-1)
         w[sl] = ww + cheb.dct1(wc, axis=-1)
     return u, v, w
 
 
-def _slit_correction(box, kx, ky, k, uu, vv, ww, zc, alt):
+def _slit_correction(box, kx, ky, k, uu, vv, ww, zc, alt, wall=None):
     """Slit-channel correction with slip lengths l_0, l_H (App. A; no slip
-    when both are zero) and zero wall velocity.
+    when both are zero) and wall velocities (wall: None, or the (4, K) xy-DFT
+    coefficients of u^W, v^W at z = 0 and at z = H).
 
     Unknowns (C0, D0, Cx, Dx, Cy, Dy, Cz, Dz) of eqs. psolfs-corr-sc ..
     wsolfs-corr-sc from the six boundary conditions (eq. 6eqs-for-constants)
     and the two continuity conditions (eq. 2eqs-for-constants).  The boundary
-    data are eq. u0uHformula: u_0 = -u_DP(0) + l_0 du_DP/dz(0), u_H = -u_DP(H)
-    - l_H du_DP/dz(H), w_0 = -w_DP(0), w_H = -w_DP(H).  Reading: the
+    data are eq. u0uHformula: u_0 = u_0^W - u_DP(0) + l_0 du_DP/dz(0), u_H =
+    u_H^W - u_DP(H) - l_H du_DP/dz(H), w_0 = -w_DP(0), w_H = -w_DP(H).  Reading: the
     D-coefficients are rescaled, D~ = D e^{kH}, so every matrix entry carries
     at most e^{-kH} <= 1 (rows scaled by e^{-kH} where needed).
     """
@@ -144,6 +152,8 @@ def _slit_correction(box, kx, ky, k, uu, vv, ww, zc, alt):
     uH = -uu.sum(-1) - lH * dH(uu)
     vH = -vv.sum(-1) - lH * dH(vv)
     wH = -ww.sum(-1)
+    if wall is not None:
+        u0, v0, uH, vH = u0 + wall[0], v0 + wall[1], uH + wall[2], vH + wall[3]
     M = np.zeros((Kc, 8, 8), complex)
     b = np.zeros((Kc, 8), complex)
     C0, D0, CX, DX, CY, DY, CZ, DZ = range(8)
@@ -196,11 +206,34 @@ def _slit_correction(box, kx, ky, k, uu, vv, ww, zc, alt):
     return uc, vc, wc
 
 
-def solve_coefficients(box, Fh, Gh):
+def wall_spectrum(box, wall):
+    """xy DFT (unnormalised, like the force densities) of tangential wall
+    velocities given at the grid nodes of the walls.
+
+    wall: (nw, 2, Ny, Nx) with (u^W, v^W) of the wall at z = 0 and, for the
+    slit channel (nw = 2), of the wall at z = H.  Returns (4, Ny, Nx/2+1):
+    u^W(0), v^W(0), u^W(H), v^W(H).  Reading: the Nyquist modes are dropped
+    like those of the forcing (a field sampled on the grid resolves only
+    |n| < N/2).
+    """
+    wall = np.asarray(wall, dtype=np.float64)
+    nw = 2 if box.geometry == "sc" else 1
+    if wall.shape != (nw, 2, box.Ny, box.Nx):
+        raise ValueError(f"wall velocities have shape {(nw, 2, box.Ny, box.Nx)}")
+    out = np.zeros((4, box.Ny, box.Nx // 2 + 1), complex)
+    out[:2 * nw] = np.fft.rfft2(wall.reshape(2 * nw, box.Ny, box.Nx),
+                                axes=(-2, -1))
+    _, _, nyq = wavenumbers(box.Lx, box.Ly, box.Nx, box.Ny)
+    return np.where(nyq[None], 0.0, out)
+
+
+def solve_coefficients(box, Fh, Gh, wall_hat=None):
     """Steps 2 (derivative part) to 6 in coefficient space.
 
     Fh, Gh: complex (3, Nz, Ny, Nx/2+1) Fourier-Chebyshev coefficients of the
-    monopole and dipole densities.  Returns (uh, omh) of the same shape.
+    monopole and dipole densities.  wall_hat: None, or wall_spectrum() of
+    non-uniform wall velocities (they add to the uniform box.wall0/wallH).
+    Returns (uh, omh) of the same shape.
     """
     H, Nz = box.H, box.Nz
     KX, KY, nyq = wavenumbers(box.Lx, box.Ly, box.Nx, box.Ny)
@@ -219,19 +252,23 @@ def solve_coefficients(box, Fh, Gh):
     U = [np.zeros((kx.size, Nz), complex) for _ in range(3)]
     cx, cy, cz = col(fx), col(fy), col(fz)
     idx = np.nonzero(live)[0]
+    wl = None if wall_hat is None else wall_hat.reshape(4, -1)
     uu, vv, ww = _dp_and_correction(box, kx[idx], ky[idx], cx[idx], cy[idx],
-                                    cz[idx])
+                                    cz[idx], None if wl is None else wl[:, idx])
     U[0][idx], U[1][idx], U[2][idx] = uu, vv, ww
     # Step 5: k = 0 mode (Sec. 3.3; App. A.2 for the slit channel); w = 0.
     # Uniform wall velocities enter only here: the unnormalised xy DFT of a
-    # constant c is c Nx Ny at k = 0.
+    # constant c is c Nx Ny at k = 0; a non-uniform field adds its mean the
+    # same way (its k = 0 coefficient).
     k0 = np.nonzero(k2 == 0)[0]
     nxy = box.Nx * box.Ny
     for j in k0:
         for c, cc in ((0, cx), (1, cy)):
+            g0, gH = nxy * box.wall0[c], nxy * box.wallH[c]
+            if wl is not None:
+                g0, gH = g0 + wl[c, j].real, gH + wl[2 + c, j].real
             U[c][j] = bvp.zero_mode_solve(-cc[j] / box.eta, H, box.geometry,
-                                          box.slip0, box.slipH,
-                                          nxy * box.wall0[c], nxy * box.wallH[c])
+                                          box.slip0, box.slipH, g0, gH)
     uh = np.stack([U[i].T.reshape(shape) for i in range(3)])
     # vorticity: omega = (1/2) curl u in Fourier-Chebyshev space
     cu = curl(uh[0], uh[1], uh[2], ikx, iky, D)
@@ -250,9 +287,11 @@ def inverse_transform(box, fh):
                          axes=(-2, -1))
 
 
-def stokes_solve(box, f, g):
-    """Velocity u and (1/2) curl u at the nodes from spread densities f, g."""
+def stokes_solve(box, f, g, wall=None):
+    """Velocity u and (1/2) curl u at the nodes from spread densities f, g
+    (wall: optional non-uniform wall velocities, see wall_spectrum)."""
     Fh = forward_transform(box, f)
     Gh = forward_transform(box, g)
-    uh, omh = solve_coefficients(box, Fh, Gh)
+    uh, omh = solve_coefficients(box, Fh, Gh,
+                                 None if wall is None else wall_spectrum(box, wall))
     return inverse_transform(box, uh), inverse_transform(box, omh)

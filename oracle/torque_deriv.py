@@ -69,12 +69,11 @@ class DerivativeSolver(fcm.Solver):
         """Indices (P, 9), phi_D and its truncated derivative on a 9-point
         window around x (derivative with respect to the grid coordinate)."""
         h = self.h
-        i0 = np.floor(x / h).astype(np.int64)
-        a = i0[:, None] + np.arange(-4, 5)[None, :]
-        t = a * h - x[:, None]
-        t = (t + 0.5 * L) % L - 0.5 * L
+        u = x / h
+        a = np.floor(u)[:, None] + np.arange(-4, 5)[None, :]
+        t = (a - u[:, None]) * h      # node offset, as in fcm.Solver
         b = self.box
-        return (a % N, phi(t, self.alpha, b.beta_d, self.norm_d),
+        return (a.astype(np.int64) % N, phi(t, self.alpha, b.beta_d, self.norm_d),
                 dphi(t, self.alpha, b.beta_d, self.norm_d, self.tstar))
 
     def _z_dweights(self, z):

@@ -58,6 +58,27 @@ def test_spread_interp_adjoint(geometry):
     assert lhs == pytest.approx(rhs, rel=1e-13)
 
 
+@pytest.mark.parametrize("L,N,k", [(1448.0, 2176, 1071), (16.0, 24, 0)])
+def test_particle_on_a_grid_node_keeps_both_support_edges(L, N, k):
+    # x = k h exactly (h = 181/272 makes every 17th node of the 2176-node
+    # grid an FP32 value; k = 0 sits on the periodic seam): the closed
+    # support |t| <= alpha = 3h (eq. es) holds seven nodes, the two edge
+    # nodes with the value e^{-beta}/norm, and the spread is symmetric
+    box = Box("bw", L, L, 8.0, N, N, 16)
+    s = oracle.Solver(box)
+    x = np.array([k * (L / N)])
+    assert x[0] / s.h == k
+    idx, w = s._axis_weights(x, L, N, box.beta_m, s.norm_m)
+    live = w[0] != 0.0
+    assert live.sum() == 7
+    got = dict(zip(idx[0][live] % N, w[0][live]))
+    edge = np.exp(-box.beta_m) / s.norm_m
+    for d in (3, -3):
+        assert got[(k + d) % N] == pytest.approx(edge, rel=1e-12)
+    for d in (1, 2, 3):
+        assert got[(k + d) % N] == pytest.approx(got[(k - d) % N], rel=1e-13)
+
+
 def test_integer_cell_shift_invariance():
     box, s, pos, rng = _setup("sc")
     F, T = rng.standard_normal((6, 3)), rng.standard_normal((6, 3))
