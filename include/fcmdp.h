@@ -185,6 +185,28 @@ int fcmdp_lanczos_sqrt_noalloc(fcmdp_solver* s, int64_t n, const void* pos,
                                const void* W, void* g, int max_iter, double tol,
                                int* iters, double* rel_change, void* hip_stream);
 
+/*
+ * Non-uniform tangential wall velocities u^W(x, y) (eq. bcnoslip0 for the
+ * bottom wall; App. A, eqs. bcslip and u0uHformula for the slit channel):
+ *   wall: device array [nw][2][Ny][Nx] of (u^W, v^W) at the grid nodes
+ *         x_a = a Lx / Nx, y_b = b Ly / Ny of the wall at z = 0 and, for the
+ *         slit channel (nw = 2), of the wall at z = H (nw = 1 for the bottom
+ *         wall).  Element type as for the particle arrays (float in MIXED,
+ *         double in FP64 mode).  Read on `hip_stream` during this call only.
+ *         NULL removes the field (walls back to the uniform params.wall0 /
+ *         wallH).
+ * The field adds to the uniform wall velocities of fcmdp_params and applies
+ * to every later fcmdp_apply_mobility, fcmdp_stage_solve and Lanczos call
+ * of this solver: its unnormalised xy DFT (Nyquist modes dropped) enters the
+ * correction's boundary data at every wavenumber and its mean the k = 0
+ * mode.  Computed on `hip_stream` with the solver's own transforms; the
+ * spectrum (4 (Nx/2+1) Ny complex words) is allocated on first use
+ * (stream-ordered) and kept with the solver.  Like every call on one
+ * solver, it must be ordered with the solver's other calls.  Returns
+ * EINVAL for s == NULL or Nz > 32 (the eight-lane column kernels), EHIP.
+ */
+int fcmdp_set_wall_velocity(fcmdp_solver* s, const void* wall, void* hip_stream);
+
 /* Derived quantities of a solver (host only): out[0] = h, out[1] = alpha,
  * out[2] = ES normalisation integral of the monopole kernel, out[3] = of the
  * dipole kernel (the integral in eq. es-scalar). */

@@ -98,6 +98,8 @@ def lib() -> ctypes.CDLL:
         L.fcmdp_stage_times.restype = ci
         L.fcmdp_set_variant.argtypes = [vp, ci, ci]
         L.fcmdp_set_variant.restype = ci
+        L.fcmdp_set_wall_velocity.argtypes = [vp, vp, vp]
+        L.fcmdp_set_wall_velocity.restype = ci
         _lib = L
     return _lib
 

@@ -343,7 +343,8 @@ void free_all(fcmdp_solver* s, hipStream_t st) {
                   s->dct_f32, s->dct_i32,
                   s->dftc, s->dftc_t, s->tw_x, s->tw_y, s->tw_r,
                   s->lz_basis, s->lz_red, s->psi64, s->fzlo, s->lowk_part,
-                  s->lowk_coef, s->lowk_ex, s->lowk_ey, s->pdw, s->dpsi};
+                  s->lowk_coef, s->lowk_ex, s->lowk_ey, s->pdw, s->dpsi,
+                  s->wallspec};
   // stream-ordered frees: no device-wide synchronisation
   for (void* q : ptrs)
     if (q) (void)hipFreeAsync(q, st);
@@ -412,6 +413,7 @@ int fcmdp_create_solver(const fcmdp_params* p, void* hip_stream,
     dp.wall0[c] = p->wall0[c];
     dp.wallH[c] = p->wallH[c];
   }
+  dp.wallspec = nullptr;
   dp.Lx = p->Lx;
   dp.Ly = p->Ly;
   dp.H = p->H;
@@ -612,6 +614,36 @@ void fcmdp_destroy_solver(fcmdp_solver* s, void* hip_stream) {
   s->events.clear();
   free_all(s, (hipStream_t)hip_stream);
   delete s;
+}
+
+int fcmdp_set_wall_velocity(fcmdp_solver* s, const void* wall,
+                            void* hip_stream) {
+  if (!s) return FCMDP_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return FCMDP_EHIP;
+  if (!wall) {
+    s->dp.wallspec = nullptr;
+    return FCMDP_OK;
+  }
+  // the wall data enter the eight-lane column kernels only
+  if (s->dp.Nz > 32) return FCMDP_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t csz = s->mixed ? 8 : 16;
+  if (!s->wallspec &&
+      hipMallocAsync(&s->wallspec, 4 * (size_t)s->dp.Nkx * s->dp.Ny * csz, st) !=
+          hipSuccess) {
+    s->wallspec = nullptr;
+    return FCMDP_EHIP;
+  }
+  const fcmdp::DevParams saved = s->dp;
+  s->dp.nch_in = 3;
+  s->dp.lowk_ns = -1;
+  s->dp.lowk_coef = nullptr;
+  s->dp.wallspec = nullptr;
+  const hipError_t e = fcmdp::launch_wall_spectrum(s, wall, st);
+  s->dp = saved;
+  if (e != hipSuccess) return FCMDP_EHIP;
+  s->dp.wallspec = s->wallspec;
+  return FCMDP_OK;
 }
 
 int fcmdp_solver_info(const fcmdp_solver* s, double out[4]) {

@@ -307,10 +307,12 @@ k_columns(ColParams cp, const int* __restrict__ band,
 
 hipError_t launch_columns(const fcmdp_solver* s, const void* spec_in,
                           void* spec_out, hipStream_t st) {
-  // (partial slip is solved by the eight-lane kernels only)
+  // (partial slip and wall velocities are solved by the eight-lane kernels
+  // only)
   const bool slip = s->dp.slip0 != 0.0 || s->dp.slipH != 0.0 ||
                     s->dp.wall0[0] != 0.0 || s->dp.wall0[1] != 0.0 ||
-                    s->dp.wallH[0] != 0.0 || s->dp.wallH[1] != 0.0;
+                    s->dp.wallH[0] != 0.0 || s->dp.wallH[1] != 0.0 ||
+                    s->dp.wallspec != nullptr;
   if (s->dp.Nz <= 32 && (!s->force_generic_columns || slip))
     return launch_columns_seg(s, spec_in, spec_out, st);
   ColParams cp;

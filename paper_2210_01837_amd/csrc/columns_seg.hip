@@ -837,11 +837,29 @@ __device__ __forceinline__ Vec ps_zero_mode(const Vec& r, double H, int N, int g
 // SPLIT selects the parity-split coefficient layout (ps_*) instead of four
 // consecutive coefficients per lane.  FO (forces only): there is no dipole
 // density, `load` provides v = 0..2 only and f is A0, A1, A2 itself.
+// Wall velocities of one column (unnormalised xy DFT; zero without a
+// non-uniform field): u^W, v^W at z = 0, then at z = H.
+template <typename T>
+__device__ __forceinline__ void wall_data(const DevParams& dp, int idx,
+                                          Z2 (&wb)[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) wb[i] = zmk(0, 0);
+  if (!dp.wallspec) return;
+  const cplx_t<T>* w = static_cast<const cplx_t<T>*>(dp.wallspec);
+  const size_t K = (size_t)dp.Nkx * dp.Ny;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const cplx_t<T> v = w[i * K + idx];
+    wb[i] = zmk((double)v.x, (double)v.y);
+  }
+}
+
 template <int GEOM, bool SPLIT = false, bool FO = false, typename Load,
           typename Basis>
 __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& basis,
                                  const DevParams& dp, int N, int l,
-                                 double kx, double ky, double k, Vec& U,
+                                 double kx, double ky, double k,
+                                 const Z2 (&wb)[4], Vec& U,
                                  Vec& V, Vec& W) {
   const double H = dp.H, eta = dp.eta, s2H = 2.0 / H;
   U = vzero();
@@ -859,11 +877,13 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
   const double a0s = GEOM == 1 ? 2.0 * dp.slip0 / H : 0.0;
   const double aHs = GEOM == 1 ? 2.0 * dp.slipH / H : 0.0;
   // uniform wall velocities: the k = 0 wall data in the unnormalised xy DFT
-  // (a constant c transforms to c Nx Ny)
+  // (a constant c transforms to c Nx Ny); a non-uniform field adds its own
+  // k = 0 coefficient (its mean times Nx Ny)
   const double nxy = (double)dp.Nx * (double)dp.Ny;
-  const double g0x = nxy * dp.wall0[0], g0y = nxy * dp.wall0[1];
-  const double gHx = GEOM == 1 ? nxy * dp.wallH[0] : 0.0;
-  const double gHy = GEOM == 1 ? nxy * dp.wallH[1] : 0.0;
+  const double g0x = nxy * dp.wall0[0] + wb[0].x;
+  const double g0y = nxy * dp.wall0[1] + wb[1].x;
+  const double gHx = GEOM == 1 ? nxy * dp.wallH[0] + wb[2].x : 0.0;
+  const double gHy = GEOM == 1 ? nxy * dp.wallH[1] + wb[3].x : 0.0;
   auto body_x = [&]() {
     Vec f = load(0);
     if constexpr (!FO) {
@@ -942,8 +962,9 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     }
     V = solve(r, imul(-ay, pH), imul(ay, p0));
 
-    // wall correction, evaluated on all nodes and transformed
-    const Z2 u0 = -1.0 * bot(U), v0 = -1.0 * bot(V), w0 = -1.0 * bot(W);
+    // wall correction, evaluated on all nodes and transformed; boundary
+    // data u^W - u_DP at the walls (eq. bcnoslip0; App. A, eq. u0uHformula)
+    const Z2 u0 = wb[0] - bot(U), v0 = wb[1] - bot(V), w0 = -1.0 * bot(W);
     double E[kNpl], ZE[kNpl];
     basis(0, E);
     basis(1, ZE);
@@ -958,7 +979,7 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
         W.v[j] = W.v[j] + ZE[j] * Bc + E[j] * w0;
       }
     } else {
-      Z2 uH = -1.0 * bsum_top(U), vH = -1.0 * bsum_top(V);
+      Z2 uH = wb[2] - bsum_top(U), vH = wb[3] - bsum_top(V);
       const Z2 wH = -1.0 * bsum_top(W);
       const double Ex = exp(-k * H);
       const double hh = 0.5 * H * ie, e2 = 0.5 * ie;
@@ -1132,8 +1153,10 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) out[j] = (which & 1) ? ZE[j] : E[j];
     };
+    Z2 wb[4];
+    wall_data<T>(dp, idx, wb);
     seg_column_solve<GEOM>([&](int v) { return A[v]; }, basis, dp, N, l, kx,
-                           ky, k, U, V, W);
+                           ky, k, wb, U, V, W);
   }
   DU = seg_deriv(U, l, s2H);
   DV = seg_deriv(V, l, s2H);
@@ -1491,7 +1514,10 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
 #pragma unroll
         for (int j = 0; j < kNpl; ++j) o[j] = (double)bbase[2 * j * kMV + which];
       };
-      seg_column_solve<GEOM, true, FO>(load, basis, dp, N, l, kx, ky, k, U, V, W);
+      Z2 wb[4];
+      wall_data<float>(dp, kxi * dp.Ny + kyi, wb);
+      seg_column_solve<GEOM, true, FO>(load, basis, dp, N, l, kx, ky, k, wb, U,
+                                       V, W);
     }
     // the column's coefficients are read only by its own eight lanes (one
     // wavefront, in lockstep): overwrite them in place

@@ -71,6 +71,10 @@ struct DevParams {
   double beta_m, beta_d, inv_norm_m, inv_norm_d;
   double slip0, slipH;          // slit channel slip lengths (0 = no slip)
   double wall0[2], wallH[2];    // uniform wall velocities (x, y)
+  // non-uniform wall velocities: unnormalised xy DFT of u^W, v^W at z = 0,
+  // then at z = H, [4][Nkx][Ny] complex in the solver's precision (Nyquist
+  // entries zero); nullptr = none
+  const void* wallspec;
   // exact low-wavenumber vertical force: columns with |nx|, |ny| <= lowk_ns
   // take the FP64 Chebyshev coefficients of f_z from lowk_coef and FP64
   // correction node functions; -1 = off for this launch
@@ -127,6 +131,7 @@ struct fcmdp_solver {
   double2* lowk_coef = nullptr;
   double2* lowk_ex = nullptr;   // e^{-2 pi i nx a / Nx}, [Nx][ns+1]
   double2* lowk_ey = nullptr;   // e^{-2 pi i m / Ny}, [Ny]
+  void* wallspec = nullptr;     // see DevParams::wallspec; kept once set
   unsigned int* nbad = nullptr;
 
   // tables (device)
@@ -197,6 +202,11 @@ hipError_t launch_interp(const fcmdp_solver* s, int n, const void* grid,
 hipError_t launch_lowk(const fcmdp_solver* s, const void* grid, hipStream_t st);
 // whether the apply's launches use the exact low-wavenumber vertical force
 bool lowk_active(const fcmdp_solver* s);
+// wall.hip: spectra of non-uniform wall velocities [nw][2][Ny][Nx] into
+// s->wallspec (uses the grid, the spectrum and the band as scratch; the
+// caller sets three input channels)
+hipError_t launch_wall_spectrum(const fcmdp_solver* s, const void* wall,
+                                hipStream_t st);
 // fft.hip
 hipError_t launch_fft_forward(const fcmdp_solver* s, const void* grid,
                               void* spec, hipStream_t st);

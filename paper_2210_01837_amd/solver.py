@@ -162,6 +162,23 @@ class Solver:
         self._mark(stream)
         return g, it.value, ch.value
 
+    def set_wall_velocity(self, wall, stream=None):
+        """Non-uniform tangential wall velocities (fcmdp_set_wall_velocity):
+        a contiguous device tensor (nw, 2, Ny, Nx) of the solver's dtype with
+        (u^W, v^W) at the grid nodes of the wall at z = 0 (and at z = H for
+        the slit channel, nw = 2), or None to remove the field."""
+        if wall is not None:
+            nw = 2 if self.params.geometry == 1 else 1
+            if (wall.dtype != self.dtype or not wall.is_cuda or
+                    not wall.is_contiguous()):
+                raise TypeError("wall velocities must be a contiguous device "
+                                f"tensor of dtype {self.dtype}")
+            if tuple(wall.shape) != (nw, 2, self.Ny, self.Nx):
+                raise ValueError(f"wall velocities have shape {(nw, 2, self.Ny, self.Nx)}")
+        L.check(L.lib().fcmdp_set_wall_velocity(self._h, _ptr(wall), _stream(stream)),
+                "fcmdp_set_wall_velocity")
+        self._mark(stream)
+
     STAGES = ("particles", "spread", "fft_forward", "columns", "fft_inverse",
               "interp")
 
