@@ -838,28 +838,29 @@ __device__ __forceinline__ Vec ps_zero_mode(const Vec& r, double H, int N, int g
 // consecutive coefficients per lane.  FO (forces only): there is no dipole
 // density, `load` provides v = 0..2 only and f is A0, A1, A2 itself.
 // Wall velocities of one column (unnormalised xy DFT; zero without a
-// non-uniform field): u^W, v^W at z = 0, then at z = H.
+// non-uniform field): (i) = u^W, v^W at z = 0, then at z = H, loaded where
+// they are used (no registers held across the solve).
 template <typename T>
-__device__ __forceinline__ void wall_data(const DevParams& dp, int idx,
-                                          Z2 (&wb)[4]) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i) wb[i] = zmk(0, 0);
-  if (!dp.wallspec) return;
-  const cplx_t<T>* w = static_cast<const cplx_t<T>*>(dp.wallspec);
-  const size_t K = (size_t)dp.Nkx * dp.Ny;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const cplx_t<T> v = w[i * K + idx];
-    wb[i] = zmk((double)v.x, (double)v.y);
+struct WallRef {
+  const cplx_t<T>* p;
+  size_t K;
+  int idx;
+  __device__ WallRef(const DevParams& dp, int idx_)
+      : p(static_cast<const cplx_t<T>*>(dp.wallspec)),
+        K((size_t)dp.Nkx * dp.Ny), idx(idx_) {}
+  __device__ Z2 operator()(int i) const {
+    if (!p) return zmk(0, 0);
+    const cplx_t<T> v = p[i * K + idx];
+    return zmk((double)v.x, (double)v.y);
   }
-}
+};
 
 template <int GEOM, bool SPLIT = false, bool FO = false, typename Load,
-          typename Basis>
+          typename Basis, typename Wall>
 __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& basis,
                                  const DevParams& dp, int N, int l,
                                  double kx, double ky, double k,
-                                 const Z2 (&wb)[4], Vec& U,
+                                 const Wall& wall, Vec& U,
                                  Vec& V, Vec& W) {
   const double H = dp.H, eta = dp.eta, s2H = 2.0 / H;
   U = vzero();
@@ -880,10 +881,6 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
   // (a constant c transforms to c Nx Ny); a non-uniform field adds its own
   // k = 0 coefficient (its mean times Nx Ny)
   const double nxy = (double)dp.Nx * (double)dp.Ny;
-  const double g0x = nxy * dp.wall0[0] + wb[0].x;
-  const double g0y = nxy * dp.wall0[1] + wb[1].x;
-  const double gHx = GEOM == 1 ? nxy * dp.wallH[0] + wb[2].x : 0.0;
-  const double gHy = GEOM == 1 ? nxy * dp.wallH[1] + wb[3].x : 0.0;
   auto body_x = [&]() {
     Vec f = load(0);
     if constexpr (!FO) {
@@ -903,6 +900,10 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     return f;
   };
   if (k == 0.0) {
+    const double g0x = nxy * dp.wall0[0] + wall(0).x;
+    const double g0y = nxy * dp.wall0[1] + wall(1).x;
+    const double gHx = GEOM == 1 ? nxy * dp.wallH[0] + wall(2).x : 0.0;
+    const double gHy = GEOM == 1 ? nxy * dp.wallH[1] + wall(3).x : 0.0;
     Vec r = body_x();
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) r.v[j] = (-1.0 / eta) * r.v[j];
@@ -964,7 +965,7 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
 
     // wall correction, evaluated on all nodes and transformed; boundary
     // data u^W - u_DP at the walls (eq. bcnoslip0; App. A, eq. u0uHformula)
-    const Z2 u0 = wb[0] - bot(U), v0 = wb[1] - bot(V), w0 = -1.0 * bot(W);
+    const Z2 u0 = wall(0) - bot(U), v0 = wall(1) - bot(V), w0 = -1.0 * bot(W);
     double E[kNpl], ZE[kNpl];
     basis(0, E);
     basis(1, ZE);
@@ -979,7 +980,7 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
         W.v[j] = W.v[j] + ZE[j] * Bc + E[j] * w0;
       }
     } else {
-      Z2 uH = wb[2] - bsum_top(U), vH = wb[3] - bsum_top(V);
+      Z2 uH = wall(2) - bsum_top(U), vH = wall(3) - bsum_top(V);
       const Z2 wH = -1.0 * bsum_top(W);
       const double Ex = exp(-k * H);
       const double hh = 0.5 * H * ie, e2 = 0.5 * ie;
@@ -1153,10 +1154,8 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) out[j] = (which & 1) ? ZE[j] : E[j];
     };
-    Z2 wb[4];
-    wall_data<T>(dp, idx, wb);
     seg_column_solve<GEOM>([&](int v) { return A[v]; }, basis, dp, N, l, kx,
-                           ky, k, wb, U, V, W);
+                           ky, k, WallRef<T>(dp, idx), U, V, W);
   }
   DU = seg_deriv(U, l, s2H);
   DV = seg_deriv(V, l, s2H);
@@ -1514,10 +1513,9 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
 #pragma unroll
         for (int j = 0; j < kNpl; ++j) o[j] = (double)bbase[2 * j * kMV + which];
       };
-      Z2 wb[4];
-      wall_data<float>(dp, kxi * dp.Ny + kyi, wb);
-      seg_column_solve<GEOM, true, FO>(load, basis, dp, N, l, kx, ky, k, wb, U,
-                                       V, W);
+      seg_column_solve<GEOM, true, FO>(load, basis, dp, N, l, kx, ky, k,
+                                       WallRef<float>(dp, kxi * dp.Ny + kyi),
+                                       U, V, W);
     }
     // the column's coefficients are read only by its own eight lanes (one
     // wavefront, in lockstep): overwrite them in place
