@@ -86,6 +86,43 @@ def measured_traffic(workload, kernel):
     return k["bytes_per_launch"]
 
 
+# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; dense peaks (TFLOP/s)
+FP64_VECTOR_PEAK = 78.6
+FP32_MATRIX_PEAK = 157.3
+SIMDS, CLOCK_HZ = 1024, 2.4e9
+
+
+def measured_compute(workload, kernel, avg_ms):
+    """Arithmetic roofline of one kernel from the committed rocprofv3 FLOP
+    and instruction counters (profiles/compute_<workload>.json) and the
+    launch time measured here, or None if there are none or the kernel's
+    sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"compute_{workload}.json")
+    if not kernel or not os.path.exists(path):
+        return None
+    from paper_2210_01837_amd.profiling import source_hash
+    with open(path) as fh:
+        t = json.load(fh)
+    k = t.get("kernels", {}).get(kernel)
+    if not k or k.get("source_hash") != source_hash(kernel):
+        return None
+    sec = avg_ms * 1e-3
+    f64 = k["fp64_vector_flops"] / sec / 1e12
+    mf = k["fp32_matrix_flops"] / sec / 1e12
+    out = {"bound": "alu", "unit": "TFLOP/s",
+           "achieved": f64, "peak": FP64_VECTOR_PEAK,
+           "frac": f64 / FP64_VECTOR_PEAK,
+           "flops_fp64_per_launch": k["fp64_vector_flops"],
+           "mfma_f32": {"achieved": mf, "peak": FP32_MATRIX_PEAK,
+                        "frac": mf / FP32_MATRIX_PEAK},
+           "source": f"profiles/compute_{workload}.json (executed FLOPs)"}
+    insts = k["counters"].get("SQ_INSTS_VALU")
+    if insts:
+        # a wave64 VALU instruction occupies its SIMD for 4 cycles
+        out["valu_issue_frac"] = insts * 4 / (SIMDS * CLOCK_HZ * sec)
+    return out
+
+
 def fp64_comparison(name="bw131k", steps=5):
     """Mixed vs FP64 GPU applies on the same inputs: time and agreement."""
     import numpy as np
@@ -448,6 +485,9 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(name, kname),
                 "algorithmic_bytes": nbytes[dom], "avg_ms": avg[dom]}
+    comp = measured_compute(name, kname, avg[dom])
+    if comp is not None:
+        roofline["compute"] = comp
     stage_gbs = {k: nbytes[k] / (avg[k] * 1e-3) / 1e9 for k in nbytes}
     # the same accounting with every plane transformed (P = Nz), for
     # comparison with a full-grid implementation

@@ -12,6 +12,13 @@
         run), written as JSON with a hash of the kernel sources so that a
         reader can tell when the counters no longer describe the code.
 
+    python -m paper_2210_01837_amd.profiling compute --pmc DIR [--pmc DIR] \
+        --workload NAME --out FILE
+        executed arithmetic per launch of every kernel from `--pmc` runs of
+        the FLOP and instruction counters (FP64 and FP32 vector FLOPs,
+        FP32 matrix-core operations, VALU instructions and wavefronts), as
+        JSON with the same source hash.
+
 Only CSV files are read; nothing here touches the GPU.
 """
 from __future__ import annotations
@@ -114,6 +121,32 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes,
             "kernels": kernels}
 
 
+def compute(pmc_dirs, workload):
+    """Executed FLOPs per launch: SQ_INSTS_VALU_FLOPS_FP64 (+ _TRANS) and
+    _FP32 (+ _TRANS) count vector FLOPs, SQ_INSTS_VALU_MFMA_MOPS_F32 counts
+    matrix-core operations in units of 512 FLOPs."""
+    merged = collections.defaultdict(dict)
+    for d in pmc_dirs:
+        for k, cs in counter_means(d).items():
+            merged[k].update(cs)
+    kernels = {}
+    for k, cs in sorted(merged.items()):
+        if not k.startswith("k_"):
+            continue
+        g = cs.get
+        e = {"counters": cs,
+             "fp64_vector_flops": g("SQ_INSTS_VALU_FLOPS_FP64", 0.0) +
+             g("SQ_INSTS_VALU_FLOPS_FP64_TRANS", 0.0),
+             "fp32_vector_flops": g("SQ_INSTS_VALU_FLOPS_FP32", 0.0) +
+             g("SQ_INSTS_VALU_FLOPS_FP32_TRANS", 0.0),
+             "fp32_matrix_flops": 512.0 * g("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0),
+             "source_hash": source_hash(k) if k in KERNEL_SOURCES else None}
+        if g("SQ_WAVES"):
+            e["valu_insts_per_wave"] = g("SQ_INSTS_VALU", 0.0) / g("SQ_WAVES")
+        kernels[k] = e
+    return {"workload": workload, "kernels": kernels}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -127,9 +160,21 @@ def main(argv=None):
     b.add_argument("--copy-bytes", type=float, default=float(1 << 30))
     b.add_argument("--workload", required=True)
     b.add_argument("--out", required=True)
+    c = sub.add_parser("compute")
+    c.add_argument("--pmc", action="append", required=True)
+    c.add_argument("--workload", required=True)
+    c.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print(stats_markdown(args.dir))
+    elif args.cmd == "compute":
+        t = compute(args.pmc, args.workload)
+        with open(args.out, "w") as fh:
+            json.dump(t, fh, indent=1)
+        print(json.dumps({k: {"fp64_gflop": round(v["fp64_vector_flops"] / 1e9, 3),
+                              "fp32_gflop": round(v["fp32_vector_flops"] / 1e9, 3),
+                              "mfma_f32_gflop": round(v["fp32_matrix_flops"] / 1e9, 3)}
+                          for k, v in t["kernels"].items()}))
     else:
         t = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write,
                     args.copy_bytes, args.workload)
