@@ -362,9 +362,11 @@ def test_apply_mixed_full_size_golden(name):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["bw1m", "sc1m"])
-def test_apply_fp64_full_size_golden(name):
-    # measured 6e-9 (bw1m) and 4e-8 (sc1m)
+@pytest.mark.parametrize("name,tol", [("bw1m", 1e-12), ("sc1m", 1e-11)])
+def test_apply_fp64_full_size_golden(name, tol):
+    # measured 3.3e-14 (bw1m) and 3.6e-13 (sc1m; the slit channel's kH < 0.1
+    # columns amplify rounding, the oracle itself agrees with extended
+    # precision to 2e-10 per column there)
     g = _golden(name)
     wl = workloads.WORKLOADS[name]
     pos, F, T = workloads.particles(name)
@@ -379,7 +381,7 @@ def test_apply_fp64_full_size_golden(name):
     pU, pO = particle_err(Ug, g["U"]), particle_err(Og, g["Omega"])
     print(f"  rel err U {eU:.2e} Omega {eO:.2e}; max particle {pU:.2e} "
           f"{pO:.2e}", flush=True)
-    assert eU < 1e-6 and eO < 1e-6
+    assert eU < tol and eO < tol and pU < 10 * tol and pO < 10 * tol
     s.close()
 
 
