@@ -282,7 +282,9 @@ int fcmdp_stage_fft_forward(fcmdp_solver* s, const void* grid, void* spectrum,
 /* Steps 2 (z part) to 6 and the vorticity curl: per-wavenumber solve from
  * the node values of f and g (planes c_lo..c_hi, zero elsewhere) to the node
  * values of u and omega on planes c_lo..c_hi, scaled by 1/(Nx*Ny) so that
- * fcmdp_stage_fft_inverse yields physical values.  Nyquist modes are zero. */
+ * fcmdp_stage_fft_inverse yields physical values.  Nyquist modes are zero.
+ * spectrum_out may be spectrum_in (in place: every column is read whole
+ * before its results are written). */
 int fcmdp_stage_solve(fcmdp_solver* s, const void* spectrum_in,
                       void* spectrum_out, int c_lo, int c_hi,
                       void* hip_stream);

@@ -123,8 +123,10 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes,
 
 def compute(pmc_dirs, workload):
     """Executed FLOPs per launch: SQ_INSTS_VALU_FLOPS_FP64 (+ _TRANS) and
-    _FP32 (+ _TRANS) count vector FLOPs, SQ_INSTS_VALU_MFMA_MOPS_F32 counts
-    matrix-core operations in units of 512 FLOPs."""
+    _FP32 (+ _TRANS) count the FLOPs of each wavefront instruction per lane
+    (2 FMA + ADD + MUL + TRANS), so the executed vector FLOPs are 64 times
+    them; SQ_INSTS_VALU_MFMA_MOPS_F32 counts matrix-core operations in units
+    of 512 FLOPs."""
     merged = collections.defaultdict(dict)
     for d in pmc_dirs:
         for k, cs in counter_means(d).items():
@@ -135,10 +137,10 @@ def compute(pmc_dirs, workload):
             continue
         g = cs.get
         e = {"counters": cs,
-             "fp64_vector_flops": g("SQ_INSTS_VALU_FLOPS_FP64", 0.0) +
-             g("SQ_INSTS_VALU_FLOPS_FP64_TRANS", 0.0),
-             "fp32_vector_flops": g("SQ_INSTS_VALU_FLOPS_FP32", 0.0) +
-             g("SQ_INSTS_VALU_FLOPS_FP32_TRANS", 0.0),
+             "fp64_vector_flops": 64.0 * (g("SQ_INSTS_VALU_FLOPS_FP64", 0.0) +
+                                          g("SQ_INSTS_VALU_FLOPS_FP64_TRANS", 0.0)),
+             "fp32_vector_flops": 64.0 * (g("SQ_INSTS_VALU_FLOPS_FP32", 0.0) +
+                                          g("SQ_INSTS_VALU_FLOPS_FP32_TRANS", 0.0)),
              "fp32_matrix_flops": 512.0 * g("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0),
              "source_hash": source_hash(k) if k in KERNEL_SOURCES else None}
         if g("SQ_WAVES"):

@@ -257,10 +257,14 @@ class Solver:
         self._mark(stream)
         return spec
 
-    def stage_solve(self, spec, c_lo, c_hi, stream=None):
+    def stage_solve(self, spec, c_lo, c_hi, stream=None, out=None):
+        """Column solve of planes c_lo..c_hi; `out` may be `spec` (in place)."""
         import torch
         self._check_buffer(spec, self.spectrum_shape(), self._cplx(), "spectrum")
-        out = torch.zeros_like(spec)
+        if out is None:
+            out = torch.zeros_like(spec)
+        else:
+            self._check_buffer(out, self.spectrum_shape(), self._cplx(), "spectrum")
         L.check(L.lib().fcmdp_stage_solve(self._h, _ptr(spec), _ptr(out), c_lo,
                                           c_hi, _stream(stream)),
                 "fcmdp_stage_solve")
