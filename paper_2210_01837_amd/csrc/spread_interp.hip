@@ -664,6 +664,10 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
   int4* pci = reinterpret_cast<int4*>(acc + cap * NOUT); // [cap]
   int* pcj = reinterpret_cast<int*>(pci + cap);         // [cap] output index
   int* pcp = pcj + cap;                                 // [cap] sorted index
+  // folded z weights of the current chunk per home particle (M, D and with
+  // DT the z derivative of D), staged with the grid planes
+  constexpr int NZS = (DT ? 3 : 2) * ZC;
+  T* pz = reinterpret_cast<T*>(pcp + cap);              // [cap][NZS]
   __shared__ int rowoff[kTile + 1];
   __shared__ int rowstart[kTile];
   __shared__ int ytab[kRX];
@@ -749,9 +753,13 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
     static_assert(kRX == 2 * kRG, "staging layout");
     constexpr int kPer = 2 * NCH * ZC;
     T pre[kPer];
+    T prez[NZS];              // home particle tid's z weights of the chunk
     const bool stager = tid < kRG * kRX;
     const size_t yrow0 = stager ? (size_t)ytab[rg] * dp.Nx + xa : 0;
     const size_t yrow1 = stager ? (size_t)ytab[rg + kRG] * dp.Nx + xa : 0;
+    const bool zstager = tid < np;
+    const T* zsrc = psi + (size_t)(zstager ? pcp[tid] : 0) * 2 * dp.Nz;
+    const T* dsrc = DT ? dpsi + (size_t)(zstager ? pcp[tid] : 0) * dp.Nz : nullptr;
     auto fetch = [&](int c0) {
       const int nz = min(ZC, c_last - c0 + 1);
       const T* gb = grid + (size_t)c0 * plane;
@@ -761,6 +769,14 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
         if (stager && sidx < nz)
           pre[e] = gb[ch * chstride + (size_t)sidx * plane + ((e & 1) ? yrow1 : yrow0)];
       }
+#pragma unroll
+      for (int sidx = 0; sidx < ZC; ++sidx) {
+        if (zstager && sidx < nz) {
+          prez[sidx] = zsrc[c0 + sidx];
+          prez[ZC + sidx] = zsrc[dp.Nz + c0 + sidx];
+          if constexpr (DT) prez[2 * ZC + sidx] = dsrc[c0 + sidx];
+        }
+      }
     };
     if (c_first <= c_last) fetch(c_first);
     for (int c0 = c_first; c0 <= c_last; c0 += ZC) {
@@ -769,6 +785,11 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
       for (int e = 0; e < kPer; ++e) {
         const int sidx = (e >> 1) / NCH;
         if (stager && sidx < nz) G[(rg + kRG * e) * kRX + rx] = pre[e];
+      }
+      if (zstager) {
+#pragma unroll
+        for (int e = 0; e < NZS; ++e)
+          if (e % ZC < nz) pz[tid * NZS + e] = prez[e];
       }
       T q[ZC];
 #pragma unroll
@@ -781,8 +802,7 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
         T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
         if (DT && l < 7) {
           const T* w = pcw + h * kRec;
-          const T* ps = psi + (size_t)pcp[h] * 2 * dp.Nz;
-          const T* dps = dpsi + (size_t)pcp[h] * dp.Nz;
+          const T* zs = pz + h * NZS;
           const T wxm = w[l], wxd = w[14 + l], wxq = w[28 + l];
           const int px = inf.x - tx0 + l;
           const int ry0 = inf.y - ty0;
@@ -790,9 +810,9 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
 #pragma unroll
           for (int sidx = 0; sidx < ZC; ++sidx) {
             const bool ok = sidx < nz;
-            pm[sidx] = ok ? q[sidx] * ps[c0 + sidx] : T(0);
-            pd[sidx] = ok ? q[sidx] * ps[dp.Nz + c0 + sidx] : T(0);
-            pq[sidx] = ok ? q[sidx] * dps[c0 + sidx] : T(0);
+            pm[sidx] = ok ? q[sidx] * zs[sidx] : T(0);
+            pd[sidx] = ok ? q[sidx] * zs[ZC + sidx] : T(0);
+            pq[sidx] = ok ? q[sidx] * zs[2 * ZC + sidx] : T(0);
           }
           for (int dy = 0; dy < 7; ++dy) {
             const T wm = wxm * w[7 + dy];
@@ -820,8 +840,9 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
           }
         } else if (!DT && l < 7) {
           const T* w = pcw + h * kRec;
-          // dense folded z weights of this particle (zero outside its window)
-          const T* ps = psi + (size_t)pcp[h] * 2 * dp.Nz;
+          // dense folded z weights of this particle (zero outside its
+          // window), staged for the chunk
+          const T* zs = pz + h * NZS;
           const T wxm = w[l], wxd = w[14 + l];
           const int px = inf.x - tx0 + l;
           const int ry0 = inf.y - ty0;
@@ -829,8 +850,8 @@ k_interp_tiled(DevParams dp, const int* __restrict__ band,
 #pragma unroll
           for (int sidx = 0; sidx < ZC; ++sidx) {
             const bool ok = sidx < nz;
-            pm[sidx] = ok ? q[sidx] * ps[c0 + sidx] : T(0);
-            pd[sidx] = ok ? q[sidx] * ps[dp.Nz + c0 + sidx] : T(0);
+            pm[sidx] = ok ? q[sidx] * zs[sidx] : T(0);
+            pd[sidx] = ok ? q[sidx] * zs[ZC + sidx] : T(0);
           }
           for (int dy = 0; dy < 7; ++dy) {
             const T wm = wxm * w[7 + dy];
@@ -905,8 +926,10 @@ __global__ void k_interp_invalid(int n, int ncells, const uint32_t* __restrict__
 template <typename T, int ZC, int NCH, bool DT = false>
 static size_t interp_lds(int cap) {
   constexpr int NOUT = (NCH == 6 || DT) ? 6 : 3;
+  constexpr int NZS = (DT ? 3 : 2) * ZC;
   return (size_t)ZC * NCH * kRX * kRX * sizeof(T) +
-         (size_t)cap * (IRec<DT>::n + NOUT) * sizeof(T) + (size_t)cap * (16 + 4 + 4);
+         (size_t)cap * (IRec<DT>::n + NOUT) * sizeof(T) + (size_t)cap * (16 + 4 + 4) +
+         (size_t)cap * NZS * sizeof(T);
 }
 
 template <typename T>
@@ -918,8 +941,8 @@ static hipError_t interp_tiled(const fcmdp_solver* s, int n, const T* grid,
   dim3 g(((dp.Nx + kTile - 1) / kTile) * ((dp.Ny + kTile - 1) / kTile));
   // home particles cached per pass: a monolayer at area fraction 0.5 with
   // R_h = 1.731 h has ~0.22 particles per xy cell, ~150 per 26 x 26 tile;
-  // denser tiles take several passes.  192 keeps two workgroups per CU.
-  const int cap = sizeof(T) == 4 ? 192 : 96;
+  // denser tiles take several passes.  176 keeps two workgroups per CU.
+  const int cap = sizeof(T) == 4 ? 176 : 96;
   // planes staged per chunk: as many for three channels as for six, so that
   // the velocities are the same bits whether or not Omega is wanted
   constexpr int ZC = sizeof(T) == 4 ? 2 : 1;
