@@ -374,25 +374,46 @@ k_spread_wave(DevParams dp, const int* __restrict__ band,
     const int range = zmax - zmin + 1;
     const int npass = (range + ZC - 1) / ZC;
     const int zc = npass > 0 ? (range + npass - 1) / npass : ZC;
+    // this lane's particle's folded z weights of a chunk (dense, zero outside
+    // its window; nodes past Nz read padding and are never stored), loaded
+    // one chunk ahead into registers so that their latency overlaps the
+    // current chunk's sums
+    T zm[ZC], zd[ZC], zq[ZC];
+    double z64[FZ ? R64 * ZC : 1];
+    auto zload = [&](int c0) {
+      if (!has) return;
+      const T* ps = psi + (size_t)p * 2 * Nz;
+#pragma unroll
+      for (int s = 0; s < ZC; ++s) {
+        if (s < zc) {
+          zm[s] = ps[c0 + s];
+          if constexpr (NCH == 6 || DT) zd[s] = ps[Nz + c0 + s];
+          if constexpr (DT) zq[s] = dpsi[(size_t)p * Nz + c0 + s];
+          if constexpr (FZ) {
+            const double* p64 = psi64 + (size_t)p * R64 * Nz;
+            z64[s] = p64[c0 + s];
+            if constexpr (DT) z64[ZC + s] = p64[Nz + c0 + s];
+          }
+        }
+      }
+    };
+    if (zmin <= zmax) zload(zmin);
     for (int c0 = zmin; c0 <= zmax; c0 += zc) {
-      // this lane's particle's folded z weights for the chunk (dense, zero
-      // outside its window; nodes past Nz read padding and are never stored)
       if (has) {
-        const T* ps = psi + (size_t)p * 2 * Nz;
 #pragma unroll
         for (int s = 0; s < ZC; ++s) {
           if (s < zc) {
-            mine[Rec::kPM + s] = ps[c0 + s];
-            if constexpr (NCH == 6 || DT) mine[Rec::kPD + s] = ps[Nz + c0 + s];
-            if constexpr (DT) mine[Rec::kPQ + s] = dpsi[(size_t)p * Nz + c0 + s];
+            mine[Rec::kPM + s] = zm[s];
+            if constexpr (NCH == 6 || DT) mine[Rec::kPD + s] = zd[s];
+            if constexpr (DT) mine[Rec::kPQ + s] = zq[s];
             if constexpr (FZ) {
-              const double* p64 = psi64 + (size_t)p * R64 * Nz;
-              rec64[wv][lane][s] = p64[c0 + s];
-              if constexpr (DT) rec64[wv][lane][ZC + s] = p64[Nz + c0 + s];
+              rec64[wv][lane][s] = z64[s];
+              if constexpr (DT) rec64[wv][lane][ZC + s] = z64[ZC + s];
             }
           }
         }
       }
+      if (c0 + zc <= zmax) zload(c0 + zc);
       // the records are read by every lane of this wavefront only
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
