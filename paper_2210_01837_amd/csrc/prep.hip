@@ -295,7 +295,7 @@ hipError_t launch_sort(const fcmdp_solver* s, int n, hipStream_t st) {
 // ----------------------------------------------------------------------------
 // per-particle records in sorted order
 // ----------------------------------------------------------------------------
-// One thread builds the records of one sorted particle and writes each as
+// Four lanes build the records of one sorted particle and write each as
 // whole 16-byte vectors (no LDS staging, so occupancy is limited by registers
 // only and the scattered reads of the unsorted inputs overlap across many
 // wavefronts).  The folded z weights are stored densely over all Nz nodes
@@ -318,7 +318,12 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
           const double* __restrict__ zc, int4* __restrict__ pinfo,
           T* __restrict__ pw, T* __restrict__ pf, T* __restrict__ psi,
           double* __restrict__ psi64, T* __restrict__ pdw, T* __restrict__ dpsi) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // four lanes per particle (its quad): lane q writes x/y weight part q,
+  // the z weights of the node groups q, q + 4, ... (four nodes each) and
+  // its share of the other records, so that the kernel evaluations of one
+  // particle run in four independent chains
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid >> 2, q = gid & 3;
   if (i >= n) return;
   const int Nz = dp.Nz;
   // FP64 z weights: the monopole's, and with torques spread through the
@@ -333,70 +338,65 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
   T* dps = dpsi ? dpsi + (size_t)i * Nz : nullptr;
   if (skeys[i] >= (uint32_t)dp.ncells) {
     // outside the domain: zero records (never read by the grid kernels)
-    for (int e = 0; e < 32; e += 4) store4(w + e, T(0), T(0), T(0), T(0));
-    store4(f, T(0), T(0), T(0), T(0));
-    store4(f + 4, T(0), T(0), T(0), T(0));
-    for (int e = 0; e < 2 * Nz; ++e) ps[e] = T(0);
+    for (int e = 8 * q; e < 8 * q + 8; e += 4) store4(w + e, T(0), T(0), T(0), T(0));
+    if (q < 2) store4(f + 4 * q, T(0), T(0), T(0), T(0));
+    for (int e = q; e < 2 * Nz; e += 4) ps[e] = T(0);
     if (ps64)
-      for (int e = 0; e < rows64 * Nz; ++e) ps64[e] = 0.0;
+      for (int e = q; e < rows64 * Nz; e += 4) ps64[e] = 0.0;
     if (dw)
-      for (int e = 0; e < 16; ++e) dw[e] = T(0);
+      for (int e = q; e < 16; e += 4) dw[e] = T(0);
     if (dps)
-      for (int e = 0; e < Nz; ++e) dps[e] = T(0);
+      for (int e = q; e < Nz; e += 4) dps[e] = T(0);
     return;
   }
   const int j = perm[i];
   const double x = wrap_coord((double)pos[3 * (size_t)j + 0], dp.Lx);
   const double y = wrap_coord((double)pos[3 * (size_t)j + 1], dp.Ly);
   const double z = (double)pos[3 * (size_t)j + 2];
-  T fv[8];
-  fv[0] = F ? (T)F[3 * (size_t)j + 0] : T(0);
-  fv[1] = F ? (T)F[3 * (size_t)j + 1] : T(0);
-  fv[2] = F ? (T)F[3 * (size_t)j + 2] : T(0);
-  fv[3] = T(0);
-  fv[4] = Tq ? (T)Tq[3 * (size_t)j + 0] : T(0);
-  fv[5] = Tq ? (T)Tq[3 * (size_t)j + 1] : T(0);
-  fv[6] = Tq ? (T)Tq[3 * (size_t)j + 2] : T(0);
-  fv[7] = T(0);
   int ix, iy;
   double fx, fy;
   cell_of(x, dp.h, dp.Nx, &ix, &fx);
   cell_of(y, dp.h, dp.Ny, &iy, &fy);
   int cA, cB;
   z_window(dp, zc, z, &cA, &cB);
-  pinfo[i] = make_int4(ix, iy, cA, cB);
-  // x and y weights of the M and D kernels, 7 each (eighth slot zero)
-#pragma unroll
-  for (int part = 0; part < 4; ++part) {
-    const double off = part & 1 ? fy : fx;
-    const double beta = part < 2 ? dp.beta_m : dp.beta_d;
-    const double inv = part < 2 ? dp.inv_norm_m : dp.inv_norm_d;
+  if (q == 0) pinfo[i] = make_int4(ix, iy, cA, cB);
+  if (q < 2) {
+    // forces (q = 0) and torques (q = 1), padded to four
+    const Tin* src = q == 0 ? F : Tq;
+    T a = T(0), b = T(0), c = T(0);
+    if (src) {
+      a = (T)src[3 * (size_t)j + 0];
+      b = (T)src[3 * (size_t)j + 1];
+      c = (T)src[3 * (size_t)j + 2];
+    }
+    store4(f + 4 * q, a, b, c, T(0));
+  }
+  // x or y weights of the M or D kernel (part q), 7 (eighth slot zero)
+  {
+    const double off = q & 1 ? fy : fx;
+    const double beta = q < 2 ? dp.beta_m : dp.beta_d;
+    const double inv = q < 2 ? dp.inv_norm_m : dp.inv_norm_d;
     T v[8];
 #pragma unroll
     for (int d = 0; d < kWin; ++d)
       v[d] = es_eval<T>(((double)(d - 3) - off) * dp.h, dp.alpha, beta, inv);
     v[7] = T(0);
-    store4(w + 8 * part, v[0], v[1], v[2], v[3]);
-    store4(w + 8 * part + 4, v[4], v[5], v[6], v[7]);
+    store4(w + 8 * q, v[0], v[1], v[2], v[3]);
+    store4(w + 8 * q + 4, v[4], v[5], v[6], v[7]);
   }
-  store4(f, fv[0], fv[1], fv[2], fv[3]);
-  store4(f + 4, fv[4], fv[5], fv[6], fv[7]);
-  // derivative of the dipole kernel along x and y (truncated), 7 each
-  if (dw) {
+  // derivative of the dipole kernel along x (q = 0) and y (q = 1), truncated
+  if (dw && q < 2) {
+    const double off = q ? fy : fx;
+    T v[8];
 #pragma unroll
-    for (int part = 0; part < 2; ++part) {
-      const double off = part ? fy : fx;
-      T v[8];
-#pragma unroll
-      for (int d = 0; d < kWin; ++d)
-        v[d] = es_deval<T>(((double)(d - 3) - off) * dp.h, dp.alpha, dp.beta_d,
-                           dp.inv_norm_d, dp.tstar_d);
-      v[7] = T(0);
-      store4(dw + 8 * part, v[0], v[1], v[2], v[3]);
-      store4(dw + 8 * part + 4, v[4], v[5], v[6], v[7]);
-    }
+    for (int d = 0; d < kWin; ++d)
+      v[d] = es_deval<T>(((double)(d - 3) - off) * dp.h, dp.alpha, dp.beta_d,
+                         dp.inv_norm_d, dp.tstar_d);
+    v[7] = T(0);
+    store4(dw + 8 * q, v[0], v[1], v[2], v[3]);
+    store4(dw + 8 * q + 4, v[4], v[5], v[6], v[7]);
   }
-  // folded z weights, four nodes at a time
+  // folded z weights
   const double zim_top = 2.0 * dp.H - z;
   auto zw = [&](int c, T& pm, T& pd) {
     pm = T(0);
@@ -413,7 +413,8 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
     }
   };
   if (Nz % 4 == 0) {
-    for (int c = 0; c < Nz; c += 4) {
+    // node groups of four: groups q, q + 4, ... of this lane
+    for (int c = 4 * q; c < Nz; c += 16) {
       T pm[4], pd[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) zw(c + e, pm[e], pd[e]);
@@ -421,7 +422,7 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
       store4(ps + Nz + c, pd[0], pd[1], pd[2], pd[3]);
     }
   } else {
-    for (int c = 0; c < Nz; ++c) zw(c, ps[c], ps[Nz + c]);
+    for (int c = q; c < Nz; c += 4) zw(c, ps[c], ps[Nz + c]);
   }
   // the monopole z weights once more in FP64 (the exact low-wavenumber
   // vertical force of the mixed slit channel)
@@ -439,11 +440,12 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
       };
       double* dst = ps64 + (size_t)row * Nz;
       if (Nz % 2 == 0) {
-        // 16-byte stores (an even Nz keeps every row 16-byte aligned)
+        // 16-byte stores (an even Nz keeps every row 16-byte aligned); node
+        // pairs q, q + 4, ... of this lane
         double2* r2 = reinterpret_cast<double2*>(dst);
-        for (int c = 0; c < Nz; c += 2) r2[c / 2] = make_double2(p64(c), p64(c + 1));
+        for (int c = 2 * q; c < Nz; c += 8) r2[c / 2] = make_double2(p64(c), p64(c + 1));
       } else {
-        for (int c = 0; c < Nz; ++c) dst[c] = p64(c);
+        for (int c = q; c < Nz; c += 4) dst[c] = p64(c);
       }
     }
   }
@@ -451,7 +453,7 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
   // and the mirror images' (phi'(z_c - z) - phi'(z_c + z), minus
   // phi'(z_c - (2H - z)) between two walls)
   if (dps) {
-    for (int c = 0; c < Nz; ++c) {
+    for (int c = q; c < Nz; c += 4) {
       T d = T(0);
       if (c >= cA && c <= cB) {
         const double zcv = zc[c];
@@ -469,7 +471,7 @@ k_records(DevParams dp, int n, const uint32_t* __restrict__ skeys,
 template <typename Tin, typename T>
 static void records_impl(const fcmdp_solver* s, int n, const void* pos,
                          const void* F, const void* Tq, hipStream_t st) {
-  hipLaunchKernelGGL((k_records<Tin, T>), dim3((n + 255) / 256), dim3(256), 0,
+  hipLaunchKernelGGL((k_records<Tin, T>), dim3((4 * (size_t)n + 255) / 256), dim3(256), 0,
                      st, s->dp, n, s->keyA, s->valA, (const Tin*)pos,
                      (const Tin*)F, (const Tin*)Tq, s->zc, s->pinfo,
                      (T*)s->pw, (T*)s->pf, (T*)s->psi,
