@@ -71,18 +71,20 @@ def zero_mode_matrix(N: int, geometry: str, H: float = 1.0, slip0: float = 0.0,
                      slipH: float = 0.0) -> np.ndarray:
     """System for y'' = rhs at k = 0.
 
-    Rows m >= 2: y_m = (H^2/4)(B^2 rhs)_m.  Row 1: y(0) = 0, or for a slit
-    channel with slip length l_0 at z = 0, y(0) - l_0 y'(0) = 0 (eq.
-    bvp-uv-k0-sc).  Row 0: bottom wall y'(H) = 0, i.e. sum n^2 y_n = 0; slit
+    Rows m >= 2: y_m = (H^2/4)(B^2 rhs)_m.  Row 1: y(0) - l_0 y'(0) = 0
+    with the slip length l_0 of the wall at z = 0 (eq. bvp-uv-k0-sc; l_0 = 0:
+    no slip).  Row 0: bottom wall y'(H) = 0, i.e. sum n^2 y_n = 0; slit
     channel y(H) + l_H y'(H) = 0.  With T_n(+-1) = (+-1)^n and
-    T_n'(+-1) = (+-1)^(n+1) n^2, d/dz = (2/H) d/ds.
+    T_n'(+-1) = (+-1)^(n+1) n^2, d/dz = (2/H) d/ds.  Reading: a bottom wall
+    with slip takes the same condition at z = 0 as the slit channel's lower
+    wall.
     """
     n = np.arange(N, dtype=np.float64)
     sgn = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
     A = np.eye(N)
     if geometry == "bw":
         A[0, :] = n ** 2
-        A[1, :] = sgn
+        A[1, :] = sgn - slip0 * (2.0 / H) * (-sgn) * n ** 2
     else:
         A[0, :] = 1.0 + slipH * (2.0 / H) * n ** 2
         A[1, :] = sgn - slip0 * (2.0 / H) * (-sgn) * n ** 2

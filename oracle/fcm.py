@@ -36,9 +36,10 @@ class Solver:
         self.box = box
         if abs(box.Lx / box.Nx - box.Ly / box.Ny) > 1e-12 * box.Lx / box.Nx:
             raise ValueError("the oracle requires hx == hy")
-        if box.slip0 < 0 or box.slipH < 0 or (
-                box.geometry == "bw" and (box.slip0 or box.slipH)):
-            raise ValueError("slip lengths are >= 0 and for the slit channel")
+        if box.slip0 < 0 or box.slipH < 0:
+            raise ValueError("slip lengths are >= 0")
+        if box.geometry == "bw" and box.slipH:
+            raise ValueError("a bottom wall has no slip length at z = H")
         if box.geometry == "bw" and any(box.wallH):
             raise ValueError("a bottom wall has no wall at z = H")
         self.h = box.Lx / box.Nx

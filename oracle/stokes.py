@@ -81,6 +81,16 @@ def correction_nodes(box, kx, ky, u, v, w, wall=None):
     tangentially with u^W, w = 0).  Slit channel: App. A.  wall: None (walls
     at rest) or (4, K) xy-DFT coefficients of u^W, v^W at z = 0 and z = H
     (the last two unused for a bottom wall).
+
+    Bottom wall with slip length l_0 (reading: the slit channel's condition
+    at z = 0, eq. bcslip0, with only the decaying modes of eqs.
+    psolfs-corr-sc .. wsolfs-corr-sc): u_corr = -(i k_x / k) B z e^{-kz} +
+    C_x e^{-kz}, v likewise, w_corr = B z e^{-kz} + w_0 e^{-kz}, where
+    B = C_0 / (2 eta).  The slip rows give (1 + k l_0) C_x + l_0 (i k_x / k)
+    B = u_0 (v likewise) and continuity at z = 0 gives B + i k_x C_x +
+    i k_y C_y - k w_0 = 0, so B = (k w_0 (1 + k l_0) - i (k_x u_0 + k_y
+    v_0)) / (1 + 2 k l_0); l_0 = 0 is the closed form above.  The boundary
+    data carry the slip term u_0 = u^W - u_DP(0) + l_0 du_DP/dz(0).
     """
     Nz = box.Nz
     _, zc = cheb.nodes(Nz, box.H)
@@ -95,6 +105,21 @@ def correction_nodes(box, kx, ky, u, v, w, wall=None):
     w0 = -(w * alt).sum(-1)
     if wall is not None:
         u0, v0 = u0 + wall[0], v0 + wall[1]
+    l0 = box.slip0
+    if l0:
+        # du/dz at z = 0: (2/H) sum T_n'(-1) a_n, T_n'(-1) = (-1)^(n+1) n^2
+        n2 = np.arange(Nz, dtype=float) ** 2
+        d0 = lambda a: (2.0 / box.H) * (a * (-alt) * n2).sum(-1)   # noqa: E731
+        u0 = u0 + l0 * d0(u)
+        v0 = v0 + l0 * d0(v)
+        Bs = (k * w0 * (1.0 + k * l0) - 1j * (kx * u0 + ky * v0)) / (1.0 + 2.0 * k * l0)
+        Cx = (u0 - l0 * (1j * kx / k) * Bs) / (1.0 + k * l0)
+        Cy = (v0 - l0 * (1j * ky / k) * Bs) / (1.0 + k * l0)
+        ze = zc[None, :] * em
+        uc = -(1j * kx / k * Bs)[:, None] * ze + Cx[:, None] * em
+        vc = -(1j * ky / k * Bs)[:, None] * ze + Cy[:, None] * em
+        wc = Bs[:, None] * ze + w0[:, None] * em
+        return uc, vc, wc
     Acoef = (1j * k * w0 + kx * u0 + ky * v0)[:, None]
     ze = zc[None, :] * em
     uc = -(kx / k)[:, None] * Acoef * ze + u0[:, None] * em

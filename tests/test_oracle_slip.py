@@ -137,3 +137,66 @@ def test_bottom_wall_moving():
     z = np.zeros((1, 3))
     U, _ = s.apply(pos, z, z)
     assert U[0, 0] == pytest.approx(0.7, rel=2e-3) and abs(U[0, 1]) < 1e-12
+
+
+# --- bottom wall with a slip length (the slit channel's condition at z = 0
+# with the decaying modes only) ----------------------------------------------
+
+BW = Box("bw", 16.0, 16.0, 8.0, 24, 24, 24)
+
+
+@pytest.mark.parametrize("l0", [0.5, 3.0])
+def test_bottom_wall_total_field_satisfies_the_slip_condition(l0):
+    box = replace(BW, slip0=l0)
+    s = oracle.Solver(box)
+    rng = np.random.default_rng(21)
+    pos = np.column_stack([rng.uniform(0, 16, 6), rng.uniform(0, 16, 6),
+                           rng.uniform(0.4, 5.5, 6)])
+    F, T = rng.standard_normal((6, 3)), rng.standard_normal((6, 3))
+    f, g = s.spread(s.wrap(pos), F, T)
+    uh, _ = stokes.solve_coefficients(box, stokes.forward_transform(box, f),
+                                      stokes.forward_transform(box, g))
+    n = np.arange(box.Nz)
+    alt = np.where(n % 2 == 0, 1.0, -1.0)
+    at0 = lambda a: np.tensordot(alt, a, axes=(0, 0))               # noqa: E731
+    d0 = lambda a: (2 / box.H) * np.tensordot(-alt * n.astype(float) ** 2, a,
+                                              axes=(0, 0))          # noqa: E731
+    scale = np.abs(uh).max()
+    for c in (0, 1):
+        assert np.abs(at0(uh[c]) - l0 * d0(uh[c])).max() < 1e-7 * scale
+    assert np.abs(at0(uh[2])).max() < 1e-12 * scale
+
+
+def test_bottom_wall_zero_mode_robin_closed_form():
+    """y'' = 1 on [0, H] with y(0) - l0 y'(0) = 0 and y'(H) = 0:
+    y = z^2/2 - H z - l0 H."""
+    H, l0, N = 5.0, 0.7, 16
+    rhs = np.zeros(N)
+    rhs[0] = 1.0
+    y = bvp.zero_mode_solve(rhs.astype(complex), H, "bw", l0, 0.0).real
+    _, zc = cheb.nodes(N, H)
+    got = cheb.eval_series(y, 2 * zc / H - 1)
+    np.testing.assert_allclose(got, zc ** 2 / 2 - H * zc - l0 * H, atol=1e-12)
+
+
+def test_bottom_wall_slip_mobility_symmetric_positive_and_faster():
+    pos = np.array([[5.3, 7.1, 2.2], [9.0, 8.4, 4.1], [12.2, 3.3, 3.0]])
+    rng = np.random.default_rng(5)
+    a, b = rng.standard_normal((2, 3, 3))
+    z = np.zeros((3, 3))
+    s = oracle.Solver(replace(BW, slip0=1.5))
+    Ua, _ = s.apply(pos, a, z)
+    Ub, _ = s.apply(pos, b, z)
+    aMa = np.sum(a * Ua)
+    assert aMa > 0
+    assert abs(np.sum(a * Ub) - np.sum(b * Ua)) < 1e-4 * aMa
+    e = np.zeros((3, 3))
+    e[0, 0] = 1.0
+    U_ns, _ = oracle.Solver(BW).apply(pos, e, z)
+    U_sl, _ = s.apply(pos, e, z)
+    assert U_sl[0, 0] > U_ns[0, 0] * 1.01
+
+
+def test_bottom_wall_slip_length_at_the_top_is_refused():
+    with pytest.raises(ValueError):
+        oracle.Solver(replace(BW, slipH=1.0))

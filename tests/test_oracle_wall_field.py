@@ -53,10 +53,12 @@ def _closed_form(box, nx, ny, a0, aH=(0.0, 0.0)):
     LH, TH = aH[0] * ex + aH[1] * ey, aH[0] * tx + aH[1] * ty
     l0, lH, H = box.slip0, box.slipH, box.H
     if box.geometry == "bw":
-        # psi = L0 z e^{-kz}: psi(0) = 0, psi'(0) = L0, bounded
-        psi = L0 * Z * np.exp(-k * Z)
-        dpsi = L0 * (1 - k * Z) * np.exp(-k * Z)
-        vt = T0 * np.exp(-k * Z)
+        # psi = A z e^{-kz}: psi(0) = 0, bounded; psi'(0) - l0 psi''(0) = L0
+        # with psi'(0) = A, psi''(0) = -2 k A
+        A = L0 / (1 + 2 * k * l0)
+        psi = A * Z * np.exp(-k * Z)
+        dpsi = A * (1 - k * Z) * np.exp(-k * Z)
+        vt = T0 / (1 + k * l0) * np.exp(-k * Z)
     else:
         # psi = A e^{-kz} + B z e^{-kz} + C e^{k(z-H)} + D z e^{k(z-H)}
         def basis(z):
@@ -94,6 +96,15 @@ def test_bottom_wall_mode_matches_stream_function(nx, ny, a0):
     u, om = _field(BW, _wall_mode(BW, nx, ny, a0))
     ref = _closed_form(BW, nx, ny, a0)
     assert np.max(np.abs(u - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("l0", [0.4, 2.5])
+@pytest.mark.parametrize("nx,ny,a0", [(2, 0, (1.0, 0.0)), (1, -2, (0.7, -0.4))])
+def test_bottom_wall_mode_with_slip_matches_stream_function(l0, nx, ny, a0):
+    box = replace(BW, slip0=l0)
+    u, _ = _field(box, _wall_mode(box, nx, ny, a0))
+    ref = _closed_form(box, nx, ny, a0)
+    assert np.max(np.abs(u - ref)) < 1e-11 * max(1.0, np.max(np.abs(ref)))
 
 
 def test_bottom_wall_mode_vorticity():
