@@ -71,9 +71,9 @@ typedef struct {
   int precision;       /* FCMDP_FP64 or FCMDP_MIXED */
   int64_t max_particles; /* capacity of the particle workspace */
   double slip0, slipH; /* slip lengths of the walls at z = 0 and z = H (App. A,
-                          partial slip u - l0 du/dz = 0 at z = 0, u + lH du/dz
-                          = 0 at z = H, zero wall velocity): slit channel
-                          with Nz <= 32 only; 0 = no slip */
+                          partial slip u - l0 du/dz = u^W at z = 0, u + lH
+                          du/dz = u^W at z = H): Nz <= 32; a bottom wall
+                          takes l0 only (slipH = 0); 0 = no slip */
   double wall0[2];     /* uniform (x, y) velocity of the wall at z = 0 */
   double wallH[2];     /* ... of the slit channel's wall at z = H (zero for a
                           bottom wall); nonzero wall velocities need

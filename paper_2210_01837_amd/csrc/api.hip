@@ -173,13 +173,13 @@ int validate(const fcmdp_params* p) {
   if (p->w != 4 && p->w != 6) return FCMDP_EINVAL;
   if (p->max_particles < 0 || p->max_particles > (int64_t)1 << 30)
     return FCMDP_EINVAL;
-  // partial slip: slit channel, solved by the eight-lane column kernels
+  // partial slip, solved by the eight-lane column kernels; a bottom wall
+  // has a slip length at z = 0 only
   if (!(p->slip0 >= 0) || !(p->slipH >= 0) || !std::isfinite(p->slip0) ||
       !std::isfinite(p->slipH))
     return FCMDP_EINVAL;
-  if ((p->slip0 != 0 || p->slipH != 0) &&
-      (p->geometry != FCMDP_SLIT_CHANNEL || p->Nz > 32))
-    return FCMDP_EINVAL;
+  if (p->geometry == FCMDP_BOTTOM_WALL && p->slipH != 0) return FCMDP_EINVAL;
+  if ((p->slip0 != 0 || p->slipH != 0) && p->Nz > 32) return FCMDP_EINVAL;
   // uniform wall velocities: finite; a bottom wall has no wall at z = H
   for (int c = 0; c < 2; ++c) {
     if (!std::isfinite(p->wall0[c]) || !std::isfinite(p->wallH[c]))

@@ -419,23 +419,27 @@ __device__ __forceinline__ Vec seg_zero_mode(const Vec& r, double H, int N, int 
   sm = red(sm);
   sn2 = red(sn2);
   const bool slip = geometry == 1 && (a0 != 0.0 || aH != 0.0 || g0 != 0.0 || gH != 0.0);
-  Z2 y0s = zmk(0, 0), y1s = zmk(0, 0);
-  if (slip) {                    // Robin conditions, as in ps_zero_mode
-    Z2 sdm = zmk(0, 0);
+  Z2 y0s = zmk(0, 0), y1s = zmk(0, 0), sdm = zmk(0, 0);
+  if (slip || a0 != 0.0) {       // Robin conditions, as in ps_zero_mode
 #pragma unroll
     for (int j = 0; j < kNpl; ++j) {
       const double n = 4.0 * l + j;
       sdm = sdm + (((j & 1) ? 1.0 : -1.0) * n * n) * y.v[j];
     }
     sdm = red(sdm);
+  }
+  if (slip) {
     y1s = frcp(2.0 + a0 + aH) * (zmk(gH - g0, 0) + sm - sp - a0 * sdm - aH * sn2);
     y0s = zmk(gH, 0) - sp - aH * sn2 - (1.0 + aH) * y1s;
   }
   if (l == 0) {
     if (geometry == 0) {
+      // y'(H) = 0: y1 = -sn2; y(0) - l_0 y'(0) = g0 (a0 = 2 l_0 / H):
+      // y0 = g0 + y1 - sm + a0 (y1 + sdm)
       y.v[1] = -1.0 * sn2;
       y.v[0] = y.v[1] - sm;
       if (g0 != 0.0) y.v[0] = y.v[0] + zmk(g0, 0);
+      if (a0 != 0.0) y.v[0] = y.v[0] + a0 * (sdm - sn2);
     } else if (slip) {
       y.v[0] = y0s;
       y.v[1] = y1s;
@@ -794,27 +798,30 @@ __device__ __forceinline__ Vec ps_zero_mode(const Vec& r, double H, int N, int g
   sn2 = red(sn2);
   // slip lengths or wall velocities: the general Robin rows
   const bool slip = geometry == 1 && (a0 != 0.0 || aH != 0.0 || g0 != 0.0 || gH != 0.0);
-  Z2 y0s = zmk(0, 0), y1s = zmk(0, 0);
-  if (slip) {
-    // y(0) - l_0 y'(0) = g0, y(H) + l_H y'(H) = gH with a = 2 l / H:
-    // y0 - (1 + a0) y1 = g0 - sm + a0 sdm, y0 + (1 + aH) y1 = gH - sp - aH sn2,
+  Z2 y0s = zmk(0, 0), y1s = zmk(0, 0), sdm = zmk(0, 0);
+  if (slip || a0 != 0.0) {
     // sdm = sum_{n >= 2} (-1)^{n+1} n^2 y_n
-    Z2 sdm = zmk(0, 0);
 #pragma unroll
     for (int s = 0; s < kNpl; ++s) {
       const double n = ps_m(l, s);
       sdm = sdm + (-sgn * n * n) * y.v[s];
     }
     sdm = red(sdm);
+  }
+  if (slip) {
+    // y(0) - l_0 y'(0) = g0, y(H) + l_H y'(H) = gH with a = 2 l / H:
+    // y0 - (1 + a0) y1 = g0 - sm + a0 sdm, y0 + (1 + aH) y1 = gH - sp - aH sn2
     y1s = frcp(2.0 + a0 + aH) * (zmk(gH - g0, 0) + sm - sp - a0 * sdm - aH * sn2);
     y0s = zmk(gH, 0) - sp - aH * sn2 - (1.0 + aH) * y1s;
   }
   if ((l & 3) == 0) {                                // slot 0 holds m = 0 or 1
     const bool odd = l >> 2;
     if (geometry == 0) {
-      // y(0) = g0 (wall velocity), y'(H) = 0
+      // y'(H) = 0: y1 = -sn2; y(0) - l_0 y'(0) = g0 (wall velocity; a0 =
+      // 2 l_0 / H): y0 = g0 + y1 - sm + a0 (y1 + sdm)
       y.v[0] = odd ? -1.0 * sn2 : -1.0 * sn2 - sm;
       if (!odd && g0 != 0.0) y.v[0] = y.v[0] + zmk(g0, 0);
+      if (!odd && a0 != 0.0) y.v[0] = y.v[0] + a0 * (sdm - sn2);
     } else if (slip) {
       y.v[0] = odd ? y1s : y0s;
     } else {
@@ -855,8 +862,8 @@ struct WallRef {
   }
 };
 
-template <int GEOM, bool SPLIT = false, bool FO = false, typename Load,
-          typename Basis, typename Wall>
+template <int GEOM, bool SPLIT = false, bool FO = false, bool BS = false,
+          typename Load, typename Basis, typename Wall>
 __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& basis,
                                  const DevParams& dp, int N, int l,
                                  double kx, double ky, double k,
@@ -874,8 +881,9 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     if constexpr (SPLIT) return ps_bsum_bottom(a, l);
     else return bsum_bottom(a);
   };
-  // slit channel slip lengths (App. A) as a = 2 l / H; zero for no slip
-  const double a0s = GEOM == 1 ? 2.0 * dp.slip0 / H : 0.0;
+  // slip lengths (App. A; a bottom wall has l_0 only) as a = 2 l / H; zero
+  // for no slip
+  const double a0s = 2.0 * dp.slip0 / H;
   const double aHs = GEOM == 1 ? 2.0 * dp.slipH / H : 0.0;
   // uniform wall velocities: the k = 0 wall data in the unnormalised xy DFT
   // (a constant c transforms to c Nx Ny); a non-uniform field adds its own
@@ -970,14 +978,40 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
     basis(0, E);
     basis(1, ZE);
     if constexpr (GEOM == 0) {
-      const Z2 Ac = imul(k, w0) + kx * u0 + ky * v0;
-      const Z2 Bc = k * w0 - imul(kx, u0) - imul(ky, v0);
-      const double rx = kx * ik, ry = ky * ik;
+      const double l0 = dp.slip0;
+      if constexpr (!BS) {
+        const Z2 Ac = imul(k, w0) + kx * u0 + ky * v0;
+        const Z2 Bc = k * w0 - imul(kx, u0) - imul(ky, v0);
+        const double rx = kx * ik, ry = ky * ik;
 #pragma unroll
-      for (int j = 0; j < kNpl; ++j) {
-        U.v[j] = U.v[j] + (-rx * ZE[j]) * Ac + E[j] * u0;
-        V.v[j] = V.v[j] + (-ry * ZE[j]) * Ac + E[j] * v0;
-        W.v[j] = W.v[j] + ZE[j] * Bc + E[j] * w0;
+        for (int j = 0; j < kNpl; ++j) {
+          U.v[j] = U.v[j] + (-rx * ZE[j]) * Ac + E[j] * u0;
+          V.v[j] = V.v[j] + (-ry * ZE[j]) * Ac + E[j] * v0;
+          W.v[j] = W.v[j] + ZE[j] * Bc + E[j] * w0;
+        }
+      } else {
+        // slip length l_0 at the bottom wall: boundary data u_0 + l_0
+        // u_DP'(0), then B = (k w_0 (1 + k l_0) - i (k_x u_0 + k_y v_0)) /
+        // (1 + 2 k l_0), C_x = (u_0 - l_0 (i k_x / k) B) / (1 + k l_0);
+        // u += -(i k_x / k) B z e^{-kz} + C_x e^{-kz}, w += B z e^{-kz} +
+        // w_0 e^{-kz}
+        Z2 tu, bu, tv, bv;
+        if constexpr (SPLIT) { ps_dsums(U, l, tu, bu); ps_dsums(V, l, tv, bv); }
+        else { seg_dsums(U, l, tu, bu); seg_dsums(V, l, tv, bv); }
+        const Z2 us0 = u0 + (l0 * s2H) * bu, vs0 = v0 + (l0 * s2H) * bv;
+        const double kl0 = k * l0;
+        const Z2 Bs = frcp(1.0 + 2.0 * kl0) *
+                      ((k * (1.0 + kl0)) * w0 - imul(kx, us0) - imul(ky, vs0));
+        const double i1 = frcp(1.0 + kl0);
+        const Z2 Cx = i1 * (us0 - imul(l0 * kx * ik, Bs));
+        const Z2 Cy = i1 * (vs0 - imul(l0 * ky * ik, Bs));
+        const Z2 Px = imul(-kx * ik, Bs), Py = imul(-ky * ik, Bs);
+#pragma unroll
+        for (int j = 0; j < kNpl; ++j) {
+          U.v[j] = U.v[j] + ZE[j] * Px + E[j] * Cx;
+          V.v[j] = V.v[j] + ZE[j] * Py + E[j] * Cy;
+          W.v[j] = W.v[j] + ZE[j] * Bs + E[j] * w0;
+        }
       }
     } else {
       Z2 uH = wall(2) - bsum_top(U), vH = wall(3) - bsum_top(V);
@@ -1067,7 +1101,7 @@ __device__ __forceinline__ void seg_column_solve(const Load& load, const Basis& 
   }
 }
 
-template <typename T, int GEOM>
+template <typename T, int GEOM, bool BS>
 __global__ void __launch_bounds__(256)
 k_columns_seg(ColParams cp, const int* __restrict__ band,
               const cplx_t<T>* in, cplx_t<T>* out,
@@ -1154,7 +1188,7 @@ k_columns_seg(ColParams cp, const int* __restrict__ band,
 #pragma unroll
       for (int j = 0; j < kNpl; ++j) out[j] = (which & 1) ? ZE[j] : E[j];
     };
-    seg_column_solve<GEOM>([&](int v) { return A[v]; }, basis, dp, N, l, kx,
+    seg_column_solve<GEOM, false, false, BS>([&](int v) { return A[v]; }, basis, dp, N, l, kx,
                            ky, k, WallRef<T>(dp, idx), U, V, W);
   }
   DU = seg_deriv(U, l, s2H);
@@ -1257,7 +1291,7 @@ __device__ __forceinline__ void col_index(int kx0, int ky0, int col, int Ny,
 
 // FO: forces only (no torques in, no vorticity out): three node vectors per
 // column instead of five and three output channels.
-template <int GEOM, bool FO>
+template <int GEOM, bool FO, bool BS>
 __global__ void __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_columns_mfma(ColParams cp, const int* __restrict__ band,
                const float2* in, float2* out,
@@ -1513,7 +1547,7 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
 #pragma unroll
         for (int j = 0; j < kNpl; ++j) o[j] = (double)bbase[2 * j * kMV + which];
       };
-      seg_column_solve<GEOM, true, FO>(load, basis, dp, N, l, kx, ky, k,
+      seg_column_solve<GEOM, true, FO, BS>(load, basis, dp, N, l, kx, ky, k,
                                        WallRef<float>(dp, kxi * dp.Ny + kyi),
                                        U, V, W);
     }
@@ -1611,29 +1645,31 @@ k_columns_mfma(ColParams cp, const int* __restrict__ band,
   }
 }
 
-template <int GEOM>
-static void launch_seg_geom(const fcmdp_solver* s, const ColParams& cp,
-                            const void* spec_in, void* spec_out, hipStream_t st) {
+// BS: slip length at a bottom wall (the correction's slip branch is a
+// separate instance, so that the no-slip kernels keep their registers)
+template <int GEOM, bool BS>
+static void launch_seg_kernels(const fcmdp_solver* s, const ColParams& cp,
+                               const void* spec_in, void* spec_out, hipStream_t st) {
   const int K = s->dp.Nkx * s->dp.Ny;
   if (s->mixed && s->dct_f32 && !s->force_vector_dct) {
     const dim3 g((K + kMCols - 1) / kMCols);
     if (s->dp.nch_in == 3 && s->dp.nch_out == 3)
-      hipLaunchKernelGGL((k_columns_mfma<GEOM, true>), g, dim3(kMThreads), 0, st,
+      hipLaunchKernelGGL((k_columns_mfma<GEOM, true, BS>), g, dim3(kMThreads), 0, st,
                          cp, s->band, (const float2*)spec_in, (float2*)spec_out,
                          s->zc, s->dct_f32, s->dct_i32);
     else
-      hipLaunchKernelGGL((k_columns_mfma<GEOM, false>), g, dim3(kMThreads), 0, st,
+      hipLaunchKernelGGL((k_columns_mfma<GEOM, false, BS>), g, dim3(kMThreads), 0, st,
                          cp, s->band, (const float2*)spec_in, (float2*)spec_out,
                          s->zc, s->dct_f32, s->dct_i32);
   } else if (s->mixed) {
     constexpr int cols = ColsPerBlock<float>::value;
-    hipLaunchKernelGGL((k_columns_seg<float, GEOM>), dim3((K + cols - 1) / cols),
+    hipLaunchKernelGGL((k_columns_seg<float, GEOM, BS>), dim3((K + cols - 1) / cols),
                        dim3(cols * kSeg), cols * 5 * 32 * sizeof(float2), st,
                        cp, s->band, (const float2*)spec_in, (float2*)spec_out,
                        s->zc, s->dct_f, s->dct_i);
   } else {
     constexpr int cols = ColsPerBlock<double>::value;
-    hipLaunchKernelGGL((k_columns_seg<double, GEOM>), dim3((K + cols - 1) / cols),
+    hipLaunchKernelGGL((k_columns_seg<double, GEOM, BS>), dim3((K + cols - 1) / cols),
                        dim3(cols * kSeg), cols * 5 * 32 * sizeof(double2), st,
                        cp, s->band, (const double2*)spec_in, (double2*)spec_out,
                        s->zc, s->dct_f, s->dct_i);
@@ -1648,10 +1684,12 @@ hipError_t launch_columns_seg(const fcmdp_solver* s, const void* spec_in,
   cp.kxs = 2.0 * M_PI / s->dp.Lx;
   cp.kys = 2.0 * M_PI / s->dp.Ly;
   cp.dctf = s->dct_f;
-  if (s->dp.geometry == 0)
-    launch_seg_geom<0>(s, cp, spec_in, spec_out, st);
+  if (s->dp.geometry == 1)
+    launch_seg_kernels<1, false>(s, cp, spec_in, spec_out, st);
+  else if (s->dp.slip0 != 0.0)
+    launch_seg_kernels<0, true>(s, cp, spec_in, spec_out, st);
   else
-    launch_seg_geom<1>(s, cp, spec_in, spec_out, st);
+    launch_seg_kernels<0, false>(s, cp, spec_in, spec_out, st);
   return hipGetLastError();
 }
 

@@ -49,8 +49,9 @@ def _params(**kw):
     dict(Nx=47), dict(Ny=6), dict(Nz=7), dict(Nz=65), dict(Nx=38),  # 19 prime
     dict(Ly=31.0), dict(H=1.9), dict(w=8), dict(w=5), dict(w=2), dict(eta=0.0),
     dict(geometry="sc", H=3.9), dict(max_particles=-1), dict(beta_m=-1.0),
-    # partial slip: slit channel only, non-negative, Nz <= 32
-    dict(slip0=0.5), dict(geometry="sc", slipH=-1.0),
+    # partial slip: non-negative, Nz <= 32, no slip length at z = H for a
+    # bottom wall
+    dict(slipH=0.5), dict(Nz=48, slip0=0.5), dict(geometry="sc", slipH=-1.0),
     dict(geometry="sc", Nz=48, slip0=1.0), dict(geometry="sc", slip0=float("inf")),
     # uniform wall velocities: no top wall for a bottom wall, Nz <= 32
     dict(wallH=(1.0, 0.0)), dict(Nz=48, wall0=(0.5, 0.0)),

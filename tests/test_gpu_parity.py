@@ -538,12 +538,41 @@ def test_apply_slit_channel_partial_slip(slip, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("case", ["bw", "sc", "sc_slip"])
+@pytest.mark.parametrize("l0", [0.6, 3.0])
+def test_apply_bottom_wall_partial_slip(l0, precision):
+    # a slip length at the bottom wall (the slit channel's condition at
+    # z = 0 with the decaying correction modes only)
+    from dataclasses import replace
+    box = replace(BOXES["bw48"], slip0=l0)
+    pos, F, T = _particles(box, 40, 18)
+    if precision == "mixed":
+        pos, F, T = (a.astype(np.float32).astype(np.float64) for a in (pos, F, T))
+    print(f"[bottom wall slip] {l0} {precision}", flush=True)
+    s = _solver(box, precision)
+    U, Om = s.apply(_dev(pos, precision), _dev(F, precision), _dev(T, precision))
+    rU, rO = oracle_apply(box, pos, F, T)
+    eU, eO = rel_err(_np(U), rU), rel_err(_np(Om), rO)
+    print(f"  rel err U {eU:.3e} Omega {eO:.3e}", flush=True)
+    tol = 1e-5 if precision == "mixed" else 1e-10
+    assert eU < tol and eO < tol
+    U2, _ = s.apply(_dev(pos, precision), _dev(F, precision), None,
+                    want_omega=False)
+    rU2, _ = oracle_apply(box, pos, F, np.zeros_like(T))
+    assert rel_err(_np(U2), rU2) < tol
+    # the slip branch changes the result: no-slip gives another answer
+    U0, _ = oracle_apply(BOXES["bw48"], pos, F, T)
+    assert rel_err(U0, rU) > 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["bw", "bw_slip", "sc", "sc_slip"])
 def test_apply_moving_walls(case, precision):
     """Uniform wall velocities (and slip) with particles forced as usual."""
     from dataclasses import replace
-    if case == "bw":
+    if case in ("bw", "bw_slip"):
         box = replace(BOXES["bw48"], wall0=(0.4, -0.3))
+        if case == "bw_slip":
+            box = replace(box, slip0=1.2)
     else:
         box = replace(BOXES["sc40x56"], wall0=(0.3, -0.2), wallH=(-0.5, 0.6))
         if case == "sc_slip":

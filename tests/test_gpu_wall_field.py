@@ -49,11 +49,13 @@ def _inputs(box, n, seed, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("case", ["bw48", "sc40x56", "sc_slip"])
+@pytest.mark.parametrize("case", ["bw48", "bw_slip", "sc40x56", "sc_slip"])
 def test_apply_with_wall_field_against_oracle(case, precision):
-    box = BOXES["sc40x56" if case == "sc_slip" else case]
+    box = BOXES[{"sc_slip": "sc40x56", "bw_slip": "bw48"}.get(case, case)]
     if case == "sc_slip":
         box = replace(box, slip0=0.6, slipH=1.4, wall0=(0.2, 0.0))
+    if case == "bw_slip":
+        box = replace(box, slip0=0.9, wall0=(0.1, -0.2))
     pos, F, T, wall = _inputs(box, 120, 91, precision)
     print(f"[wall field] {case} {precision}", flush=True)
     rU, rO = oracle.Solver(box).apply(pos, F, T, wall=wall)
