@@ -231,7 +231,8 @@ int fcmdp_stage_times(fcmdp_solver* s, double ms[8], int64_t* napplies);
  * different parallel decomposition and exist for cross-checks and tuning.
  * value: 0/1 for the switches; for the FFT row counts a power of two, or 12
  * for the x pass (rows per workgroup of the wave-per-row x and y passes,
- * 0 = default), rejected with FCMDP_EINVAL if the rows do not fit in LDS.
+ * 0 = default), rejected with FCMDP_EINVAL if the rows do not fit in LDS;
+ * for the spread's block rows 8 or 16 (0 = default), else FCMDP_EINVAL.
  * Not thread safe with respect to applies on the same solver.
  */
 enum {
@@ -247,9 +248,15 @@ enum {
   FCMDP_VARIANT_NO_PIPELINE = 8,     /* one workgroup per y row instead of
                                         the persistent row loop that loads
                                         the next row during a transform */
-  FCMDP_VARIANT_NO_LOWK = 9          /* MIXED slit channel: take the vertical
+  FCMDP_VARIANT_NO_LOWK = 9,         /* MIXED slit channel: take the vertical
                                         force of the kH < 1 columns from the
                                         FP32 path too (no FP64 route) */
+  FCMDP_VARIANT_WAVE_SPREAD = 10,    /* MIXED: per-patch gather spread on the
+                                        vector units instead of the matrix-core
+                                        spread of the FP32 grid */
+  FCMDP_VARIANT_SPREAD_BLOCK_ROWS = 11 /* MIXED: grid rows per workgroup of
+                                        the matrix-core spread (8 or 16;
+                                        0 = default 8) */
 };
 int fcmdp_set_variant(fcmdp_solver* s, int key, int value);
 

@@ -801,6 +801,13 @@ int fcmdp_set_variant(fcmdp_solver* s, int key, int value) {
     case FCMDP_VARIANT_NO_LOWK:
       s->no_lowk = on;
       return FCMDP_OK;
+    case FCMDP_VARIANT_WAVE_SPREAD:
+      s->force_wave_spread = on;
+      return FCMDP_OK;
+    case FCMDP_VARIANT_SPREAD_BLOCK_ROWS:
+      if (value != 0 && value != 8 && value != 16) return FCMDP_EINVAL;
+      s->spread_block_rows = value == 0 ? 8 : value;
+      return FCMDP_OK;
     default:
       return FCMDP_EINVAL;
   }

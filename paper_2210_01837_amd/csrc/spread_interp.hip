@@ -565,6 +565,8 @@ hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st) {
   if (!s->force_simple_spread) {
     // without torques only the three force channels are spread
     const bool dip = s->dp.nch_in == 6;
+    if (s->mixed && s->dp.lowk_ns < 0 && !s->force_wave_spread && spread_mfma_fits(s))
+      return launch_spread_mfma(s, grid, st);
     if (s->mixed && s->dp.lowk_ns >= 0)
       dip ? spread_wave<float, 6, true>(s, grid, st)
           : spread_wave<float, 3, true>(s, grid, st);

@@ -1,0 +1,143 @@
+"""GPU parity of the matrix-core spread of the FP32 grid (step 1 of Sec. 3.4;
+eq. fcm with the wall images of eq. kernelnearwall).
+
+The mixed-precision spread computes each 16-column tile row's grid values as
+a product of weight matrices on the matrix cores.  Checked here, element by
+element, against the oracle's FP64 grid (FP32 rounding only) and against the
+per-patch gather spread on the vector units: both block heights, grids at
+the smallest size the blocks take and grids whose rows are not 16-byte
+aligned (Nx % 4 != 0) with z-weight rows that are not either (Nz % 4 != 0),
+particles across the periodic seams and at both walls, bands wider than one
+20-plane chunk, regions holding more particles than one staged batch, forces
+only, and bitwise repeatability.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from workloads import Box
+
+from _parity import max_rel, oracle_apply, oracle_spread, particle_err, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+BOXES = {
+    "bw48": Box("bw", 32.0, 32.0, 8.0, 48, 48, 32),
+    "sc40x56": Box("sc", 20.0, 28.0, 7.0, 40, 56, 24),
+    # rows of 30 floats (no 16-byte alignment) and 12 z-nodes (Nz % 4 != 0)
+    "bw30x28": Box("bw", 15.0, 14.0, 6.0, 30, 28, 12),
+    # the smallest grid of 8-row blocks (a 22 x 14 cell region)
+    "bw22x14": Box("bw", 11.0, 7.0, 5.0, 22, 14, 16),
+    # 48 nodes: particles at all heights make a band of several chunks
+    "sc32x48": Box("sc", 16.0, 24.0, 8.0, 32, 48, 48),
+}
+
+
+def _solver(box, precision="mixed", cap=1 << 14, rows=None, wave=False):
+    from paper_2210_01837_amd import Solver
+    s = Solver.from_box(box, precision=precision, max_particles=cap)
+    if rows is not None:
+        s.set_variant("spread_block_rows", rows)
+    if wave:
+        s.set_variant("wave_spread", 1)
+    return s
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _particles(box, n, seed, zlo=0.2):
+    alpha = 3 * box.h
+    zhi = box.H - alpha - 0.05 if box.geometry == "bw" else box.H - 0.2
+    pos, F, T = workloads.random_particles(box, n, seed, zlo, zhi)
+    pos[0, :2] = [box.Lx - 1e-3, 0.3]
+    pos[1, :2] = [0.2, box.Ly - 0.7 * box.h]
+    pos[2, 2] = 0.4 * alpha
+    if box.geometry == "sc":
+        pos[3, 2] = box.H - 0.3 * alpha
+    # the FP32 inputs are the exact inputs of the oracle
+    return tuple(a.astype(np.float32).astype(np.float64) for a in (pos, F, T))
+
+
+def _check_grid(g, ref, tol=5e-6):
+    e, m = rel_err(g, ref), max_rel(g, ref)
+    print(f"  rel {e:.3e} max {m:.3e}", flush=True)
+    assert e < tol and m < tol
+
+
+@pytest.mark.parametrize("rows", [8, 16])
+@pytest.mark.parametrize("name", ["bw48", "sc40x56", "bw30x28", "bw22x14", "sc32x48"])
+def test_stage_spread_matches_oracle(name, rows):
+    box = BOXES[name]
+    pos, F, T = _particles(box, 97, 21)
+    print(f"[spread mfma] {name} block rows {rows}", flush=True)
+    s = _solver(box, rows=rows)
+    g = _np(s.stage_spread(_dev(pos), _dev(F), _dev(T)))
+    _check_grid(g, oracle_spread(box, pos, F, T))
+
+
+@pytest.mark.parametrize("name", ["bw48", "bw30x28", "sc32x48"])
+def test_stage_spread_matches_gather(name):
+    box = BOXES[name]
+    pos, F, T = _particles(box, 150, 22)
+    print(f"[spread mfma vs gather] {name}", flush=True)
+    g1 = _np(_solver(box).stage_spread(_dev(pos), _dev(F), _dev(T)))
+    g2 = _np(_solver(box, wave=True).stage_spread(_dev(pos), _dev(F), _dev(T)))
+    _check_grid(g1, g2, 1e-6)
+
+
+def test_stage_spread_dense_cluster():
+    """400 particles in 4 x 4 cells next to the seam: block regions of
+    several staged batches."""
+    box = BOXES["bw48"]
+    pos, F, T = _particles(box, 420, 23)
+    rng = np.random.default_rng(4321)
+    pos[20:, 0] = ((box.Lx - 2 * box.h) + 4 * box.h * rng.random(400)) % box.Lx
+    pos[20:, 1] = 10.0 + 4 * box.h * rng.random(400)
+    pos = pos.astype(np.float32).astype(np.float64)
+    print("[spread mfma] dense cluster", flush=True)
+    for rows in (8, 16):
+        g = _np(_solver(box, rows=rows).stage_spread(_dev(pos), _dev(F), _dev(T)))
+        _check_grid(g, oracle_spread(box, pos, F, T))
+
+
+def test_apply_forces_only_and_repeatable():
+    """Bottom wall, mixed: the three-channel (forces only) instance against
+    the oracle, the six-channel one applied twice with identical bits, and
+    zero torques giving the force-only velocities bit for bit."""
+    box = BOXES["bw48"]
+    pos, F, T = _particles(box, 200, 24)
+    print("[spread mfma] forces only, repeatability", flush=True)
+    s = _solver(box)
+    P, Fd, Td = _dev(pos), _dev(F), _dev(T)
+    U0, _ = s.apply(P, Fd, None, want_omega=False)
+    rU, _ = oracle_apply(box, pos, F, np.zeros_like(T))
+    eU = rel_err(_np(U0), rU)
+    pU = particle_err(_np(U0), rU)
+    print(f"  forces only: rel {eU:.3e} particle {pU:.3e}", flush=True)
+    assert eU < 1e-5 and pU < 1e-4
+    U1, O1 = s.apply(P, Fd, Td)
+    U2, O2 = s.apply(P, Fd, Td)
+    assert torch.equal(U1, U2) and torch.equal(O1, O2)
+    U3, _ = s.apply(P, Fd, torch.zeros_like(Td), want_omega=False)
+    assert torch.equal(U3, U0)
+    rU, rO = oracle_apply(box, pos, F, T)
+    eU, eO = rel_err(_np(U1), rU), rel_err(_np(O1), rO)
+    print(f"  with torques: U {eU:.3e} Omega {eO:.3e}", flush=True)
+    assert eU < 1e-5 and eO < 1e-5
+
+
+def test_block_rows_refused():
+    from paper_2210_01837_amd import FcmdpError
+    s = _solver(BOXES["bw48"])
+    for bad in (4, 12, 32, -8):
+        with pytest.raises(FcmdpError):
+            s.set_variant("spread_block_rows", bad)
