@@ -232,7 +232,8 @@ int fcmdp_stage_times(fcmdp_solver* s, double ms[8], int64_t* napplies);
  * value: 0/1 for the switches; for the FFT row counts a power of two, or 12
  * for the x pass (rows per workgroup of the wave-per-row x and y passes,
  * 0 = default), rejected with FCMDP_EINVAL if the rows do not fit in LDS;
- * for the spread's block rows 8 or 16 (0 = default), else FCMDP_EINVAL.
+ * for the spread's workgroups 1..65535, block rows 8 or 16 and block order
+ * 1 or 2 (0 = default), else FCMDP_EINVAL.
  * Not thread safe with respect to applies on the same solver.
  */
 enum {
@@ -254,9 +255,18 @@ enum {
   FCMDP_VARIANT_WAVE_SPREAD = 10,    /* MIXED: per-patch gather spread on the
                                         vector units instead of the matrix-core
                                         spread of the FP32 grid */
-  FCMDP_VARIANT_SPREAD_BLOCK_ROWS = 11 /* MIXED: grid rows per workgroup of
-                                        the matrix-core spread (8 or 16;
-                                        0 = default 8) */
+  FCMDP_VARIANT_SPREAD_WORKGROUPS = 11, /* MIXED: workgroups of the
+                                        matrix-core spread, which share its
+                                        blocks evenly (1..65535; 0 = default,
+                                        three per CU: as many as fit at once) */
+  FCMDP_VARIANT_SPREAD_BLOCK_ROWS = 12, /* MIXED: grid rows per block of the
+                                        matrix-core spread (8 or 16; 0 =
+                                        default, chosen by particle density) */
+  FCMDP_VARIANT_SPREAD_ORDER = 13    /* MIXED: block order of the matrix-core
+                                        spread: 1 strip-major, shared evenly;
+                                        2 neighbouring strips side by side;
+                                        0 = default: 1 if grid rows are whole
+                                        128-byte lines, else 2 */
 };
 int fcmdp_set_variant(fcmdp_solver* s, int key, int value);
 

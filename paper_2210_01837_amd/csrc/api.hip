@@ -719,7 +719,7 @@ int fcmdp_apply_mobility(fcmdp_solver* s, int64_t n, const void* pos,
   v = particle_front(s, ni, pos, F, T, st);
   if (v != FCMDP_OK) return v;
   mark(1);
-  if (fcmdp::launch_spread(s, s->grid, st) != hipSuccess) return FCMDP_EHIP;
+  if (fcmdp::launch_spread(s, (int)n, s->grid, st) != hipSuccess) return FCMDP_EHIP;
   mark(2);
   if (fcmdp::launch_fft_forward(s, s->grid, s->spec, st) != hipSuccess)
     return FCMDP_EHIP;
@@ -804,9 +804,17 @@ int fcmdp_set_variant(fcmdp_solver* s, int key, int value) {
     case FCMDP_VARIANT_WAVE_SPREAD:
       s->force_wave_spread = on;
       return FCMDP_OK;
+    case FCMDP_VARIANT_SPREAD_WORKGROUPS:
+      if (value < 0 || value > 65535) return FCMDP_EINVAL;
+      s->spread_workgroups = value;
+      return FCMDP_OK;
     case FCMDP_VARIANT_SPREAD_BLOCK_ROWS:
       if (value != 0 && value != 8 && value != 16) return FCMDP_EINVAL;
-      s->spread_block_rows = value == 0 ? 8 : value;
+      s->spread_block_rows = value;
+      return FCMDP_OK;
+    case FCMDP_VARIANT_SPREAD_ORDER:
+      if (value < 0 || value > 2) return FCMDP_EINVAL;
+      s->spread_order = value;
       return FCMDP_OK;
     default:
       return FCMDP_EINVAL;
@@ -877,7 +885,7 @@ int fcmdp_stage_spread(fcmdp_solver* s, int64_t n, const void* pos,
   if (n == 0) return FCMDP_OK;
   v = particle_front(s, (int)n, pos, F, T, st);
   if (v != FCMDP_OK) return v;
-  return fcmdp::launch_spread(s, grid, st) == hipSuccess ? FCMDP_OK
+  return fcmdp::launch_spread(s, (int)n, grid, st) == hipSuccess ? FCMDP_OK
                                                          : FCMDP_EHIP;
 }
 

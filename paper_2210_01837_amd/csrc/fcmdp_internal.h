@@ -163,9 +163,12 @@ struct fcmdp_solver {
   // use the untiled gather spread (tests)
   bool force_simple_spread = false;
   // use the per-patch gather spread instead of the matrix-core spread of the
-  // FP32 grid (tests), and the block height of the latter (8 or 16 rows)
+  // FP32 grid (tests), the workgroups of the latter (0: three per CU, the
+  // number that fit at once) and its rows per block (0: by density)
   bool force_wave_spread = false;
-  int spread_block_rows = 8;
+  int spread_workgroups = 0;
+  int spread_block_rows = 0;
+  int spread_order = 0;         // 0: by row alignment, 1: strip-major, 2: strips side by side
   // use the per-lane FP64 Chebyshev transforms in the mixed path (tests)
   bool force_vector_dct = false;
   // use the workgroup-per-row-batch transforms (tests)
@@ -198,11 +201,11 @@ hipError_t launch_set_band(const fcmdp_solver* s, int lo, int hi,
                            hipStream_t st);
 hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t st);
 // spread_interp.hip
-hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st);
+hipError_t launch_spread(const fcmdp_solver* s, int n, void* grid, hipStream_t st);
 // spread_mfma.hip: the FP32 grid's spread on the matrix cores (grids of at
-// least 22 x (block rows + 6) nodes)
+// least 22 x 14 nodes)
 bool spread_mfma_fits(const fcmdp_solver* s);
-hipError_t launch_spread_mfma(const fcmdp_solver* s, void* grid, hipStream_t st);
+hipError_t launch_spread_mfma(const fcmdp_solver* s, int n, void* grid, hipStream_t st);
 hipError_t launch_interp(const fcmdp_solver* s, int n, const void* grid,
                          void* U, void* Omega, hipStream_t st);
 // lowk.hip: exact FP64 Chebyshev coefficients of the vertical force density

@@ -551,7 +551,7 @@ static void spread_wave(const fcmdp_solver* s, void* grid, hipStream_t st) {
                      (T*)grid, FZ ? s->fzlo : nullptr);
 }
 
-hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st) {
+hipError_t launch_spread(const fcmdp_solver* s, int n, void* grid, hipStream_t st) {
   if (s->dp.dt_torque) {
     // torques through the derivative of the dipole kernel: three channels
     if (s->mixed && s->dp.lowk_ns >= 0)
@@ -566,7 +566,7 @@ hipError_t launch_spread(const fcmdp_solver* s, void* grid, hipStream_t st) {
     // without torques only the three force channels are spread
     const bool dip = s->dp.nch_in == 6;
     if (s->mixed && s->dp.lowk_ns < 0 && !s->force_wave_spread && spread_mfma_fits(s))
-      return launch_spread_mfma(s, grid, st);
+      return launch_spread_mfma(s, n, grid, st);
     if (s->mixed && s->dp.lowk_ns >= 0)
       dip ? spread_wave<float, 6, true>(s, grid, st)
           : spread_wave<float, 3, true>(s, grid, st);

@@ -22,6 +22,16 @@
 // c0 + 4 (n / 3) + b in block b = 0..3, so lane l finishes with four
 // neighbouring x columns of one (channel, plane, row) per block: one 16-byte
 // store each.  Slot 15 is unused.
+//
+// Work layout: the grid is cut into strips 16 columns wide and blocks of 8
+// rows; a tile row (16 columns of one grid row) draws on the particles of
+// the 22 x 7 cells around it, which in cell-sorted order are one contiguous
+// slice of its block's region (22 x 14 cells).  Each workgroup walks a run
+// of blocks down a strip and keeps the region's particle records in an LDS
+// ring: moving to the next block stages only its 8 new cell rows, and does
+// so (16-byte loads straight from global memory into LDS) while the current
+// block's matrix steps run.  Blocks whose region holds more particles than
+// the ring are staged in batches.
 #include "fcmdp_internal.h"
 
 namespace fcmdp {
@@ -36,232 +46,385 @@ typedef float sf4 __attribute__((ext_vector_type(4)));
 // the chunk, [64, 84) dipole z weights, [84, 96) unused
 constexpr int kSlots = 24;
 constexpr int kSRec = 4 * kSlots;
-constexpr int kSZ = 20;      // planes per chunk
-constexpr int kSNB = 4;      // blocks of 16 slots per kernel
-constexpr int kSW = 16;      // block (and tile) width in x
+constexpr int kSZ = 20;          // planes per chunk
+constexpr int kSNB = 4;          // blocks of 16 slots per kernel
+constexpr int kSW = 16;          // strip (and tile row) width in x
+constexpr int kCap = 128;        // staged particles (ring or batch), 2^k
 
 __device__ __forceinline__ int lane_value(int x, int l) {
   return __builtin_amdgcn_readlane(x, l);
 }
 
-template <int BY> struct SpreadCap;            // staged particles per batch
-template <> struct SpreadCap<8> { static constexpr int n = 96; };
-template <> struct SpreadCap<16> { static constexpr int n = 128; };
-
-// NCH = 6: forces and torques; 3: forces only.  A workgroup owns a block of
-// 16 x BY grid columns; its four wavefronts take BY / 4 tile rows each.
-template <int NCH, int BY>
-__global__ void __launch_bounds__(256)
-k_spread_mfma(DevParams dp, const int* __restrict__ band,
-              const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
-              const float* __restrict__ pw, const float* __restrict__ pf,
-              const float* __restrict__ psi, float* __restrict__ grid) {
-  constexpr int kRows = BY + 6;            // cell rows of the block's region
-  constexpr int TPW = BY / 4;              // tile rows per wavefront
-  constexpr int CAP = SpreadCap<BY>::n;
-  static_assert(2 * kRows <= 64, "one lane per row segment");
-  __shared__ __align__(16) float rec[CAP][kSRec];
-  __shared__ int pidx[CAP];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int Nx = dp.Nx, Ny = dp.Ny, Nz = dp.Nz;
-  const int gx = (Nx + kSW - 1) / kSW;
-  const int gy = (Ny + BY - 1) / BY;
-  const int blk = xcd_tile(blockIdx.x, gx * gy);
-  const int xb = (blk % gx) * kSW, yb = (blk / gx) * BY;
-  const int lo = band[0], hi = band[1];
-  const size_t plane = (size_t)Nx * Ny;
-  const size_t chstride = plane * Nz;
-
-  // the region: cell rows yb - 3 .. yb + BY + 2 and cells xb - 3 .. xb + 18
-  // of each (the grid is at least that large), split at the periodic seam;
-  // lane 2r + s holds segment s of row r: its first particle and count
-  const int xs = wrap_index(xb - 3, Nx);
-  const int xe0 = xs + kSW + 6 <= Nx ? xs + kSW + 6 : Nx;
-  const int xe1 = xs + kSW + 6 - xe0;      // cells [0, xe1) after the seam
-  int sstart = 0, scnt = 0;
-  if (lane < 2 * kRows) {
-    const int r = lane >> 1, sg = lane & 1;
-    const int row = wrap_index(yb - 3 + r, Ny) * Nx;
-    const int ca = sg ? 0 : xs, cb = sg ? xe1 : xe0;
-    if (ca < cb) {
-      sstart = cell_start[row + ca];
-      scnt = cell_start[row + cb] - sstart;
-    }
-  }
-  int incl = scnt;                         // inclusive prefix over lanes
+__device__ __forceinline__ int lane_prefix(int v, int lane) {
+  int incl = v;                            // inclusive prefix over lanes
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const int t = __shfl_up(incl, d);
     if (lane >= d) incl += t;
   }
-  const int soff = incl - scnt;            // staged-list index of the segment
-  const int total = lane_value(incl, 63);
-  // tile row t draws on region rows t .. t + 6: one contiguous slice
-  auto row_start = [&](int r) { return r < kRows ? lane_value(soff, 2 * r) : total; };
+  return incl;
+}
 
-  // operand roles: A column j of the tile row, B / D slot j
-  const int g = lane >> 4, j = lane & 15;
-  const int a = xb + j;
-  const bool inside = a < Nx;
-  const bool slot = j < 15;
-  const int ch = j % 3, zg = slot ? j / 3 : 0;
-  const int xo = xb + 4 * g;               // D: x columns xo .. xo + 3
-  const bool vec = (Nz & 3) == 0;          // 16-byte aligned z-weight rows
-  const bool vst = (Nx & 3) == 0;          // 16-byte aligned grid rows
-  const int nbatch = (total + CAP - 1) / CAP;
+// A lane's parts: A column j of a tile row (x = xb + j), B / D slot j
+// (channel ch, plane group zg), D rows 4g .. 4g + 3 (x = xo .. xo + 3).
+struct Roles {
+  int g, j, a, ch, zg, xo;
+  bool inside, slot;
+};
 
-  // stage particles [base, base + cnt) of the region's list for chunk c0
-  auto stage = [&](int c0, int base, int cnt) {
-    __syncthreads();                       // the previous batch is read
-    // staged-list index -> particle
-    if (wv == 0 && lane < 2 * kRows) {
-      const int k0 = base - soff > 0 ? base - soff : 0;
-      const int k1 = base + cnt - soff < scnt ? base + cnt - soff : scnt;
-      for (int k = k0; k < k1; ++k) pidx[soff + k - base] = sstart + k;
-    }
-    __syncthreads();
-    // records: piece e of the batch (particle e / 24, piece e % 24) is one
-    // 16-byte load straight from global memory into LDS at byte 16 e, so
-    // every load of the batch is in flight at once; consecutive lanes read
-    // consecutive pieces of a particle.  Pieces: x/y weights (8), forces
-    // and torques (2), node base (1), z weights of the chunk (5 monopole,
-    // 5 dipole), unused (3).
-    const int nel = cnt * kSlots;
-    for (int e0 = wv * 64; e0 < nel; e0 += 256) {
-      const int e = e0 + lane;
-      const int idx = e / kSlots, part = e - idx * kSlots;
-      const int p = pidx[e < nel ? idx : 0];
-      const float* src;
-      bool on;
-      if (part < 8) {
-        src = pw + (size_t)p * 32 + 4 * part;
-        on = NCH == 6 || part < 4;
-      } else if (part < 10) {
-        src = pf + (size_t)p * 8 + 4 * (part - 8);
-        on = NCH == 6 || part == 8;
-      } else if (part == 10) {
-        src = reinterpret_cast<const float*>(pinfo + p);
-        on = true;
-      } else {
-        const int u = part - 11, h = u >= 5 ? 1 : 0, uu = u - 5 * h;
-        const int z = c0 + 4 * uu;
-        // planes past Nz read a clamped address (never stored)
-        src = psi + (size_t)p * 2 * Nz + h * Nz + (z < Nz ? z : Nz - 4);
-        on = vec && part < 21 && (NCH == 6 || h == 0);
-      }
-      if (on && e < nel)
-        __builtin_amdgcn_global_load_lds(
-            src, (__attribute__((address_space(3))) void*)(&rec[0][0] + 4 * e0), 16, 0, 0);
-    }
-    if (!vec) {
-      // z-weight rows not 16-byte aligned: one float per thread and load
-      constexpr int kZ = NCH == 6 ? 2 * kSZ : kSZ;
-      for (int e = tid; e < cnt * kZ; e += 256) {
-        const int idx = e / kZ, sl = e - idx * kZ;
-        const int h = sl >= kSZ ? 1 : 0, z = c0 + sl - kSZ * h;
-        const int p = pidx[idx];
-        rec[idx][44 + sl] = psi[(size_t)p * 2 * Nz + h * Nz + (z < Nz ? z : Nz - 1)];
-      }
-    }
-    // the direct loads write LDS behind the compiler's back: wait for them
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-  };
+__device__ __forceinline__ Roles lane_roles(int lane, int xb, int Nx) {
+  Roles r;
+  r.g = lane >> 4;
+  r.j = lane & 15;
+  r.a = xb + r.j;
+  r.inside = r.a < Nx;
+  r.slot = r.j < 15;
+  r.ch = r.j % 3;
+  r.zg = r.slot ? r.j / 3 : 0;
+  r.xo = xb + 4 * r.g;
+  return r;
+}
 
-  for (int c0 = vec ? (lo & ~3) : lo; c0 <= hi; c0 += kSZ) {
-    // one batch (the usual case): staged once for all tile rows; dense
-    // regions: every batch again for each tile row
-    if (nbatch <= 1) stage(c0, 0, total);
-    for (int tt = 0; tt < TPW; ++tt) {
-      const int t = wv * TPW + tt;
-      const int y = yb + t;
-      sf4 acc[2][kSNB];
+// Matrix steps of tile row y over staged particles [s0, s1); particle k's
+// record is in slot (k - base) & (kCap - 1).
+template <int NCH>
+__device__ __forceinline__ void tile_steps(const float (*rec)[kSRec], int s0, int s1,
+                                           int base, int y, const Roles& ro, int Nx,
+                                           int Ny, sf4 (&acc)[2][kSNB]) {
+  for (int k0 = s0; k0 < s1; k0 += 4) {
+    const int k = k0 + ro.g;
+    const bool have = k < s1;
+    const float* rk = rec[(have ? k - base : 0) & (kCap - 1)];
+    const int ix = __float_as_int(rk[40]), iy = __float_as_int(rk[41]);
+    int dx = ro.a - ix + 3;
+    if (dx < 0) dx += Nx; else if (dx >= Nx) dx -= Nx;
+    int dy = y - iy + 3;
+    if (dy < 0) dy += Ny; else if (dy >= Ny) dy -= Ny;
+    const bool ok = have && ro.inside && (unsigned)dx <= 6u && (unsigned)dy <= 6u;
+    const int dxs = ok ? dx : 0, dys = ok ? dy : 0;
+    const bool bok = have && ro.slot;
 #pragma unroll
-      for (int pt = 0; pt < 2; ++pt)
-#pragma unroll
-        for (int k = 0; k < kSNB; ++k) acc[pt][k] = sf4{0.f, 0.f, 0.f, 0.f};
-      for (int bt = 0; bt < nbatch; ++bt) {
-        const int base = bt * CAP;
-        const int cnt = total - base < CAP ? total - base : CAP;
-        if (nbatch > 1) stage(c0, base, cnt);
-        if (y >= Ny) continue;
-        // this tile row's particles within the batch
-        int s0 = row_start(t), s1 = row_start(t + 7);
-        s0 = s0 > base ? s0 : base;
-        s1 = s1 < base + cnt ? s1 : base + cnt;
-        for (int k0 = s0; k0 < s1; k0 += 4) {
-          const int k = k0 + g;
-          const bool have = k < s1;
-          const float* rk = &rec[have ? k - base : 0][0];
-          const int ix = __float_as_int(rk[40]), iy = __float_as_int(rk[41]);
-          int dx = a - ix + 3;
-          if (dx < 0) dx += Nx; else if (dx >= Nx) dx -= Nx;
-          int dy = y - iy + 3;
-          if (dy < 0) dy += Ny; else if (dy >= Ny) dy -= Ny;
-          const bool ok = have && inside && (unsigned)dx <= 6u && (unsigned)dy <= 6u;
-          const int dxs = ok ? dx : 0, dys = ok ? dy : 0;
-          const bool bok = have && slot;
-#pragma unroll
-          for (int pt = 0; pt < (NCH == 6 ? 2 : 1); ++pt) {
-            const float w = rk[16 * pt + dxs] * rk[16 * pt + 8 + dys];
-            const float av = ok ? w : 0.f;
-            const float f = rk[32 + 4 * pt + ch];
-            const sf4 zw = *reinterpret_cast<const sf4*>(rk + 44 + kSZ * pt + 4 * zg);
-#pragma unroll
-            for (int bl = 0; bl < kSNB; ++bl) {
-              const float bv = bok ? f * zw[bl] : 0.f;
-              acc[pt][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[pt][bl], 0, 0, 0);
-            }
-          }
-        }
-      }
-      // every band plane of the chunk, zeros included
-      if (!slot || y >= Ny || xo >= Nx) continue;
-      const size_t col = (size_t)y * Nx + xo;
+    for (int pt = 0; pt < (NCH == 6 ? 2 : 1); ++pt) {
+      const float w = rk[16 * pt + dxs] * rk[16 * pt + 8 + dys];
+      const float av = ok ? w : 0.f;
+      const float f = rk[32 + 4 * pt + ro.ch];
+      const sf4 zw = *reinterpret_cast<const sf4*>(rk + 44 + kSZ * pt + 4 * ro.zg);
 #pragma unroll
       for (int bl = 0; bl < kSNB; ++bl) {
-        const int z = c0 + 4 * zg + bl;
-        if (z < lo || z > hi) continue;
-#pragma unroll
-        for (int pt = 0; pt < (NCH == 6 ? 2 : 1); ++pt) {
-          const sf4 v = acc[pt][bl];
-          float* dst = grid + (size_t)(ch + 3 * pt) * chstride + z * plane + col;
-          if (vst) {
-            *reinterpret_cast<sf4*>(dst) = v;
-          } else {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (xo + r < Nx) dst[r] = v[r];
-          }
-        }
+        const float bv = bok ? f * zw[bl] : 0.f;
+        acc[pt][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[pt][bl], 0, 0, 0);
       }
     }
   }
 }
 
+// Every band plane of the chunk of tile row y, zeros included.
+template <int NCH>
+__device__ __forceinline__ void tile_store(float* __restrict__ grid,
+                                           const sf4 (&acc)[2][kSNB], int c0, int lo,
+                                           int hi, int y, const Roles& ro, int Nx,
+                                           int Ny, size_t plane, size_t chstride,
+                                           bool vst) {
+  if (!ro.slot || y >= Ny || ro.xo >= Nx) return;
+  const size_t col = (size_t)y * Nx + ro.xo;
+#pragma unroll
+  for (int bl = 0; bl < kSNB; ++bl) {
+    const int z = c0 + 4 * ro.zg + bl;
+    if (z < lo || z > hi) continue;
+#pragma unroll
+    for (int pt = 0; pt < (NCH == 6 ? 2 : 1); ++pt) {
+      const sf4 v = acc[pt][bl];
+      float* dst = grid + (size_t)(ro.ch + 3 * pt) * chstride + z * plane + col;
+      if (vst) {
+        *reinterpret_cast<sf4*>(dst) = v;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (ro.xo + r < Nx) dst[r] = v[r];
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void wait_loads() {
+  // the direct loads write LDS behind the compiler's back
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// NCH = 6: forces and torques; 3: forces only.  Blocks of BY rows (8, or 16
+// for sparse particles: more work per staged row); the workgroups share the
+// strip-major sequence of blocks evenly.
 template <int NCH, int BY>
-void spread_mfma_impl(const fcmdp_solver* s, void* grid, hipStream_t st) {
-  const int gx = (s->dp.Nx + kSW - 1) / kSW;
-  const int gy = (s->dp.Ny + BY - 1) / BY;
-  hipLaunchKernelGGL((k_spread_mfma<NCH, BY>), dim3(gx * gy), dim3(256), 0, st,
-                     s->dp, s->band, s->cell_start, s->pinfo,
-                     (const float*)s->pw, (const float*)s->pf,
-                     (const float*)s->psi, (float*)grid);
+__global__ void __launch_bounds__(256)
+k_spread_mfma(DevParams dp, const int* __restrict__ band,
+              const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
+              const float* __restrict__ pw, const float* __restrict__ pf,
+              const float* __restrict__ psi, float* __restrict__ grid, int nseg) {
+  constexpr int kBY = BY, kTPW = BY / 4;
+  constexpr int kRows = BY + 6;            // cell rows of a block's region
+  static_assert(2 * kRows <= 64 && 2 * BY + 7 <= 64, "lanes per segment, rows in rs");
+  __shared__ __align__(16) float rec[kCap][kSRec];
+  __shared__ int rs[64];      // stream index of the first particle of row r (r mod 64)
+  __shared__ int pidx[kCap];  // batched staging: batch index -> particle
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Nx = dp.Nx, Ny = dp.Ny, Nz = dp.Nz;
+  const int gx = (Nx + kSW - 1) / kSW, nby = (Ny + kBY - 1) / kBY;
+  // block bi = sx * nby + by (strip sx, block row by).  nseg = 0: the
+  // workgroups share this strip-major sequence evenly.  nseg > 0: workgroup
+  // w takes row segment w / gx of strip w % gx, so that all strips advance
+  // through the same rows together and neighbouring strips' pieces of a
+  // 128-byte line are written at about the same time (rows of Nx floats
+  // that are not a whole number of lines put every strip's 64-byte piece
+  // across two lines).
+  const int nblk = gx * nby, nwg = gridDim.x;
+  const int w = xcd_tile(blockIdx.x, nwg);
+  int bA, bB;
+  if (nseg > 0) {
+    const int sxw = w % gx, sg = w / gx;
+    bA = sxw * nby + (int)((long long)sg * nby / nseg);
+    bB = sxw * nby + (int)((long long)(sg + 1) * nby / nseg);
+  } else {
+    bA = (int)((long long)w * nblk / nwg);
+    bB = (int)((long long)(w + 1) * nblk / nwg);
+  }
+  const int lo = band[0], hi = band[1];
+  const size_t plane = (size_t)Nx * Ny;
+  const size_t chstride = plane * Nz;
+  const bool vec = (Nz & 3) == 0;          // 16-byte aligned z-weight rows
+  const bool vst = (Nx & 3) == 0;          // 16-byte aligned grid rows
+
+  for (int c0 = vec ? (lo & ~3) : lo; c0 <= hi; c0 += kSZ) {
+    // piece `lane` of a record (lanes < 24): source and bytes per particle
+    const char* pbase;
+    unsigned pstride;
+    bool pon;
+    {
+      const int part = lane < kSlots ? lane : kSlots - 1;
+      if (part < 8) {
+        pbase = reinterpret_cast<const char*>(pw + 4 * part); pstride = 128;
+        pon = NCH == 6 || part < 4;
+      } else if (part < 10) {
+        pbase = reinterpret_cast<const char*>(pf + 4 * (part - 8)); pstride = 32;
+        pon = NCH == 6 || part == 8;
+      } else if (part == 10) {
+        pbase = reinterpret_cast<const char*>(pinfo); pstride = 16;
+        pon = true;
+      } else {
+        const int u = part - 11, h = u >= 5 ? 1 : 0, uu = u - 5 * h;
+        const int z = c0 + 4 * uu;
+        // planes past Nz read a clamped address (never stored)
+        pbase = reinterpret_cast<const char*>(psi + h * Nz + (z < Nz ? z : Nz - 4));
+        pstride = 8u * Nz;
+        pon = vec && part < 21 && (NCH == 6 || h == 0);
+      }
+      pon = pon && lane < kSlots;
+    }
+    // z-weight rows that are not 16-byte aligned: one float per lane
+    // (lanes < 40: monopole then dipole planes of the chunk)
+    const float* zbase;
+    bool zon;
+    {
+      const int h = lane >= kSZ ? 1 : 0, z = c0 + lane - kSZ * h;
+      zbase = psi + h * Nz + (z < Nz ? z : Nz - 1);
+      zon = !vec && lane < (NCH == 6 ? 2 : 1) * kSZ;
+    }
+    // stage particle p's record in slot s & (kCap - 1) (s uniform)
+    auto put = [&](int s, int p) {
+      float* dst = rec[s & (kCap - 1)];
+      if (pon)
+        __builtin_amdgcn_global_load_lds(pbase + (size_t)p * pstride,
+                                         (__attribute__((address_space(3))) void*)dst,
+                                         16, 0, 0);
+      if (zon)
+        __builtin_amdgcn_global_load_lds(zbase + (size_t)p * 2 * Nz,
+                                         (__attribute__((address_space(3))) void*)(dst + 44),
+                                         4, 0, 0);
+    };
+
+    int S = 0;                 // stream index of the next staged particle
+    bool ring = false;         // the ring holds the current block's region
+    int cur_sx = -1;
+    int nm_st = 0, nm_ct = 0;  // the next block's new rows (lanes < 16)
+    for (int bi = bA; bi < bB; ++bi) {
+      const int sx = bi / nby, by = bi - sx * nby;
+      const int xb = sx * kSW, yb = by * kBY;
+      if (sx != cur_sx) ring = false;      // a new strip: start over
+      cur_sx = sx;
+      const Roles ro = lane_roles(lane, xb, Nx);
+      // the strip's cells xb - 3 .. xb + 18, split at the periodic seam
+      const int xs = wrap_index(xb - 3, Nx);
+      const int xe0 = xs + kSW + 6 <= Nx ? xs + kSW + 6 : Nx;
+      const int xe1 = xs + kSW + 6 - xe0;
+      // segment (lane & 1) of cell row ra + (lane >> 1), lanes < 2n: first
+      // particle and count
+      auto row_meta = [&](int ra, int n, int& st, int& ct) {
+        st = 0;
+        ct = 0;
+        if (lane < 2 * n) {
+          const int row = wrap_index(ra + (lane >> 1), Ny) * Nx;
+          const int sg = lane & 1;
+          const int ca = sg ? 0 : xs, cb = sg ? xe1 : xe0;
+          if (ca < cb) {
+            st = cell_start[row + ca];
+            ct = cell_start[row + cb] - st;
+          }
+        }
+      };
+      // append rows ra .. ra + n - 1 to the stream: their starts (and the
+      // end) in rs, their records into the ring (each wavefront takes every
+      // fourth segment)
+      auto add_rows = [&](int ra, int n, int st, int ct) {
+        const int incl = lane_prefix(ct, lane);
+        const int excl = incl - ct;
+        const int tot = lane_value(incl, 63);
+        const int e2 = __shfl(excl, (2 * lane) & 63);
+        if (wv == 0 && lane <= n) rs[(ra + lane) & 63] = S + e2;
+        for (int l = wv; l < 2 * n; l += 4) {
+          const int sst = lane_value(st, l), sc = lane_value(ct, l);
+          const int se = lane_value(excl, l);
+          for (int k = 0; k < sc; ++k) put(S + se + k, sst + k);
+        }
+        S += tot;
+      };
+      // the next block (and the one after) continue down the same strip
+      auto follows = [&](int d) { return bi + d < bB && (bi + d) / nby == sx; };
+      const bool more = follows(1);
+
+      if (!ring) {
+        int st, ct;
+        row_meta(yb - 3, kRows, st, ct);
+        const int incl = lane_prefix(ct, lane);
+        const int tot = lane_value(incl, 63);
+        if (tot <= kCap) {
+          S = 0;
+          add_rows(yb - 3, kRows, st, ct);
+          ring = true;
+          if (more) row_meta(yb + kBY + 3, kBY, nm_st, nm_ct);
+          wait_loads();
+          __syncthreads();
+        } else {
+          // a dense region: every batch again for each tile row
+          const int excl = incl - ct;
+          for (int tt = 0; tt < kTPW; ++tt) {
+            const int t = wv * kTPW + tt;
+            const int y = yb + t;
+            const int r0 = lane_value(excl, 2 * t), r1 = lane_value(excl, 2 * (t + 7));
+            sf4 acc[2][kSNB];
+#pragma unroll
+            for (int pt = 0; pt < 2; ++pt)
+#pragma unroll
+              for (int q = 0; q < kSNB; ++q) acc[pt][q] = sf4{0.f, 0.f, 0.f, 0.f};
+            for (int base = 0; base < tot; base += kCap) {
+              const int cnt = tot - base < kCap ? tot - base : kCap;
+              if (lane < 2 * kRows) {
+                const int k0 = base - excl > 0 ? base - excl : 0;
+                const int k1 = base + cnt - excl < ct ? base + cnt - excl : ct;
+                if (wv == 0)
+                  for (int k = k0; k < k1; ++k) pidx[excl + k - base] = st + k;
+              }
+              __syncthreads();
+              for (int q = wv; q < cnt; q += 4) put(q, pidx[q]);
+              wait_loads();
+              __syncthreads();
+              if (y < Ny)
+                tile_steps<NCH>(rec, r0 > base ? r0 : base,
+                                r1 < base + cnt ? r1 : base + cnt, base, y, ro, Nx, Ny,
+                                acc);
+              __syncthreads();             // the batch is read
+            }
+            tile_store<NCH>(grid, acc, c0, lo, hi, y, ro, Nx, Ny, plane, chstride, vst);
+          }
+          continue;                        // ring stays empty
+        }
+      }
+
+      // the ring holds this block's region: stage the next block's new rows
+      // now if they fit beside it, else after this block
+      int nst2 = 0, nct2 = 0;
+      bool pend = false;
+      if (more) {
+        const int cn = lane_value(lane_prefix(nm_ct, lane), 63);
+        if (S + cn - rs[(yb - 3) & 63] <= kCap)
+          add_rows(yb + kBY + 3, kBY, nm_st, nm_ct);
+        else
+          pend = true;
+        if (follows(2)) row_meta(yb + 2 * kBY + 3, kBY, nst2, nct2);
+      }
+#pragma unroll
+      for (int tt = 0; tt < kTPW; ++tt) {
+        sf4 acc[2][kSNB];
+#pragma unroll
+        for (int pt = 0; pt < 2; ++pt)
+#pragma unroll
+          for (int q = 0; q < kSNB; ++q) acc[pt][q] = sf4{0.f, 0.f, 0.f, 0.f};
+        const int y = yb + wv * kTPW + tt;
+        if (y < Ny)
+          tile_steps<NCH>(rec, rs[(y - 3) & 63], rs[(y + 4) & 63], 0, y, ro, Nx, Ny, acc);
+        // the next rows' loads were issued before the steps (and the first
+        // tile row's stores one tile row ago): wait before the last stores
+        if (tt == kTPW - 1) wait_loads();
+        tile_store<NCH>(grid, acc, c0, lo, hi, y, ro, Nx, Ny, plane, chstride, vst);
+      }
+      __syncthreads();
+      if (pend) {
+        const int cn = lane_value(lane_prefix(nm_ct, lane), 63);
+        if (S + cn - rs[(yb + kBY - 3) & 63] <= kCap) {
+          add_rows(yb + kBY + 3, kBY, nm_st, nm_ct);
+          wait_loads();
+          __syncthreads();
+        } else {
+          ring = false;
+        }
+      }
+      if (!more) ring = false;
+      nm_st = nst2;
+      nm_ct = nct2;
+    }
+    __syncthreads();                       // before the next chunk's staging
+  }
 }
 
 }  // namespace
 
 bool spread_mfma_fits(const fcmdp_solver* s) {
-  // the block's region (22 cells wide, BY + 6 rows) must not wrap onto
+  // a block's region (22 cells wide, 14 rows at least) must not wrap onto
   // itself
-  const int by = s->spread_block_rows;
-  return s->dp.Nx >= kSW + 6 && s->dp.Ny >= by + 6;
+  return s->dp.Nx >= kSW + 6 && s->dp.Ny >= 8 + 6;
 }
 
-hipError_t launch_spread_mfma(const fcmdp_solver* s, void* grid, hipStream_t st) {
+template <int NCH, int BY>
+static void spread_mfma_impl(const fcmdp_solver* s, void* grid, hipStream_t st) {
+  const int gx = (s->dp.Nx + kSW - 1) / kSW, nby = (s->dp.Ny + BY - 1) / BY;
+  const int nblk = gx * nby;
+  const int cus = s->num_cu > 0 ? s->num_cu : 256;
+  int nwg = s->spread_workgroups > 0 ? s->spread_workgroups : 3 * cus;
+  // strips side by side when grid rows are not whole 128-byte lines (and
+  // when asked); the segments per strip then keep every workgroup resident
+  const bool aligned = ((size_t)s->dp.Nx * sizeof(float)) % 128 == 0;
+  int nseg = 0;
+  if (s->spread_order == 2 || (s->spread_order == 0 && !aligned)) {
+    nseg = nwg / gx;
+    if (nseg < 1) nseg = 1;
+    if (nseg > nby) nseg = nby;
+    nwg = gx * nseg;
+  }
+  if (nwg > nblk) nwg = nblk;
+  hipLaunchKernelGGL((k_spread_mfma<NCH, BY>), dim3(nwg), dim3(256), 0, st, s->dp,
+                     s->band, s->cell_start, s->pinfo, (const float*)s->pw,
+                     (const float*)s->pf, (const float*)s->psi, (float*)grid, nseg);
+}
+
+hipError_t launch_spread_mfma(const fcmdp_solver* s, int n, void* grid, hipStream_t st) {
+  // 16-row blocks when a region and the next block's rows (22 x 38 cells)
+  // hold about 100 particles or fewer, so that the next rows still load
+  // beside the current block
+  int by = s->spread_block_rows;
+  if (by == 0)
+    by = (double)n * (22.0 * 38.0) <= 100.0 * (double)s->dp.Nx * s->dp.Ny ? 16 : 8;
+  if (s->dp.Ny < 16 + 6) by = 8;
   const bool dip = s->dp.nch_in == 6;
-  if (s->spread_block_rows == 16)
+  if (by == 16)
     dip ? spread_mfma_impl<6, 16>(s, grid, st) : spread_mfma_impl<3, 16>(s, grid, st);
   else
     dip ? spread_mfma_impl<6, 8>(s, grid, st) : spread_mfma_impl<3, 8>(s, grid, st);

@@ -185,7 +185,9 @@ class Solver:
     VARIANTS = {"generic_fft": 0, "fft_rows_x": 1, "fft_rows_y": 2,
                 "simple_spread": 3, "simple_interp": 4, "generic_columns": 5,
                 "vector_dct": 6, "no_codelet": 7, "no_pipeline": 8,
-                "no_lowk": 9, "wave_spread": 10, "spread_block_rows": 11}
+                "no_lowk": 9, "wave_spread": 10, "spread_workgroups": 11,
+                "spread_block_rows": 12,
+                "spread_order": 13}
 
     def set_variant(self, name, value):
         """Select an alternative kernel (see fcmdp_set_variant)."""

@@ -2,14 +2,18 @@
 eq. fcm with the wall images of eq. kernelnearwall).
 
 The mixed-precision spread computes each 16-column tile row's grid values as
-a product of weight matrices on the matrix cores.  Checked here, element by
-element, against the oracle's FP64 grid (FP32 rounding only) and against the
-per-patch gather spread on the vector units: both block heights, grids at
-the smallest size the blocks take and grids whose rows are not 16-byte
-aligned (Nx % 4 != 0) with z-weight rows that are not either (Nz % 4 != 0),
-particles across the periodic seams and at both walls, bands wider than one
-20-plane chunk, regions holding more particles than one staged batch, forces
-only, and bitwise repeatability.
+a product of weight matrices on the matrix cores; workgroups walk runs of
+8- or 16-row blocks down 16-column strips (strip after strip, or neighbouring
+strips side by side) and keep the region's particles in an LDS ring.  Checked here, element by element, against the oracle's FP64 grid
+(FP32 rounding only) and against the per-patch gather spread on the vector
+units: one block per workgroup and long walks across several strips (the
+workgroup count is a tuning switch), grids at the smallest size the blocks
+take and grids whose rows are not 16-byte aligned (Nx % 4 != 0) with z-weight
+rows that are not either (Nz % 4 != 0), particles across the periodic seams
+and at both walls, bands wider than one 20-plane chunk, densities at which
+the next rows are staged after a block instead of beside it or a region
+outgrows the ring (staged in batches), forces only, and bitwise
+repeatability.
 """
 import numpy as np
 import pytest
@@ -35,11 +39,15 @@ BOXES = {
 }
 
 
-def _solver(box, precision="mixed", cap=1 << 14, rows=None, wave=False):
+def _solver(box, precision="mixed", cap=1 << 14, wgs=0, rows=0, order=0, wave=False):
     from paper_2210_01837_amd import Solver
     s = Solver.from_box(box, precision=precision, max_particles=cap)
-    if rows is not None:
+    if wgs:
+        s.set_variant("spread_workgroups", wgs)
+    if rows:
         s.set_variant("spread_block_rows", rows)
+    if order:
+        s.set_variant("spread_order", order)
     if wave:
         s.set_variant("wave_spread", 1)
     return s
@@ -73,13 +81,14 @@ def _check_grid(g, ref, tol=5e-6):
     assert e < tol and m < tol
 
 
-@pytest.mark.parametrize("rows", [8, 16])
+@pytest.mark.parametrize("wgs,rows,order", [(0, 0, 0), (1, 8, 1), (5, 16, 1), (1, 16, 2),
+                                             (7, 8, 2)])
 @pytest.mark.parametrize("name", ["bw48", "sc40x56", "bw30x28", "bw22x14", "sc32x48"])
-def test_stage_spread_matches_oracle(name, rows):
+def test_stage_spread_matches_oracle(name, wgs, rows, order):
     box = BOXES[name]
     pos, F, T = _particles(box, 97, 21)
-    print(f"[spread mfma] {name} block rows {rows}", flush=True)
-    s = _solver(box, rows=rows)
+    print(f"[spread mfma] {name} workgroups {wgs} block rows {rows} order {order}", flush=True)
+    s = _solver(box, wgs=wgs, rows=rows, order=order)
     g = _np(s.stage_spread(_dev(pos), _dev(F), _dev(T)))
     _check_grid(g, oracle_spread(box, pos, F, T))
 
@@ -96,7 +105,7 @@ def test_stage_spread_matches_gather(name):
 
 def test_stage_spread_dense_cluster():
     """400 particles in 4 x 4 cells next to the seam: block regions of
-    several staged batches."""
+    several staged batches, then the ring started again."""
     box = BOXES["bw48"]
     pos, F, T = _particles(box, 420, 23)
     rng = np.random.default_rng(4321)
@@ -104,9 +113,22 @@ def test_stage_spread_dense_cluster():
     pos[20:, 1] = 10.0 + 4 * box.h * rng.random(400)
     pos = pos.astype(np.float32).astype(np.float64)
     print("[spread mfma] dense cluster", flush=True)
-    for rows in (8, 16):
-        g = _np(_solver(box, rows=rows).stage_spread(_dev(pos), _dev(F), _dev(T)))
+    for wgs, rows, order in ((0, 8, 0), (1, 8, 1), (1, 16, 2)):
+        s = _solver(box, wgs=wgs, rows=rows, order=order)
+        g = _np(s.stage_spread(_dev(pos), _dev(F), _dev(T)))
         _check_grid(g, oracle_spread(box, pos, F, T))
+
+
+@pytest.mark.parametrize("wgs,rows", [(0, 8), (2, 8), (2, 16)])
+def test_stage_spread_near_ring_capacity(wgs, rows):
+    """0.4 particles per cell: block regions of about 120 particles, so the
+    next rows sometimes wait for the block to finish and some regions
+    outgrow the ring."""
+    box = BOXES["bw48"]
+    pos, F, T = _particles(box, 920, 25)
+    print(f"[spread mfma] near ring capacity, workgroups {wgs} rows {rows}", flush=True)
+    g = _np(_solver(box, wgs=wgs, rows=rows).stage_spread(_dev(pos), _dev(F), _dev(T)))
+    _check_grid(g, oracle_spread(box, pos, F, T))
 
 
 def test_apply_forces_only_and_repeatable():
@@ -135,9 +157,15 @@ def test_apply_forces_only_and_repeatable():
     assert eU < 1e-5 and eO < 1e-5
 
 
-def test_block_rows_refused():
+def test_workgroups_refused():
     from paper_2210_01837_amd import FcmdpError
     s = _solver(BOXES["bw48"])
-    for bad in (4, 12, 32, -8):
+    for bad in (-1, 65536):
+        with pytest.raises(FcmdpError):
+            s.set_variant("spread_workgroups", bad)
+    for bad in (4, 12, 32):
         with pytest.raises(FcmdpError):
             s.set_variant("spread_block_rows", bad)
+    for bad in (-1, 3):
+        with pytest.raises(FcmdpError):
+            s.set_variant("spread_order", bad)
