@@ -66,7 +66,7 @@ PAPER_FORCES_ONLY_RATE = 663552 / 0.370
 
 
 # the kernel each single-kernel stage launches once per apply
-STAGE_KERNEL = {"spread": "k_spread_wave", "columns": "k_columns_mfma",
+STAGE_KERNEL = {"spread": "k_spread_mfma", "columns": "k_columns_mfma",
                 "interp": "k_interp_tiled"}
 
 

@@ -39,6 +39,7 @@ CSRC = os.path.join(PKG, "csrc")
 KERNEL_SOURCES = {
     "k_columns_mfma": ["columns_seg.hip", "colmath.h", "fcmdp_internal.h"],
     "k_spread_wave": ["spread_interp.hip", "es.h", "fcmdp_internal.h"],
+    "k_spread_mfma": ["spread_mfma.hip", "fcmdp_internal.h"],
     "k_interp_tiled": ["spread_interp.hip", "es.h", "fcmdp_internal.h"],
     "k_fftw_x_r2c": ["fft.hip", "fcmdp_internal.h"],
     "k_fftw_y": ["fft.hip", "fcmdp_internal.h"],
@@ -57,8 +58,9 @@ def source_hash(kernel: str) -> str:
 
 
 def short_name(name: str) -> str:
-    """fcmdp::k_columns_mfma<0>(...) -> k_columns_mfma"""
-    base = name.split("(")[0]
+    """fcmdp::k_columns_mfma<0>(...) -> k_columns_mfma (also inside an
+    anonymous namespace)"""
+    base = name.replace("(anonymous namespace)::", "").split("(")[0]
     base = base.split("<")[0]
     return base.split("::")[-1].strip()
 
