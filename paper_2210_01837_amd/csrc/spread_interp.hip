@@ -556,6 +556,9 @@ hipError_t launch_spread(const fcmdp_solver* s, int n, void* grid, hipStream_t s
     // torques through the derivative of the dipole kernel: three channels
     if (s->mixed && s->dp.lowk_ns >= 0)
       spread_wave<float, 3, true, true>(s, grid, st);
+    else if (s->mixed && !s->force_wave_spread && !s->force_simple_spread &&
+             spread_mfma_fits(s))
+      return launch_spread_mfma(s, n, grid, st);
     else if (s->mixed)
       spread_wave<float, 3, false, true>(s, grid, st);
     else

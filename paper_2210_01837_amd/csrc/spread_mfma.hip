@@ -40,16 +40,25 @@ namespace {
 
 typedef float sf4 __attribute__((ext_vector_type(4)));
 
-// staged record: 24 pieces of 16 bytes (floats [0, 96)): [0, 32) x/y
-// weights (M x, M y, D x, D y; 8 each), [32, 40) forces and torques,
-// [40, 44) node base (ix, iy, as int bits), [44, 64) monopole z weights of
-// the chunk, [64, 84) dipole z weights, [84, 96) unused
-constexpr int kSlots = 24;
-constexpr int kSRec = 4 * kSlots;
 constexpr int kSZ = 20;          // planes per chunk
 constexpr int kSNB = 4;          // blocks of 16 slots per kernel
 constexpr int kSW = 16;          // strip (and tile row) width in x
-constexpr int kCap = 128;        // staged particles (ring or batch), 2^k
+
+// Staged record of a particle, in 16-byte pieces (floats in brackets):
+// pieces 0-7 x/y weights [0, 32) (M x, M y, D x, D y; 8 each), 8-9 forces
+// and torques [32, 40), 10 node base [40, 44) (ix, iy as int bits), 11-15
+// monopole z weights of the chunk [44, 64), 16-20 dipole z weights
+// [64, 84).  With torques through the kernel derivative (DT) also 21-25
+// the dipole's z-derivative weights [84, 104) and 26-29 its x/y derivative
+// weights [104, 120) (D' x, D' y; 8 each).  The LDS ring holds kCap
+// records (three workgroups per CU).
+template <bool DT> struct SRec {
+  static constexpr int kSlots = DT ? 32 : 24;
+  static constexpr int kLen = 4 * kSlots;
+  static constexpr int kCap = DT ? 96 : 128;
+  static constexpr int kZ = DT ? 3 : 2;          // z-weight rows
+  static __device__ __forceinline__ int slot(int s) { return (unsigned)s % kCap; }
+};
 
 __device__ __forceinline__ int lane_value(int x, int l) {
   return __builtin_amdgcn_readlane(x, l);
@@ -86,15 +95,18 @@ __device__ __forceinline__ Roles lane_roles(int lane, int xb, int Nx) {
 }
 
 // Matrix steps of tile row y over staged particles [s0, s1); particle k's
-// record is in slot (k - base) & (kCap - 1).
-template <int NCH>
-__device__ __forceinline__ void tile_steps(const float (*rec)[kSRec], int s0, int s1,
-                                           int base, int y, const Roles& ro, int Nx,
-                                           int Ny, sf4 (&acc)[2][kSNB]) {
+// record is in ring slot k - base.  DT: the three force channels
+// receive F phi_M phi_M psi_M + (1/2) grad Delta_D x tau, one weight matrix
+// per term of grad Delta_D = (phi_D' phi_D psi_D, phi_D phi_D' psi_D,
+// phi_D phi_D psi_D') (same slots, one accumulator set).
+template <int NCH, bool DT>
+__device__ __forceinline__ void tile_steps(const float (*rec)[SRec<DT>::kLen], int s0,
+                                           int s1, int base, int y, const Roles& ro,
+                                           int Nx, int Ny, sf4 (&acc)[2][kSNB]) {
   for (int k0 = s0; k0 < s1; k0 += 4) {
     const int k = k0 + ro.g;
     const bool have = k < s1;
-    const float* rk = rec[(have ? k - base : 0) & (kCap - 1)];
+    const float* rk = rec[SRec<DT>::slot(have ? k - base : 0)];
     const int ix = __float_as_int(rk[40]), iy = __float_as_int(rk[41]);
     int dx = ro.a - ix + 3;
     if (dx < 0) dx += Nx; else if (dx >= Nx) dx -= Nx;
@@ -103,16 +115,48 @@ __device__ __forceinline__ void tile_steps(const float (*rec)[kSRec], int s0, in
     const bool ok = have && ro.inside && (unsigned)dx <= 6u && (unsigned)dy <= 6u;
     const int dxs = ok ? dx : 0, dys = ok ? dy : 0;
     const bool bok = have && ro.slot;
-#pragma unroll
-    for (int pt = 0; pt < (NCH == 6 ? 2 : 1); ++pt) {
-      const float w = rk[16 * pt + dxs] * rk[16 * pt + 8 + dys];
-      const float av = ok ? w : 0.f;
-      const float f = rk[32 + 4 * pt + ro.ch];
-      const sf4 zw = *reinterpret_cast<const sf4*>(rk + 44 + kSZ * pt + 4 * ro.zg);
+    if constexpr (DT) {
+      // A: the four weight products of the tile column; B: coefficient of
+      // channel ch times the z weight row of the term
+      const float g0 = rk[36], g1 = rk[37], g2 = rk[38];
+      const float am = rk[dxs] * rk[8 + dys];                   // phi_M phi_M
+      const float aa = rk[104 + dxs] * rk[24 + dys];            // phi_D' phi_D
+      const float ab = rk[16 + dxs] * rk[112 + dys];            // phi_D phi_D'
+      const float ac = rk[16 + dxs] * rk[24 + dys];             // phi_D phi_D
+      const float cm = rk[32 + ro.ch];
+      // (1/2) grad Delta_D x tau by channel: x: a_b g2 - a_c' g1,
+      // y: -a_a g2 + a_c' g0, z: a_a g1 - a_b g0 (halved)
+      const float ca = ro.ch == 0 ? 0.f : (ro.ch == 1 ? -0.5f * g2 : 0.5f * g1);
+      const float cb = ro.ch == 0 ? 0.5f * g2 : (ro.ch == 1 ? 0.f : -0.5f * g0);
+      const float cc = ro.ch == 0 ? -0.5f * g1 : (ro.ch == 1 ? 0.5f * g0 : 0.f);
+      const sf4 zm = *reinterpret_cast<const sf4*>(rk + 44 + 4 * ro.zg);
+      const sf4 zd = *reinterpret_cast<const sf4*>(rk + 64 + 4 * ro.zg);
+      const sf4 zq = *reinterpret_cast<const sf4*>(rk + 84 + 4 * ro.zg);
+      const float avm = ok ? am : 0.f, ava = ok ? aa : 0.f;
+      const float avb = ok ? ab : 0.f, avc = ok ? ac : 0.f;
 #pragma unroll
       for (int bl = 0; bl < kSNB; ++bl) {
-        const float bv = bok ? f * zw[bl] : 0.f;
-        acc[pt][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[pt][bl], 0, 0, 0);
+        const float bm = bok ? cm * zm[bl] : 0.f;
+        const float ba = bok ? ca * zd[bl] : 0.f;
+        const float bb = bok ? cb * zd[bl] : 0.f;
+        const float bc = bok ? cc * zq[bl] : 0.f;
+        acc[0][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(avm, bm, acc[0][bl], 0, 0, 0);
+        acc[0][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(ava, ba, acc[0][bl], 0, 0, 0);
+        acc[0][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(avb, bb, acc[0][bl], 0, 0, 0);
+        acc[0][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(avc, bc, acc[0][bl], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int pt = 0; pt < (NCH == 6 ? 2 : 1); ++pt) {
+        const float w = rk[16 * pt + dxs] * rk[16 * pt + 8 + dys];
+        const float av = ok ? w : 0.f;
+        const float f = rk[32 + 4 * pt + ro.ch];
+        const sf4 zw = *reinterpret_cast<const sf4*>(rk + 44 + kSZ * pt + 4 * ro.zg);
+#pragma unroll
+        for (int bl = 0; bl < kSNB; ++bl) {
+          const float bv = bok ? f * zw[bl] : 0.f;
+          acc[pt][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[pt][bl], 0, 0, 0);
+        }
       }
     }
   }
@@ -151,15 +195,19 @@ __device__ __forceinline__ void wait_loads() {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
-// NCH = 6: forces and torques; 3: forces only.  Blocks of BY rows (8, or 16
-// for sparse particles: more work per staged row); the workgroups share the
-// strip-major sequence of blocks evenly.
-template <int NCH, int BY>
+// NCH = 6: forces and torques; 3: forces only, or (DT) forces with the
+// torques through the derivative of the dipole kernel.  Blocks of BY rows
+// (8, or 16 for sparse particles: more work per staged row).
+template <int NCH, int BY, bool DT>
 __global__ void __launch_bounds__(256)
 k_spread_mfma(DevParams dp, const int* __restrict__ band,
               const int* __restrict__ cell_start, const int4* __restrict__ pinfo,
               const float* __restrict__ pw, const float* __restrict__ pf,
-              const float* __restrict__ psi, float* __restrict__ grid, int nseg) {
+              const float* __restrict__ psi, const float* __restrict__ pdw,
+              const float* __restrict__ dpsi, float* __restrict__ grid, int nseg) {
+  static_assert(!DT || NCH == 3, "derivative torques spread three channels");
+  using R = SRec<DT>;
+  constexpr int kSlots = R::kSlots, kSRec = R::kLen, kCap = R::kCap;
   constexpr int kBY = BY, kTPW = BY / 4;
   constexpr int kRows = BY + 6;            // cell rows of a block's region
   static_assert(2 * kRows <= 64 && 2 * BY + 7 <= 64, "lanes per segment, rows in rs");
@@ -195,7 +243,7 @@ k_spread_mfma(DevParams dp, const int* __restrict__ band,
   const bool vst = (Nx & 3) == 0;          // 16-byte aligned grid rows
 
   for (int c0 = vec ? (lo & ~3) : lo; c0 <= hi; c0 += kSZ) {
-    // piece `lane` of a record (lanes < 24): source and bytes per particle
+    // piece `lane` of a record (lanes < kSlots): source and bytes per particle
     const char* pbase;
     unsigned pstride;
     bool pon;
@@ -203,41 +251,58 @@ k_spread_mfma(DevParams dp, const int* __restrict__ band,
       const int part = lane < kSlots ? lane : kSlots - 1;
       if (part < 8) {
         pbase = reinterpret_cast<const char*>(pw + 4 * part); pstride = 128;
-        pon = NCH == 6 || part < 4;
+        pon = NCH == 6 || DT || part < 4;
       } else if (part < 10) {
         pbase = reinterpret_cast<const char*>(pf + 4 * (part - 8)); pstride = 32;
-        pon = NCH == 6 || part == 8;
+        pon = NCH == 6 || DT || part == 8;
       } else if (part == 10) {
         pbase = reinterpret_cast<const char*>(pinfo); pstride = 16;
         pon = true;
-      } else {
-        const int u = part - 11, h = u >= 5 ? 1 : 0, uu = u - 5 * h;
+      } else if (part < 11 + 5 * R::kZ) {
+        // z weights: monopole, dipole, (DT) dipole derivative rows of the chunk
+        const int u = part - 11, h = u / 5, uu = u - 5 * h;
         const int z = c0 + 4 * uu;
-        // planes past Nz read a clamped address (never stored)
-        pbase = reinterpret_cast<const char*>(psi + h * Nz + (z < Nz ? z : Nz - 4));
-        pstride = 8u * Nz;
-        pon = vec && part < 21 && (NCH == 6 || h == 0);
+        const int zc = z < Nz ? z : Nz - 4;      // past Nz: never stored
+        if (h < 2) {
+          pbase = reinterpret_cast<const char*>(psi + h * Nz + zc); pstride = 8u * Nz;
+        } else {
+          pbase = reinterpret_cast<const char*>(dpsi + zc); pstride = 4u * Nz;
+        }
+        pon = vec && (NCH == 6 || DT || h == 0);
+      } else if (DT && part < 30) {
+        // x/y weights of the dipole kernel's derivative
+        pbase = reinterpret_cast<const char*>(pdw + 4 * (part - 26)); pstride = 64;
+        pon = true;
+      } else {
+        pbase = reinterpret_cast<const char*>(pinfo); pstride = 16;
+        pon = false;
       }
       pon = pon && lane < kSlots;
     }
     // z-weight rows that are not 16-byte aligned: one float per lane
-    // (lanes < 40: monopole then dipole planes of the chunk)
+    // (lanes < 20 per row: monopole, dipole, dipole derivative)
     const float* zbase;
+    unsigned zstride;
     bool zon;
     {
-      const int h = lane >= kSZ ? 1 : 0, z = c0 + lane - kSZ * h;
-      zbase = psi + h * Nz + (z < Nz ? z : Nz - 1);
-      zon = !vec && lane < (NCH == 6 ? 2 : 1) * kSZ;
+      const int h = lane / kSZ, z = c0 + lane - kSZ * h;
+      const int zc = z < Nz ? z : Nz - 1;
+      if (h < 2) {
+        zbase = psi + h * Nz + zc; zstride = 2u * Nz;
+      } else {
+        zbase = dpsi + zc; zstride = Nz;
+      }
+      zon = !vec && lane < (NCH == 6 ? 2 : DT ? 3 : 1) * kSZ;
     }
-    // stage particle p's record in slot s & (kCap - 1) (s uniform)
+    // stage particle p's record in ring slot s (s uniform)
     auto put = [&](int s, int p) {
-      float* dst = rec[s & (kCap - 1)];
+      float* dst = rec[R::slot(s)];
       if (pon)
         __builtin_amdgcn_global_load_lds(pbase + (size_t)p * pstride,
                                          (__attribute__((address_space(3))) void*)dst,
                                          16, 0, 0);
       if (zon)
-        __builtin_amdgcn_global_load_lds(zbase + (size_t)p * 2 * Nz,
+        __builtin_amdgcn_global_load_lds(zbase + (size_t)p * zstride,
                                          (__attribute__((address_space(3))) void*)(dst + 44),
                                          4, 0, 0);
     };
@@ -328,9 +393,9 @@ k_spread_mfma(DevParams dp, const int* __restrict__ band,
               wait_loads();
               __syncthreads();
               if (y < Ny)
-                tile_steps<NCH>(rec, r0 > base ? r0 : base,
-                                r1 < base + cnt ? r1 : base + cnt, base, y, ro, Nx, Ny,
-                                acc);
+                tile_steps<NCH, DT>(rec, r0 > base ? r0 : base,
+                                    r1 < base + cnt ? r1 : base + cnt, base, y, ro, Nx,
+                                    Ny, acc);
               __syncthreads();             // the batch is read
             }
             tile_store<NCH>(grid, acc, c0, lo, hi, y, ro, Nx, Ny, plane, chstride, vst);
@@ -360,7 +425,8 @@ k_spread_mfma(DevParams dp, const int* __restrict__ band,
           for (int q = 0; q < kSNB; ++q) acc[pt][q] = sf4{0.f, 0.f, 0.f, 0.f};
         const int y = yb + wv * kTPW + tt;
         if (y < Ny)
-          tile_steps<NCH>(rec, rs[(y - 3) & 63], rs[(y + 4) & 63], 0, y, ro, Nx, Ny, acc);
+          tile_steps<NCH, DT>(rec, rs[(y - 3) & 63], rs[(y + 4) & 63], 0, y, ro, Nx, Ny,
+                              acc);
         // the next rows' loads were issued before the steps (and the first
         // tile row's stores one tile row ago): wait before the last stores
         if (tt == kTPW - 1) wait_loads();
@@ -393,7 +459,7 @@ bool spread_mfma_fits(const fcmdp_solver* s) {
   return s->dp.Nx >= kSW + 6 && s->dp.Ny >= 8 + 6;
 }
 
-template <int NCH, int BY>
+template <int NCH, int BY, bool DT = false>
 static void spread_mfma_impl(const fcmdp_solver* s, void* grid, hipStream_t st) {
   const int gx = (s->dp.Nx + kSW - 1) / kSW, nby = (s->dp.Ny + BY - 1) / BY;
   const int nblk = gx * nby;
@@ -410,19 +476,29 @@ static void spread_mfma_impl(const fcmdp_solver* s, void* grid, hipStream_t st) 
     nwg = gx * nseg;
   }
   if (nwg > nblk) nwg = nblk;
-  hipLaunchKernelGGL((k_spread_mfma<NCH, BY>), dim3(nwg), dim3(256), 0, st, s->dp,
+  hipLaunchKernelGGL((k_spread_mfma<NCH, BY, DT>), dim3(nwg), dim3(256), 0, st, s->dp,
                      s->band, s->cell_start, s->pinfo, (const float*)s->pw,
-                     (const float*)s->pf, (const float*)s->psi, (float*)grid, nseg);
+                     (const float*)s->pf, (const float*)s->psi,
+                     DT ? (const float*)s->pdw : nullptr,
+                     DT ? (const float*)s->dpsi : nullptr, (float*)grid, nseg);
 }
 
 hipError_t launch_spread_mfma(const fcmdp_solver* s, int n, void* grid, hipStream_t st) {
   // 16-row blocks when a region and the next block's rows (22 x 38 cells)
-  // hold about 100 particles or fewer, so that the next rows still load
-  // beside the current block
+  // hold about three quarters of the ring or fewer, so that the next rows
+  // still load beside the current block
+  const bool dt = s->dp.dt_torque != 0;
   int by = s->spread_block_rows;
-  if (by == 0)
-    by = (double)n * (22.0 * 38.0) <= 100.0 * (double)s->dp.Nx * s->dp.Ny ? 16 : 8;
+  if (by == 0) {
+    const double fill = 0.78 * (dt ? SRec<true>::kCap : SRec<false>::kCap);
+    by = (double)n * (22.0 * 38.0) <= fill * (double)s->dp.Nx * s->dp.Ny ? 16 : 8;
+  }
   if (s->dp.Ny < 16 + 6) by = 8;
+  if (dt) {
+    by == 16 ? spread_mfma_impl<3, 16, true>(s, grid, st)
+             : spread_mfma_impl<3, 8, true>(s, grid, st);
+    return hipGetLastError();
+  }
   const bool dip = s->dp.nch_in == 6;
   if (by == 16)
     dip ? spread_mfma_impl<6, 16>(s, grid, st) : spread_mfma_impl<3, 16>(s, grid, st);

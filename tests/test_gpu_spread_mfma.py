@@ -15,6 +15,8 @@ the next rows are staged after a block instead of beside it or a region
 outgrows the ring (staged in batches), forces only, and bitwise
 repeatability.
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 
@@ -169,3 +171,46 @@ def test_workgroups_refused():
     for bad in (-1, 3):
         with pytest.raises(FcmdpError):
             s.set_variant("spread_order", bad)
+
+
+DT_BOXES = {
+    "bw48": replace(BOXES["bw48"], torque_route="derivative"),
+    "bw30x28": replace(BOXES["bw30x28"], torque_route="derivative"),
+    "sc40x56": replace(BOXES["sc40x56"], torque_route="derivative"),
+}
+
+
+@pytest.mark.parametrize("name", list(DT_BOXES))
+def test_derivative_torques_match_gather_and_oracle(name):
+    """Torques through the derivative of the dipole kernel (the second torque
+    route of Sec. 3.4): the three-channel matrix-core spread (four weight
+    matrices per step) against the gather spread and the oracle's
+    DerivativeSolver; the slit channel without its FP64 vertical-force
+    route, which keeps the gather."""
+    from oracle import torque_deriv
+    box = DT_BOXES[name]
+    pos, F, T = _particles(box, 160, 26)
+    if name == "bw48":
+        # a cluster of 150 in 3 x 3 cells: regions staged in batches
+        rng = np.random.default_rng(77)
+        pos[10:, 0] = 20.0 + 3 * box.h * rng.random(150)
+        pos[10:, 1] = 5.0 + 3 * box.h * rng.random(150)
+        pos = pos.astype(np.float32).astype(np.float64)
+    print(f"[spread mfma] derivative torques {name}", flush=True)
+    out = []
+    for wave in (False, True):
+        s = _solver(box, wave=wave)
+        if box.geometry == "sc":
+            s.set_variant("no_lowk", 1)
+        U, Om = s.apply(_dev(pos), _dev(F), _dev(T))
+        out.append((_np(U), _np(Om)))
+    (U1, O1), (U2, O2) = out
+    eU, eO = rel_err(U1, U2), rel_err(O1, O2)
+    print(f"  vs gather: U {eU:.3e} Omega {eO:.3e}", flush=True)
+    assert eU < 2e-6 and eO < 2e-6
+    if box.geometry == "bw":
+        rU, rO = torque_deriv.DerivativeSolver(box).apply(pos, F, T)
+        eU, eO = rel_err(U1, rU), rel_err(O1, rO)
+        print(f"  vs oracle: U {eU:.3e} Omega {eO:.3e}", flush=True)
+        assert eU < 1e-5 and eO < 1e-5
+        assert particle_err(U1, rU) < 1e-4 and particle_err(O1, rO) < 1e-4
