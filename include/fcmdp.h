@@ -262,11 +262,17 @@ enum {
   FCMDP_VARIANT_SPREAD_BLOCK_ROWS = 12, /* MIXED: grid rows per block of the
                                         matrix-core spread (8 or 16; 0 =
                                         default, chosen by particle density) */
-  FCMDP_VARIANT_SPREAD_ORDER = 13    /* MIXED: block order of the matrix-core
+  FCMDP_VARIANT_SPREAD_ORDER = 13,   /* MIXED: block order of the matrix-core
                                         spread: 1 strip-major, shared evenly;
                                         2 neighbouring strips side by side;
                                         0 = default: 1 if grid rows are whole
                                         128-byte lines, else 2 */
+  FCMDP_VARIANT_HALO_INTERP = 14     /* interpolation by workgroups that own
+                                        the particles of 26 x 26 cells and
+                                        stage their planes with a 3-node halo,
+                                        instead of partial sums over aligned
+                                        32 x 16 tiles (read once) added per
+                                        particle in a fixed order */
 };
 int fcmdp_set_variant(fcmdp_solver* s, int key, int value);
 
@@ -312,7 +318,8 @@ int fcmdp_stage_fft_inverse(fcmdp_solver* s, const void* spectrum, void* grid,
                             int c_lo, int c_hi, void* hip_stream);
 
 /* Step 8: interpolation (eqs. getpartvel, getpartvort) of u and omega from
- * the grid (all planes may be read). */
+ * the grid (all planes may be read).  The solver's own spectrum buffer holds
+ * the per-tile partial sums, so its contents are not kept. */
 int fcmdp_stage_interp(fcmdp_solver* s, int64_t n, const void* pos,
                        const void* grid, void* U, void* Omega,
                        void* hip_stream);

@@ -812,6 +812,9 @@ int fcmdp_set_variant(fcmdp_solver* s, int key, int value) {
       if (value != 0 && value != 8 && value != 16) return FCMDP_EINVAL;
       s->spread_block_rows = value;
       return FCMDP_OK;
+    case FCMDP_VARIANT_HALO_INTERP:
+      s->force_halo_interp = on;
+      return FCMDP_OK;
     case FCMDP_VARIANT_SPREAD_ORDER:
       if (value < 0 || value > 2) return FCMDP_EINVAL;
       s->spread_order = value;

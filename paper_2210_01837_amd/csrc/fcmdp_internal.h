@@ -160,6 +160,9 @@ struct fcmdp_solver {
   bool force_generic_columns = false;
   // use the one-thread-per-particle interpolation (tests)
   bool force_simple_interp = false;
+  // home-particle interpolation tiles with a staged halo instead of the
+  // partial sums over aligned tiles
+  bool force_halo_interp = false;
   // use the untiled gather spread (tests)
   bool force_simple_spread = false;
   // use the per-patch gather spread instead of the matrix-core spread of the
@@ -208,6 +211,12 @@ bool spread_mfma_fits(const fcmdp_solver* s);
 hipError_t launch_spread_mfma(const fcmdp_solver* s, int n, void* grid, hipStream_t st);
 hipError_t launch_interp(const fcmdp_solver* s, int n, const void* grid,
                          void* U, void* Omega, hipStream_t st);
+// interp_part.hip: interpolation over aligned 32 x 16 tiles with per-tile
+// partial sums kept in the spectrum buffer (grids of at least 38 x 22 nodes
+// and partial sums that fit there)
+bool interp_part_fits(const fcmdp_solver* s, int n);
+hipError_t launch_interp_part(const fcmdp_solver* s, int n, const void* grid,
+                              void* U, void* Omega, hipStream_t st);
 // lowk.hip: exact FP64 Chebyshev coefficients of the vertical force density
 // at the low wavenumbers (from the spread's f_z and fzlo planes)
 hipError_t launch_lowk(const fcmdp_solver* s, const void* grid, hipStream_t st);

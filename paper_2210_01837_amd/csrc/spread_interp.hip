@@ -998,6 +998,9 @@ static hipError_t interp_tiled(const fcmdp_solver* s, int n, const T* grid,
 hipError_t launch_interp(const fcmdp_solver* s, int n, const void* grid,
                          void* U, void* Omega, hipStream_t st) {
   if (n == 0) return hipSuccess;
+  if ((!s->force_simple_interp || s->dp.dt_omega) && !s->force_halo_interp &&
+      interp_part_fits(s, n))
+    return launch_interp_part(s, n, grid, U, Omega, st);
   if (!s->force_simple_interp || s->dp.dt_omega) {
     if (s->mixed)
       return interp_tiled<float>(s, n, (const float*)grid, (float*)U,

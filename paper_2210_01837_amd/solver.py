@@ -187,7 +187,7 @@ class Solver:
                 "vector_dct": 6, "no_codelet": 7, "no_pipeline": 8,
                 "no_lowk": 9, "wave_spread": 10, "spread_workgroups": 11,
                 "spread_block_rows": 12,
-                "spread_order": 13}
+                "spread_order": 13, "halo_interp": 14}
 
     def set_variant(self, name, value):
         """Select an alternative kernel (see fcmdp_set_variant)."""

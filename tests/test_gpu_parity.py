@@ -140,6 +140,50 @@ def test_stage_interp_fp64(name):
     assert rel_err(_np(Om), rO) < 1e-13
 
 
+# Shapes of the aligned-tile interpolation (32 x 16 tiles): whole and
+# ragged last tiles, last tiles narrower than six nodes (a window then meets
+# three tiles along that axis), and the smallest grid it takes (40 x 22).
+INTERP_BOXES = {
+    "bw48": BOXES["bw48"],
+    "sc40x56": BOXES["sc40x56"],
+    "bw68x70": Box("bw", 34.0, 35.0, 6.0, 68, 70, 16),
+    "sc100x36": Box("sc", 50.0, 18.0, 6.0, 100, 36, 12),
+    "bw40x22": Box("bw", 20.0, 11.0, 5.0, 40, 22, 12),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(INTERP_BOXES))
+def test_stage_interp_tiles(name, precision):
+    """Partial sums over aligned tiles against the oracle, the halo-tile
+    kernel and itself (bit for bit on a second run)."""
+    box = INTERP_BOXES[name]
+    pos, F, T = _particles(box, 150, 21)
+    grid = workloads.random_array((6, box.Nz, box.Ny, box.Nx), 22)
+    if precision == "mixed":
+        pos, grid = (a.astype(np.float32).astype(np.float64) for a in (pos, grid))
+    print(f"[interp tiles] {name} {precision}", flush=True)
+    s = _solver(box, precision)
+    P, G = _dev(pos, precision), _dev(grid, precision)
+    U, Om = s.stage_interp(P, G)
+    U2, O2 = s.stage_interp(P, G)
+    torch.cuda.synchronize()
+    assert torch.equal(U, U2) and torch.equal(Om, O2)
+    s.set_variant("halo_interp", 1)
+    Uh, Oh = s.stage_interp(P, G)
+    s.set_variant("halo_interp", 0)
+    rU, rO = oracle_interp(box, pos, grid)
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    for got, ref in ((U, rU), (Om, rO)):
+        e, ep = rel_err(_np(got), ref), particle_err(_np(got), ref)
+        print(f"  vs oracle rel {e:.3e} particle {ep:.3e}", flush=True)
+        assert e < tol and ep < 4 * tol
+    for got, ref in ((U, Uh), (Om, Oh)):
+        e = rel_err(_np(got), _np(ref))
+        print(f"  vs halo tiles rel {e:.3e}", flush=True)
+        assert e < tol
+
+
 @pytest.mark.parametrize("name", ["bw48", "sc40x56"])
 def test_apply_fp64_small(name):
     box = BOXES[name]
