@@ -67,7 +67,7 @@ PAPER_FORCES_ONLY_RATE = 663552 / 0.370
 
 # the kernel each single-kernel stage launches once per apply
 STAGE_KERNEL = {"spread": "k_spread_mfma", "columns": "k_columns_mfma",
-                "interp": "k_interp_tiled"}
+                "interp": "k_interp_part"}
 
 
 def measured_traffic(workload, kernel):
@@ -475,8 +475,9 @@ def main():
                          complex_bytes=8 if wl.precision == "mixed" else 16,
                          real_bytes=4 if wl.precision == "mixed" else 8,
                          torques=wl.torques, lowk=lowk)
-    # dominant stage; its kernel (one launch per apply for the columns,
-    # spread and interp stages) is what the roofline describes
+    # dominant stage; its kernel (one launch per apply for the columns and
+    # spread stages; the interp stage is its tile kernel plus a small
+    # per-particle sum) is what the roofline describes
     dom = max((k for k in nbytes), key=lambda k: avg[k])
     achieved = nbytes[dom] / (avg[dom] * 1e-3) / 1e9
     kname = STAGE_KERNEL.get(dom)

@@ -37,8 +37,9 @@ template <typename T> struct V8;
 template <> struct V8<float> { typedef float type __attribute__((ext_vector_type(2))); };
 template <> struct V8<double> { typedef double type __attribute__((ext_vector_type(2))); };
 
-// per particle: wxM[7] wyM[7] wxD[7] wyD[7] (and with DT wxD'[7] wyD'[7])
-template <bool DT> struct PRec { static constexpr int n = DT ? 42 : 28; };
+// per particle in LDS: the y weights wyM[7] wyD[7] (and with DT wyD'[7]);
+// the x weights are read from the records once, at the end of a pass
+template <bool DT> struct PRec { static constexpr int n = DT ? 21 : 14; };
 
 __device__ __forceinline__ int wrap_near(int v, int n) {
   // v in [-n, 2n)
@@ -71,7 +72,7 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
   T* G = reinterpret_cast<T*>(lds_raw);                 // [ZC][NCH][kPY][kPX]
   T* pcw = G + NROW * kPX;                              // [cap][kRec]
   T* pz = pcw + cap * kRec;                             // [cap][NZS]
-  int4* pci = reinterpret_cast<int4*>(pz + cap * NZS);  // [cap]
+  int4* pci = reinterpret_cast<int4*>(pz + cap * NZS);  // [cap] window
   int* pcp = reinterpret_cast<int*>(pci + cap);         // [cap] sorted index
   int* pcs = pcp + cap;                                 // [cap] slot
   __shared__ int segoff[kPSeg + 1];
@@ -157,7 +158,12 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
       }
       const int p = segst[a] + (hp - segoff[a]);
       const int4 inf = pinfo[p];
-      pci[h] = inf;
+      // first column and row of the window, tile-local and unwrapped so
+      // that the window meets the tile
+      int sx = inf.x - 3 - tx0, sy = inf.y - 3 - ty0;
+      sx += sx + 6 < 0 ? Nx : (sx >= tw ? -Nx : 0);
+      sy += sy + 6 < 0 ? Ny : (sy >= th ? -Ny : 0);
+      pci[h] = make_int4(sx, sy, inf.z, inf.w);
       pcp[h] = p;
       // slot: tiles counted from the one holding the window's first node
       const int fx = wrap_near(inf.x - 3, Nx) / kPX;
@@ -170,14 +176,9 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
       T* d = pcw + h * kRec;
 #pragma unroll
       for (int e = 0; e < 7; ++e) {
-        d[e] = w[e];
-        d[7 + e] = w[8 + e];
-        d[14 + e] = w[16 + e];
-        d[21 + e] = w[24 + e];
-        if constexpr (DT) {
-          d[28 + e] = pdw[(size_t)p * 16 + e];
-          d[35 + e] = pdw[(size_t)p * 16 + 8 + e];
-        }
+        d[e] = w[8 + e];
+        d[7 + e] = w[24 + e];
+        if constexpr (DT) d[14 + e] = pdw[(size_t)p * 16 + 8 + e];
       }
     }
     if (zhi >= 0) {
@@ -253,18 +254,15 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
       for (int k = 0; k < 2; ++k) {
         const int h = g + NG * k;
         if (h >= np) continue;
-        const int4 inf = pci[h];
-        if (inf.w < c0 || inf.z > c0 + nz - 1) continue;   // no z overlap
-        // tile-local first column and row of the window (unwrapped so that
-        // the window meets the tile)
-        int sx = inf.x - 3 - tx0, sy = inf.y - 3 - ty0;
-        sx += sx + 6 < 0 ? Nx : (sx >= tw ? -Nx : 0);
-        sy += sy + 6 < 0 ? Ny : (sy >= th ? -Ny : 0);
+        // (first window column, first row, z window), tile-local
+        const int4 geo = pci[h];
+        if (geo.w < c0 || geo.z > c0 + nz - 1) continue;   // no z overlap
+        const int sy = geo.y;
         // the lane's column pair: both in the tile or both outside (tile
         // widths are even)
-        const int e0 = (sx & ~1) + 2 * l;
-        const int ec = (e0 >= 0 && e0 < tw) ? e0 : 0;
-        const bool xon = e0 >= 0 && e0 < tw;
+        const int e0 = (geo.x & ~1) + 2 * l;
+        const bool xon = (unsigned)e0 < (unsigned)tw;
+        const int ec = xon ? e0 : 0;
         const int ra = max(sy, 0), rb = min(sy + 6, th - 1);
         const T* w = pcw + h * kRec;
         const T* zs = pz + h * NZS;
@@ -276,11 +274,13 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
           pd[sidx] = ok ? q[sidx] * zs[ZC + sidx] : T(0);
           if constexpr (DT) pq[sidx] = ok ? q[sidx] * zs[2 * ZC + sidx] : T(0);
         }
-        for (int ry = ra; ry <= rb; ++ry) {
+        // the window's seven rows, unrolled (rows outside the tile skipped)
+#pragma unroll
+        for (int ry = ra; ry < ra + 7; ++ry) if (ry <= rb) {
           const int dy = ry - sy;
-          const T wym = w[7 + dy], wyd = w[21 + dy];
+          const T wym = w[dy], wyd = w[7 + dy];
           T wyq = T(0);
-          if constexpr (DT) wyq = w[35 + dy];
+          if constexpr (DT) wyq = w[14 + dy];
 #pragma unroll
           for (int sidx = 0; sidx < ZC; ++sidx) {
             if (sidx < nz) {
@@ -336,11 +336,10 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
       const int h = g + NG * k;
       const bool on = h < np;
       const int hc = on ? h : 0;
-      const int4 inf = pci[hc];
-      int sx = inf.x - 3 - tx0;
-      sx += sx + 6 < 0 ? Nx : (sx >= tw ? -Nx : 0);
+      const int sx = pci[hc].x;
       const int e0 = (sx & ~1) + 2 * l;
-      const T* w = pcw + hc * kRec;
+      const int p = pcp[hc];
+      const T* w = pw + (size_t)p * 32;
       T o[NOUT];
 #pragma unroll
       for (int a = 0; a < NOUT; ++a) o[a] = T(0);
@@ -349,13 +348,13 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
         const int dx = e0 + e - sx;                     // window offset
         const bool in = e0 >= 0 && e0 < tw && dx >= 0 && dx < 7;
         const int dxc = in ? dx : 0;
-        const T wxm = in ? w[dxc] : T(0), wxd = in ? w[14 + dxc] : T(0);
+        const T wxm = in ? w[dxc] : T(0), wxd = in ? w[16 + dxc] : T(0);
         const T* a = sacc[k][e];
         o[0] += wxm * a[0];
         o[1] += wxm * a[1];
         o[2] += wxm * a[2];
         if constexpr (DT) {
-          const T wxq = in ? w[28 + dxc] : T(0);
+          const T wxq = in ? pdw[(size_t)p * 16 + dxc] : T(0);
           o[3] += wxd * a[3];
           o[4] += wxq * a[4] - wxd * a[5];
           o[5] += wxd * a[6] - wxq * a[7];
@@ -370,7 +369,7 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
 #pragma unroll
         for (int a = 0; a < NOUT; ++a) o[a] += __shfl_xor(o[a], m, GL);
       if (on && l == 0) {
-        T* dst = part + ((size_t)pcp[h] * nslot + pcs[h]) * NOUT;
+        T* dst = part + ((size_t)p * nslot + pcs[h]) * NOUT;
 #pragma unroll
         for (int a = 0; a < NOUT; ++a) dst[a] = o[a];
       }
@@ -477,9 +476,11 @@ hipError_t part_impl(const fcmdp_solver* s, int n, const T* grid, T* U, T* Om,
   const int nqx = tiles_met(dp.Nx, kPX), nqy = tiles_met(dp.Ny, kPY);
   // particles cached per pass: a monolayer at area fraction 0.5 has ~0.22
   // particles per xy cell, ~185 in a tile's 38 x 22 cells; denser tiles
-  // take several passes.  Two workgroups fit on a CU.
-  constexpr int ZC = sizeof(T) == 4 ? 2 : 1;
-  const int cap = sizeof(T) == 4 ? 256 : 160;
+  // take several passes.  One plane per chunk keeps the LDS of a workgroup
+  // small (35 KB in FP32, 64 KB in FP64), so that several share a CU:
+  // the kernel waits on LDS and memory latency more than on either's rate.
+  constexpr int ZC = 1;
+  const int cap = 256;
   if (cap > 2 * (kPThreads / 4)) return hipErrorInvalidValue;  // two per lane group
   if (Om && dp.dt_omega)
     part_launch<T, ZC, 3, true>(s, n, grid, U, Om, cap, nqx, nqy, st);

@@ -41,6 +41,8 @@ KERNEL_SOURCES = {
     "k_spread_wave": ["spread_interp.hip", "es.h", "fcmdp_internal.h"],
     "k_spread_mfma": ["spread_mfma.hip", "fcmdp_internal.h"],
     "k_interp_tiled": ["spread_interp.hip", "es.h", "fcmdp_internal.h"],
+    "k_interp_part": ["interp_part.hip", "fcmdp_internal.h"],
+    "k_interp_sum": ["interp_part.hip", "fcmdp_internal.h"],
     "k_fftw_x_r2c": ["fft.hip", "fcmdp_internal.h"],
     "k_fftw_y": ["fft.hip", "fcmdp_internal.h"],
     "k_fftw_y_pipe": ["fft.hip", "fcmdp_internal.h"],
