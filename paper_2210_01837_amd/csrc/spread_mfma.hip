@@ -99,7 +99,12 @@ __device__ __forceinline__ Roles lane_roles(int lane, int xb, int Nx) {
 // receive F phi_M phi_M psi_M + (1/2) grad Delta_D x tau, one weight matrix
 // per term of grad Delta_D = (phi_D' phi_D psi_D, phi_D phi_D' psi_D,
 // phi_D phi_D psi_D') (same slots, one accumulator set).
-template <int NCH, bool DT>
+// WRAP: the block's particle region crosses a periodic seam (offsets are
+// then taken modulo the grid size; elsewhere they already lie in range).
+// The B operand needs no zeroing: a particle that is out of range, or a
+// step slot past the end, has a zero A column, and every ring slot holds a
+// record (finite values), so its products vanish; slot 15 is never stored.
+template <int NCH, bool DT, bool WRAP>
 __device__ __forceinline__ void tile_steps(const float (*rec)[SRec<DT>::kLen], int s0,
                                            int s1, int base, int y, const Roles& ro,
                                            int Nx, int Ny, sf4 (&acc)[2][kSNB]) {
@@ -109,12 +114,13 @@ __device__ __forceinline__ void tile_steps(const float (*rec)[SRec<DT>::kLen], i
     const float* rk = rec[SRec<DT>::slot(have ? k - base : 0)];
     const int ix = __float_as_int(rk[40]), iy = __float_as_int(rk[41]);
     int dx = ro.a - ix + 3;
-    if (dx < 0) dx += Nx; else if (dx >= Nx) dx -= Nx;
     int dy = y - iy + 3;
-    if (dy < 0) dy += Ny; else if (dy >= Ny) dy -= Ny;
+    if constexpr (WRAP) {
+      if (dx < 0) dx += Nx; else if (dx >= Nx) dx -= Nx;
+      if (dy < 0) dy += Ny; else if (dy >= Ny) dy -= Ny;
+    }
     const bool ok = have && ro.inside && (unsigned)dx <= 6u && (unsigned)dy <= 6u;
     const int dxs = ok ? dx : 0, dys = ok ? dy : 0;
-    const bool bok = have && ro.slot;
     if constexpr (DT) {
       // A: the four weight products of the tile column; B: coefficient of
       // channel ch times the z weight row of the term
@@ -136,10 +142,10 @@ __device__ __forceinline__ void tile_steps(const float (*rec)[SRec<DT>::kLen], i
       const float avb = ok ? ab : 0.f, avc = ok ? ac : 0.f;
 #pragma unroll
       for (int bl = 0; bl < kSNB; ++bl) {
-        const float bm = bok ? cm * zm[bl] : 0.f;
-        const float ba = bok ? ca * zd[bl] : 0.f;
-        const float bb = bok ? cb * zd[bl] : 0.f;
-        const float bc = bok ? cc * zq[bl] : 0.f;
+        const float bm = cm * zm[bl];
+        const float ba = ca * zd[bl];
+        const float bb = cb * zd[bl];
+        const float bc = cc * zq[bl];
         acc[0][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(avm, bm, acc[0][bl], 0, 0, 0);
         acc[0][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(ava, ba, acc[0][bl], 0, 0, 0);
         acc[0][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(avb, bb, acc[0][bl], 0, 0, 0);
@@ -154,7 +160,7 @@ __device__ __forceinline__ void tile_steps(const float (*rec)[SRec<DT>::kLen], i
         const sf4 zw = *reinterpret_cast<const sf4*>(rk + 44 + kSZ * pt + 4 * ro.zg);
 #pragma unroll
         for (int bl = 0; bl < kSNB; ++bl) {
-          const float bv = bok ? f * zw[bl] : 0.f;
+          const float bv = f * zw[bl];
           acc[pt][bl] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[pt][bl], 0, 0, 0);
         }
       }
@@ -317,6 +323,9 @@ k_spread_mfma(DevParams dp, const int* __restrict__ band,
       if (sx != cur_sx) ring = false;      // a new strip: start over
       cur_sx = sx;
       const Roles ro = lane_roles(lane, xb, Nx);
+      // the block's particle region (cells xb - 3 .. xb + 18, rows yb - 3 ..
+      // yb + kBY + 2) crosses a periodic seam
+      const bool seam = xb < 3 || xb + kSW + 3 > Nx || yb < 3 || yb + kBY + 3 > Ny;
       // the strip's cells xb - 3 .. xb + 18, split at the periodic seam
       const int xs = wrap_index(xb - 3, Nx);
       const int xe0 = xs + kSW + 6 <= Nx ? xs + kSW + 6 : Nx;
@@ -393,9 +402,9 @@ k_spread_mfma(DevParams dp, const int* __restrict__ band,
               wait_loads();
               __syncthreads();
               if (y < Ny)
-                tile_steps<NCH, DT>(rec, r0 > base ? r0 : base,
-                                    r1 < base + cnt ? r1 : base + cnt, base, y, ro, Nx,
-                                    Ny, acc);
+                tile_steps<NCH, DT, true>(rec, r0 > base ? r0 : base,
+                                          r1 < base + cnt ? r1 : base + cnt, base, y, ro,
+                                          Nx, Ny, acc);
               __syncthreads();             // the batch is read
             }
             tile_store<NCH>(grid, acc, c0, lo, hi, y, ro, Nx, Ny, plane, chstride, vst);
@@ -424,9 +433,14 @@ k_spread_mfma(DevParams dp, const int* __restrict__ band,
 #pragma unroll
           for (int q = 0; q < kSNB; ++q) acc[pt][q] = sf4{0.f, 0.f, 0.f, 0.f};
         const int y = yb + wv * kTPW + tt;
-        if (y < Ny)
-          tile_steps<NCH, DT>(rec, rs[(y - 3) & 63], rs[(y + 4) & 63], 0, y, ro, Nx, Ny,
-                              acc);
+        if (y < Ny) {
+          if (seam)
+            tile_steps<NCH, DT, true>(rec, rs[(y - 3) & 63], rs[(y + 4) & 63], 0, y, ro,
+                                      Nx, Ny, acc);
+          else
+            tile_steps<NCH, DT, false>(rec, rs[(y - 3) & 63], rs[(y + 4) & 63], 0, y, ro,
+                                       Nx, Ny, acc);
+        }
         // the next rows' loads were issued before the steps (and the first
         // tile row's stores one tile row ago): wait before the last stores
         if (tt == kTPW - 1) wait_loads();
