@@ -99,15 +99,15 @@ __device__ __forceinline__ Roles lane_roles(int lane, int xb, int Nx) {
 // receive F phi_M phi_M psi_M + (1/2) grad Delta_D x tau, one weight matrix
 // per term of grad Delta_D = (phi_D' phi_D psi_D, phi_D phi_D' psi_D,
 // phi_D phi_D psi_D') (same slots, one accumulator set).
-// WRAP: the block's particle region crosses a periodic seam (offsets are
+// wrap: the block's particle region crosses a periodic seam (offsets are
 // then taken modulo the grid size; elsewhere they already lie in range).
 // The B operand needs no zeroing: a particle that is out of range, or a
 // step slot past the end, has a zero A column, and every ring slot holds a
 // record (finite values), so its products vanish; slot 15 is never stored.
-template <int NCH, bool DT, bool WRAP>
+template <int NCH, bool DT>
 __device__ __forceinline__ void tile_steps(const float (*rec)[SRec<DT>::kLen], int s0,
                                            int s1, int base, int y, const Roles& ro,
-                                           int Nx, int Ny, sf4 (&acc)[2][kSNB]) {
+                                           int Nx, int Ny, bool wrap, sf4 (&acc)[2][kSNB]) {
   for (int k0 = s0; k0 < s1; k0 += 4) {
     const int k = k0 + ro.g;
     const bool have = k < s1;
@@ -115,7 +115,7 @@ __device__ __forceinline__ void tile_steps(const float (*rec)[SRec<DT>::kLen], i
     const int ix = __float_as_int(rk[40]), iy = __float_as_int(rk[41]);
     int dx = ro.a - ix + 3;
     int dy = y - iy + 3;
-    if constexpr (WRAP) {
+    if (wrap) {                    // wave-uniform
       if (dx < 0) dx += Nx; else if (dx >= Nx) dx -= Nx;
       if (dy < 0) dy += Ny; else if (dy >= Ny) dy -= Ny;
     }
@@ -402,9 +402,9 @@ k_spread_mfma(DevParams dp, const int* __restrict__ band,
               wait_loads();
               __syncthreads();
               if (y < Ny)
-                tile_steps<NCH, DT, true>(rec, r0 > base ? r0 : base,
-                                          r1 < base + cnt ? r1 : base + cnt, base, y, ro,
-                                          Nx, Ny, acc);
+                tile_steps<NCH, DT>(rec, r0 > base ? r0 : base,
+                                    r1 < base + cnt ? r1 : base + cnt, base, y, ro, Nx,
+                                    Ny, true, acc);
               __syncthreads();             // the batch is read
             }
             tile_store<NCH>(grid, acc, c0, lo, hi, y, ro, Nx, Ny, plane, chstride, vst);
@@ -433,14 +433,9 @@ k_spread_mfma(DevParams dp, const int* __restrict__ band,
 #pragma unroll
           for (int q = 0; q < kSNB; ++q) acc[pt][q] = sf4{0.f, 0.f, 0.f, 0.f};
         const int y = yb + wv * kTPW + tt;
-        if (y < Ny) {
-          if (seam)
-            tile_steps<NCH, DT, true>(rec, rs[(y - 3) & 63], rs[(y + 4) & 63], 0, y, ro,
-                                      Nx, Ny, acc);
-          else
-            tile_steps<NCH, DT, false>(rec, rs[(y - 3) & 63], rs[(y + 4) & 63], 0, y, ro,
-                                       Nx, Ny, acc);
-        }
+        if (y < Ny)
+          tile_steps<NCH, DT>(rec, rs[(y - 3) & 63], rs[(y + 4) & 63], 0, y, ro, Nx, Ny,
+                              seam, acc);
         // the next rows' loads were issued before the steps (and the first
         // tile row's stores one tile row ago): wait before the last stores
         if (tt == kTPW - 1) wait_loads();
