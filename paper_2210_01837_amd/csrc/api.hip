@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "fcmdp_internal.h"
@@ -63,6 +64,15 @@ double sinpi_frac(long num, long den) {
   long r = num % (2 * den);
   if (r < 0) r += 2 * den;
   return (double)std::sin((long double)kPi * (long double)r / (long double)den);
+}
+// e^{-2 pi i j / n} for j < n (interleaved re, im)
+std::vector<double> roots_of_unity(int n) {
+  std::vector<double> r(2 * (size_t)n);
+  for (int j = 0; j < n; ++j) {
+    r[2 * (size_t)j] = cospi_frac(2L * j, n);
+    r[2 * (size_t)j + 1] = -sinpi_frac(2L * j, n);
+  }
+  return r;
 }
 
 // Clenshaw-Curtis weights on the N extrema points of [-1, 1] (the classical
@@ -303,48 +313,77 @@ Sizes sizes_for(const fcmdp_params* p, int64_t cap, int ZW) {
   return s;
 }
 
-// Device tables are uploaded in stream order on the creation stream; the host
-// copies stay alive (in `keep`) until that stream has been synchronised.
+// Device tables are staged host-side into one buffer and uploaded with one
+// allocation and one copy in stream order on the creation stream (finish());
+// the host copy stays alive until that stream has been synchronised.  Each
+// table starts on a 256-byte boundary.
 struct Uploader {
   hipStream_t st;
-  std::vector<std::vector<unsigned char>> keep;
-  int* err;
-  template <typename T>
-  void* operator()(const std::vector<T>& v) {
-    if (*err != FCMDP_OK) return nullptr;
-    void* d = nullptr;
+  std::vector<unsigned char> host;
+  std::vector<std::pair<void**, size_t>> slots;   // destination, offset
+  void* base = nullptr;
+  template <typename P, typename T>
+  void to(P** dst, const std::vector<T>& v) {
+    const size_t off = (host.size() + 255) & ~(size_t)255;
     const size_t bytes = sizeof(T) * v.size();
-    if (hipMallocAsync(&d, bytes ? bytes : 16, st) != hipSuccess) {
-      *err = FCMDP_ENOMEM;
-      return nullptr;
-    }
-    keep.emplace_back(reinterpret_cast<const unsigned char*>(v.data()),
-                      reinterpret_cast<const unsigned char*>(v.data()) + bytes);
-    if (bytes && hipMemcpyAsync(d, keep.back().data(), bytes,
-                                hipMemcpyHostToDevice, st) != hipSuccess)
-      *err = FCMDP_EHIP;
-    return d;
+    host.resize(off + (bytes ? bytes : 16), 0);
+    if (bytes) std::memcpy(host.data() + off, v.data(), bytes);
+    slots.emplace_back(reinterpret_cast<void**>(dst), off);
   }
-  template <typename T>
-  void* twiddles(int n, int count) {
+  // e^{-2 pi i m s / n} for m < count, from root[] = e^{-2 pi i j / N}
+  // (N = n s, j < N; each root evaluated once)
+  template <typename T, typename P>
+  void twiddles(P** dst, const std::vector<double>& root, int s, int count) {
     std::vector<T> v(2 * (size_t)count);
+    const size_t N = root.size() / 2;
     for (int m = 0; m < count; ++m) {
-      v[2 * m] = (T)cospi_frac(2L * m, n);
-      v[2 * m + 1] = (T)(-sinpi_frac(2L * m, n));
+      const size_t j = ((size_t)m * s) % N;
+      v[2 * m] = (T)root[2 * j];
+      v[2 * m + 1] = (T)root[2 * j + 1];
     }
-    return (*this)(v);
+    to(dst, v);
+  }
+  int finish() {
+    if (host.empty()) return FCMDP_OK;
+    if (hipMallocAsync(&base, host.size(), st) != hipSuccess) {
+      base = nullptr;
+      return FCMDP_ENOMEM;
+    }
+    for (auto& sl : slots) *sl.first = static_cast<unsigned char*>(base) + sl.second;
+    if (hipMemcpyAsync(base, host.data(), host.size(), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return FCMDP_EHIP;
+    return FCMDP_OK;
+  }
+};
+
+// The workspace buffers of a solver, carved from one stream-ordered
+// allocation (one hipMallocAsync and one hipFreeAsync per solver; a serving
+// pool creates and releases solvers while requests run).  256-byte aligned.
+struct Arena {
+  std::vector<std::pair<void**, size_t>> slots;   // destination, offset
+  size_t total = 0;
+  void* base = nullptr;
+  template <typename P>
+  void add(P** dst, size_t bytes) {
+    const size_t off = (total + 255) & ~(size_t)255;
+    total = off + (bytes ? bytes : 16);
+    slots.emplace_back(reinterpret_cast<void**>(dst), off);
+  }
+  int finish(hipStream_t st) {
+    if (hipMallocAsync(&base, total ? total : 16, st) != hipSuccess) {
+      base = nullptr;
+      return FCMDP_ENOMEM;
+    }
+    for (auto& sl : slots) *sl.first = static_cast<unsigned char*>(base) + sl.second;
+    return FCMDP_OK;
   }
 };
 
 void free_all(fcmdp_solver* s, hipStream_t st) {
-  void* ptrs[] = {s->grid, s->spec, s->keyA, s->keyB, s->valA, s->valB,
-                  s->hist, s->cell_start, s->pinfo, s->pw, s->pf, s->psi,
-                  s->band, s->nbad, s->zc, s->quad, s->dct_f, s->dct_i,
-                  s->dct_f32, s->dct_i32,
-                  s->dftc, s->dftc_t, s->tw_x, s->tw_y, s->tw_r,
-                  s->lz_basis, s->lz_red, s->psi64, s->fzlo, s->lowk_part,
-                  s->lowk_coef, s->lowk_ex, s->lowk_ey, s->pdw, s->dpsi,
-                  s->wallspec};
+  // the workspace and table arenas hold every buffer of creation; the wall
+  // spectrum and the Lanczos buffers are allocated on their own
+  void* ptrs[] = {s->arena, s->tables, s->lz_basis, s->lz_red, s->wallspec};
   // stream-ordered frees: no device-wide synchronisation
   for (void* q : ptrs)
     if (q) (void)hipFreeAsync(q, st);
@@ -477,23 +516,18 @@ int fcmdp_create_solver(const fcmdp_params* p, void* hip_stream,
   const Sizes z = sizes_for(p, s->cap, dp.ZW);
   // stream-ordered allocations on the creation stream (no device-wide
   // synchronisation, so applies in flight on other streams keep running)
-  auto alloc = [&](void** ptr, size_t bytes) {
-    if (err != FCMDP_OK) return;
-    if (hipMallocAsync(ptr, bytes ? bytes : 16, st) != hipSuccess) {
-      *ptr = nullptr;
-      err = FCMDP_ENOMEM;
-    }
-  };
-  Uploader upload{st, {}, &err};
+  Arena arena;
+  auto alloc = [&](auto** ptr, size_t bytes) { arena.add(ptr, bytes); };
+  Uploader upload{st, {}, {}, nullptr};
   alloc(&s->grid, z.grid);
   alloc(&s->spec, z.spec);
-  alloc((void**)&s->keyA, z.keys);
-  alloc((void**)&s->keyB, z.keys);
-  alloc((void**)&s->valA, z.vals);
-  alloc((void**)&s->valB, z.vals);
-  alloc((void**)&s->hist, z.hist);
-  alloc((void**)&s->cell_start, z.cells);
-  alloc((void**)&s->pinfo, z.pinfo);
+  alloc(&s->keyA, z.keys);
+  alloc(&s->keyB, z.keys);
+  alloc(&s->valA, z.vals);
+  alloc(&s->valB, z.vals);
+  alloc(&s->hist, z.hist);
+  alloc(&s->cell_start, z.cells);
+  alloc(&s->pinfo, z.pinfo);
   alloc(&s->pw, z.pw);
   alloc(&s->pf, z.pf);
   alloc(&s->psi, z.psi);
@@ -502,13 +536,15 @@ int fcmdp_create_solver(const fcmdp_params* p, void* hip_stream,
     alloc(&s->dpsi, z.dpsi);
   }
   if (s->lowk_ns > 0) {
-    alloc((void**)&s->psi64, z.psi64);
-    alloc((void**)&s->fzlo, z.fzlo);
-    alloc((void**)&s->lowk_part, z.lowk_part);
-    alloc((void**)&s->lowk_coef, z.lowk_coef);
+    alloc(&s->psi64, z.psi64);
+    alloc(&s->fzlo, z.fzlo);
+    alloc(&s->lowk_part, z.lowk_part);
+    alloc(&s->lowk_coef, z.lowk_coef);
   }
-  alloc((void**)&s->band, 2 * sizeof(int));
-  alloc((void**)&s->nbad, sizeof(unsigned int));
+  alloc(&s->band, 2 * sizeof(int));
+  alloc(&s->nbad, sizeof(unsigned int));
+  err = arena.finish(st);
+  s->arena = arena.base;
 
   // Chebyshev tables
   if (err == FCMDP_OK) {
@@ -526,22 +562,22 @@ int fcmdp_create_solver(const fcmdp_params* p, void* hip_stream,
       }
     const std::vector<double> w = clenshaw_curtis(Nz);
     const double h2 = dp.h * dp.h;
-    s->zc = (double*)upload(zc);
-    s->dct_f = (double*)upload(Mf);
-    s->dct_i = (double*)upload(Pi);
+    upload.to(&s->zc, zc);
+    upload.to(&s->dct_f, Mf);
+    upload.to(&s->dct_i, Pi);
     if (s->mixed) {
       std::vector<float> mf(Mf.begin(), Mf.end()), pf(Pi.begin(), Pi.end());
-      s->dct_f32 = (float*)upload(mf);
-      s->dct_i32 = (float*)upload(pf);
+      upload.to(&s->dct_f32, mf);
+      upload.to(&s->dct_i32, pf);
     }
     if (s->mixed) {
       std::vector<float> q(Nz);
       for (int c = 0; c < Nz; ++c) q[c] = (float)(h2 * 0.5 * p->H * w[c]);
-      s->quad = upload(q);
+      upload.to(&s->quad, q);
     } else {
       std::vector<double> q(Nz);
       for (int c = 0; c < Nz; ++c) q[c] = h2 * 0.5 * p->H * w[c];
-      s->quad = upload(q);
+      upload.to(&s->quad, q);
     }
     // small prime DFT constants
     std::vector<double> cs;
@@ -554,40 +590,47 @@ int fcmdp_create_solver(const fcmdp_params* p, void* hip_stream,
         cs.push_back(sinpi_frac(2L * m, P));
       }
     }
-    s->dftc = (double*)upload(cs);
+    upload.to(&s->dftc, cs);
     if (s->mixed) {
       std::vector<float> c32(cs.begin(), cs.end());
-      s->dftc_t = upload(c32);
+      upload.to(&s->dftc_t, c32);
     } else {
-      s->dftc_t = upload(cs);
+      upload.to(&s->dftc_t, cs);
     }
     if (s->lowk_ns > 0) {
       // e^{-2 pi i nx a / Nx} for nx = 0..ns ([a][nx]) and e^{-2 pi i m / Ny}
       const int nk = s->lowk_ns + 1;
       std::vector<double> ex(2 * (size_t)p->Nx * nk), ey(2 * (size_t)p->Ny);
+      const std::vector<double> root = roots_of_unity(p->Nx);
       for (int a = 0; a < p->Nx; ++a)
         for (int n = 0; n < nk; ++n) {
           const long m = ((long)n * a) % p->Nx;
-          ex[2 * ((size_t)a * nk + n)] = cospi_frac(2L * m, p->Nx);
-          ex[2 * ((size_t)a * nk + n) + 1] = -sinpi_frac(2L * m, p->Nx);
+          ex[2 * ((size_t)a * nk + n)] = root[2 * (size_t)m];
+          ex[2 * ((size_t)a * nk + n) + 1] = root[2 * (size_t)m + 1];
         }
       for (int m = 0; m < p->Ny; ++m) {
         ey[2 * (size_t)m] = cospi_frac(2L * m, p->Ny);
         ey[2 * (size_t)m + 1] = -sinpi_frac(2L * m, p->Ny);
       }
-      s->lowk_ex = (double2*)upload(ex);
-      s->lowk_ey = (double2*)upload(ey);
+      upload.to(&s->lowk_ex, ex);
+      upload.to(&s->lowk_ey, ey);
     }
     const int M = p->Nx / 2;
+    const std::vector<double> rx = roots_of_unity(p->Nx);
+    const std::vector<double> ry = p->Ny == p->Nx ? rx : roots_of_unity(p->Ny);
     if (s->mixed) {
-      s->tw_x = upload.twiddles<float>(M, M);
-      s->tw_y = upload.twiddles<float>(p->Ny, p->Ny);
-      s->tw_r = upload.twiddles<float>(p->Nx, M + 1);
+      upload.twiddles<float>(&s->tw_x, rx, 2, M);       // roots of Nx / 2
+      upload.twiddles<float>(&s->tw_y, ry, 1, p->Ny);
+      upload.twiddles<float>(&s->tw_r, rx, 1, M + 1);
     } else {
-      s->tw_x = upload.twiddles<double>(M, M);
-      s->tw_y = upload.twiddles<double>(p->Ny, p->Ny);
-      s->tw_r = upload.twiddles<double>(p->Nx, M + 1);
+      upload.twiddles<double>(&s->tw_x, rx, 2, M);
+      upload.twiddles<double>(&s->tw_y, ry, 1, p->Ny);
+      upload.twiddles<double>(&s->tw_r, rx, 1, M + 1);
     }
+  }
+  if (err == FCMDP_OK) {
+    err = upload.finish();
+    s->tables = upload.base;
   }
   if (err == FCMDP_OK) {
     if (fcmdp::launch_set_band(s, Nz, -1, st) != hipSuccess ||

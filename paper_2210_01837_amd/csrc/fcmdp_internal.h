@@ -106,7 +106,10 @@ struct fcmdp_solver {
   int key_passes = 0;
   int nblk_cap = 0;
 
-  // device buffers
+  // device buffers: every workspace buffer below is carved from `arena`,
+  // every table from `tables` (one stream-ordered allocation each)
+  void* arena = nullptr;
+  void* tables = nullptr;
   void* grid = nullptr;
   void* spec = nullptr;
   uint32_t* keyA = nullptr;
