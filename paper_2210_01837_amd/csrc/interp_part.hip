@@ -254,25 +254,31 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
       for (int k = 0; k < 2; ++k) {
         const int h = g + NG * k;
         if (h >= np) continue;
-        // (first window column, first row, z window), tile-local
+        // (first window column, first row, z window), tile-local, in one
+        // 16-byte read; without z overlap the row range is empty
         const int4 geo = pci[h];
-        if (geo.w < c0 || geo.z > c0 + nz - 1) continue;   // no z overlap
+        const bool zin = (geo.w >= c0) & (geo.z <= c0 + nz - 1);
         const int sy = geo.y;
         // the lane's column pair: both in the tile or both outside (tile
         // widths are even)
         const int e0 = (geo.x & ~1) + 2 * l;
         const bool xon = (unsigned)e0 < (unsigned)tw;
         const int ec = xon ? e0 : 0;
-        const int ra = max(sy, 0), rb = min(sy + 6, th - 1);
+        const int ra = max(sy, 0), rb = zin ? min(sy + 6, th - 1) : ra - 1;
         const T* w = pcw + h * kRec;
         const T* zs = pz + h * NZS;
         T pm[ZC], pd[ZC], pq[ZC];
 #pragma unroll
         for (int sidx = 0; sidx < ZC; ++sidx) {
-          const bool ok = sidx < nz && xon;
-          pm[sidx] = ok ? q[sidx] * zs[sidx] : T(0);
-          pd[sidx] = ok ? q[sidx] * zs[ZC + sidx] : T(0);
-          if constexpr (DT) pq[sidx] = ok ? q[sidx] * zs[2 * ZC + sidx] : T(0);
+          // read unconditionally (the staged row of particle h), then select
+          const T zm = zs[sidx], zd = zs[ZC + sidx];
+          const bool ok = (sidx < nz) & xon;
+          pm[sidx] = ok ? q[sidx] * zm : T(0);
+          pd[sidx] = ok ? q[sidx] * zd : T(0);
+          if constexpr (DT) {
+            const T zq = zs[2 * ZC + sidx];
+            pq[sidx] = ok ? q[sidx] * zq : T(0);
+          }
         }
         // the window's seven rows, unrolled (rows outside the tile skipped)
 #pragma unroll
