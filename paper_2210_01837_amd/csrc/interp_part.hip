@@ -23,11 +23,12 @@ namespace {
 
 constexpr int kPX = 32;               // tile columns (128-byte rows in FP32)
 constexpr int kPY = 16;               // tile rows
+constexpr int kKP = 2;                // particles per four-lane group and pass
 constexpr int kPRW = kPX + 6;         // cell columns whose windows meet a tile
 constexpr int kPRH = kPY + 6;         // cell rows
 constexpr int kPSeg = 2 * kPRH;       // cell-row segments (split at the seam)
 constexpr int kPThreads = 512;
-static_assert(kPSeg <= 64, "one wavefront scans the segments");
+constexpr int kSegW = (kPSeg + 63) / 64;  // wavefronts of the segment scan
 
 template <typename T> struct V16;
 template <> struct V16<float> { typedef float type __attribute__((ext_vector_type(4))); };
@@ -77,6 +78,7 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
   int* pcs = pcp + cap;                                 // [cap] slot
   __shared__ int segoff[kPSeg + 1];
   __shared__ int segst[kPSeg];
+  __shared__ int wsum[kSegW];
   __shared__ int zr[2];
 
   const int lo = band[0], hi = band[1];
@@ -90,9 +92,10 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
   const int tw = min(kPX, Nx - tx0), th = min(kPY, Ny - ty0);
 
   // cell-row segments of the particles' region: row r, part k (k = 1 is the
-  // part past the periodic seam in x)
-  if (tid < 64) {
-    int cnt = 0, st = 0;
+  // part past the periodic seam in x); a prefix sum over the segments, one
+  // wavefront per 64 of them
+  int sg_cnt = 0, sg_st = 0, sg_incl = 0;
+  if (tid < 64 * kSegW) {
     if (tid < 2 * (th + 6)) {
       const int r = tid >> 1, k = tid & 1;
       const int row = wrap_near(ty0 - 3 + r, Ny) * Nx;
@@ -100,19 +103,25 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
       const int xe0 = xs + len <= Nx ? xs + len : Nx;
       const int ca = k ? 0 : xs, cb = k ? xs + len - xe0 : xe0;
       if (ca < cb) {
-        st = cell_start[row + ca];
-        cnt = cell_start[row + cb] - st;
+        sg_st = cell_start[row + ca];
+        sg_cnt = cell_start[row + cb] - sg_st;
       }
     }
-    int incl = cnt;
+    const int lane = tid & 63;
+    sg_incl = sg_cnt;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-      const int t = __shfl_up(incl, d);
-      if (tid >= d) incl += t;
+      const int t = __shfl_up(sg_incl, d);
+      if (lane >= d) sg_incl += t;
     }
+    if (lane == 63) wsum[tid >> 6] = sg_incl;
+  }
+  __syncthreads();
+  if (tid < 64 * kSegW) {
+    for (int w = 0; w < (tid >> 6); ++w) sg_incl += wsum[w];
     if (tid < kPSeg) {
-      segst[tid] = st;
-      segoff[tid + 1] = incl;
+      segst[tid] = sg_st;
+      segoff[tid + 1] = sg_incl;
     }
     if (tid == 0) segoff[0] = 0;
   }
@@ -123,7 +132,7 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
   const size_t chstride = plane * dp.Nz;
   // four lanes per particle, two neighbouring columns each (one 8- or
   // 16-byte LDS read per plane, channel and row); a group holds the sums of
-  // its particles h = g and h = g + NG in registers over all z-chunks
+  // its particles h = g + NG k (k < kKP) in registers over all z-chunks
   constexpr int GL = 4;
   const int g = tid / GL, l = tid % GL;
   constexpr int NG = kPThreads / GL;
@@ -194,9 +203,9 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
     // Y = psi_D phi_D'(y), Z = psi_D' phi_D(y) (Omega = (1/2) u x grad
     // Delta_D takes the x weights phi_D, phi_D' per term).
     constexpr int NA = DT ? 8 : NOUT;
-    T sacc[2][2][NA];
+    T sacc[kKP][2][NA];
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < kKP; ++k)
 #pragma unroll
       for (int e = 0; e < 2; ++e)
 #pragma unroll
@@ -251,7 +260,7 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
       __syncthreads();
       if (c0 + ZC <= c_last) fetch(c0 + ZC);
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < kKP; ++k) {
         const int h = g + NG * k;
         if (h >= np) continue;
         // (first window column, first row, z window), tile-local, in one
@@ -338,7 +347,7 @@ k_interp_part(DevParams dp, const int* __restrict__ band,
     // (fixed order), and the partial sums of this tile
     const int nslot = nqx * nqy;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kKP; ++k) {
       const int h = g + NG * k;
       const bool on = h < np;
       const int hc = on ? h : 0;
@@ -486,8 +495,7 @@ hipError_t part_impl(const fcmdp_solver* s, int n, const T* grid, T* U, T* Om,
   // small (35 KB in FP32, 64 KB in FP64), so that several share a CU:
   // the kernel waits on LDS and memory latency more than on either's rate.
   constexpr int ZC = 1;
-  const int cap = 256;
-  if (cap > 2 * (kPThreads / 4)) return hipErrorInvalidValue;  // two per lane group
+  const int cap = kKP * (kPThreads / 4);
   if (Om && dp.dt_omega)
     part_launch<T, ZC, 3, true>(s, n, grid, U, Om, cap, nqx, nqy, st);
   else if (Om && dp.nch_out == 6)
