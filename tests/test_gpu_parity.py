@@ -404,6 +404,30 @@ def _golden(name):
     return np.load(path)
 
 
+@pytest.mark.parametrize("name", ["bw1m", "sc1m"])
+def test_interp_tiles_full_size_every_particle(name):
+    """At N = 1M, every particle's U and Omega from the aligned-tile
+    interpolation against the halo-tile kernel in the same apply (the two
+    differ only in the summation order of the FP32 interpolation)."""
+    wl = workloads.WORKLOADS[name]
+    pos, F, T = workloads.particles(name)
+    print(f"[interp tiles full size] {name} N={len(pos)}", flush=True)
+    from paper_2210_01837_amd import Solver
+    s = Solver.from_box(wl.box, precision="mixed", max_particles=wl.n)
+    P, Fd, Td = _dev(pos, "mixed"), _dev(F, "mixed"), _dev(T, "mixed")
+    U, Om = s.apply(P, Fd, Td)
+    s.set_variant("halo_interp", 1)
+    Uh, Oh = s.apply(P, Fd, Td)
+    assert s.status() == (0, 0)
+    for got, ref in ((U, Uh), (Om, Oh)):
+        g, r = _np(got), _np(ref)
+        assert np.all(np.isfinite(g))
+        e, ep = rel_err(g, r), particle_err(g, r)
+        print(f"  rel {e:.2e} max particle {ep:.2e}", flush=True)
+        assert e < 1e-6 and ep < 1e-5
+    s.close()
+
+
 @pytest.mark.parametrize("name", list(GOLDEN))
 def test_apply_mixed_full_size_golden(name):
     g = _golden(name)
