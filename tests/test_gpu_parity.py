@@ -428,6 +428,31 @@ def test_interp_tiles_full_size_every_particle(name):
     s.close()
 
 
+def test_spread_mfma_full_size_every_particle():
+    """At N = 1M, every particle's U and Omega with the matrix-core spread
+    against the per-patch gather spread in the same apply (FP32 sums in a
+    different order)."""
+    wl = workloads.WORKLOADS["bw1m"]
+    pos, F, T = workloads.particles("bw1m")
+    print(f"[spread mfma full size] bw1m N={len(pos)}", flush=True)
+    from paper_2210_01837_amd import Solver
+    s = Solver.from_box(wl.box, precision="mixed", max_particles=wl.n)
+    P, Fd, Td = _dev(pos, "mixed"), _dev(F, "mixed"), _dev(T, "mixed")
+    U, Om = s.apply(P, Fd, Td)
+    s.set_variant("wave_spread", 1)
+    Uw, Ow = s.apply(P, Fd, Td)
+    assert s.status() == (0, 0)
+    # each spread is within 2.3e-6 (U) of the oracle at this size (the
+    # golden test), so the two agree to their sum; per particle 10x that,
+    # as in the golden tests
+    for got, ref in ((U, Uw), (Om, Ow)):
+        g, r = _np(got), _np(ref)
+        e, ep = rel_err(g, r), particle_err(g, r)
+        print(f"  rel {e:.2e} max particle {ep:.2e}", flush=True)
+        assert e < 5e-6 and ep < 5e-5
+    s.close()
+
+
 @pytest.mark.parametrize("name", list(GOLDEN))
 def test_apply_mixed_full_size_golden(name):
     g = _golden(name)
